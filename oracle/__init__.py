@@ -1,0 +1,230 @@
+"""FP64 CPU oracle for the ray-query path (TEST INFRASTRUCTURE ONLY).
+
+Only the test suite, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this package.  The product library never
+loads it: it is the independent reference the HIP path is checked against.
+
+The arithmetic lives in ``rt_oracle.c`` (plain C, double precision, OpenMP
+over rays); this module compiles it with gcc and marshals numpy arrays.
+
+Every query is a linear search over all triangles, the definition of the
+closest hit in the paper's §3.3, with the plane-then-edge test of §3.1.  See
+the header of ``rt_oracle.c`` for the readings taken where the paper is
+silent.  ``accept`` implements the FP32 tolerance model (acceptable sets),
+``adjoint`` the implicit-function adjoint of (t,u,v) and ``fd`` central finite
+differences of the plane formula.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rt_oracle.c")
+_HDR = os.path.join(_HERE, "rt_oracle.h")
+_OUT_DIR = os.path.join(_HERE, "_build")
+LIB_PATH = os.path.join(_OUT_DIR, "librt_oracle.so")
+
+NONE = 0xFFFFFFFF
+DELTA = 2.0 ** -20  # relative input slack of the acceptable-set model (16 float32 unit roundoffs)
+
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    os.makedirs(_OUT_DIR, exist_ok=True)
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + f".tmp{os.getpid()}"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
+               "-ffp-contract=off", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            build(force=False)
+        lib = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        i64 = C.c_int64
+        for name, args in {
+            "orc_closest": [P, P, i64, P, P, P],
+            "orc_any": [P, P, i64, P],
+            "orc_accept": [P, P, i64, C.c_double, C.c_int32, P, P, P, P, P, P, P],
+            "orc_adjoint": [P, P, P, i64, P, P, P, P],
+            "orc_fd": [P, P, P, i64, P, C.c_double, P],
+            "orc_fixed_tuv": [P, P, P, i64, P],
+        }.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        lib.orc_num_threads.restype = C.c_int
+        lib.orc_set_num_threads.argtypes = [C.c_int]
+        _lib = lib
+        return lib
+
+
+class _Scene(C.Structure):
+    _fields_ = [
+        ("n_mesh", C.c_int32),
+        ("vertices", C.c_void_p),
+        ("n_vertices", C.c_void_p),
+        ("indices", C.c_void_p),
+        ("n_triangles", C.c_void_p),
+        ("n_inst", C.c_int64),
+        ("inst_mesh", C.c_void_p),
+        ("inst_srt", C.c_void_p),
+    ]
+
+
+class OracleScene:
+    """Holds contiguous float32/uint32 copies of a scene and its C descriptor.
+
+    ``meshes``: list of (vertices (V,3) float32, indices (N,3) uint32).
+    ``inst_mesh``/``inst_srt``: optional instance arrays (see workloads)."""
+
+    def __init__(self, meshes, inst_mesh=None, inst_srt=None):
+        self._v = [np.ascontiguousarray(v, dtype=np.float32).reshape(-1, 3) for v, _ in meshes]
+        self._i = [np.ascontiguousarray(i, dtype=np.uint32).reshape(-1, 3) for _, i in meshes]
+        n = len(meshes)
+        self._vp = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in self._v])
+        self._ip = (C.c_void_p * n)(*[a.ctypes.data if a.size else None for a in self._i])
+        self._nv = np.array([a.shape[0] for a in self._v], dtype=np.int64)
+        self._nt = np.array([a.shape[0] for a in self._i], dtype=np.int64)
+        if inst_mesh is not None:
+            self._im = np.ascontiguousarray(inst_mesh, dtype=np.uint32).reshape(-1)
+            self._is = np.ascontiguousarray(inst_srt, dtype=np.float32).reshape(-1, 10)
+            ninst = self._im.shape[0]
+        else:
+            self._im = self._is = None
+            ninst = 0
+        self.n_inst = ninst
+        self.desc = _Scene(
+            n, C.cast(self._vp, C.c_void_p), self._nv.ctypes.data, C.cast(self._ip, C.c_void_p),
+            self._nt.ctypes.data, ninst,
+            self._im.ctypes.data if ninst else None, self._is.ctypes.data if ninst else None)
+
+    @classmethod
+    def from_scene(cls, scene):
+        return cls([(m.vertices, m.indices) for m in scene.meshes], scene.inst_mesh, scene.inst_srt)
+
+    @property
+    def ptr(self):
+        return C.addressof(self.desc)
+
+
+def _rays(rays):
+    r = np.ascontiguousarray(rays, dtype=np.float32).reshape(-1, 8)
+    return r, r.shape[0]
+
+
+def _p(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+def _check(rc, name):
+    if rc != 0:
+        raise ValueError(f"oracle {name}: invalid arguments")
+
+
+def closest(scene: OracleScene, rays):
+    """Returns (inst (n,) uint32, prim (n,) uint32, tuv (n,3) float64)."""
+    lib = _load()
+    r, n = _rays(rays)
+    inst = np.empty(n, np.uint32)
+    prim = np.empty(n, np.uint32)
+    tuv = np.empty((n, 3), np.float64)
+    _check(lib.orc_closest(scene.ptr, _p(r), n, _p(inst), _p(prim), _p(tuv)), "closest")
+    return inst, prim, tuv
+
+
+def any_hit(scene: OracleScene, rays):
+    lib = _load()
+    r, n = _rays(rays)
+    occ = np.empty(n, np.uint8)
+    _check(lib.orc_any(scene.ptr, _p(r), n, _p(occ)), "any")
+    return occ
+
+
+class Accept:
+    """Acceptable sets per ray (see ``rt_oracle.c``)."""
+
+    def __init__(self, miss_ok, count, inst, prim, tuv, scale, any_class, K):
+        self.miss_ok, self.count, self.inst, self.prim = miss_ok, count, inst, prim
+        self.tuv, self.scale, self.any_class, self.K = tuv, scale, any_class, K
+
+    @property
+    def pinned(self):
+        return (self.count + self.miss_ok.astype(np.int32)) == 1
+
+    @property
+    def overflow(self):
+        return self.count > self.K
+
+
+def accept(scene: OracleScene, rays, delta: float = DELTA, K: int = 8) -> Accept:
+    lib = _load()
+    r, n = _rays(rays)
+    miss_ok = np.empty(n, np.uint8)
+    count = np.empty(n, np.int32)
+    ai = np.empty((n, K), np.uint32)
+    ap = np.empty((n, K), np.uint32)
+    at = np.empty((n, K, 3), np.float64)
+    asc = np.empty((n, K), np.float64)
+    ac = np.empty(n, np.uint8)
+    _check(lib.orc_accept(scene.ptr, _p(r), n, float(delta), int(K), _p(miss_ok), _p(count),
+                          _p(ai), _p(ap), _p(at), _p(asc), _p(ac)), "accept")
+    return Accept(miss_ok.astype(bool), count, ai, ap, at, asc, ac, K)
+
+
+def adjoint(scene: OracleScene, rays, prim, g):
+    """Returns (d_vertices (V,3), d_orig (n,3), d_dir (n,3)) in float64."""
+    lib = _load()
+    r, n = _rays(rays)
+    prim = np.ascontiguousarray(prim, dtype=np.uint32).reshape(-1)
+    g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1, 3)
+    nv = int(scene._nv[0])
+    dV = np.zeros((nv, 3), np.float64)
+    do = np.empty((n, 3), np.float64)
+    dd = np.empty((n, 3), np.float64)
+    _check(lib.orc_adjoint(scene.ptr, _p(r), _p(prim), n, _p(g), _p(dV), _p(do), _p(dd)), "adjoint")
+    return dV, do, dd
+
+
+def fd(scene: OracleScene, rays, prim, g, h: float = 1e-6):
+    """Central differences: (n,15) = d/d(v0,v1,v2,o,d) of g.(t,u,v)."""
+    lib = _load()
+    r, n = _rays(rays)
+    prim = np.ascontiguousarray(prim, dtype=np.uint32).reshape(-1)
+    g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1, 3)
+    out = np.empty((n, 15), np.float64)
+    _check(lib.orc_fd(scene.ptr, _p(r), _p(prim), n, _p(g), float(h), _p(out)), "fd")
+    return out
+
+
+def fixed_tuv(scene: OracleScene, rays, prim):
+    lib = _load()
+    r, n = _rays(rays)
+    prim = np.ascontiguousarray(prim, dtype=np.uint32).reshape(-1)
+    tuv = np.empty((n, 3), np.float64)
+    _check(lib.orc_fixed_tuv(scene.ptr, _p(r), _p(prim), n, _p(tuv)), "fixed_tuv")
+    return tuv
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    _load().orc_set_num_threads(int(n))

@@ -1,0 +1,640 @@
+/* rt_oracle.c -- FP64 CPU reference for ray/triangle queries.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg; never by the product library.  It shares no
+ * code, header or table with the HIP path.
+ *
+ * What it follows (arxiv 2603.00292, "Ray Tracing using HIP"):
+ *   - the ray R(t) = o + t d (§3.1, ray equation);
+ *   - the plane parameter t = n.(v0 - o) / n.d with n = (v1-v0) x (v2-v1)
+ *     (§3.1, plane equation and its solution for t);
+ *   - the three inclusive edge tests 0 <= n.((v_{i+1}-v_i) x (R(t)-v_i))
+ *     (§3.1, edge-test inequalities);
+ *   - the accepted range MIN_T <= t <= MAX_T (§3.1 listing), read as the
+ *     per-ray [tmin, tmax], both ends inclusive;
+ *   - the closest hit as the linear search with a strict "t < minT" update in
+ *     ascending triangle order, so the lowest index wins at equal t (§3.3);
+ *   - any hit as "some triangle is hit within the ray's length" (§4.2);
+ *   - two-level scenes: the ray is taken to object space with the inverse of
+ *     the instance transform (§6.2, two-level hierarchy) whose frame is given
+ *     as scale, rotation, translation (§7.3).
+ * Readings where the paper is silent (all documented with the design):
+ *   degenerate triangles (n = 0) and rays parallel to the plane (n.d = 0)
+ *   never hit; t must be finite; rays with a NaN, a zero direction or
+ *   tmin > tmax are misses; faces are two-sided; (u,v) are the barycentric
+ *   weights of v1 and v2, so the hit point is (1-u-v) v0 + u v1 + v v2; a miss
+ *   reports t = +inf, u = v = 0, prim = 0xFFFFFFFF.
+ * The acceptable-set classification, the adjoint and the finite differences
+ * are test machinery derived from those definitions (see each function). */
+#include "rt_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct { double x, y, z; } vec3;
+
+static vec3 mk(double x, double y, double z) { vec3 r = {x, y, z}; return r; }
+static vec3 sub(vec3 a, vec3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+static vec3 add(vec3 a, vec3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+static vec3 scl(vec3 a, double s) { return mk(a.x * s, a.y * s, a.z * s); }
+static double dot(vec3 a, vec3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+static vec3 cross(vec3 a, vec3 b) {
+  return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+static double amax(vec3 a) {
+  double m = fabs(a.x);
+  if (fabs(a.y) > m) m = fabs(a.y);
+  if (fabs(a.z) > m) m = fabs(a.z);
+  return m;
+}
+
+/* ------------------------------------------------------------------------- */
+/* rays and frames                                                            */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+  vec3 o, d;
+  double tmin, tmax;
+} ray64;
+
+static ray64 load_ray(const float* r) {
+  ray64 q;
+  q.o = mk(r[0], r[1], r[2]);
+  q.tmin = r[3];
+  q.d = mk(r[4], r[5], r[6]);
+  q.tmax = r[7];
+  return q;
+}
+
+/* Rays that can never hit (reading of the paper's silence): any NaN, a zero
+ * direction, or an empty range tmin > tmax. */
+static int ray_is_void(const ray64* q) {
+  if (isnan(q->o.x) || isnan(q->o.y) || isnan(q->o.z)) return 1;
+  if (isnan(q->d.x) || isnan(q->d.y) || isnan(q->d.z)) return 1;
+  if (isnan(q->tmin) || isnan(q->tmax)) return 1;
+  if (q->d.x == 0.0 && q->d.y == 0.0 && q->d.z == 0.0) return 1;
+  if (q->tmin > q->tmax) return 1;
+  return 0;
+}
+
+/* Frame world = T + R(qhat)(S*x) and its inverse x = S^-1 R^T (world - T). */
+typedef struct {
+  double R[3][3];
+  vec3 S, T;
+} frame64;
+
+static frame64 load_frame(const float* f) {
+  frame64 F;
+  double qx = f[3], qy = f[4], qz = f[5], qw = f[6];
+  double nq = sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
+  qx /= nq; qy /= nq; qz /= nq; qw /= nq;
+  F.R[0][0] = 1 - 2 * (qy * qy + qz * qz);
+  F.R[0][1] = 2 * (qx * qy - qz * qw);
+  F.R[0][2] = 2 * (qx * qz + qy * qw);
+  F.R[1][0] = 2 * (qx * qy + qz * qw);
+  F.R[1][1] = 1 - 2 * (qx * qx + qz * qz);
+  F.R[1][2] = 2 * (qy * qz - qx * qw);
+  F.R[2][0] = 2 * (qx * qz - qy * qw);
+  F.R[2][1] = 2 * (qy * qz + qx * qw);
+  F.R[2][2] = 1 - 2 * (qx * qx + qy * qy);
+  F.S = mk(f[0], f[1], f[2]);
+  F.T = mk(f[7], f[8], f[9]);
+  return F;
+}
+
+/* R^T a, then divide by the per-axis scale. */
+static vec3 to_object_dir(const frame64* F, vec3 a) {
+  vec3 r = mk(F->R[0][0] * a.x + F->R[1][0] * a.y + F->R[2][0] * a.z,
+              F->R[0][1] * a.x + F->R[1][1] * a.y + F->R[2][1] * a.z,
+              F->R[0][2] * a.x + F->R[1][2] * a.y + F->R[2][2] * a.z);
+  return mk(r.x / F->S.x, r.y / F->S.y, r.z / F->S.z);
+}
+
+/* Infinity norm of the inverse linear part S^-1 R^T (used for slack only). */
+static double inv_linear_norm(const frame64* F) {
+  double m = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    double s = (i == 0 ? F->S.x : (i == 1 ? F->S.y : F->S.z));
+    double row = (fabs(F->R[0][i]) + fabs(F->R[1][i]) + fabs(F->R[2][i])) / fabs(s);
+    if (row > m) m = row;
+  }
+  return m;
+}
+
+/* ------------------------------------------------------------------------- */
+/* scene access                                                               */
+/* ------------------------------------------------------------------------- */
+
+static int scene_valid(const orc_scene* s) {
+  if (!s || s->n_mesh < 1 || !s->vertices || !s->indices || !s->n_vertices || !s->n_triangles)
+    return 0;
+  for (int m = 0; m < s->n_mesh; ++m) {
+    if (s->n_triangles[m] > 0 && (!s->vertices[m] || !s->indices[m])) return 0;
+    for (int64_t k = 0; k < 3 * s->n_triangles[m]; ++k)
+      if ((int64_t)s->indices[m][k] >= s->n_vertices[m]) return 0;
+  }
+  if (s->n_inst > 0) {
+    if (!s->inst_mesh || !s->inst_srt) return 0;
+    for (int64_t j = 0; j < s->n_inst; ++j)
+      if ((int32_t)s->inst_mesh[j] >= s->n_mesh) return 0;
+  }
+  return 1;
+}
+
+static vec3 vtx(const orc_scene* s, int m, uint32_t i) {
+  const float* p = s->vertices[m] + 3 * (int64_t)i;
+  return mk(p[0], p[1], p[2]);
+}
+
+static void tri(const orc_scene* s, int m, int64_t k, vec3* v0, vec3* v1, vec3* v2) {
+  const uint32_t* ix = s->indices[m] + 3 * k;
+  *v0 = vtx(s, m, ix[0]);
+  *v1 = vtx(s, m, ix[1]);
+  *v2 = vtx(s, m, ix[2]);
+}
+
+/* The object-space ray of instance j (or the world ray when there are no
+ * instances); also the mesh id and an extra slack scale (the magnitude of the
+ * rounding a float32 transform of the origin would carry, in object units). */
+static void object_ray(const orc_scene* s, const ray64* w, int64_t j, ray64* q, int* mesh,
+                       double* extra_scale, double* extra_dir) {
+  if (s->n_inst == 0) {
+    *q = *w;
+    *mesh = 0;
+    *extra_scale = 0.0;
+    *extra_dir = 0.0;
+    return;
+  }
+  frame64 F = load_frame(s->inst_srt + 10 * j);
+  q->o = to_object_dir(&F, sub(w->o, F.T));
+  q->d = to_object_dir(&F, w->d);
+  q->tmin = w->tmin;
+  q->tmax = w->tmax;
+  *mesh = (int)s->inst_mesh[j];
+  *extra_scale = inv_linear_norm(&F) * (amax(w->o) + amax(F.T));
+  *extra_dir = inv_linear_norm(&F) * amax(w->d);
+}
+
+/* ------------------------------------------------------------------------- */
+/* §3.1: plane-then-edge ray/triangle test                                    */
+/* ------------------------------------------------------------------------- */
+
+static int intersect_paper(const ray64* q, vec3 v0, vec3 v1, vec3 v2, double* t_out, double* u_out,
+                           double* v_out) {
+  vec3 e0 = sub(v1, v0), e1 = sub(v2, v1), e2 = sub(v0, v2);
+  vec3 n = cross(e0, e1);
+  double nn = dot(n, n);
+  if (!(nn > 0.0) || !isfinite(nn)) return 0; /* degenerate triangle */
+  double den = dot(n, q->d);
+  if (den == 0.0) return 0;                   /* parallel or in-plane ray */
+  double t = dot(sub(v0, q->o), n) / den;
+  if (!isfinite(t)) return 0;
+  if (!(q->tmin <= t && t <= q->tmax)) return 0;
+  vec3 p = add(q->o, scl(q->d, t));
+  double a = dot(n, cross(e0, sub(p, v0)));
+  double b = dot(n, cross(e1, sub(p, v1)));
+  double c = dot(n, cross(e2, sub(p, v2)));
+  if (a < 0.0 || b < 0.0 || c < 0.0) return 0;
+  /* a, b, c are (2 area)*(sub-triangle doubled areas); the sub-triangle
+   * opposite a vertex gives that vertex's weight: c -> v1, a -> v2. */
+  *t_out = t;
+  *u_out = c / nn;
+  *v_out = a / nn;
+  (void)b;
+  return 1;
+}
+
+/* Plane formula at a fixed triangle with no range or inside test; used by the
+ * finite differences, so that perturbations across an edge stay smooth. */
+static void plane_tuv(vec3 o, vec3 d, vec3 v0, vec3 v1, vec3 v2, double* t_out, double* u_out,
+                      double* v_out) {
+  vec3 e0 = sub(v1, v0), e1 = sub(v2, v1), e2 = sub(v0, v2);
+  vec3 n = cross(e0, e1);
+  double nn = dot(n, n);
+  double t = dot(sub(v0, o), n) / dot(n, d);
+  vec3 p = add(o, scl(d, t));
+  *t_out = t;
+  *u_out = dot(n, cross(e2, sub(p, v2))) / nn;
+  *v_out = dot(n, cross(e0, sub(p, v0))) / nn;
+}
+
+/* ------------------------------------------------------------------------- */
+/* closest and any                                                            */
+/* ------------------------------------------------------------------------- */
+
+static int64_t n_units(const orc_scene* s) { return s->n_inst > 0 ? s->n_inst : 1; }
+
+int orc_closest(const orc_scene* s, const float* rays, int64_t nr, uint32_t* inst_out,
+                uint32_t* prim_out, double* tuv_out) {
+  if (nr < 0 || (nr > 0 && (!rays || !prim_out || !tuv_out)) || !scene_valid(s)) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t r = 0; r < nr; ++r) {
+    ray64 w = load_ray(rays + 8 * r);
+    double minT = INFINITY, bu = 0.0, bv = 0.0;
+    uint32_t bi = ORC_NONE, bp = ORC_NONE;
+    if (!ray_is_void(&w)) {
+      for (int64_t j = 0; j < n_units(s); ++j) {
+        ray64 q;
+        int m;
+        double xs, xd;
+        object_ray(s, &w, j, &q, &m, &xs, &xd);
+        for (int64_t k = 0; k < s->n_triangles[m]; ++k) {
+          vec3 v0, v1, v2;
+          double t, u, v;
+          tri(s, m, k, &v0, &v1, &v2);
+          if (intersect_paper(&q, v0, v1, v2, &t, &u, &v) && t < minT) {
+            minT = t; bu = u; bv = v;
+            bi = (uint32_t)j; bp = (uint32_t)k;
+          }
+        }
+      }
+    }
+    if (inst_out) inst_out[r] = bi;
+    prim_out[r] = bp;
+    tuv_out[3 * r + 0] = minT;
+    tuv_out[3 * r + 1] = bu;
+    tuv_out[3 * r + 2] = bv;
+  }
+  return 0;
+}
+
+int orc_any(const orc_scene* s, const float* rays, int64_t nr, uint8_t* occluded) {
+  if (nr < 0 || (nr > 0 && (!rays || !occluded)) || !scene_valid(s)) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t r = 0; r < nr; ++r) {
+    ray64 w = load_ray(rays + 8 * r);
+    int hit = 0;
+    if (!ray_is_void(&w)) {
+      for (int64_t j = 0; j < n_units(s) && !hit; ++j) {
+        ray64 q;
+        int m;
+        double xs, xd;
+        object_ray(s, &w, j, &q, &m, &xs, &xd);
+        for (int64_t k = 0; k < s->n_triangles[m]; ++k) {
+          vec3 v0, v1, v2;
+          double t, u, v;
+          tri(s, m, k, &v0, &v1, &v2);
+          if (intersect_paper(&q, v0, v1, v2, &t, &u, &v)) { hit = 1; break; }
+        }
+      }
+    }
+    occluded[r] = (uint8_t)hit;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* acceptable sets                                                            */
+/* ------------------------------------------------------------------------- */
+/* A float32 implementation decides hit or miss from rounded quantities, so at
+ * edges, silhouettes, ties and range ends several answers are correct.  The
+ * model: the float32 evaluation is exact for inputs moved by a small relative
+ * amount delta; near the triangle this moves the ray line relative to the
+ * triangle by at most
+ *     eta = 2 delta s + 2 tilt L,
+ * s = largest coordinate magnitude involved (origin, vertices and, for
+ * instances, the rounding of the object-space transform of the origin),
+ * L = largest distance from the origin to a vertex, tilt = delta (times the
+ * transform's amplification of the direction for instances).  Then a pair is
+ *   a sure miss when the ray's line stays farther than eta from the triangle,
+ *               or the triangle's extent along the line, widened by eta,
+ *               lies outside [tmin, tmax];
+ *               or (when the plane crossing is well defined) the crossing t
+ *               lies outside [tmin, tmax] by more than rho_t = 2 eta/(cos |d|)
+ *               (cos = |n.d| / (|n||d|): the line and the plane each move by
+ *               at most eta near the triangle);
+ *   a sure hit  when the line crosses the triangle's plane inside the
+ *               triangle at distance at least eta/cos + eta from each edge
+ *               (a shift eta of the line moves the crossing by eta/cos in the
+ *               plane) and t is inside [tmin, tmax] by at least rho_t;
+ *   a maybe     otherwise.
+ * The acceptable closest answers of a ray are the sure and maybe pairs whose
+ * lowest possible t (t - rho_t for a sure hit, the widened extent's start for
+ * a maybe) does not exceed t* = min over sure hits of t + rho_t, plus "miss"
+ * when there is no sure hit. */
+
+typedef struct {
+  double t, u, v, lo, scale;
+  uint32_t inst, prim;
+  int sure;
+} cand;
+
+static int cand_less(const cand* a, const cand* b) {
+  if (a->t != b->t) return a->t < b->t;
+  if (a->inst != b->inst) return a->inst < b->inst;
+  return a->prim < b->prim;
+}
+
+static double norm(vec3 a) { return sqrt(dot(a, a)); }
+
+/* distance between the segment [A,B] and the line o + t d */
+static double seg_line_dist(vec3 A, vec3 B, vec3 o, vec3 d) {
+  vec3 w = cross(sub(A, o), d), z = cross(sub(B, A), d);
+  double zz = dot(z, z), u = 0.0;
+  if (zz > 0.0) {
+    u = -dot(w, z) / zz;
+    if (u < 0.0) u = 0.0;
+    if (u > 1.0) u = 1.0;
+  }
+  return norm(add(w, scl(z, u))) / norm(d);
+}
+
+/* distance from the point p to the line through A and B */
+static double point_line_dist(vec3 p, vec3 A, vec3 B) {
+  vec3 e = sub(B, A);
+  return norm(cross(sub(p, A), e)) / norm(e);
+}
+
+/* classification: 0 sure miss, 1 maybe, 2 sure hit; c->t = t* contribution */
+static int classify(const ray64* q, vec3 v0, vec3 v1, vec3 v2, double delta, double extra_scale,
+                    double extra_dir, cand* c, double* hi) {
+  vec3 a0 = sub(v0, q->o), a1 = sub(v1, q->o), a2 = sub(v2, q->o);
+  double s = amax(q->o);
+  if (amax(v0) > s) s = amax(v0);
+  if (amax(v1) > s) s = amax(v1);
+  if (amax(v2) > s) s = amax(v2);
+  if (extra_scale > s) s = extra_scale;
+  double L = norm(a0);
+  if (norm(a1) > L) L = norm(a1);
+  if (norm(a2) > L) L = norm(a2);
+  double dm = amax(q->d), tilt = delta;
+  if (extra_dir > dm) tilt = delta * extra_dir / dm;
+  double eta = 2.0 * delta * s + 2.0 * tilt * L;
+  double dn = norm(q->d);
+
+  /* does the line cross the triangle (edge functions of one sign)? */
+  double E0 = dot(q->d, cross(a1, a2)), E1 = dot(q->d, cross(a2, a0)), E2 = dot(q->d, cross(a0, a1));
+  int crosses = (E0 + E1 + E2 != 0.0) &&
+                ((E0 >= 0.0 && E1 >= 0.0 && E2 >= 0.0) || (E0 <= 0.0 && E1 <= 0.0 && E2 <= 0.0));
+  double dist = 0.0;
+  if (!crosses) {
+    dist = seg_line_dist(v0, v1, q->o, q->d);
+    double d1 = seg_line_dist(v1, v2, q->o, q->d), d2 = seg_line_dist(v2, v0, q->o, q->d);
+    if (d1 < dist) dist = d1;
+    if (d2 < dist) dist = d2;
+  }
+  if (!(dist <= eta)) return 0;
+  /* extent of the triangle along the line, widened by eta */
+  double dd = dot(q->d, q->d);
+  double p0 = dot(a0, q->d) / dd, p1 = dot(a1, q->d) / dd, p2 = dot(a2, q->d) / dd;
+  double tlo = p0, thi = p0;
+  if (p1 < tlo) tlo = p1;
+  if (p2 < tlo) tlo = p2;
+  if (p1 > thi) thi = p1;
+  if (p2 > thi) thi = p2;
+  tlo -= eta / dn;
+  thi += eta / dn;
+  if (thi < q->tmin || tlo > q->tmax) return 0;
+
+  double t, u, v;
+  plane_tuv(q->o, q->d, v0, v1, v2, &t, &u, &v); /* values by the plane formula of §3.1 */
+  vec3 n = cross(sub(v1, v0), sub(v2, v0));
+  double nl = norm(n);
+  double cs = (nl > 0.0) ? fabs(dot(n, q->d)) / (nl * dn) : 0.0;
+  /* where the plane crossing is well defined, the line and the plane near the
+   * triangle each move by at most eta, so the crossing moves along the ray
+   * by at most rt */
+  double rt = (cs > 0.0 && isfinite(t)) ? 2.0 * eta / (cs * dn) : INFINITY;
+  if (isfinite(rt)) {
+    if (t - rt > tlo) tlo = t - rt;
+    if (t + rt < thi) thi = t + rt;
+    if (thi < q->tmin || tlo > q->tmax) return 0;
+  }
+  c->t = t;
+  c->u = u;
+  c->v = v;
+  c->scale = s;
+  c->lo = tlo;
+  *hi = INFINITY;
+  if (crosses && isfinite(rt)) {
+    double need = eta / cs + eta;
+    vec3 p = add(q->o, scl(q->d, t));
+    double cl = point_line_dist(p, v0, v1);
+    double c1 = point_line_dist(p, v1, v2), c2 = point_line_dist(p, v2, v0);
+    if (c1 < cl) cl = c1;
+    if (c2 < cl) cl = c2;
+    if (cl >= need && t - rt >= q->tmin && t + rt <= q->tmax) {
+      c->lo = t - rt;
+      *hi = t + rt;
+      return 2;
+    }
+  }
+  return 1;
+}
+
+int orc_accept(const orc_scene* s, const float* rays, int64_t nr, double delta, int32_t K,
+               uint8_t* miss_ok, int32_t* count, uint32_t* acc_inst, uint32_t* acc_prim,
+               double* acc_tuv, double* acc_scale, uint8_t* any_class) {
+  if (nr < 0 || K < 1 || !scene_valid(s)) return -1;
+  if (nr > 0 && (!rays || !miss_ok || !count || !acc_inst || !acc_prim || !acc_tuv ||
+                 !acc_scale || !any_class))
+    return -1;
+  int bad = 0;
+#pragma omp parallel
+  {
+    int64_t cap = 64, n = 0;
+    cand* buf = (cand*)malloc(sizeof(cand) * cap);
+    if (!buf) {
+#pragma omp atomic write
+      bad = 1;
+    }
+#pragma omp for schedule(dynamic, 8)
+    for (int64_t r = 0; r < nr; ++r) {
+      if (!buf) continue;
+      ray64 w = load_ray(rays + 8 * r);
+      double tstar = INFINITY;
+      int any_sure = 0;
+      n = 0;
+      if (!ray_is_void(&w)) {
+        for (int64_t j = 0; j < n_units(s); ++j) {
+          ray64 q;
+          int m;
+          double xs, xd;
+          object_ray(s, &w, j, &q, &m, &xs, &xd);
+          for (int64_t k = 0; k < s->n_triangles[m]; ++k) {
+            vec3 v0, v1, v2;
+            cand c;
+            tri(s, m, k, &v0, &v1, &v2);
+            double hi;
+            int cls = classify(&q, v0, v1, v2, delta, xs, xd, &c, &hi);
+            if (cls == 0) continue;
+            c.inst = s->n_inst > 0 ? (uint32_t)j : 0u;
+            c.prim = (uint32_t)k;
+            c.sure = (cls == 2);
+            if (c.sure) {
+              any_sure = 1;
+              if (hi < tstar) tstar = hi;
+            }
+            if (n == cap) {
+              cand* nb = (cand*)realloc(buf, sizeof(cand) * cap * 2);
+              if (!nb) continue;
+              buf = nb;
+              cap *= 2;
+            }
+            buf[n++] = c;
+          }
+        }
+      }
+      /* keep the candidates that can still be the closest, sorted by (t, inst, prim) */
+      int64_t kept = 0;
+      for (int64_t i = 0; i < n; ++i)
+        if (!(buf[i].lo > tstar)) buf[kept++] = buf[i];
+      for (int64_t i = 1; i < kept; ++i) {
+        cand x = buf[i];
+        int64_t jj = i - 1;
+        while (jj >= 0 && cand_less(&x, &buf[jj])) { buf[jj + 1] = buf[jj]; --jj; }
+        buf[jj + 1] = x;
+      }
+      miss_ok[r] = (uint8_t)(!any_sure);
+      count[r] = (int32_t)kept;
+      any_class[r] = any_sure ? 1 : (n == 0 ? 0 : 2);
+      for (int64_t i = 0; i < K; ++i) {
+        int64_t o = r * K + i;
+        if (i < kept) {
+          acc_inst[o] = buf[i].inst;
+          acc_prim[o] = buf[i].prim;
+          acc_tuv[3 * o + 0] = buf[i].t;
+          acc_tuv[3 * o + 1] = buf[i].u;
+          acc_tuv[3 * o + 2] = buf[i].v;
+          acc_scale[o] = buf[i].scale;
+        } else {
+          acc_inst[o] = ORC_NONE;
+          acc_prim[o] = ORC_NONE;
+          acc_tuv[3 * o + 0] = INFINITY;
+          acc_tuv[3 * o + 1] = 0.0;
+          acc_tuv[3 * o + 2] = 0.0;
+          acc_scale[o] = 0.0;
+        }
+      }
+    }
+    free(buf);
+  }
+  return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* adjoint and finite differences                                             */
+/* ------------------------------------------------------------------------- */
+/* Implicit differentiation of M x = o - v0 with M = [-d | v1-v0 | v2-v0] and
+ * x = (t,u,v): for g = dL/dx, lambda = M^-T g and
+ *   dL/do = lambda, dL/dd = t lambda,
+ *   dL/dv0 = -(1-u-v) lambda, dL/dv1 = -u lambda, dL/dv2 = -v lambda. */
+
+int orc_adjoint(const orc_scene* s, const float* rays, const uint32_t* prim, int64_t nr,
+                const double* g, double* d_vertices, double* d_orig, double* d_dir) {
+  if (nr < 0 || !scene_valid(s) || s->n_inst != 0) return -1;
+  if (nr > 0 && (!rays || !prim || !g || !d_vertices || !d_orig || !d_dir)) return -1;
+  for (int64_t r = 0; r < nr; ++r) {
+    double* go = d_orig + 3 * r;
+    double* gd = d_dir + 3 * r;
+    go[0] = go[1] = go[2] = 0.0;
+    gd[0] = gd[1] = gd[2] = 0.0;
+    uint32_t k = prim[r];
+    if (k == ORC_NONE) continue;
+    if ((int64_t)k >= s->n_triangles[0]) return -1;
+    ray64 q = load_ray(rays + 8 * r);
+    const uint32_t* ix = s->indices[0] + 3 * (int64_t)k;
+    vec3 v0 = vtx(s, 0, ix[0]), v1 = vtx(s, 0, ix[1]), v2 = vtx(s, 0, ix[2]);
+    vec3 e1 = sub(v1, v0), e2 = sub(v2, v0), c0 = scl(q.d, -1.0);
+    vec3 r0 = cross(e1, e2), r1 = cross(e2, c0), r2 = cross(c0, e1);
+    double det = dot(c0, r0);
+    if (det == 0.0) continue;
+    r0 = scl(r0, 1.0 / det);
+    r1 = scl(r1, 1.0 / det);
+    r2 = scl(r2, 1.0 / det);
+    vec3 rhs = sub(q.o, v0);
+    double t = dot(r0, rhs), u = dot(r1, rhs), v = dot(r2, rhs);
+    const double* gr = g + 3 * r;
+    /* lambda = M^-T g = sum_i g_i row_i(M^-1) */
+    vec3 lam = add(add(scl(r0, gr[0]), scl(r1, gr[1])), scl(r2, gr[2]));
+    go[0] = lam.x; go[1] = lam.y; go[2] = lam.z;
+    gd[0] = t * lam.x; gd[1] = t * lam.y; gd[2] = t * lam.z;
+    double w[3] = {1.0 - u - v, u, v};
+    for (int c = 0; c < 3; ++c) {
+      double* dv = d_vertices + 3 * (int64_t)ix[c];
+      dv[0] -= w[c] * lam.x;
+      dv[1] -= w[c] * lam.y;
+      dv[2] -= w[c] * lam.z;
+    }
+  }
+  return 0;
+}
+
+static double coord(vec3* v, int i) { return i == 0 ? v->x : (i == 1 ? v->y : v->z); }
+static void set_coord(vec3* v, int i, double x) {
+  if (i == 0) v->x = x; else if (i == 1) v->y = x; else v->z = x;
+}
+
+int orc_fd(const orc_scene* s, const float* rays, const uint32_t* prim, int64_t nr,
+           const double* g, double h, double* out) {
+  if (nr < 0 || !scene_valid(s) || s->n_inst != 0 || !(h > 0.0)) return -1;
+  if (nr > 0 && (!rays || !prim || !g || !out)) return -1;
+  for (int64_t r = 0; r < nr; ++r)
+    if (prim[r] != ORC_NONE && (int64_t)prim[r] >= s->n_triangles[0]) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t r = 0; r < nr; ++r) {
+    double* res = out + 15 * r;
+    if (prim[r] == ORC_NONE) {
+      for (int i = 0; i < 15; ++i) res[i] = 0.0;
+      continue;
+    }
+    ray64 q = load_ray(rays + 8 * r);
+    vec3 p[5];
+    tri(s, 0, prim[r], &p[0], &p[1], &p[2]);
+    p[3] = q.o;
+    p[4] = q.d;
+    const double* gr = g + 3 * r;
+    for (int a = 0; a < 5; ++a) {
+      for (int i = 0; i < 3; ++i) {
+        double x0 = coord(&p[a], i), lp, lm, t, u, v;
+        set_coord(&p[a], i, x0 + h);
+        plane_tuv(p[3], p[4], p[0], p[1], p[2], &t, &u, &v);
+        lp = gr[0] * t + gr[1] * u + gr[2] * v;
+        set_coord(&p[a], i, x0 - h);
+        plane_tuv(p[3], p[4], p[0], p[1], p[2], &t, &u, &v);
+        lm = gr[0] * t + gr[1] * u + gr[2] * v;
+        set_coord(&p[a], i, x0);
+        res[3 * a + i] = (lp - lm) / (2.0 * h);
+      }
+    }
+  }
+  return 0;
+}
+
+int orc_fixed_tuv(const orc_scene* s, const float* rays, const uint32_t* prim, int64_t nr,
+                  double* tuv) {
+  if (nr < 0 || !scene_valid(s) || s->n_inst != 0) return -1;
+  if (nr > 0 && (!rays || !prim || !tuv)) return -1;
+  for (int64_t r = 0; r < nr; ++r) {
+    if (prim[r] == ORC_NONE) {
+      tuv[3 * r] = INFINITY; tuv[3 * r + 1] = 0.0; tuv[3 * r + 2] = 0.0;
+      continue;
+    }
+    if ((int64_t)prim[r] >= s->n_triangles[0]) return -1;
+    ray64 q = load_ray(rays + 8 * r);
+    vec3 v0, v1, v2;
+    tri(s, 0, prim[r], &v0, &v1, &v2);
+    plane_tuv(q.o, q.d, v0, v1, v2, &tuv[3 * r], &tuv[3 * r + 1], &tuv[3 * r + 2]);
+  }
+  return 0;
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

@@ -1,0 +1,87 @@
+/* rt_oracle.h -- FP64 CPU reference for ray/triangle queries.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  The product path never
+ * links, loads or calls it, and it shares no code with the HIP library.
+ *
+ * Everything is computed in double precision from float32 inputs promoted
+ * exactly to double.  The functions are plain linear searches over every
+ * triangle (the definition of the closest hit in the paper's §3.3 listing of
+ * the naive linear search), using the plane-then-edge ray/triangle test of
+ * §3.1.  No acceleration structure, blocking or reordering is used.
+ *
+ * Shared array conventions:
+ *   vertices  float[nv*3]           (x,y,z) per vertex
+ *   indices   uint32[nt*3]          three vertex indices per triangle
+ *   rays      float[nr*8]           (ox,oy,oz,tmin, dx,dy,dz,tmax)
+ *   srt       float[ninst*10]       (sx,sy,sz, qx,qy,qz,qw, tx,ty,tz):
+ *                                   world = T + R(q/|q|)(S*x)
+ *   prim/inst outputs use 0xFFFFFFFF for "none" (a miss).
+ * Return value: 0 on success, -1 on invalid arguments (an index >= nv, a
+ * null pointer with a non-zero count, a mesh id >= mesh count).
+ */
+#ifndef RT_ORACLE_H
+#define RT_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_NONE 0xFFFFFFFFu
+
+/* A scene: n_mesh meshes; either no instances (n_inst == 0: mesh 0 is traced
+ * in world space) or n_inst instances of the meshes with SRT frames. */
+typedef struct {
+  int32_t n_mesh;
+  const float* const* vertices;   /* [n_mesh] */
+  const int64_t* n_vertices;      /* [n_mesh] */
+  const uint32_t* const* indices; /* [n_mesh] */
+  const int64_t* n_triangles;     /* [n_mesh] */
+  int64_t n_inst;
+  const uint32_t* inst_mesh;      /* [n_inst] */
+  const float* inst_srt;          /* [n_inst*10] */
+} orc_scene;
+
+/* Closest hit: lexicographic minimum of (t, inst, prim) over all hits.
+ * Miss: inst = prim = ORC_NONE, t = +inf, u = v = 0.  inst_out may be NULL. */
+int orc_closest(const orc_scene* s, const float* rays, int64_t nr,
+                uint32_t* inst_out, uint32_t* prim_out, double* tuv_out /* nr*3 */);
+
+/* Any hit: 1 when some triangle is hit with t in [tmin, tmax]. */
+int orc_any(const orc_scene* s, const float* rays, int64_t nr, uint8_t* occluded);
+
+/* Acceptable sets of the FP32 tolerance model (delta = relative slack).
+ * For each ray: miss_ok (1 when no pair is a sure hit), count (number of
+ * acceptable (inst, prim) pairs; may exceed K, then only the K smallest by
+ * (t, inst, prim) are stored), the pairs and their FP64 (t,u,v) and the
+ * scale s used in the t tolerance.  any_class: 1 = must be occluded,
+ * 0 = must not be occluded, 2 = either (for an any-hit query). */
+int orc_accept(const orc_scene* s, const float* rays, int64_t nr, double delta, int32_t K,
+               uint8_t* miss_ok, int32_t* count, uint32_t* acc_inst /* nr*K */,
+               uint32_t* acc_prim /* nr*K */, double* acc_tuv /* nr*K*3 */,
+               double* acc_scale /* nr*K */, uint8_t* any_class);
+
+/* Adjoint of (t,u,v) at fixed triangles, single-level scenes only.
+ * prim[r] = ORC_NONE contributes nothing.  g = dL/d(t,u,v) per ray (nr*3).
+ * d_vertices (nv*3) is ACCUMULATED; d_orig / d_dir (nr*3) are overwritten. */
+int orc_adjoint(const orc_scene* s, const float* rays, const uint32_t* prim, int64_t nr,
+                const double* g, double* d_vertices, double* d_orig, double* d_dir);
+
+/* Central finite differences (step h) of l = g.(t,u,v) evaluated at the fixed
+ * triangle prim[r] with the plane formula of §3.1 (no inside or range test).
+ * Output per ray: 15 derivatives: v0.xyz, v1.xyz, v2.xyz, o.xyz, d.xyz. */
+int orc_fd(const orc_scene* s, const float* rays, const uint32_t* prim, int64_t nr,
+           const double* g, double h, double* out /* nr*15 */);
+
+/* (t,u,v) of ray r against triangle prim[r] by the plane formula, no tests. */
+int orc_fixed_tuv(const orc_scene* s, const float* rays, const uint32_t* prim, int64_t nr,
+                  double* tuv);
+
+int orc_num_threads(void);
+void orc_set_num_threads(int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
