@@ -1,0 +1,239 @@
+/* rt.h -- C ABI of the MI355X ray-query library (librtq.so).
+ *
+ * The library answers ray queries against triangle meshes: the closest hit
+ * (t, triangle id, barycentrics u, v), any hit (occlusion) and the adjoint of
+ * the closest hit.  It implements the data-parallel hot path of the method in
+ * arxiv 2603.00292 ("Ray Tracing using HIP"): traversal of a bounding-volume
+ * hierarchy with ray/triangle tests (§6.2 and its traversal paragraph), over
+ * indexed triangle meshes given as float3 vertices and uint3 indices (§7.2),
+ * optionally instanced with scale/rotation/translation frames in a two-level
+ * hierarchy (§6.2 two-level paragraph, §7.3).
+ *
+ * Conventions for every function below
+ *  - Buffers called "device" are HIP device pointers owned by the caller;
+ *    "host" pointers are ordinary host memory read before the call returns.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Query calls only enqueue work on it and return; results are valid once
+ *    the stream has reached that point.
+ *  - Every function returns an rt_status.  Argument errors are detected on the
+ *    host and returned before anything is enqueued; a device fault surfaces as
+ *    RT_ERROR_HIP from a later call.  No C++ exception crosses the boundary.
+ *    rt_last_error_message() gives a thread-local detail string.
+ *  - Ray record (32 bytes, float32): origin o, tmin, direction d, tmax.  The
+ *    ray is R(t) = o + t d (§3.1); t is measured in units of the given d (d is
+ *    never normalised); a hit needs tmin <= t <= tmax (both inclusive, the
+ *    MIN_T/MAX_T of the §3.1 listing).  A ray with a NaN, a zero direction or
+ *    tmin > tmax is a miss, never an error.
+ *  - Triangles are two-sided; edges and vertices are inclusive.  Degenerate
+ *    triangles (zero normal or non-finite vertices) are never hit.
+ *  - Closest hit = lexicographic minimum of (t, instance id, triangle id)
+ *    (the strict "t < minT" linear search of §3.3 visits ids in ascending
+ *    order, so the lowest id wins a tie in t).  A miss reports
+ *    t = +inf, prim_id = RT_INVALID_ID, u = v = 0.
+ *  - (u, v) are the barycentric weights of v1 and v2: the hit point is
+ *    (1-u-v) v0 + u v1 + v v2 (the paper names u, v without defining them).
+ *  - Traversal and the hit search run in float32; the reported (t, u, v) of
+ *    the winning triangle is recomputed in float64 from the float32 inputs and
+ *    rounded once to float32.
+ */
+#ifndef RTQ_RT_H
+#define RTQ_RT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rt_status {
+  RT_SUCCESS = 0,
+  RT_ERROR_INVALID_VALUE = 1,      /* null pointer with n > 0, bad stride/scale/option */
+  RT_ERROR_OUT_OF_MEMORY = 2,      /* a device or host allocation failed */
+  RT_ERROR_NO_DEVICE = 3,          /* no HIP device, or the device id is out of range */
+  RT_ERROR_HIP = 4,                /* a HIP runtime call failed (detail in the message) */
+  RT_ERROR_UNSUPPORTED = 5,        /* valid request this build does not implement */
+  RT_ERROR_INDEX_OUT_OF_RANGE = 6  /* a triangle index >= vertex_count, a mesh id >= mesh_count */
+} rt_status;
+
+/* Miss / no instance (the linear search of §3.3 starts from triIdx = -1). */
+#define RT_INVALID_ID 0xFFFFFFFFu
+
+typedef struct rt_context_s* rt_context;
+typedef struct rt_accel_s* rt_accel;
+typedef struct rt_batch_plan_s* rt_batch_plan;
+
+/* 32-byte ray (ray fields of §7.5: origin, direction, minT, maxT). */
+typedef struct rt_ray {
+  float ox, oy, oz, tmin;
+  float dx, dy, dz, tmax;
+} rt_ray;
+
+/* 16-byte closest-hit record. */
+typedef struct rt_hit {
+  float t;
+  uint32_t prim_id;
+  float u, v;
+} rt_hit;
+
+/* Instance frame (§7.3 lists scale, rotation, translation components):
+ * world = T + R(q/|q|) (S * x), S per axis (non-zero, finite), q = (x,y,z,w)
+ * a non-zero quaternion, normalised by the library. */
+typedef struct rt_srt {
+  float sx, sy, sz;
+  float qx, qy, qz, qw;
+  float tx, ty, tz;
+} rt_srt;
+
+/* Indexed triangle mesh (§7.2): device pointers; strides in bytes (>= 12).
+ * vertices: vertex_count records of 3 float32; indices: triangle_count
+ * records of 3 uint32. */
+typedef struct rt_mesh_desc {
+  const float* vertices;
+  uint32_t vertex_count;
+  uint32_t vertex_stride;
+  const uint32_t* indices;
+  uint32_t triangle_count;
+  uint32_t index_stride;
+} rt_mesh_desc;
+
+/* Build options.  node_width: 0 = default (4), or 2, 4, 8 (§6.2: wide trees
+ * of branching factor 4 or 8).  max_leaf_size: 0 = default (4), at most 15.
+ * flags: reserved, must be 0. */
+typedef struct rt_build_options {
+  uint32_t node_width;
+  uint32_t max_leaf_size;
+  uint32_t flags;
+} rt_build_options;
+
+/* Trace variant (launch configuration of the traversal kernels):
+ * stack_entries = per-lane traversal stack kept in LDS (4, 8, 16, 32; deeper
+ * entries spill to a global stack), workgroup = threads per workgroup (64,
+ * 128, 256, 512).  The defaults are 16 and 256.  Results do not depend on the
+ * variant. */
+typedef struct rt_variant {
+  uint32_t stack_entries;
+  uint32_t workgroup;
+} rt_variant;
+
+/* Statistics of a built acceleration structure (host-side copy). */
+typedef struct rt_accel_info {
+  uint32_t node_width;
+  uint32_t node_count;         /* all levels */
+  uint32_t triangle_count;     /* triangles stored (degenerate ones are dropped) */
+  uint32_t input_triangles;    /* triangles given */
+  uint32_t instance_count;
+  uint32_t max_depth;          /* longest root-to-leaf path in nodes, over both levels */
+  uint32_t max_stack;          /* traversal stack entries a lane can need */
+  uint32_t leaf_count;
+  double sah_cost;             /* sum of internal-node surface areas / root area (§6.2) */
+  uint64_t device_bytes;       /* device memory owned by the accel */
+} rt_accel_info;
+
+/* ---- context (§7.1) ---------------------------------------------------- */
+
+/* Creates a context on HIP device `hip_device` and makes it current for the
+ * calling thread's later library calls.  Errors: RT_ERROR_NO_DEVICE,
+ * RT_ERROR_INVALID_VALUE (out == NULL), RT_ERROR_HIP. */
+rt_status rt_context_create(int hip_device, rt_context* out);
+/* Frees the context's scratch (global stacks, queue counters).  An accel
+ * keeps the context it was built with and traces with that context's
+ * variant and scratch, so destroy every accel and batch plan of a context
+ * before the context.  Trace calls of one context on different streams are
+ * ordered one after another (they share the scratch). */
+rt_status rt_context_destroy(rt_context ctx);
+/* Sets the variant used by later trace calls on this context (see
+ * rt_variant); RT_ERROR_INVALID_VALUE for unsupported values. */
+rt_status rt_context_set_variant(rt_context ctx, const rt_variant* v);
+rt_status rt_context_get_variant(rt_context ctx, rt_variant* out);
+
+/* ---- build (§7.2, §7.3; top-down construction of §6.2) ----------------- */
+
+/* Builds an acceleration structure.
+ *  instance_count == 0: a single-level BVH over meshes[0] (mesh_count must
+ *    be 1); instance_mesh / instance_srt must be NULL.
+ *  instance_count > 0: a bottom-level BVH per mesh and a top-level BVH over
+ *    the instances; instance_mesh[j] (HOST) < mesh_count selects the mesh of
+ *    instance j and instance_srt[j] (HOST) its frame.
+ * The mesh buffers are read on `stream`; the call returns after the build
+ * has completed, and the caller may then free or modify them (the accel
+ * keeps its own copies).  Triangles whose normal is zero or whose vertices
+ * are not finite are not stored (they can never be hit).
+ * Errors: RT_ERROR_INVALID_VALUE (null pointers, stride < 12, mesh_count
+ * mismatch, zero/non-finite scale, zero quaternion, bad options),
+ * RT_ERROR_INDEX_OUT_OF_RANGE (an index >= vertex_count, a mesh id >=
+ * mesh_count), RT_ERROR_OUT_OF_MEMORY, RT_ERROR_HIP. */
+rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_count,
+                   const uint32_t* instance_mesh, const rt_srt* instance_srt,
+                   uint32_t instance_count, const rt_build_options* options, void* stream,
+                   rt_accel* out);
+rt_status rt_accel_destroy(rt_accel accel);
+rt_status rt_accel_get_info(rt_accel accel, rt_accel_info* out);
+
+/* ---- queries (§6.2 traversal paragraph; §7.5 closest and any-hit) ------- */
+
+/* Closest hit for n rays (device) into hits (device, n records).
+ * inst_ids (device, n uint32, nullable): instance of the hit, RT_INVALID_ID
+ * on a miss (0 on hits of a single-level accel).  n == 0 does nothing. */
+rt_status rt_trace_closest(rt_accel accel, const rt_ray* rays, uint32_t n, rt_hit* hits,
+                           uint32_t* inst_ids, void* stream);
+
+/* Any hit (§4.2: stop at the first hit found within the ray's length):
+ * occluded[i] (device, n bytes) = 1 when some triangle is hit with
+ * t in [tmin, tmax], else 0. */
+rt_status rt_trace_any(rt_accel accel, const rt_ray* rays, uint32_t n, uint8_t* occluded,
+                       void* stream);
+
+/* Adjoint of the closest hit at fixed triangles (single-level accels).
+ * For each ray with hits[i].prim_id != RT_INVALID_ID and g = d_tuv[3i..3i+2]
+ * = dL/d(t,u,v): with M = [-d | v1-v0 | v2-v0] and lambda = M^-T g,
+ *   d_origins[i] = lambda, d_directions[i] = t lambda,
+ *   d_vertices[v_k] += -w_k lambda  (w = (1-u-v, u, v))
+ * using the accel's copy of the vertices it was built from.  d_vertices
+ * (device, vertex_count*3 float32) is ACCUMULATED with float32 atomics (the
+ * summation order is not deterministic); d_origins / d_directions (device,
+ * n*3 float32) are overwritten (zero for misses).  t, u, v are recomputed in
+ * float64 from the triangle, so `hits` contributes only the triangle id.
+ * Errors: RT_ERROR_UNSUPPORTED on a two-level accel. */
+rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hits,
+                            const float* d_tuv, uint32_t n, float* d_vertices, float* d_origins,
+                            float* d_directions, void* stream);
+
+/* Diagnostics: the query of rt_trace_closest (any == 0, into hits) or
+ * rt_trace_any (any != 0, into occluded) run with a counting kernel variant
+ * (stack 16, workgroup 256) that ADDS to counters (device, 3 uint64): node
+ * visits, triangle tests, stack entries spilled to global memory.  Used to
+ * measure the bytes a query fetches per ray.  Single-level accels only
+ * (RT_ERROR_UNSUPPORTED otherwise). */
+rt_status rt_trace_counters(rt_accel accel, const rt_ray* rays, uint32_t n, int any, rt_hit* hits,
+                            uint8_t* occluded, uint64_t* counters, void* stream);
+
+/* ---- batched queries (many meshes, one persistent launch) --------------- */
+
+/* Plans closest-hit queries for batch_count (accel, rays, hits, count)
+ * tuples: accels, rays, hits and counts are HOST arrays of length
+ * batch_count whose rays/hits entries are device pointers.  All accels must
+ * be single-level and belong to ctx's device.  The plan copies its
+ * descriptors to the device once. */
+rt_status rt_batch_plan_create(rt_context ctx, const rt_accel* accels, const rt_ray* const* rays,
+                               rt_hit* const* hits, const uint32_t* counts, uint32_t batch_count,
+                               rt_batch_plan* out);
+/* Enqueues the whole batch: a queue reset and one persistent kernel launch. */
+rt_status rt_batch_plan_launch(rt_batch_plan plan, void* stream);
+/* Captures the launch into a HIP graph (queue reset by a fill kernel, not a
+ * memset node) and instantiates it; *out is a hipGraphExec_t owned by the
+ * plan (freed by rt_batch_plan_destroy).  Replay it with hipGraphLaunch. */
+rt_status rt_batch_plan_graph(rt_batch_plan plan, void* stream, void** out_graph_exec);
+rt_status rt_batch_plan_destroy(rt_batch_plan plan);
+
+/* ---- diagnostics -------------------------------------------------------- */
+
+const char* rt_status_string(rt_status s);
+const char* rt_last_error_message(void);
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+uint32_t rt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RTQ_RT_H */

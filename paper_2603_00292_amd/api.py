@@ -1,0 +1,271 @@
+"""Torch-facing wrappers over the C ABI (device memory and streams only).
+
+Every query runs in librtq's HIP kernels; these functions only check tensor
+shapes/devices, allocate outputs with torch and pass raw pointers and the
+current HIP stream.  ``RayQueryFn`` adds the adjoint as a
+``torch.autograd.Function``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _capi as capi
+
+
+def _stream() -> int:
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _require(t: torch.Tensor, name: str, dtype, last: int | None = None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU (got {t.device})")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if last is not None and (t.dim() != 2 or t.shape[1] != last):
+        raise ValueError(f"{name} must have shape (n, {last}) (got {tuple(t.shape)})")
+
+
+class Context:
+    """An rt_context on one HIP device (default: torch's current device)."""
+
+    def __init__(self, device: int | None = None, stack_entries: int | None = None,
+                 workgroup: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        h = C.c_void_p()
+        capi.call("rt_context_create", self.device, C.byref(h))
+        self.handle = h
+        if stack_entries is not None or workgroup is not None:
+            v = self.variant
+            self.set_variant(stack_entries or v[0], workgroup or v[1])
+
+    @property
+    def variant(self):
+        v = capi.rt_variant()
+        capi.call("rt_context_get_variant", self.handle, C.byref(v))
+        return int(v.stack_entries), int(v.workgroup)
+
+    def set_variant(self, stack_entries: int, workgroup: int):
+        v = capi.rt_variant(int(stack_entries), int(workgroup))
+        capi.call("rt_context_set_variant", self.handle, C.byref(v))
+
+    def close(self):
+        if self.handle:
+            capi.call("rt_context_destroy", self.handle)
+            self.handle = None
+
+
+class Accel:
+    """An acceleration structure built with ``rt_build``.
+
+    meshes: list of (vertices (V,3) float32 cuda, indices (N,3) int32/uint32
+    cuda).  Single level: one mesh and no instances.  Two-level:
+    ``inst_mesh`` (J,) and ``inst_srt`` (J,10) host arrays (numpy or CPU
+    tensors) of mesh ids and (sx,sy,sz,qx,qy,qz,qw,tx,ty,tz) frames."""
+
+    def __init__(self, ctx: Context, meshes, inst_mesh=None, inst_srt=None, node_width: int = 0,
+                 max_leaf_size: int = 0):
+        import numpy as np
+
+        self.ctx = ctx
+        self._keep = []
+        descs = (capi.rt_mesh_desc * len(meshes))()
+        for i, (v, f) in enumerate(meshes):
+            _require(v, "vertices", torch.float32, 3)
+            if f.dtype not in (torch.int32, torch.uint32):
+                raise ValueError("indices must be int32 or uint32")
+            if not f.is_contiguous() or f.dim() != 2 or f.shape[1] != 3 or f.device.type != "cuda":
+                raise ValueError("indices must be a contiguous (N,3) cuda tensor")
+            descs[i] = capi.rt_mesh_desc(v.data_ptr() if v.numel() else None, v.shape[0], 12,
+                                         f.data_ptr() if f.numel() else None, f.shape[0], 12)
+            self._keep += [v, f]
+        self.vertex_count = int(meshes[0][0].shape[0])
+        n_inst = 0
+        im_p = srt_p = None
+        if inst_mesh is not None:
+            im = np.ascontiguousarray(np.asarray(inst_mesh), dtype=np.uint32).reshape(-1)
+            srt = np.ascontiguousarray(np.asarray(inst_srt), dtype=np.float32).reshape(-1, 10)
+            if srt.shape[0] != im.shape[0]:
+                raise ValueError("inst_mesh and inst_srt lengths differ")
+            n_inst = im.shape[0]
+            self._im, self._srt = im, srt
+            im_p = C.c_void_p(im.ctypes.data)
+            srt_p = C.c_void_p(srt.ctypes.data)
+        opts = capi.rt_build_options(int(node_width), int(max_leaf_size), 0)
+        h = C.c_void_p()
+        capi.call("rt_build", ctx.handle, descs, len(meshes), im_p, srt_p, n_inst, C.byref(opts),
+                  C.c_void_p(_stream()), C.byref(h))
+        self.handle = h
+        self.two_level = n_inst > 0
+        self._keep = []
+
+    @property
+    def info(self) -> dict:
+        i = capi.rt_accel_info()
+        capi.call("rt_accel_get_info", self.handle, C.byref(i))
+        return {f: getattr(i, f) for f, _ in capi.rt_accel_info._fields_}
+
+    def close(self):
+        if self.handle:
+            capi.call("rt_accel_destroy", self.handle)
+            self.handle = None
+
+
+def trace_closest(accel: Accel, rays: torch.Tensor, want_inst: bool = False):
+    """Closest hits of rays (n,8) float32: returns (hits (n,4) float32 with
+    columns t, prim_id bits, u, v; inst_ids (n,) int32 or None)."""
+    _require(rays, "rays", torch.float32, 8)
+    n = rays.shape[0]
+    hits = torch.empty((n, 4), dtype=torch.float32, device=rays.device)
+    inst = torch.empty((n,), dtype=torch.int32, device=rays.device) if want_inst else None
+    capi.call("rt_trace_closest", accel.handle, _ptr(rays), n, _ptr(hits), _ptr(inst),
+              C.c_void_p(_stream()))
+    return hits, inst
+
+
+def hit_fields(hits: torch.Tensor):
+    """(t, prim_id (int64, -1 for a miss), u, v) views of a hit tensor."""
+    t = hits[:, 0]
+    prim = hits[:, 1].contiguous().view(torch.int32).to(torch.int64)
+    return t, prim, hits[:, 2], hits[:, 3]
+
+
+def trace_any(accel: Accel, rays: torch.Tensor) -> torch.Tensor:
+    _require(rays, "rays", torch.float32, 8)
+    n = rays.shape[0]
+    occ = torch.empty((n,), dtype=torch.uint8, device=rays.device)
+    capi.call("rt_trace_any", accel.handle, _ptr(rays), n, _ptr(occ), C.c_void_p(_stream()))
+    return occ
+
+
+def trace_counters(accel: Accel, rays: torch.Tensor, any_hit: bool = False):
+    """Runs the counting variant; returns (node visits, triangle tests,
+    spilled stack entries) summed over the rays, and the query's output."""
+    _require(rays, "rays", torch.float32, 8)
+    n = rays.shape[0]
+    cnt = torch.zeros((3,), dtype=torch.int64, device=rays.device)
+    hits = occ = None
+    if any_hit:
+        occ = torch.empty((n,), dtype=torch.uint8, device=rays.device)
+    else:
+        hits = torch.empty((n, 4), dtype=torch.float32, device=rays.device)
+    capi.call("rt_trace_counters", accel.handle, _ptr(rays), n, int(any_hit), _ptr(hits), _ptr(occ),
+              _ptr(cnt), C.c_void_p(_stream()))
+    c = cnt.cpu().tolist()
+    return (c[0], c[1], c[2]), (occ if any_hit else hits)
+
+
+def trace_backward(accel: Accel, rays: torch.Tensor, hits: torch.Tensor, d_tuv: torch.Tensor,
+                   d_vertices: torch.Tensor):
+    """Adjoint at fixed triangles; d_vertices is accumulated in place.
+    Returns (d_origins (n,3), d_directions (n,3))."""
+    _require(rays, "rays", torch.float32, 8)
+    _require(hits, "hits", torch.float32, 4)
+    _require(d_tuv, "d_tuv", torch.float32, 3)
+    _require(d_vertices, "d_vertices", torch.float32, 3)
+    n = rays.shape[0]
+    do = torch.empty((n, 3), dtype=torch.float32, device=rays.device)
+    dd = torch.empty((n, 3), dtype=torch.float32, device=rays.device)
+    capi.call("rt_trace_backward", accel.handle, _ptr(rays), _ptr(hits), _ptr(d_tuv), n,
+              _ptr(d_vertices), _ptr(do), _ptr(dd), C.c_void_p(_stream()))
+    return do, dd
+
+
+class RayQueryFn(torch.autograd.Function):
+    """Differentiable closest hit.
+
+    forward(accel, vertices, origins, directions, tmin, tmax) ->
+    (t, u, v, prim_id).  ``vertices`` must be the (V,3) tensor the accel was
+    built from; gradients flow to vertices, origins and directions through
+    the hand-written adjoint kernel (rt_trace_backward)."""
+
+    @staticmethod
+    def forward(ctx, accel, vertices, origins, directions, tmin, tmax):
+        n = origins.shape[0]
+        rays = torch.empty((n, 8), dtype=torch.float32, device=origins.device)
+        rays[:, 0:3] = origins
+        rays[:, 3] = tmin
+        rays[:, 4:7] = directions
+        rays[:, 7] = tmax
+        hits, _ = trace_closest(accel, rays)
+        t, prim, u, v = hit_fields(hits)
+        ctx.accel = accel
+        ctx.save_for_backward(rays, hits)
+        ctx.vshape = vertices.shape
+        ctx.mark_non_differentiable(prim)
+        return t.clone(), u.clone(), v.clone(), prim
+
+    @staticmethod
+    def backward(ctx, gt, gu, gv, gprim):
+        rays, hits = ctx.saved_tensors
+        n = rays.shape[0]
+        z = torch.zeros(n, dtype=torch.float32, device=rays.device)
+        d_tuv = torch.stack([gt if gt is not None else z, gu if gu is not None else z,
+                             gv if gv is not None else z], 1).contiguous().float()
+        dV = torch.zeros(ctx.vshape, dtype=torch.float32, device=rays.device)
+        do, dd = trace_backward(ctx.accel, rays, hits, d_tuv, dV)
+        return None, dV, do, dd, None, None
+
+
+class BatchPlan:
+    """Closest-hit queries of many (accel, rays) pairs in one persistent
+    launch; ``graph()`` captures it into a HIP graph for replay."""
+
+    def __init__(self, ctx: Context, accels, rays_list, hits_list=None):
+        n = len(accels)
+        if hits_list is None:
+            hits_list = [torch.empty((r.shape[0], 4), dtype=torch.float32, device=r.device)
+                         for r in rays_list]
+        for r, h in zip(rays_list, hits_list):
+            _require(r, "rays", torch.float32, 8)
+            _require(h, "hits", torch.float32, 4)
+        self.hits = hits_list
+        self._rays = rays_list
+        A = (C.c_void_p * n)(*[a.handle.value for a in accels])
+        R = (C.c_void_p * n)(*[r.data_ptr() if r.numel() else None for r in rays_list])
+        H = (C.c_void_p * n)(*[h.data_ptr() if h.numel() else None for h in hits_list])
+        cnt = (C.c_uint32 * n)(*[r.shape[0] for r in rays_list])
+        h = C.c_void_p()
+        capi.call("rt_batch_plan_create", ctx.handle, A, R, H, cnt, n, C.byref(h))
+        self.handle = h
+        self._graph = None
+
+    def launch(self):
+        capi.call("rt_batch_plan_launch", self.handle, C.c_void_p(_stream()))
+
+    def graph_exec(self, stream: torch.cuda.Stream) -> int:
+        g = C.c_void_p()
+        capi.call("rt_batch_plan_graph", self.handle, C.c_void_p(int(stream.cuda_stream)), C.byref(g))
+        return int(g.value)
+
+    def close(self):
+        if self.handle:
+            capi.call("rt_batch_plan_destroy", self.handle)
+            self.handle = None
+
+
+_hip = None
+
+
+def graph_launch(graph_exec: int, stream: torch.cuda.Stream | None = None) -> None:
+    """Replays a graph returned by ``BatchPlan.graph_exec`` (hipGraphLaunch)."""
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipGraphLaunch.argtypes = [C.c_void_p, C.c_void_p]
+        _hip.hipGraphLaunch.restype = C.c_int
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = _hip.hipGraphLaunch(C.c_void_p(graph_exec), C.c_void_p(int(s.cuda_stream)))
+    if rc != 0:
+        raise RuntimeError(f"hipGraphLaunch failed with HIP error {rc}")

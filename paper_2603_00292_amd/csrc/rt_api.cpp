@@ -1,0 +1,837 @@
+// rt_api.cpp -- host runtime behind the C ABI of include/rt.h.
+//
+// Owns contexts (device, trace variant, scratch: ray-queue counters and the
+// global spill stack), acceleration structures (device copies of the BVH
+// nodes, triangle records, instance maps and the original vertices and
+// indices) and batch plans.  All argument checks happen here, before any
+// work is enqueued; no C++ exception leaves this file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/rt.h"
+#include "bvh_build.h"
+#include "rt_kernels.h"
+#include "rt_layout.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rt_status fail(rt_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+rt_status ok() {
+  g_last_error.clear();
+  return RT_SUCCESS;
+}
+
+#define RT_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      if (e_ == hipErrorOutOfMemory)                                                      \
+        return fail(RT_ERROR_OUT_OF_MEMORY, "%s: %s", #call, hipGetErrorString(e_));      \
+      return fail(RT_ERROR_HIP, "%s: %s", #call, hipGetErrorString(e_));                  \
+    }                                                                                     \
+  } while (0)
+
+int env_int(const char* name, int dflt) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return dflt;
+  return std::atoi(v);
+}
+
+bool valid_variant(const rt_variant& v) {
+  bool s_ok = v.stack_entries == 4 || v.stack_entries == 8 || v.stack_entries == 16 ||
+              v.stack_entries == 32;
+  bool wg_ok = v.workgroup == 64 || v.workgroup == 128 || v.workgroup == 256 || v.workgroup == 512;
+  return s_ok && wg_ok && !(v.stack_entries == 32 && v.workgroup == 512);
+}
+
+// device scratch of one launch: queue counter + global spill stack
+struct Scratch {
+  uint32_t* counter = nullptr;
+  uint32_t* gstack = nullptr;
+  size_t gstack_entries = 0;
+};
+
+void free_scratch(Scratch& s) {
+  if (s.counter) (void)hipFree(s.counter);
+  if (s.gstack) (void)hipFree(s.gstack);
+  s = Scratch();
+}
+
+}  // namespace
+
+struct rt_context_s {
+  int device = 0;
+  int cu_count = 0;
+  rt_variant variant{16, 256};
+  uint32_t refill_min = 16;
+  std::mutex mu;
+  Scratch scratch;
+  hipEvent_t last_event = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool has_last = false;
+  std::vector<std::pair<const void*, uint32_t>> occupancy;  // kernel -> resident blocks
+};
+
+struct rt_accel_s {
+  rt_context ctx = nullptr;                  // context it was built with (variant, scratch)
+  int device = 0;
+  int width = 4;
+  bool two_level = false;
+  uint32_t root = RT_CHILD_EMPTY;
+  uint32_t max_stack = 1;
+  float* nodes = nullptr;
+  rt_tri_rec* tris = nullptr;
+  rt_inst_rec* insts = nullptr;
+  rt_inst_rec64* insts64 = nullptr;
+  rt_mesh_dev* meshes = nullptr;             // device array of mesh records
+  std::vector<void*> owned;                  // every device allocation
+  std::vector<rt_mesh_dev> host_meshes;      // device pointers, host copy
+  rt_accel_info info{};
+};
+
+struct rt_batch_plan_s {
+  rt_context ctx = nullptr;
+  int width = 4;
+  uint32_t batch_count = 0;
+  uint32_t total = 0;
+  uint32_t max_stack = 1;
+  BatchDesc* descs = nullptr;
+  uint32_t* offsets = nullptr;
+  Scratch scratch;
+  uint32_t grid = 0;
+  const void* kernel = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+};
+
+namespace {
+
+template <typename T>
+rt_status dev_alloc(rt_accel_s* a, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return RT_SUCCESS;
+  void* q = nullptr;
+  RT_HIP(hipMalloc(&q, count * sizeof(T)));
+  a->owned.push_back(q);
+  a->info.device_bytes += count * sizeof(T);
+  *p = static_cast<T*>(q);
+  return RT_SUCCESS;
+}
+
+void destroy_accel(rt_accel_s* a) {
+  for (void* p : a->owned) (void)hipFree(p);
+  delete a;
+}
+
+// Resident workgroups of a kernel on the whole device.
+uint32_t resident_blocks(const void* kern, int wg, int cu_count) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, wg, 0) != hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  return (uint32_t)per_cu * (uint32_t)std::max(cu_count, 1);
+}
+
+// Makes sure scratch holds a counter and a spill stack of `entries` entries.
+rt_status ensure_scratch(Scratch& s, size_t entries) {
+  if (!s.counter) RT_HIP(hipMalloc(&s.counter, 256));
+  if (entries > s.gstack_entries) {
+    if (s.gstack) {
+      RT_HIP(hipDeviceSynchronize());
+      RT_HIP(hipFree(s.gstack));
+      s.gstack = nullptr;
+      s.gstack_entries = 0;
+    }
+    RT_HIP(hipMalloc(&s.gstack, entries * sizeof(uint32_t)));
+    s.gstack_entries = entries;
+  }
+  return RT_SUCCESS;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+rt_status check_device(int dev) {
+  int cur = -1;
+  RT_HIP(hipGetDevice(&cur));
+  if (cur != dev) RT_HIP(hipSetDevice(dev));
+  return RT_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rt_status_string(rt_status s) {
+  switch (s) {
+    case RT_SUCCESS: return "RT_SUCCESS";
+    case RT_ERROR_INVALID_VALUE: return "RT_ERROR_INVALID_VALUE";
+    case RT_ERROR_OUT_OF_MEMORY: return "RT_ERROR_OUT_OF_MEMORY";
+    case RT_ERROR_NO_DEVICE: return "RT_ERROR_NO_DEVICE";
+    case RT_ERROR_HIP: return "RT_ERROR_HIP";
+    case RT_ERROR_UNSUPPORTED: return "RT_ERROR_UNSUPPORTED";
+    case RT_ERROR_INDEX_OUT_OF_RANGE: return "RT_ERROR_INDEX_OUT_OF_RANGE";
+  }
+  return "RT_ERROR_UNKNOWN";
+}
+
+const char* rt_last_error_message(void) { return g_last_error.c_str(); }
+
+uint32_t rt_version(void) { return 100; }
+
+rt_status rt_context_create(int hip_device, rt_context* out) {
+  if (!out) return fail(RT_ERROR_INVALID_VALUE, "rt_context_create: out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0)
+    return fail(RT_ERROR_NO_DEVICE, "rt_context_create: no HIP device (%s)", hipGetErrorString(e));
+  if (hip_device < 0 || hip_device >= n)
+    return fail(RT_ERROR_NO_DEVICE, "rt_context_create: device %d out of range (%d devices)",
+                hip_device, n);
+  RT_HIP(hipSetDevice(hip_device));
+  rt_context_s* c = new (std::nothrow) rt_context_s();
+  if (!c) return fail(RT_ERROR_OUT_OF_MEMORY, "rt_context_create: host allocation");
+  c->device = hip_device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) {
+    delete c;
+    return fail(RT_ERROR_HIP, "rt_context_create: hipGetDeviceProperties failed");
+  }
+  c->cu_count = prop.multiProcessorCount;
+  rt_variant v{(uint32_t)env_int("RT_STACK", 16), (uint32_t)env_int("RT_WG", 256)};
+  if (valid_variant(v)) c->variant = v;
+  c->refill_min = (uint32_t)std::min(64, std::max(1, env_int("RT_REFILL", 16)));
+  if (hipEventCreateWithFlags(&c->last_event, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    return fail(RT_ERROR_HIP, "rt_context_create: hipEventCreate failed");
+  }
+  *out = c;
+  return ok();
+}
+
+rt_status rt_context_destroy(rt_context ctx) {
+  if (!ctx) return fail(RT_ERROR_INVALID_VALUE, "rt_context_destroy: NULL context");
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  free_scratch(ctx->scratch);
+  if (ctx->last_event) (void)hipEventDestroy(ctx->last_event);
+  delete ctx;
+  return ok();
+}
+
+rt_status rt_context_set_variant(rt_context ctx, const rt_variant* v) {
+  if (!ctx || !v) return fail(RT_ERROR_INVALID_VALUE, "rt_context_set_variant: NULL argument");
+  if (!valid_variant(*v))
+    return fail(RT_ERROR_INVALID_VALUE,
+                "rt_context_set_variant: stack_entries must be 4/8/16/32 and workgroup "
+                "64/128/256/512 (not 32 with 512)");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ctx->variant = *v;
+  return ok();
+}
+
+rt_status rt_context_get_variant(rt_context ctx, rt_variant* out) {
+  if (!ctx || !out) return fail(RT_ERROR_INVALID_VALUE, "rt_context_get_variant: NULL argument");
+  *out = ctx->variant;
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// build
+// ---------------------------------------------------------------------------
+
+static rt_status read_mesh(const rt_mesh_desc& m, hipStream_t s, std::vector<float>& V,
+                           std::vector<uint32_t>& I) {
+  V.assign((size_t)m.vertex_count * 3, 0.0f);
+  I.assign((size_t)m.triangle_count * 3, 0u);
+  if (m.vertex_count) {
+    if (m.vertex_stride == 12) {
+      RT_HIP(hipMemcpyAsync(V.data(), m.vertices, V.size() * 4, hipMemcpyDefault, s));
+    } else {
+      std::vector<uint8_t> raw((size_t)(m.vertex_count - 1) * m.vertex_stride + 12);
+      RT_HIP(hipMemcpyAsync(raw.data(), m.vertices, raw.size(), hipMemcpyDefault, s));
+      RT_HIP(hipStreamSynchronize(s));
+      for (uint32_t i = 0; i < m.vertex_count; ++i)
+        std::memcpy(&V[3 * (size_t)i], raw.data() + (size_t)i * m.vertex_stride, 12);
+    }
+  }
+  if (m.triangle_count) {
+    if (m.index_stride == 12) {
+      RT_HIP(hipMemcpyAsync(I.data(), m.indices, I.size() * 4, hipMemcpyDefault, s));
+    } else {
+      std::vector<uint8_t> raw((size_t)(m.triangle_count - 1) * m.index_stride + 12);
+      RT_HIP(hipMemcpyAsync(raw.data(), m.indices, raw.size(), hipMemcpyDefault, s));
+      RT_HIP(hipStreamSynchronize(s));
+      for (uint32_t i = 0; i < m.triangle_count; ++i)
+        std::memcpy(&I[3 * (size_t)i], raw.data() + (size_t)i * m.index_stride, 12);
+    }
+  }
+  RT_HIP(hipStreamSynchronize(s));
+  return RT_SUCCESS;
+}
+
+// world = T + R(q/|q|)(S x); returns the world->object map in float64 rows
+static void srt_inverse(const rt_srt& f, double m[12]) {
+  double qx = f.qx, qy = f.qy, qz = f.qz, qw = f.qw;
+  double nq = std::sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
+  qx /= nq; qy /= nq; qz /= nq; qw /= nq;
+  double R[3][3] = {{1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qz * qw), 2 * (qx * qz + qy * qw)},
+                    {2 * (qx * qy + qz * qw), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qx * qw)},
+                    {2 * (qx * qz - qy * qw), 2 * (qy * qz + qx * qw), 1 - 2 * (qx * qx + qy * qy)}};
+  double S[3] = {f.sx, f.sy, f.sz}, T[3] = {f.tx, f.ty, f.tz};
+  for (int i = 0; i < 3; ++i) {
+    // row i of S^-1 R^T is column i of R divided by S_i
+    double a = R[0][i] / S[i], b = R[1][i] / S[i], c = R[2][i] / S[i];
+    m[4 * i + 0] = a;
+    m[4 * i + 1] = b;
+    m[4 * i + 2] = c;
+    m[4 * i + 3] = -(a * T[0] + b * T[1] + c * T[2]);
+  }
+}
+
+static rtb::Box world_box(const rtb::Box& b, const rt_srt& f) {
+  double qx = f.qx, qy = f.qy, qz = f.qz, qw = f.qw;
+  double nq = std::sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
+  qx /= nq; qy /= nq; qz /= nq; qw /= nq;
+  double R[3][3] = {{1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qz * qw), 2 * (qx * qz + qy * qw)},
+                    {2 * (qx * qy + qz * qw), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qx * qw)},
+                    {2 * (qx * qz - qy * qw), 2 * (qy * qz + qx * qw), 1 - 2 * (qx * qx + qy * qy)}};
+  double S[3] = {f.sx, f.sy, f.sz}, T[3] = {f.tx, f.ty, f.tz};
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int c = 0; c < 8; ++c) {
+    double x[3] = {(c & 1) ? b.hi[0] : b.lo[0], (c & 2) ? b.hi[1] : b.lo[1],
+                   (c & 4) ? b.hi[2] : b.lo[2]};
+    for (int i = 0; i < 3; ++i) {
+      double w = T[i] + R[i][0] * S[0] * x[0] + R[i][1] * S[1] * x[1] + R[i][2] * S[2] * x[2];
+      lo[i] = std::min(lo[i], w);
+      hi[i] = std::max(hi[i], w);
+    }
+  }
+  rtb::Box out;
+  for (int i = 0; i < 3; ++i) {
+    // round outward, with a relative margin for the float64 arithmetic above
+    double pad = 1e-12 * (std::fabs(lo[i]) + std::fabs(hi[i]) + 1.0);
+    out.lo[i] = std::nextafter((float)(lo[i] - pad), -INFINITY);
+    out.hi[i] = std::nextafter((float)(hi[i] + pad), INFINITY);
+  }
+  return out;
+}
+
+rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_count,
+                   const uint32_t* instance_mesh, const rt_srt* instance_srt,
+                   uint32_t instance_count, const rt_build_options* options, void* stream,
+                   rt_accel* out) {
+  if (!out) return fail(RT_ERROR_INVALID_VALUE, "rt_build: out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(RT_ERROR_INVALID_VALUE, "rt_build: NULL context");
+  if (!meshes || mesh_count == 0) return fail(RT_ERROR_INVALID_VALUE, "rt_build: no meshes");
+  if (instance_count == 0 && mesh_count != 1)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_build: a single-level build takes exactly one mesh");
+  if (instance_count == 0 && (instance_mesh || instance_srt))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_build: instance arrays given with instance_count 0");
+  if (instance_count > 0 && (!instance_mesh || !instance_srt))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_build: instance arrays are NULL");
+  if (instance_count > RT_INST_INDEX_MASK)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_build: too many instances");
+  int width = 4, max_leaf = 4;
+  if (options) {
+    if (options->flags != 0) return fail(RT_ERROR_INVALID_VALUE, "rt_build: flags must be 0");
+    if (options->node_width != 0) width = (int)options->node_width;
+    if (options->max_leaf_size != 0) max_leaf = (int)options->max_leaf_size;
+  }
+  if (width != 2 && width != 4 && width != 8)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_build: node_width must be 0, 2, 4 or 8");
+  if (max_leaf < 1 || max_leaf > (int)RT_MAX_LEAF_SIZE)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_build: max_leaf_size must be 1..15");
+  for (uint32_t m = 0; m < mesh_count; ++m) {
+    const rt_mesh_desc& d = meshes[m];
+    if ((d.vertex_count > 0 && !d.vertices) || (d.triangle_count > 0 && !d.indices))
+      return fail(RT_ERROR_INVALID_VALUE, "rt_build: mesh %u has a NULL buffer", m);
+    if (d.vertex_stride < 12 || d.index_stride < 12)
+      return fail(RT_ERROR_INVALID_VALUE, "rt_build: mesh %u stride < 12", m);
+  }
+  for (uint32_t j = 0; j < instance_count; ++j) {
+    if (instance_mesh[j] >= mesh_count)
+      return fail(RT_ERROR_INDEX_OUT_OF_RANGE, "rt_build: instance %u refers to mesh %u of %u", j,
+                  instance_mesh[j], mesh_count);
+    const rt_srt& f = instance_srt[j];
+    const float all[10] = {f.sx, f.sy, f.sz, f.qx, f.qy, f.qz, f.qw, f.tx, f.ty, f.tz};
+    for (float x : all)
+      if (!std::isfinite(x)) return fail(RT_ERROR_INVALID_VALUE, "rt_build: instance %u frame is not finite", j);
+    if (f.sx == 0.0f || f.sy == 0.0f || f.sz == 0.0f)
+      return fail(RT_ERROR_INVALID_VALUE, "rt_build: instance %u has a zero scale", j);
+    if (f.qx == 0.0f && f.qy == 0.0f && f.qz == 0.0f && f.qw == 0.0f)
+      return fail(RT_ERROR_INVALID_VALUE, "rt_build: instance %u has a zero quaternion", j);
+  }
+  rt_status st = check_device(ctx->device);
+  if (st != RT_SUCCESS) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+
+  rt_accel_s* a = new (std::nothrow) rt_accel_s();
+  if (!a) return fail(RT_ERROR_OUT_OF_MEMORY, "rt_build: host allocation");
+  a->ctx = ctx;
+  a->device = ctx->device;
+  a->width = width;
+  a->two_level = instance_count > 0;
+  a->info.node_width = (uint32_t)width;
+  a->info.instance_count = instance_count;
+
+  auto bail = [&](rt_status e) {
+    destroy_accel(a);
+    return e;
+  };
+
+  try {
+    std::vector<rtb::WideTree> blas(mesh_count);
+    std::vector<std::vector<float>> hv(mesh_count);
+    std::vector<std::vector<uint32_t>> hi(mesh_count);
+    uint64_t input_tris = 0;
+    for (uint32_t m = 0; m < mesh_count; ++m) {
+      st = read_mesh(meshes[m], s, hv[m], hi[m]);
+      if (st != RT_SUCCESS) return bail(st);
+      rtb::BuildInput in{hv[m].data(), hi[m].data(), meshes[m].vertex_count, meshes[m].triangle_count};
+      std::string err;
+      if (!rtb::build_mesh(in, width, max_leaf, blas[m], err, threads)) {
+        rt_status code = err.find("vertex index") != std::string::npos ? RT_ERROR_INDEX_OUT_OF_RANGE
+                                                                        : RT_ERROR_INVALID_VALUE;
+        return bail(fail(code, "rt_build: mesh %u: %s", m, err.c_str()));
+      }
+      input_tris += meshes[m].triangle_count;
+    }
+    rtb::WideTree tlas;
+    if (a->two_level) {
+      std::vector<rtb::Box> boxes(instance_count);
+      for (uint32_t j = 0; j < instance_count; ++j) {
+        const rtb::WideTree& b = blas[instance_mesh[j]];
+        if (b.root == RT_CHILD_EMPTY) {
+          for (int k = 0; k < 3; ++k) {
+            boxes[j].lo[k] = INFINITY;
+            boxes[j].hi[k] = -INFINITY;
+          }
+        } else {
+          boxes[j] = world_box(b.bounds, instance_srt[j]);
+        }
+      }
+      rtb::build_instances(boxes, width, tlas, threads);
+    }
+    // concatenate node and triangle arrays: [tlas][blas 0][blas 1]...
+    const uint32_t fpn = 8u * (uint32_t)width;
+    uint64_t node_total = tlas.node_count, tri_total = 0;
+    std::vector<uint32_t> node_base(mesh_count), tri_base(mesh_count);
+    for (uint32_t m = 0; m < mesh_count; ++m) {
+      node_base[m] = (uint32_t)node_total;
+      tri_base[m] = (uint32_t)tri_total;
+      node_total += blas[m].node_count;
+      tri_total += blas[m].tris.size();
+    }
+    if (node_total >= 0x7FFFFFFFull || tri_total > RT_MAX_TRI_RECORDS)
+      return bail(fail(RT_ERROR_INVALID_VALUE, "rt_build: scene too large for one accel"));
+    std::vector<float> nodes((size_t)node_total * fpn);
+    std::vector<rt_tri_rec> tris((size_t)tri_total);
+    auto relocate = [&](const rtb::WideTree& t, uint32_t nb, uint32_t tb, float* dst) {
+      std::memcpy(dst, t.nodes.data(), t.nodes.size() * 4);
+      for (uint32_t i = 0; i < t.node_count; ++i)
+        for (int c = 0; c < width; ++c) {
+          uint32_t ref;
+          float* slot = dst + (size_t)i * fpn + 6 * width + c;
+          std::memcpy(&ref, slot, 4);
+          if (ref == RT_CHILD_EMPTY) continue;
+          if ((ref & RT_LEAF_BIT) == 0) ref += nb;
+          else if ((ref & RT_INST_BIT) == 0) ref += tb;  // first-record field is the low bits
+          std::memcpy(slot, &ref, 4);
+        }
+    };
+    if (tlas.node_count) relocate(tlas, 0, 0, nodes.data());
+    uint32_t max_blas_stack = 0, max_blas_depth = 0;
+    for (uint32_t m = 0; m < mesh_count; ++m) {
+      if (blas[m].node_count) relocate(blas[m], node_base[m], tri_base[m], nodes.data() + (size_t)node_base[m] * fpn);
+      std::copy(blas[m].tris.begin(), blas[m].tris.end(), tris.begin() + tri_base[m]);
+      max_blas_stack = std::max(max_blas_stack, blas[m].max_stack);
+      max_blas_depth = std::max(max_blas_depth, blas[m].max_depth);
+      a->info.leaf_count += blas[m].leaf_count;
+    }
+    double sah = 0.0;
+    if (a->two_level) {
+      a->root = tlas.root;  // node 0 or empty
+      a->max_stack = tlas.max_stack + 1 + max_blas_stack;
+      a->info.max_depth = tlas.max_depth + max_blas_depth;
+      a->info.leaf_count += tlas.leaf_count;
+      sah = tlas.sah_cost;
+    } else {
+      a->root = blas[0].root == RT_CHILD_EMPTY ? RT_CHILD_EMPTY : node_base[0];
+      a->max_stack = blas[0].max_stack;
+      a->info.max_depth = blas[0].max_depth;
+      sah = blas[0].sah_cost;
+    }
+    a->max_stack = std::max(a->max_stack, 1u);
+    a->info.node_count = (uint32_t)node_total;
+    a->info.triangle_count = (uint32_t)tri_total;
+    a->info.input_triangles = (uint32_t)std::min<uint64_t>(input_tris, 0xFFFFFFFFull);
+    a->info.max_stack = a->max_stack;
+    a->info.sah_cost = sah;
+
+    // device copies
+    st = dev_alloc(a, &a->nodes, nodes.size());
+    if (st != RT_SUCCESS) return bail(st);
+    st = dev_alloc(a, &a->tris, tris.size());
+    if (st != RT_SUCCESS) return bail(st);
+    if (!nodes.empty()) RT_HIP(hipMemcpyAsync(a->nodes, nodes.data(), nodes.size() * 4, hipMemcpyHostToDevice, s));
+    if (!tris.empty())
+      RT_HIP(hipMemcpyAsync(a->tris, tris.data(), tris.size() * sizeof(rt_tri_rec), hipMemcpyHostToDevice, s));
+    a->host_meshes.resize(mesh_count);
+    for (uint32_t m = 0; m < mesh_count; ++m) {
+      float* dv = nullptr;
+      uint32_t* di = nullptr;
+      st = dev_alloc(a, &dv, hv[m].size());
+      if (st != RT_SUCCESS) return bail(st);
+      st = dev_alloc(a, &di, hi[m].size());
+      if (st != RT_SUCCESS) return bail(st);
+      if (!hv[m].empty()) RT_HIP(hipMemcpyAsync(dv, hv[m].data(), hv[m].size() * 4, hipMemcpyHostToDevice, s));
+      if (!hi[m].empty()) RT_HIP(hipMemcpyAsync(di, hi[m].data(), hi[m].size() * 4, hipMemcpyHostToDevice, s));
+      a->host_meshes[m] = rt_mesh_dev{dv, di, meshes[m].vertex_count, meshes[m].triangle_count};
+    }
+    st = dev_alloc(a, &a->meshes, mesh_count);
+    if (st != RT_SUCCESS) return bail(st);
+    RT_HIP(hipMemcpyAsync(a->meshes, a->host_meshes.data(), mesh_count * sizeof(rt_mesh_dev), hipMemcpyHostToDevice, s));
+    if (a->two_level) {
+      std::vector<rt_inst_rec> ir(instance_count);
+      std::vector<rt_inst_rec64> ir64(instance_count);
+      for (uint32_t j = 0; j < instance_count; ++j) {
+        double m[12];
+        srt_inverse(instance_srt[j], m);
+        std::memcpy(ir64[j].m, m, sizeof(m));
+        for (int k = 0; k < 4; ++k) {
+          ir[j].r0[k] = (float)m[k];
+          ir[j].r1[k] = (float)m[4 + k];
+          ir[j].r2[k] = (float)m[8 + k];
+        }
+        uint32_t mm = instance_mesh[j];
+        ir[j].root = blas[mm].root == RT_CHILD_EMPTY ? RT_CHILD_EMPTY : node_base[mm];
+        ir[j].mesh = mm;
+        ir[j].pad[0] = ir[j].pad[1] = 0;
+      }
+      st = dev_alloc(a, &a->insts, ir.size());
+      if (st != RT_SUCCESS) return bail(st);
+      st = dev_alloc(a, &a->insts64, ir64.size());
+      if (st != RT_SUCCESS) return bail(st);
+      RT_HIP(hipMemcpyAsync(a->insts, ir.data(), ir.size() * sizeof(rt_inst_rec), hipMemcpyHostToDevice, s));
+      RT_HIP(hipMemcpyAsync(a->insts64, ir64.data(), ir64.size() * sizeof(rt_inst_rec64), hipMemcpyHostToDevice, s));
+    }
+    RT_HIP(hipStreamSynchronize(s));
+  } catch (const std::bad_alloc&) {
+    return bail(fail(RT_ERROR_OUT_OF_MEMORY, "rt_build: host allocation failed"));
+  } catch (const std::exception& ex) {
+    return bail(fail(RT_ERROR_INVALID_VALUE, "rt_build: %s", ex.what()));
+  }
+  *out = a;
+  return ok();
+}
+
+rt_status rt_accel_destroy(rt_accel accel) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_accel_destroy: NULL accel");
+  (void)hipSetDevice(accel->device);
+  (void)hipDeviceSynchronize();
+  destroy_accel(accel);
+  return ok();
+}
+
+rt_status rt_accel_get_info(rt_accel accel, rt_accel_info* out) {
+  if (!accel || !out) return fail(RT_ERROR_INVALID_VALUE, "rt_accel_get_info: NULL argument");
+  *out = accel->info;
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// queries
+// ---------------------------------------------------------------------------
+
+static uint32_t cached_resident(rt_context ctx, const void* kern, int wg) {
+  for (auto& e : ctx->occupancy)
+    if (e.first == kern) return e.second;
+  uint32_t b = resident_blocks(kern, wg, ctx->cu_count);
+  ctx->occupancy.emplace_back(kern, b);
+  return b;
+}
+
+static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit* hits,
+                              uint32_t* inst_ids, uint8_t* occ, bool any, hipStream_t s,
+                              uint64_t* counters = nullptr) {
+  rt_context ctx = a->ctx;
+  rt_status st = check_device(a->device);
+  if (st != RT_SUCCESS) return st;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  rt_variant v = ctx->variant;
+  if (counters) v = rt_variant{16, 256};
+  const void* kern = counters ? rtk_count_kernel(a->width, any)
+                              : rtk_trace_kernel(a->width, (int)v.stack_entries, (int)v.workgroup,
+                                                 any, a->two_level, 0);
+  if (!kern) return fail(RT_ERROR_UNSUPPORTED, "trace: variant not compiled");
+  uint32_t wg = v.workgroup;
+  uint32_t blocks = std::min<uint32_t>((n + wg - 1) / wg, cached_resident(ctx, kern, (int)wg));
+  blocks = std::max(blocks, 1u);
+  uint32_t gstride = blocks * wg;
+  size_t spill = a->max_stack > v.stack_entries ? (size_t)(a->max_stack - v.stack_entries) : 1;
+  st = ensure_scratch(ctx->scratch, spill * gstride);
+  if (st != RT_SUCCESS) return st;
+  if (ctx->has_last && ctx->last_stream != s) RT_HIP(hipStreamWaitEvent(s, ctx->last_event, 0));
+  TraceParams p{};
+  p.nodes = a->nodes;
+  p.tris = a->tris;
+  p.insts = a->insts;
+  p.insts64 = a->insts64;
+  p.meshes = a->meshes;
+  p.rays = rays;
+  p.hits = hits;
+  p.inst_ids = inst_ids;
+  p.occluded = occ;
+  p.counter = ctx->scratch.counter;
+  p.gstack = ctx->scratch.gstack;
+  p.root = a->root;
+  p.n = n;
+  p.max_stack = a->max_stack;
+  p.gstride = gstride;
+  p.refill_min = ctx->refill_min;
+  p.counters = counters;
+  RT_HIP(rtk_launch_fill(ctx->scratch.counter, 1, 0u, s));
+  RT_HIP(rtk_launch_trace(kern, blocks, wg, p, s));
+  RT_HIP(hipEventRecord(ctx->last_event, s));
+  ctx->last_stream = s;
+  ctx->has_last = true;
+  return ok();
+}
+
+rt_status rt_trace_closest(rt_accel accel, const rt_ray* rays, uint32_t n, rt_hit* hits,
+                           uint32_t* inst_ids, void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest: NULL accel");
+  if (n == 0) return ok();
+  if (!rays || !hits) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest: NULL buffer with n > 0");
+  if (n > 0x7FFFFFFFu) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest: n >= 2^31");
+  if (!aligned16(rays) || !aligned16(hits))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest: rays and hits must be 16-byte aligned");
+  return launch_trace(accel, rays, n, hits, inst_ids, nullptr, false, static_cast<hipStream_t>(stream));
+}
+
+rt_status rt_trace_any(rt_accel accel, const rt_ray* rays, uint32_t n, uint8_t* occluded,
+                       void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_any: NULL accel");
+  if (n == 0) return ok();
+  if (!rays || !occluded) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_any: NULL buffer with n > 0");
+  if (n > 0x7FFFFFFFu) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_any: n >= 2^31");
+  if (!aligned16(rays)) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_any: rays must be 16-byte aligned");
+  return launch_trace(accel, rays, n, nullptr, nullptr, occluded, true, static_cast<hipStream_t>(stream));
+}
+
+rt_status rt_trace_counters(rt_accel accel, const rt_ray* rays, uint32_t n, int any, rt_hit* hits,
+                            uint8_t* occluded, uint64_t* counters, void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_counters: NULL accel");
+  if (accel->two_level)
+    return fail(RT_ERROR_UNSUPPORTED, "rt_trace_counters: two-level accels are not supported");
+  if (n == 0) return ok();
+  if (!rays || !counters || (any ? !occluded : !hits))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_counters: NULL buffer with n > 0");
+  if (n > 0x7FFFFFFFu) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_counters: n >= 2^31");
+  if (!aligned16(rays) || (!any && !aligned16(hits)))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_counters: rays and hits must be 16-byte aligned");
+  return launch_trace(accel, rays, n, any ? nullptr : hits, nullptr, any ? occluded : nullptr,
+                      any != 0, static_cast<hipStream_t>(stream), counters);
+}
+
+rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hits,
+                            const float* d_tuv, uint32_t n, float* d_vertices, float* d_origins,
+                            float* d_directions, void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_backward: NULL accel");
+  if (accel->two_level)
+    return fail(RT_ERROR_UNSUPPORTED, "rt_trace_backward: two-level accels are not supported");
+  if (n == 0) return ok();
+  if (!rays || !hits || !d_tuv || !d_vertices || !d_origins || !d_directions)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_backward: NULL buffer with n > 0");
+  if (!aligned16(rays) || !aligned16(hits))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_backward: rays and hits must be 16-byte aligned");
+  rt_status st = check_device(accel->device);
+  if (st != RT_SUCCESS) return st;
+  BackwardParams p{};
+  p.mesh = accel->host_meshes[0];
+  p.rays = rays;
+  p.hits = hits;
+  p.d_tuv = d_tuv;
+  p.n = n;
+  p.d_vertices = d_vertices;
+  p.d_origins = d_origins;
+  p.d_directions = d_directions;
+  RT_HIP(rtk_launch_backward(p, static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// batched plans
+// ---------------------------------------------------------------------------
+
+rt_status rt_batch_plan_create(rt_context ctx, const rt_accel* accels, const rt_ray* const* rays,
+                               rt_hit* const* hits, const uint32_t* counts, uint32_t batch_count,
+                               rt_batch_plan* out) {
+  if (!out) return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_create: out is NULL");
+  *out = nullptr;
+  if (!ctx || !accels || !rays || !hits || !counts || batch_count == 0)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_create: NULL argument or empty batch");
+  int width = -1;
+  uint64_t total = 0;
+  uint32_t max_stack = 1;
+  for (uint32_t b = 0; b < batch_count; ++b) {
+    rt_accel a = accels[b];
+    if (!a) return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_create: accel %u is NULL", b);
+    if (a->two_level) return fail(RT_ERROR_UNSUPPORTED, "rt_batch_plan_create: accel %u is two-level", b);
+    if (a->device != ctx->device)
+      return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_create: accel %u is on another device", b);
+    if (width < 0) width = a->width;
+    if (a->width != width)
+      return fail(RT_ERROR_UNSUPPORTED, "rt_batch_plan_create: accels must share one node width");
+    if (counts[b] > 0 && (!rays[b] || !hits[b]))
+      return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_create: batch %u has a NULL buffer", b);
+    if (counts[b] > 0 && (!aligned16(rays[b]) || !aligned16(hits[b])))
+      return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_create: batch %u buffers not 16-byte aligned", b);
+    total += counts[b];
+    max_stack = std::max(max_stack, a->max_stack);
+  }
+  if (total > 0x7FFFFFFFull) return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_create: >= 2^31 rays");
+  rt_status st = check_device(ctx->device);
+  if (st != RT_SUCCESS) return st;
+  rt_batch_plan_s* p = new (std::nothrow) rt_batch_plan_s();
+  if (!p) return fail(RT_ERROR_OUT_OF_MEMORY, "rt_batch_plan_create: host allocation");
+  p->ctx = ctx;
+  p->width = width;
+  p->batch_count = batch_count;
+  p->total = (uint32_t)total;
+  p->max_stack = max_stack;
+  auto bail = [&](rt_status e) {
+    free_scratch(p->scratch);
+    if (p->descs) (void)hipFree(p->descs);
+    if (p->offsets) (void)hipFree(p->offsets);
+    delete p;
+    return e;
+  };
+  std::vector<BatchDesc> d(batch_count);
+  std::vector<uint32_t> off(batch_count + 1, 0);
+  for (uint32_t b = 0; b < batch_count; ++b) {
+    rt_accel a = accels[b];
+    d[b] = BatchDesc{a->nodes, a->tris, a->meshes, rays[b], hits[b], a->root, counts[b]};
+    off[b + 1] = off[b] + counts[b];
+  }
+  rt_variant v = ctx->variant;
+  p->kernel = rtk_trace_kernel(width, (int)v.stack_entries, (int)v.workgroup, false, false, 1);
+  if (!p->kernel) return bail(fail(RT_ERROR_UNSUPPORTED, "rt_batch_plan_create: variant not compiled"));
+  uint32_t wg = v.workgroup;
+  uint32_t resident;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    resident = cached_resident(ctx, p->kernel, (int)wg);
+  }
+  p->grid = std::max(1u, std::min<uint32_t>((p->total + wg - 1) / wg, resident));
+  size_t spill = max_stack > v.stack_entries ? (size_t)(max_stack - v.stack_entries) : 1;
+  hipError_t e1 = hipMalloc(&p->descs, d.size() * sizeof(BatchDesc));
+  hipError_t e2 = hipMalloc(&p->offsets, off.size() * sizeof(uint32_t));
+  if (e1 != hipSuccess || e2 != hipSuccess)
+    return bail(fail(RT_ERROR_OUT_OF_MEMORY, "rt_batch_plan_create: device allocation failed"));
+  st = ensure_scratch(p->scratch, spill * p->grid * wg);
+  if (st != RT_SUCCESS) return bail(st);
+  if (hipMemcpy(p->descs, d.data(), d.size() * sizeof(BatchDesc), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->offsets, off.data(), off.size() * sizeof(uint32_t), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(RT_ERROR_HIP, "rt_batch_plan_create: descriptor upload failed"));
+  *out = p;
+  return ok();
+}
+
+static rt_status enqueue_plan(rt_batch_plan p, hipStream_t s) {
+  rt_variant v = p->ctx->variant;
+  TraceParams q{};
+  q.counter = p->scratch.counter;
+  q.gstack = p->scratch.gstack;
+  q.batches = p->descs;
+  q.batch_offsets = p->offsets;
+  q.batch_count = p->batch_count;
+  q.n = p->total;
+  q.max_stack = p->max_stack;
+  q.gstride = p->grid * v.workgroup;
+  q.refill_min = p->ctx->refill_min;
+  q.root = RT_CHILD_EMPTY;
+  RT_HIP(rtk_launch_fill(p->scratch.counter, 1, 0u, s));
+  RT_HIP(rtk_launch_trace(p->kernel, p->grid, v.workgroup, q, s));
+  return RT_SUCCESS;
+}
+
+rt_status rt_batch_plan_launch(rt_batch_plan plan, void* stream) {
+  if (!plan) return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_launch: NULL plan");
+  if (plan->total == 0) return ok();
+  rt_status st = check_device(plan->ctx->device);
+  if (st != RT_SUCCESS) return st;
+  st = enqueue_plan(plan, static_cast<hipStream_t>(stream));
+  if (st != RT_SUCCESS) return st;
+  return ok();
+}
+
+rt_status rt_batch_plan_graph(rt_batch_plan plan, void* stream, void** out_graph_exec) {
+  if (!plan || !out_graph_exec) return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_graph: NULL argument");
+  *out_graph_exec = nullptr;
+  if (!stream) return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_graph: capture needs a non-null stream");
+  rt_status st = check_device(plan->ctx->device);
+  if (st != RT_SUCCESS) return st;
+  if (!plan->graph_exec) {
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    RT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    rt_status e = (plan->total > 0) ? enqueue_plan(plan, s) : RT_SUCCESS;
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(s, &g);
+    if (e != RT_SUCCESS) {
+      if (g) (void)hipGraphDestroy(g);
+      return e;
+    }
+    if (ee != hipSuccess) return fail(RT_ERROR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ee));
+    hipGraphExec_t x = nullptr;
+    hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(RT_ERROR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+    }
+    plan->graph = g;
+    plan->graph_exec = x;
+  }
+  *out_graph_exec = plan->graph_exec;
+  return ok();
+}
+
+rt_status rt_batch_plan_destroy(rt_batch_plan plan) {
+  if (!plan) return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_destroy: NULL plan");
+  (void)hipSetDevice(plan->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  free_scratch(plan->scratch);
+  if (plan->descs) (void)hipFree(plan->descs);
+  if (plan->offsets) (void)hipFree(plan->offsets);
+  delete plan;
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// rt_kernels.h -- kernel parameter blocks and launch entry points of librtq
+// (internal to the library; not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/rt.h"
+#include "rt_layout.h"
+
+// One batch entry of a batched plan (device copy).
+struct BatchDesc {
+  const float* nodes;
+  const rt_tri_rec* tris;
+  const rt_mesh_dev* meshes;
+  const rt_ray* rays;
+  rt_hit* hits;
+  uint32_t root;
+  uint32_t count;
+};
+
+struct TraceParams {
+  const float* nodes;
+  const rt_tri_rec* tris;
+  const rt_inst_rec* insts;
+  const rt_inst_rec64* insts64;
+  const rt_mesh_dev* meshes;
+  const rt_ray* rays;
+  rt_hit* hits;
+  uint32_t* inst_ids;
+  uint8_t* occluded;
+  uint32_t* counter;     // ray queue head, zero before the launch
+  uint32_t* gstack;      // global stack: (max_stack - S) * gstride entries
+  const BatchDesc* batches;
+  const uint32_t* batch_offsets;  // batch_count + 1 prefix sums of counts
+  uint32_t batch_count;
+  uint32_t root;
+  uint32_t n;            // rays in the launch (batched: total)
+  uint32_t max_stack;    // stack entries a lane may need
+  uint32_t gstride;      // threads in the grid
+  uint32_t refill_min;   // refill a wave once this many lanes are idle
+  uint64_t* counters;    // counting variants: node visits, triangle tests, spills
+};
+
+struct BackwardParams {
+  rt_mesh_dev mesh;
+  const rt_ray* rays;
+  const rt_hit* hits;
+  const float* d_tuv;
+  uint32_t n;
+  float* d_vertices;
+  float* d_origins;
+  float* d_directions;
+};
+
+// Kernel handle for a variant (mode 0: one accel, mode 1: batched closest);
+// nullptr when the combination is not compiled.
+const void* rtk_trace_kernel(int width, int stack, int wg, bool any, bool inst, int mode);
+const void* rtk_count_kernel(int width, bool any);
+hipError_t rtk_launch_trace(const void* kern, uint32_t grid, uint32_t wg, const TraceParams& p,
+                            hipStream_t stream);
+hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream);
+hipError_t rtk_launch_fill(uint32_t* ptr, uint32_t n, uint32_t value, hipStream_t stream);

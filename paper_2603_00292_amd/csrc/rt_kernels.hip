@@ -1,0 +1,656 @@
+// rt_kernels.hip -- traversal, adjoint and batched kernels of librtq (gfx950).
+//
+// One ray per lane (the paper's §3.3 observes that rays through pixels are
+// independent and map to parallel threads).  Waves are persistent: lanes
+// whose ray is finished take new rays from a global counter, one atomic per
+// wave, with lane offsets from a ballot and a prefix popcount (wave-level
+// compaction).  Each lane walks a W-wide BVH (§6.2) with a stack (the
+// traversal paragraph of §6.2) whose top S entries live in LDS and whose
+// deeper entries spill to a global buffer (§7.5 describes the shared-memory
+// stack with a global fallback).  Internal nodes are visited until every
+// live lane of the wave has reached a leaf, then the leaves are tested
+// (Aila & Laine 2009, "while-while").  No matrix cores: this is pointer
+// chasing, not a dense contraction.
+//
+// Numerics: float32 traversal with a conservative slab test (boxes are exact
+// float32 bounds; the far distance is widened by 2*gamma(3), Ize 2013) and a
+// watertight float32 ray/triangle test on canonically ordered edges (each
+// shared edge is evaluated from the same endpoint with the same operations
+// on both triangles, so no ray passes between them).  The winning triangle's
+// (t, u, v) is recomputed in float64 from the float32 inputs.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rt_kernels.h"
+#include "rt_layout.h"
+
+namespace rtk {
+
+// 1 + 2 gamma(3), gamma(n) = n u / (1 - n u), u = 2^-24, rounded up
+__device__ constexpr float kSlabWiden = 3.5762793e-7f;
+// relative widening of the best distance in the box test, so that a box
+// holding an exact tie in t with a lower id is still visited
+__device__ constexpr float kTieWiden = 9.5367432e-7f;  // 2^-20
+
+#define RT_STACK_MARKER 0xFFFFFFFEu  // "leave the instance, restore the world ray"
+
+struct RayState {
+  float ox, oy, oz, dx, dy, dz;
+  float ix, iy, iz;
+  float tmin, tmax;
+  uint32_t sx, sy, sz;  // 1 when the direction's sign bit is set
+};
+
+__device__ __forceinline__ void ray_setup(RayState& r) {
+  r.ix = 1.0f / r.dx;
+  r.iy = 1.0f / r.dy;
+  r.iz = 1.0f / r.dz;
+  r.sx = __float_as_uint(r.dx) >> 31;
+  r.sy = __float_as_uint(r.dy) >> 31;
+  r.sz = __float_as_uint(r.dz) >> 31;
+}
+
+// Rays that can never hit: a NaN, a zero direction, or tmin > tmax.
+__device__ __forceinline__ bool ray_void(const rt_ray& q) {
+  bool nan = (q.ox != q.ox) | (q.oy != q.oy) | (q.oz != q.oz) | (q.dx != q.dx) | (q.dy != q.dy) |
+             (q.dz != q.dz) | (q.tmin != q.tmin) | (q.tmax != q.tmax);
+  bool zero = (q.dx == 0.0f) & (q.dy == 0.0f) & (q.dz == 0.0f);
+  return nan | zero | (q.tmin > q.tmax);
+}
+
+__device__ __forceinline__ rt_ray load_ray(const rt_ray* rays, uint32_t i) {
+  const float4* p = reinterpret_cast<const float4*>(rays + i);
+  float4 a = p[0], b = p[1];
+  rt_ray q;
+  q.ox = a.x; q.oy = a.y; q.oz = a.z; q.tmin = a.w;
+  q.dx = b.x; q.dy = b.y; q.dz = b.z; q.tmax = b.w;
+  return q;
+}
+
+// ---------------------------------------------------------------------------
+// per-lane traversal stack: top S entries in LDS, the rest in global memory
+// ---------------------------------------------------------------------------
+// Entry i of a lane's stack lives in LDS slot (i mod S) while it is one of the
+// S newest entries; older entries live at gstack[(i - S) * gstride + gtid].
+template <int S, int WG>
+struct Stack {
+  uint32_t* lds;       // this lane's column: lds[slot * WG]
+  uint32_t* glob;      // this lane's column: glob[i * gstride]
+  uint32_t gstride;
+  uint32_t cap;        // total entries this lane may hold
+  uint32_t sp;
+
+  __device__ __forceinline__ void push(uint32_t v) {
+    if (sp >= cap) return;  // cannot happen when cap is the builder's bound
+    uint32_t slot = sp & (S - 1);
+    if (sp >= S) glob[(size_t)(sp - S) * gstride] = lds[slot * WG];
+    lds[slot * WG] = v;
+    ++sp;
+  }
+  __device__ __forceinline__ uint32_t pop() {
+    if (sp == 0) return RT_CHILD_EMPTY;
+    --sp;
+    uint32_t slot = sp & (S - 1);
+    uint32_t v = lds[slot * WG];
+    if (sp >= S) lds[slot * WG] = glob[(size_t)(sp - S) * gstride];
+    return v;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// geometry access
+// ---------------------------------------------------------------------------
+struct Geo {
+  const float* nodes;          // node_count * 8W floats
+  const float4* tris;          // 3 float4 per record
+  const rt_inst_rec* insts;    // two-level only
+  const rt_inst_rec64* insts64;
+  const rt_mesh_dev* meshes;
+  uint32_t root;
+  uint32_t max_stack;
+};
+
+// W-wide node visit: returns the child refs that the ray enters, nearest
+// first, in keys k[0..W-1] (0xFFFFFFFF = no child).
+template <int W>
+__device__ __forceinline__ void visit_node(const float* nodes, uint32_t idx, const RayState& r,
+                                           float tcull, uint32_t* out_ref, int& n_out) {
+  constexpr int NF4 = (W == 2) ? 4 : (7 * W) / 4;  // skip trailing pad when it fills a float4
+  const float4* p = reinterpret_cast<const float4*>(nodes + (size_t)idx * (8 * W));
+  float nd[4 * NF4];
+#pragma unroll
+  for (int i = 0; i < NF4; ++i) {
+    float4 v = p[i];
+    nd[4 * i + 0] = v.x;
+    nd[4 * i + 1] = v.y;
+    nd[4 * i + 2] = v.z;
+    nd[4 * i + 3] = v.w;
+  }
+  constexpr int SH = (W == 2) ? 1 : ((W == 4) ? 2 : 3);
+  uint32_t key[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    float lox = nd[0 * W + i], hix = nd[1 * W + i];
+    float loy = nd[2 * W + i], hiy = nd[3 * W + i];
+    float loz = nd[4 * W + i], hiz = nd[5 * W + i];
+    float nx = r.sx ? hix : lox, fx = r.sx ? lox : hix;
+    float ny = r.sy ? hiy : loy, fy = r.sy ? loy : hiy;
+    float nz = r.sz ? hiz : loz, fz = r.sz ? loz : hiz;
+    float tnx = (nx - r.ox) * r.ix, tfx = (fx - r.ox) * r.ix;
+    float tny = (ny - r.oy) * r.iy, tfy = (fy - r.oy) * r.iy;
+    float tnz = (nz - r.oz) * r.iz, tfz = (fz - r.oz) * r.iz;
+    // fmaxf/fminf ignore a NaN operand (0 * inf on a slab boundary with a
+    // zero direction component), which is the correct "no constraint".
+    float tn = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, r.tmin));
+    float tf = fminf(fminf(tfx, tfy), tfz);
+    tf = fmaf(fabsf(tf), kSlabWiden, tf);
+    tf = fminf(tf, tcull);
+    bool hit = (tn <= tf) & (tn < __int_as_float(0x7f800000));
+    key[i] = hit ? ((__float_as_uint(tn) & ~((1u << SH) - 1u)) | (uint32_t)i) : 0xFFFFFFFFu;
+  }
+  // sort keys ascending (nearest first)
+#define RT_CSWAP(a, b)                     \
+  {                                        \
+    uint32_t lo_ = min(key[a], key[b]);    \
+    uint32_t hi_ = max(key[a], key[b]);    \
+    key[a] = lo_;                          \
+    key[b] = hi_;                          \
+  }
+  if constexpr (W == 2) {
+    RT_CSWAP(0, 1);
+  } else if constexpr (W == 4) {
+    RT_CSWAP(0, 1); RT_CSWAP(2, 3); RT_CSWAP(0, 2); RT_CSWAP(1, 3); RT_CSWAP(1, 2);
+  } else {
+    // Batcher odd-even merge sort for 8 keys (19 compare-exchanges)
+    RT_CSWAP(0, 1); RT_CSWAP(2, 3); RT_CSWAP(4, 5); RT_CSWAP(6, 7);
+    RT_CSWAP(0, 2); RT_CSWAP(1, 3); RT_CSWAP(4, 6); RT_CSWAP(5, 7);
+    RT_CSWAP(1, 2); RT_CSWAP(5, 6);
+    RT_CSWAP(0, 4); RT_CSWAP(1, 5); RT_CSWAP(2, 6); RT_CSWAP(3, 7);
+    RT_CSWAP(2, 4); RT_CSWAP(3, 5);
+    RT_CSWAP(1, 2); RT_CSWAP(3, 4); RT_CSWAP(5, 6);
+  }
+#undef RT_CSWAP
+  n_out = 0;
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    uint32_t slot = key[i] & ((1u << SH) - 1u);
+    uint32_t ref = RT_CHILD_EMPTY;
+#pragma unroll
+    for (int j = 0; j < W; ++j) ref = (slot == (uint32_t)j) ? __float_as_uint(nd[6 * W + j]) : ref;
+    out_ref[i] = (key[i] == 0xFFFFFFFFu) ? RT_CHILD_EMPTY : ref;
+    n_out += (key[i] != 0xFFFFFFFFu) ? 1 : 0;
+  }
+}
+
+// Watertight float32 ray/triangle test.  The record's vertices are sorted
+// (p0 < p1 < p2 lexicographically), so each edge function
+//   g(P,Q) = d . ((Q - P) x (P - o)),  P < Q,
+// is computed from the same operands wherever the edge appears.  The edge
+// functions of the triangle are F0 = -g(p1,p2), F1 = g(p0,p2), F2 = -g(p0,p1)
+// (F_k is proportional to the weight of p_k); the ray crosses the closed
+// triangle when they share a sign and their sum d.n is non-zero.  Then
+// t = n.(p0 - o) / d.n with n = (p1 - p0) x (p2 - p0) (§3.1, plane solution).
+__device__ __forceinline__ bool tri_test(const float4& A, const float4& B, const float4& C,
+                                         const RayState& r, float& t_out) {
+  float w0x = A.x - r.ox, w0y = A.y - r.oy, w0z = A.z - r.oz;
+  float w1x = B.x - r.ox, w1y = B.y - r.oy, w1z = B.z - r.oz;
+  float e01x = B.x - A.x, e01y = B.y - A.y, e01z = B.z - A.z;
+  float e12x = C.x - B.x, e12y = C.y - B.y, e12z = C.z - B.z;
+  float e02x = C.x - A.x, e02y = C.y - A.y, e02z = C.z - A.z;
+  // c = e x w, g = d . c
+  float g01 = r.dx * (e01y * w0z - e01z * w0y) + r.dy * (e01z * w0x - e01x * w0z) +
+              r.dz * (e01x * w0y - e01y * w0x);
+  float g12 = r.dx * (e12y * w1z - e12z * w1y) + r.dy * (e12z * w1x - e12x * w1z) +
+              r.dz * (e12x * w1y - e12y * w1x);
+  float g02 = r.dx * (e02y * w0z - e02z * w0y) + r.dy * (e02z * w0x - e02x * w0z) +
+              r.dz * (e02x * w0y - e02y * w0x);
+  float F0 = -g12, F1 = g02, F2 = -g01;
+  bool pos = (F0 >= 0.0f) & (F1 >= 0.0f) & (F2 >= 0.0f);
+  bool neg = (F0 <= 0.0f) & (F1 <= 0.0f) & (F2 <= 0.0f);
+  float det = F0 + F1 + F2;
+  if (!((pos | neg) & (det != 0.0f))) return false;
+  float nx = e01y * e02z - e01z * e02y;
+  float ny = e01z * e02x - e01x * e02z;
+  float nz = e01x * e02y - e01y * e02x;
+  float T = nx * w0x + ny * w0y + nz * w0z;
+  t_out = T / det;
+  return true;
+}
+
+// float64 (t, u, v) of a triangle in its original vertex order
+// (Moeller-Trumbore solution of o + t d = (1-u-v) v0 + u v1 + v v2).
+__device__ __forceinline__ bool finalize64(const rt_mesh_dev& m, uint32_t prim, double ox,
+                                           double oy, double oz, double dx, double dy, double dz,
+                                           float& t, float& u, float& v) {
+  const uint32_t* ix = m.indices + 3 * (size_t)prim;
+  uint32_t i0 = ix[0], i1 = ix[1], i2 = ix[2];
+  const float* V = m.vertices;
+  double v0x = V[3 * (size_t)i0], v0y = V[3 * (size_t)i0 + 1], v0z = V[3 * (size_t)i0 + 2];
+  double e1x = V[3 * (size_t)i1] - v0x, e1y = V[3 * (size_t)i1 + 1] - v0y,
+         e1z = V[3 * (size_t)i1 + 2] - v0z;
+  double e2x = V[3 * (size_t)i2] - v0x, e2y = V[3 * (size_t)i2 + 1] - v0y,
+         e2z = V[3 * (size_t)i2 + 2] - v0z;
+  double px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+  double det = e1x * px + e1y * py + e1z * pz;
+  if (det == 0.0) return false;
+  double inv = 1.0 / det;
+  double sx = ox - v0x, sy = oy - v0y, sz = oz - v0z;
+  double uu = (sx * px + sy * py + sz * pz) * inv;
+  double qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+  double vv = (dx * qx + dy * qy + dz * qz) * inv;
+  double tt = (e2x * qx + e2y * qy + e2z * qz) * inv;
+  if (!(tt == tt) || !(uu == uu) || !(vv == vv)) return false;
+  t = (float)tt;
+  u = (float)uu;
+  v = (float)vv;
+  return true;
+}
+
+// world -> object ray with the float32 instance map (no renormalisation, so
+// t is shared between the two spaces)
+__device__ __forceinline__ void to_object(const rt_inst_rec& I, const rt_ray& w, RayState& r) {
+  r.ox = I.r0[0] * w.ox + I.r0[1] * w.oy + I.r0[2] * w.oz + I.r0[3];
+  r.oy = I.r1[0] * w.ox + I.r1[1] * w.oy + I.r1[2] * w.oz + I.r1[3];
+  r.oz = I.r2[0] * w.ox + I.r2[1] * w.oy + I.r2[2] * w.oz + I.r2[3];
+  r.dx = I.r0[0] * w.dx + I.r0[1] * w.dy + I.r0[2] * w.dz;
+  r.dy = I.r1[0] * w.dx + I.r1[1] * w.dy + I.r1[2] * w.dz;
+  r.dz = I.r2[0] * w.dx + I.r2[1] * w.dy + I.r2[2] * w.dz;
+  ray_setup(r);
+}
+
+__device__ __forceinline__ void world_state(const rt_ray& w, RayState& r) {
+  r.ox = w.ox; r.oy = w.oy; r.oz = w.oz;
+  r.dx = w.dx; r.dy = w.dy; r.dz = w.dz;
+  r.tmin = w.tmin; r.tmax = w.tmax;
+  ray_setup(r);
+}
+
+__device__ __forceinline__ bool is_internal(uint32_t ref) { return (ref & RT_LEAF_BIT) == 0u; }
+__device__ __forceinline__ bool is_inst(uint32_t ref) {
+  return (ref & (RT_LEAF_BIT | RT_INST_BIT)) == (RT_LEAF_BIT | RT_INST_BIT) && ref != RT_CHILD_EMPTY;
+}
+__device__ __forceinline__ bool is_tri_leaf(uint32_t ref) {
+  return (ref & (RT_LEAF_BIT | RT_INST_BIT)) == RT_LEAF_BIT;
+}
+
+// ---------------------------------------------------------------------------
+// the persistent traversal kernel
+// ---------------------------------------------------------------------------
+// MODE 0: one accel (uniform geometry); MODE 1: batched (geometry per lane
+// from the batch descriptor of the lane's ray).
+template <int W, int S, int WG, bool ANY, bool INST, int MODE, bool COUNT = false>
+__global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
+  __shared__ uint32_t lds_stack[S * WG];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63u;
+  const uint32_t gtid = blockIdx.x * WG + tid;
+  const uint64_t lanemask_lt = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
+
+  Geo g;
+  g.nodes = P.nodes;
+  g.tris = reinterpret_cast<const float4*>(P.tris);
+  g.insts = P.insts;
+  g.insts64 = P.insts64;
+  g.meshes = P.meshes;
+  g.root = P.root;
+  g.max_stack = P.max_stack;
+
+  Stack<S, WG> st;
+  st.lds = lds_stack + tid;
+  st.glob = P.gstack + gtid;
+  st.gstride = P.gstride;
+  st.cap = P.max_stack;
+  st.sp = 0;
+
+  RayState r;
+  rt_ray wray;
+  uint32_t ray_id = 0;
+  uint32_t cur = RT_CHILD_EMPTY;
+  float best_t = 0.0f;
+  uint32_t best_prim = RT_INVALID_ID, best_inst = RT_INVALID_ID, cur_inst = 0;
+  rt_hit* hit_out = P.hits;
+  uint32_t* inst_out = P.inst_ids;
+  uint8_t* occ_out = P.occluded;
+  const rt_ray* ray_in = P.rays;
+  bool live = false, retired = false;
+  uint32_t batch = 0;
+  uint64_t n_nodes = 0, n_tris = 0, n_spill = 0;
+
+  while (true) {
+    // ---- refill finished lanes (one atomic per wave) --------------------
+    bool need = !live && !retired;
+    uint64_t m = __ballot(need);
+    uint64_t mlive = __ballot(live);
+    uint32_t n_need = __popcll(m);
+    if (n_need > 0 && (mlive == 0 || n_need >= P.refill_min)) {
+      uint32_t leader = __ffsll((unsigned long long)m) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(P.counter, n_need);
+      base = (uint32_t)__shfl((int)base, (int)leader);
+      if (need) {
+        uint32_t my = base + __popcll(m & lanemask_lt);
+        if (my < P.n) {
+          ray_id = my;
+          uint32_t local = my;
+          if constexpr (MODE == 1) {
+            // the batch whose ray range holds `my` (offsets has batch_count+1 entries)
+            uint32_t lo = 0, hi = P.batch_count;
+            while (hi - lo > 1) {
+              uint32_t mid = (lo + hi) >> 1;
+              if (P.batch_offsets[mid] <= my) lo = mid; else hi = mid;
+            }
+            batch = lo;
+            const BatchDesc& bd = P.batches[lo];
+            local = my - P.batch_offsets[lo];
+            g.nodes = bd.nodes;
+            g.tris = reinterpret_cast<const float4*>(bd.tris);
+            g.meshes = bd.meshes;
+            g.root = bd.root;
+            ray_in = bd.rays;
+            hit_out = bd.hits;
+          }
+          wray = load_ray(ray_in, local);
+          ray_id = local;
+          world_state(wray, r);
+          best_t = r.tmax;
+          best_prim = RT_INVALID_ID;
+          best_inst = RT_INVALID_ID;
+          cur_inst = 0;
+          st.sp = 0;
+          cur = ray_void(wray) ? RT_CHILD_EMPTY : g.root;
+          live = true;
+        } else {
+          retired = true;
+        }
+      }
+    }
+    if (__ballot(live) == 0) {
+      if (__ballot(!retired) == 0) break;
+      continue;
+    }
+    if (live) {
+      float tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
+      // ---- internal nodes until this lane holds a leaf or is done ------
+      while (cur != RT_CHILD_EMPTY && !is_tri_leaf(cur)) {
+        if constexpr (INST) {
+          if (cur == RT_STACK_MARKER) {
+            world_state(wray, r);
+            r.tmax = best_t;
+            cur = st.pop();
+            continue;
+          }
+          if (is_inst(cur)) {
+            uint32_t j = cur & RT_INST_INDEX_MASK;
+            const rt_inst_rec& I = g.insts[j];
+            to_object(I, wray, r);
+            r.tmin = wray.tmin;
+            cur_inst = j;
+            st.push(RT_STACK_MARKER);
+            cur = I.root;
+            continue;
+          }
+        }
+        uint32_t refs[W];
+        int nh;
+        if constexpr (COUNT) n_nodes++;
+        visit_node<W>(g.nodes, cur, r, tcull, refs, nh);
+        if (nh == 0) {
+          cur = st.pop();
+        } else {
+          cur = refs[0];
+#pragma unroll
+          for (int i = W - 1; i >= 1; --i)
+            if (i < nh) {
+              if constexpr (COUNT) n_spill += (st.sp >= S) ? 1 : 0;
+              st.push(refs[i]);
+            }
+        }
+      }
+      // ---- triangle leaves ------------------------------------------------
+      while (cur != RT_CHILD_EMPTY && is_tri_leaf(cur)) {
+        uint32_t first = cur & RT_LEAF_FIRST_MASK;
+        uint32_t count = (cur >> RT_LEAF_COUNT_SHIFT) & RT_LEAF_COUNT_MASK;
+        bool stop = false;
+        for (uint32_t k = 0; k < count; ++k) {
+          const float4* tp = g.tris + 3 * (size_t)(first + k);
+          if constexpr (COUNT) n_tris++;
+          float4 A = tp[0], B = tp[1], C = tp[2];
+          float t;
+          if (tri_test(A, B, C, r, t) && t >= r.tmin && t <= best_t) {
+            uint32_t prim = __float_as_uint(A.w);
+            if constexpr (ANY) {
+              best_prim = prim;
+              stop = true;
+              break;
+            } else {
+              uint32_t inst = INST ? cur_inst : 0u;
+              bool better = (t < best_t) || (inst < best_inst) ||
+                            (inst == best_inst && prim < best_prim);
+              if (better) {
+                best_t = t;
+                best_prim = prim;
+                best_inst = inst;
+              }
+            }
+          }
+        }
+        if (ANY && stop) {
+          cur = RT_CHILD_EMPTY;
+          st.sp = 0;
+          break;
+        }
+        tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
+        cur = st.pop();
+        if constexpr (INST) {
+          // a marker ends the instance: restore the world ray
+          while (cur == RT_STACK_MARKER) {
+            world_state(wray, r);
+            cur = st.pop();
+          }
+        }
+      }
+      // ---- finished: write the result --------------------------------------
+      if (cur == RT_CHILD_EMPTY) {
+        if constexpr (ANY) {
+          occ_out[ray_id] = (best_prim != RT_INVALID_ID) ? 1 : 0;
+        } else {
+          rt_hit h;
+          h.t = __int_as_float(0x7f800000);
+          h.prim_id = RT_INVALID_ID;
+          h.u = 0.0f;
+          h.v = 0.0f;
+          if (best_prim != RT_INVALID_ID) {
+            h.t = best_t;
+            h.prim_id = best_prim;
+            double ox = wray.ox, oy = wray.oy, oz = wray.oz;
+            double dx = wray.dx, dy = wray.dy, dz = wray.dz;
+            uint32_t mesh = 0;
+            if constexpr (INST) {
+              const rt_inst_rec64& M = g.insts64[best_inst];
+              double a = M.m[0] * ox + M.m[1] * oy + M.m[2] * oz + M.m[3];
+              double b = M.m[4] * ox + M.m[5] * oy + M.m[6] * oz + M.m[7];
+              double c = M.m[8] * ox + M.m[9] * oy + M.m[10] * oz + M.m[11];
+              double e = M.m[0] * dx + M.m[1] * dy + M.m[2] * dz;
+              double f = M.m[4] * dx + M.m[5] * dy + M.m[6] * dz;
+              double gg = M.m[8] * dx + M.m[9] * dy + M.m[10] * dz;
+              ox = a; oy = b; oz = c; dx = e; dy = f; dz = gg;
+              mesh = g.insts[best_inst].mesh;
+            }
+            float t, u, v;
+            if (finalize64(g.meshes[mesh], best_prim, ox, oy, oz, dx, dy, dz, t, u, v)) {
+              h.t = t;
+              h.u = u;
+              h.v = v;
+            }
+          }
+          float4* hp = reinterpret_cast<float4*>(hit_out + ray_id);
+          *hp = make_float4(h.t, __uint_as_float(h.prim_id), h.u, h.v);
+          if (MODE == 0 && inst_out)
+            inst_out[ray_id] = (best_prim != RT_INVALID_ID) ? (INST ? best_inst : 0u) : RT_INVALID_ID;
+        }
+        live = false;
+      }
+    }
+  }
+  if constexpr (COUNT) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(P.counters) + 0, (unsigned long long)n_nodes);
+    atomicAdd(reinterpret_cast<unsigned long long*>(P.counters) + 1, (unsigned long long)n_tris);
+    atomicAdd(reinterpret_cast<unsigned long long*>(P.counters) + 2, (unsigned long long)n_spill);
+  }
+  (void)batch;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of the closest hit at fixed triangles (one ray per thread)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void backward_kernel(BackwardParams P) {
+  uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= P.n) return;
+  const float4* hp = reinterpret_cast<const float4*>(P.hits + i);
+  uint32_t prim = __float_as_uint(hp->y);
+  float* go = P.d_origins + 3 * (size_t)i;
+  float* gd = P.d_directions + 3 * (size_t)i;
+  if (prim == RT_INVALID_ID || prim >= P.mesh.triangle_count) {
+    go[0] = go[1] = go[2] = 0.0f;
+    gd[0] = gd[1] = gd[2] = 0.0f;
+    return;
+  }
+  rt_ray q = load_ray(P.rays, i);
+  const uint32_t* ix = P.mesh.indices + 3 * (size_t)prim;
+  uint32_t id[3] = {ix[0], ix[1], ix[2]};
+  const float* V = P.mesh.vertices;
+  double v0x = V[3 * (size_t)id[0]], v0y = V[3 * (size_t)id[0] + 1], v0z = V[3 * (size_t)id[0] + 2];
+  double e1x = V[3 * (size_t)id[1]] - v0x, e1y = V[3 * (size_t)id[1] + 1] - v0y,
+         e1z = V[3 * (size_t)id[1] + 2] - v0z;
+  double e2x = V[3 * (size_t)id[2]] - v0x, e2y = V[3 * (size_t)id[2] + 1] - v0y,
+         e2z = V[3 * (size_t)id[2] + 2] - v0z;
+  double dx = q.dx, dy = q.dy, dz = q.dz;
+  // M = [c0 | e1 | e2], c0 = -d; rows of M^-1 are (e1 x e2, e2 x c0, c0 x e1) / det
+  double c0x = -dx, c0y = -dy, c0z = -dz;
+  double r0x = e1y * e2z - e1z * e2y, r0y = e1z * e2x - e1x * e2z, r0z = e1x * e2y - e1y * e2x;
+  double r1x = e2y * c0z - e2z * c0y, r1y = e2z * c0x - e2x * c0z, r1z = e2x * c0y - e2y * c0x;
+  double r2x = c0y * e1z - c0z * e1y, r2y = c0z * e1x - c0x * e1z, r2z = c0x * e1y - c0y * e1x;
+  double det = c0x * r0x + c0y * r0y + c0z * r0z;
+  if (det == 0.0) {
+    go[0] = go[1] = go[2] = 0.0f;
+    gd[0] = gd[1] = gd[2] = 0.0f;
+    return;
+  }
+  double inv = 1.0 / det;
+  double sx = q.ox - v0x, sy = q.oy - v0y, sz = q.oz - v0z;
+  double t = (r0x * sx + r0y * sy + r0z * sz) * inv;
+  double u = (r1x * sx + r1y * sy + r1z * sz) * inv;
+  double v = (r2x * sx + r2y * sy + r2z * sz) * inv;
+  const float* gr = P.d_tuv + 3 * (size_t)i;
+  double gt = gr[0], gu = gr[1], gv = gr[2];
+  // lambda = M^-T g = sum_i g_i row_i(M^-1)
+  double lx = (gt * r0x + gu * r1x + gv * r2x) * inv;
+  double ly = (gt * r0y + gu * r1y + gv * r2y) * inv;
+  double lz = (gt * r0z + gu * r1z + gv * r2z) * inv;
+  go[0] = (float)lx; go[1] = (float)ly; go[2] = (float)lz;
+  gd[0] = (float)(t * lx); gd[1] = (float)(t * ly); gd[2] = (float)(t * lz);
+  double w[3] = {1.0 - u - v, u, v};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float* dv = P.d_vertices + 3 * (size_t)id[k];
+    atomicAdd(dv + 0, (float)(-w[k] * lx));
+    atomicAdd(dv + 1, (float)(-w[k] * ly));
+    atomicAdd(dv + 2, (float)(-w[k] * lz));
+  }
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t n, uint32_t value) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+}  // namespace rtk
+
+// ---------------------------------------------------------------------------
+// launch table
+// ---------------------------------------------------------------------------
+namespace {
+
+template <int W, int S, int WG, bool ANY, bool INST, int MODE>
+const void* kernel_ptr() {
+  return reinterpret_cast<const void*>(&rtk::trace_kernel<W, S, WG, ANY, INST, MODE>);
+}
+
+template <int W, bool ANY>
+const void* kernel_ptr_c() {
+  return reinterpret_cast<const void*>(&rtk::trace_kernel<W, 16, 256, ANY, false, 0, true>);
+}
+
+template <int W, int S, int WG>
+const void* pick_mode(bool any, bool inst, int mode) {
+  if (mode == 1) return kernel_ptr<W, S, WG, false, false, 1>();
+  if (any) return inst ? kernel_ptr<W, S, WG, true, true, 0>() : kernel_ptr<W, S, WG, true, false, 0>();
+  return inst ? kernel_ptr<W, S, WG, false, true, 0>() : kernel_ptr<W, S, WG, false, false, 0>();
+}
+
+template <int W, int S>
+const void* pick_wg(int wg, bool any, bool inst, int mode) {
+  switch (wg) {
+    case 64: return pick_mode<W, S, 64>(any, inst, mode);
+    case 128: return pick_mode<W, S, 128>(any, inst, mode);
+    case 256: return pick_mode<W, S, 256>(any, inst, mode);
+    case 512: return pick_mode<W, S, 512>(any, inst, mode);
+    default: return nullptr;
+  }
+}
+
+template <int W>
+const void* pick_s(int s, int wg, bool any, bool inst, int mode) {
+  switch (s) {
+    case 4: return pick_wg<W, 4>(wg, any, inst, mode);
+    case 8: return pick_wg<W, 8>(wg, any, inst, mode);
+    case 16: return pick_wg<W, 16>(wg, any, inst, mode);
+    case 32: return pick_wg<W, 32>(wg, any, inst, mode);
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+// Counting variants (node visits, triangle tests, stack spills per launch):
+// stack 16, workgroup 256, single level.
+const void* rtk_count_kernel(int width, bool any) {
+  switch (width) {
+    case 2: return any ? kernel_ptr_c<2, true>() : kernel_ptr_c<2, false>();
+    case 4: return any ? kernel_ptr_c<4, true>() : kernel_ptr_c<4, false>();
+    case 8: return any ? kernel_ptr_c<8, true>() : kernel_ptr_c<8, false>();
+    default: return nullptr;
+  }
+}
+
+const void* rtk_trace_kernel(int width, int stack, int wg, bool any, bool inst, int mode) {
+  if (stack == 32 && wg == 512) return nullptr;  // 64 KB of LDS: not offered
+  switch (width) {
+    case 2: return pick_s<2>(stack, wg, any, inst, mode);
+    case 4: return pick_s<4>(stack, wg, any, inst, mode);
+    case 8: return pick_s<8>(stack, wg, any, inst, mode);
+    default: return nullptr;
+  }
+}
+
+hipError_t rtk_launch_trace(const void* kern, uint32_t grid, uint32_t wg, const TraceParams& p,
+                            hipStream_t stream) {
+  TraceParams q = p;
+  void* args[] = {&q};
+  return hipLaunchKernel(kern, dim3(grid), dim3(wg), args, 0, stream);
+}
+
+hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream) {
+  if (p.n == 0) return hipSuccess;
+  BackwardParams q = p;
+  void* args[] = {&q};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::backward_kernel),
+                         dim3((p.n + 255) / 256), dim3(256), args, 0, stream);
+}
+
+hipError_t rtk_launch_fill(uint32_t* ptr, uint32_t n, uint32_t value, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  void* args[] = {&ptr, &n, &value};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::fill_u32_kernel),
+                         dim3((n + 255) / 256), dim3(256), args, 0, stream);
+}
