@@ -1,16 +1,24 @@
 """Benchmark: incoherent closest-hit ray queries at about a million triangles.
 
-Workload (synthetic, seeded): the noisy icosphere with 1,310,720 triangles
-(radius 1 +- 0.02) and 4,194,304 rays with origins uniform in [-1,1]^3 and
-directions uniform on the sphere, tmin = 0, tmax = +inf.  A step is one
-closest-hit query over all rays (rt_trace_closest: persistent traversal
-kernel with the float64 finalize), inputs and outputs resident in HBM.
+Headline workload (synthetic, seeded): the noisy icosphere with 1,310,720
+triangles (radius 1 +- 0.02) and 4,194,304 rays with origins uniform in
+[-1,1]^3 and directions uniform on the sphere, tmin = 0, tmax = +inf.  A step
+is one closest-hit query over all rays (rt_trace_closest: the persistent
+traversal kernel with the float64 finalize); inputs, accel and outputs are
+resident in HBM before timing starts.
+
+Secondary figures (same JSON line, "secondary"): any-hit on the same rays,
+the adjoint (rt_trace_backward) on the 262,144-triangle displaced grid with
+1,048,576 rays, and 256 meshes traced by one batched launch (HIP graph)
+versus 256 per-mesh launches.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes as C
+import hashlib
 import json
 import os
 import sys
@@ -24,10 +32,53 @@ TRI_BYTES = 48
 RAY_BYTES = 32
 HIT_BYTES = 16
 FINALIZE_BYTES = 12 + 36  # indices + vertices of the winning triangle
+BACKWARD_HIT_BYTES = 32 + 16 + 12 + 12 + 36 + 24 + 36  # per hit ray
+BACKWARD_MISS_BYTES = 32 + 16 + 12 + 24
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_closest_icosphere_incoherent_pmc_traffic.txt")
+TRAFFIC_KERNEL = "trace_kernel<4, 16, 256, false, false, 0, false>"
+KERNEL_SRC = os.path.join(ROOT, "paper_2603_00292_amd", "csrc", "rt_kernels.hip")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(info, variant):
+    """HBM-side bytes per launch of the closest-hit kernel from the committed
+    rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE, calibrated on a copy of
+    known size), or None when the kernel source or configuration differs."""
+    if not os.path.exists(TRAFFIC_FILE) or info["node_width"] != 4 or tuple(variant) != (16, 256):
+        return None
+    sha, val = None, None
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if "rt_kernels.hip sha256[:16] =" in line:
+                sha = line.split("=")[-1].strip()
+            elif TRAFFIC_KERNEL in line:
+                val = int(line.split()[-1])
+    return val if sha == kernel_sha() else None
+
+
+def timed(fn, steps, stream, torch):
+    """Mean and per-launch durations (ms) of fn() with HIP events on `stream`."""
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    tb, te = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    tb.record(stream)
+    for i in range(steps):
+        starts[i].record(stream)
+        fn()
+        ends[i].record(stream)
+    te.record(stream)
+    torch.cuda.synchronize()
+    per = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
+    return tb.elapsed_time(te) / steps, per
 
 
 def main():
@@ -35,9 +86,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target host time of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 512 MiB device copy first (for HBM counter calibration)")
     ap.add_argument("--width", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -49,16 +103,27 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2603_00292_amd import api, workloads
+    from paper_2603_00292_amd import _capi, api, workloads
 
     torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    sptr = C.c_void_p(int(stream.cuda_stream))
+    if args.copy_calibration:
+        x = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy calibration: 536870912 bytes read, 536870912 bytes written")
+        del x, y
+
     t0 = time.time()
     W = workloads.icosphere_incoherent()
     mesh = W.scene.meshes[0]
     n = W.rays.shape[0]
     log(f"workload generated in {time.time() - t0:.1f}s: {mesh.n_tri} triangles, {n} rays")
     ctx = api.Context(0)
-    dev = torch.device("cuda:0")
     V = torch.from_numpy(mesh.vertices).to(dev)
     I = torch.from_numpy(mesh.indices.view(np.int32)).to(dev)
     t0 = time.time()
@@ -69,36 +134,16 @@ def main():
     hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
-    # per-ray traversal statistics from the counting variant (same query)
     (nodes, tris, spills), _ = api.trace_counters(acc, rays)
     node_bytes = 32 * info["node_width"]
-    hit_rows = None
 
     def launch():
-        from paper_2603_00292_amd import _capi
-        import ctypes as C
         _capi.call("rt_trace_closest", acc.handle, C.c_void_p(rays.data_ptr()), n,
-                   C.c_void_p(hits.data_ptr()), None, C.c_void_p(int(torch.cuda.current_stream().cuda_stream)))
+                   C.c_void_p(hits.data_ptr()), None, sptr)
 
     for _ in range(args.warmup):
         launch()
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    t_begin = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_begin.record(stream)
-    for i in range(args.steps):
-        starts[i].record(stream)
-        launch()
-        ends[i].record(stream)
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    total_ms = t_begin.elapsed_time(t_end)
-    per = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
-    ms_per_step = total_ms / args.steps
+    ms_per_step, per = timed(launch, args.steps, stream, torch)
     mean_launch_ms = sum(per) / len(per)
     value = n / (ms_per_step * 1e-3) / 1e6
     h = hits.cpu().numpy()
@@ -109,44 +154,47 @@ def main():
     log(f"closest: {ms_per_step:.3f} ms/step, {value:.1f} Mrays/s; nodes/ray {nodes / n:.2f}, "
         f"tris/ray {tris / n:.2f}, spills/ray {spills / n:.3f}, hits {hit_rows}")
 
-    # secondary: any-hit on the same rays
+    traffic = measured_traffic(info, ctx.variant)
+
+    secondary = {"launch_ms_min": round(per[0], 4), "launch_ms_median": round(per[len(per) // 2], 4),
+                 "nodes_per_ray": round(nodes / n, 3), "tris_per_ray": round(tris / n, 3),
+                 "spills_per_ray": round(spills / n, 4)}
+
+    # any-hit on the same rays
     occ = torch.empty((n,), dtype=torch.uint8, device=dev)
 
     def launch_any():
-        from paper_2603_00292_amd import _capi
-        import ctypes as C
         _capi.call("rt_trace_any", acc.handle, C.c_void_p(rays.data_ptr()), n,
-                   C.c_void_p(occ.data_ptr()), C.c_void_p(int(torch.cuda.current_stream().cuda_stream)))
+                   C.c_void_p(occ.data_ptr()), sptr)
 
-    for _ in range(2):
-        launch_any()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        launch_any()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    any_mrays = n / (e0.elapsed_time(e1) / args.steps * 1e-3) / 1e6
-    log(f"any-hit: {any_mrays:.1f} Mrays/s")
+    launch_any()
+    ms_any, _ = timed(launch_any, args.steps, stream, torch)
+    secondary["any_hit_mrays"] = round(n / (ms_any * 1e-3) / 1e6, 3)
+    log(f"any-hit: {secondary['any_hit_mrays']} Mrays/s")
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
 
         S = oracle.OracleScene.from_scene(W.scene)
-        sample = 16
-        t0 = time.time()
-        oracle.closest(S, W.rays[:sample])
-        dt = time.time() - t0
-        m = int(min(n, max(sample, sample * args.cpu_seconds / max(dt, 1e-3))))
-        t0 = time.time()
-        oracle.closest(S, W.rays[:m])
-        dt = time.time() - t0
+        m = 32
+        while True:
+            t0 = time.time()
+            oracle.closest(S, W.rays[:m])
+            dt = time.time() - t0
+            if dt >= args.cpu_seconds / 3 or m >= n:
+                break
+            m = min(n, int(m * max(2.0, args.cpu_seconds / max(dt, 1e-3))))
         cpu = {"value": m / dt / 1e6, "unit": "Mrays/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"first {m} of the {n} rays, brute force over all {mesh.n_tri} triangles "
-                         f"(FP64 linear search), {dt:.1f} s"}
+               "sample": f"first {m} of the {n} rays, FP64 linear search over all {mesh.n_tri} "
+                         f"triangles, {dt:.1f} s"}
         log(f"oracle: {cpu}")
+    acc.close()
+    del rays, hits, occ
+
+    if not args.no_secondary:
+        secondary.update(backward_bench(args, torch, np, api, workloads, ctx, stream))
+        secondary.update(batched_bench(args, torch, np, api, _capi, workloads, ctx, stream))
 
     out = {
         "metric": "Mrays/s closest-hit incoherent @1M tris",
@@ -165,17 +213,105 @@ def main():
                    "origins": "U[-1,1]^3", "directions": "uniform sphere", "node_width": info["node_width"],
                    "variant": list(ctx.variant), "query": "closest"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_ray": round(bytes_per_launch / n, 1),
-                     "nodes_per_ray": round(nodes / n, 3), "tris_per_ray": round(tris / n, 3),
-                     "kernel_ms": round(mean_launch_ms, 4)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "bytes_per_ray": round(bytes_per_launch / n, 1), "kernel_ms": round(mean_launch_ms, 4)},
         "cpu_baseline": cpu,
-        "secondary": {"any_hit_mrays": round(any_mrays, 3),
-                      "launch_ms_min": round(per[0], 4), "launch_ms_median": round(per[len(per) // 2], 4)},
+        "secondary": secondary,
     }
     print(json.dumps(out), flush=True)
-    acc.close()
     ctx.close()
+
+
+def backward_bench(args, torch, np, api, workloads, ctx, stream):
+    """Adjoint throughput on the displaced grid (262,144 triangles, 1,048,576
+    rays): forward once, then time rt_trace_backward."""
+    W = workloads.displaced_grid()
+    m = W.scene.meshes[0]
+    dev = torch.device("cuda:0")
+    V = torch.from_numpy(m.vertices).to(dev)
+    I = torch.from_numpy(m.indices.view(np.int32)).to(dev)
+    acc = api.Accel(ctx, [(V, I)])
+    rays = torch.from_numpy(W.rays).to(dev)
+    hits, _ = api.trace_closest(acc, rays)
+    g = torch.from_numpy(W.extra["abc"]).to(dev)
+    dV = torch.zeros_like(V)
+    do = torch.empty((rays.shape[0], 3), dtype=torch.float32, device=dev)
+    dd = torch.empty_like(do)
+    from paper_2603_00292_amd import _capi
+    sptr = C.c_void_p(int(stream.cuda_stream))
+    n = rays.shape[0]
+
+    def bwd():
+        _capi.call("rt_trace_backward", acc.handle, C.c_void_p(rays.data_ptr()), C.c_void_p(hits.data_ptr()),
+                   C.c_void_p(g.data_ptr()), n, C.c_void_p(dV.data_ptr()), C.c_void_p(do.data_ptr()),
+                   C.c_void_p(dd.data_ptr()), sptr)
+
+    def fwd():
+        _capi.call("rt_trace_closest", acc.handle, C.c_void_p(rays.data_ptr()), n,
+                   C.c_void_p(hits.data_ptr()), None, sptr)
+
+    bwd()
+    ms_b, per_b = timed(bwd, args.steps, stream, torch)
+    ms_f, _ = timed(fwd, args.steps, stream, torch)
+    nh = int((hits[:, 1].contiguous().view(torch.int32) != -1).sum().item())
+    alg = nh * BACKWARD_HIT_BYTES + (n - nh) * BACKWARD_MISS_BYTES
+    mean_b = sum(per_b) / len(per_b)
+    r = {"backward_mrays": round(n / (ms_b * 1e-3) / 1e6, 3),
+         "backward_forward_mrays": round(n / (ms_f * 1e-3) / 1e6, 3),
+         "backward_workload": "displaced_grid_512x256 (262144 triangles), 1048576 rays",
+         "backward_hbm_frac": round(alg / (mean_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"backward: {r}")
+    acc.close()
+    return r
+
+
+def batched_bench(args, torch, np, api, _capi, workloads, ctx, stream):
+    """256 meshes (log-uniform 1k-500k triangles, 1k-1M rays each): one
+    batched persistent launch replayed from a HIP graph versus 256 per-mesh
+    rt_trace_closest launches on one stream."""
+    t0 = time.time()
+    works = workloads.batched_meshes()
+    dev = torch.device("cuda:0")
+    accs, rays = [], []
+    for w in works:
+        m = w.scene.meshes[0]
+        accs.append(api.Accel(ctx, [(torch.from_numpy(m.vertices).to(dev),
+                                     torch.from_numpy(m.indices.view(np.int32)).to(dev))]))
+        rays.append(torch.from_numpy(w.rays).to(dev))
+    total = sum(r.shape[0] for r in rays)
+    log(f"batched set up in {time.time() - t0:.1f}s: {total} rays, "
+        f"{sum(w.scene.meshes[0].n_tri for w in works)} triangles")
+    plan = api.BatchPlan(ctx, accs, rays)
+    hits = [torch.empty_like(h) for h in plan.hits]
+    sptr = C.c_void_p(int(stream.cuda_stream))
+
+    def per_mesh():
+        for a, r, h in zip(accs, rays, hits):
+            _capi.call("rt_trace_closest", a.handle, C.c_void_p(r.data_ptr()), r.shape[0],
+                       C.c_void_p(h.data_ptr()), None, sptr)
+
+    s2 = torch.cuda.Stream()
+    g = plan.graph_exec(s2)
+
+    def batched():
+        api.graph_launch(g, stream)
+
+    per_mesh()
+    batched()
+    steps = max(3, args.steps // 4)
+    ms_pm, _ = timed(per_mesh, steps, stream, torch)
+    ms_b, _ = timed(batched, steps, stream, torch)
+    same = all(torch.equal(a.view(torch.int32), b.view(torch.int32)) for a, b in zip(hits, plan.hits))
+    r = {"batched_mrays": round(total / (ms_b * 1e-3) / 1e6, 3),
+         "per_mesh_mrays": round(total / (ms_pm * 1e-3) / 1e6, 3),
+         "batched_vs_per_mesh": round(ms_pm / ms_b, 3),
+         "batched_identical": bool(same),
+         "batched_workload": f"256 meshes, {total} rays"}
+    log(f"batched: {r}")
+    plan.close()
+    for a in accs:
+        a.close()
+    return r
 
 
 if __name__ == "__main__":

@@ -1,0 +1,188 @@
+"""GPU parity of the adjoint (rt_trace_backward) and of the autograd Function
+against the FP64 oracle adjoint and FP64 finite differences."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from helpers import NONE, check_closest, to_gpu_scene
+from paper_2603_00292_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+GRAD_REL = 1e-4      # per-ray |grad_gpu - grad_ref| <= GRAD_REL |grad_ref|
+DV_FROB_REL = 1e-5   # whole tensor
+FD_REL = 1e-6        # FD vs analytic (FP64 on both sides)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    from paper_2603_00292_amd import api
+
+    torch.cuda.set_device(0)
+    ctx = api.Context(0)
+    yield torch, api, ctx
+    torch.cuda.synchronize()
+
+
+def _run(gpu, W, g):
+    torch, api, ctx = gpu
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    rays = torch.from_numpy(W.rays).cuda()
+    hits, _ = api.trace_closest(acc, rays)
+    gt = torch.from_numpy(np.ascontiguousarray(g, dtype=np.float32)).cuda()
+    nv = W.scene.meshes[0].vertices.shape[0]
+    dV = torch.zeros((nv, 3), dtype=torch.float32, device="cuda")
+    do, dd = api.trace_backward(acc, rays, hits, gt, dV)
+    torch.cuda.synchronize()
+    out = hits.cpu().numpy(), dV.cpu().numpy().astype(np.float64), do.cpu().numpy(), dd.cpu().numpy()
+    return acc, out
+
+
+def test_backward_small_full_check(gpu, orc):
+    """64x32-quad displaced grid, 16,384 rays: every pinned hit ray's gradient
+    and the whole vertex-gradient tensor against the oracle."""
+    W = wl.displaced_grid(nx=64, nz=32, n_rays=16384, k=300)
+    S = orc.OracleScene.from_scene(W.scene)
+    A = orc.accept(S, W.rays)
+    _, oprim, otuv = orc.closest(S, W.rays)
+    pinned_hit = A.pinned & (oprim != NONE)
+    g = W.extra["abc"].astype(np.float64) * pinned_hit[:, None]  # only pinned rays contribute
+    acc, (h, dV, do, dd) = _run(gpu, W, g)
+    check_closest(h, A, label="grid forward")
+    prim = h[:, 1].copy().view(np.uint32)
+    assert (prim[pinned_hit] == oprim[pinned_hit]).all()
+    rV, ro, rd = orc.adjoint(S, W.rays, np.where(pinned_hit, oprim, NONE), g)
+    r = np.flatnonzero(pinned_hit)
+    assert r.size > 12000
+    eo = np.linalg.norm(do[r] - ro[r], axis=1) / np.maximum(np.linalg.norm(ro[r], axis=1), 1e-30)
+    ed = np.linalg.norm(dd[r] - rd[r], axis=1) / np.maximum(np.linalg.norm(rd[r], axis=1), 1e-30)
+    say("max rel err d_origin", eo.max(), "d_direction", ed.max())
+    assert eo.max() <= GRAD_REL and ed.max() <= GRAD_REL
+    # misses and unpinned rays (g = 0) give zero ray gradients
+    z = ~pinned_hit
+    assert np.abs(do[z]).max() == 0 and np.abs(dd[z]).max() == 0
+    frob = np.linalg.norm(dV - rV) / np.linalg.norm(rV)
+    say("d_vertices Frobenius rel err", frob)
+    assert frob <= DV_FROB_REL
+    per = np.linalg.norm(dV - rV, axis=1)
+    rms = np.sqrt((rV ** 2).sum(1).mean())
+    assert (per <= 1e-3 * np.linalg.norm(rV, axis=1) + 1e-6 * rms).all()
+    acc.close()
+
+
+def test_backward_full_size_sampled(gpu, orc):
+    """512x256-quad grid (262,144 triangles), 1,048,576 rays: forward on all
+    rays, backward of L = sum(a t + b u + c v); 1,000 sampled pinned hit rays
+    checked against the oracle adjoint and FP64 finite differences (h=1e-6);
+    translation invariance of the summed gradients on all rays."""
+    W = wl.displaced_grid()
+    g = W.extra["abc"].astype(np.float64)
+    acc, (h, dV, do, dd) = _run(gpu, W, g)
+    prim = h[:, 1].copy().view(np.uint32)
+    hit = prim != NONE
+    say("hit fraction", hit.mean())
+    assert hit.mean() > 0.99
+    rng = wl.rng_for(301)
+    cand = np.sort(rng.choice(W.rays.shape[0], 1400, replace=False))
+    S = orc.OracleScene.from_scene(W.scene)
+    A = orc.accept(S, W.rays[cand])
+    check_closest(h[cand], A, label="grid sampled")
+    keep = A.pinned & ~A.miss_ok
+    idx = cand[keep][:1000]
+    assert idx.size == 1000
+    p = prim[idx]
+    _, ro, rd = orc.adjoint(S, W.rays[idx], p, g[idx])
+    eo = np.linalg.norm(do[idx] - ro, axis=1) / np.linalg.norm(ro, axis=1)
+    ed = np.linalg.norm(dd[idx] - rd, axis=1) / np.linalg.norm(rd, axis=1)
+    say("sampled max rel err d_origin", eo.max(), "d_direction", ed.max())
+    assert eo.max() <= GRAD_REL and ed.max() <= GRAD_REL
+    fd = orc.fd(S, W.rays[idx], p, g[idx], h=1e-6)
+    an = np.concatenate([ro, rd], 1)
+    rel = np.abs(fd[:, 9:15] - an).max(1) / np.abs(an).max(1)
+    assert rel.max() <= FD_REL
+    # vertex-gradient rows of single sampled rays against FD
+    torch, api, _ = gpu
+    rays_t = torch.from_numpy(W.rays).cuda()
+    hits_t = torch.from_numpy(h).cuda()
+    I = W.scene.meshes[0].indices
+    nv = W.scene.meshes[0].vertices.shape[0]
+    dv_fd = fd[:, 0:9]
+    for j in range(0, 1000, 50):
+        r = int(idx[j])
+        dV1 = torch.zeros((nv, 3), dtype=torch.float32, device="cuda")
+        g1 = torch.from_numpy(g[r:r + 1].astype(np.float32)).cuda()
+        api.trace_backward(acc, rays_t[r:r + 1].contiguous(), hits_t[r:r + 1].contiguous(), g1, dV1)
+        dV1 = dV1.cpu().numpy().astype(np.float64)
+        tri = I[p[j]]
+        got = np.concatenate([dV1[tri[0]], dV1[tri[1]], dV1[tri[2]]])
+        assert np.abs(got - dv_fd[j]).max() <= GRAD_REL * np.abs(dv_fd[j]).max() + 1e-7
+    # translation invariance: sum of vertex gradients = - sum of origin gradients
+    s_v = dV.sum(0)
+    s_o = do[hit].astype(np.float64).sum(0)
+    assert np.abs(s_v + s_o).max() <= 1e-4 * np.abs(do[hit]).sum()
+    # homogeneity per ray: d . dL/dd = -t g_t
+    d = W.rays[hit, 4:7].astype(np.float64)
+    lhs = (d * dd[hit]).sum(1)
+    rhs = -h[hit, 0].astype(np.float64) * g[hit, 0]
+    assert np.allclose(lhs, rhs, rtol=1e-4, atol=1e-5 * np.abs(rhs).max())
+    acc.close()
+
+
+def test_autograd_function(gpu, orc):
+    """RayQueryFn: gradients of a masked loss equal rt_trace_backward's."""
+    torch, api, ctx = gpu
+    W = wl.displaced_grid(nx=32, nz=16, n_rays=4096, k=302)
+    m = W.scene.meshes[0]
+    V = torch.from_numpy(m.vertices).cuda().requires_grad_(True)
+    I = torch.from_numpy(m.indices.view(np.int32)).cuda()
+    acc = api.Accel(ctx, [(V.detach(), I)])
+    rays = torch.from_numpy(W.rays).cuda()
+    o = rays[:, 0:3].clone().requires_grad_(True)
+    d = rays[:, 4:7].clone().requires_grad_(True)
+    t, u, v, prim = api.RayQueryFn.apply(acc, V, o, d, 0.0, float("inf"))
+    abc = torch.from_numpy(W.extra["abc"]).cuda()
+    hit = prim >= 0
+    loss = (abc[hit, 0] * t[hit] + abc[hit, 1] * u[hit] + abc[hit, 2] * v[hit]).sum()
+    loss.backward()
+    hits, _ = api.trace_closest(acc, rays)
+    g = torch.zeros((rays.shape[0], 3), dtype=torch.float32, device="cuda")
+    g[hit] = abc[hit]
+    dV = torch.zeros_like(V)
+    do, dd = api.trace_backward(acc, rays, hits, g.contiguous(), dV)
+    torch.cuda.synchronize()
+    assert torch.allclose(o.grad, do, rtol=1e-6, atol=1e-6)
+    assert torch.allclose(d.grad, dd, rtol=1e-6, atol=1e-6)
+    assert torch.allclose(V.grad, dV, rtol=1e-4, atol=1e-5)
+    # and against the oracle on pinned hits
+    S = orc.OracleScene.from_scene(W.scene)
+    A = orc.accept(S, W.rays)
+    p = prim.cpu().numpy()
+    keep = A.pinned & (p >= 0)
+    _, ro, rd = orc.adjoint(S, W.rays[keep], p[keep].astype(np.uint32), W.extra["abc"][keep].astype(np.float64))
+    assert np.allclose(o.grad.cpu().numpy()[keep], ro, rtol=1e-4, atol=1e-6 * np.abs(ro).max())
+    acc.close()
+
+
+def test_backward_rejects_two_level(gpu):
+    torch, api, ctx = gpu
+    from paper_2603_00292_amd import _capi
+
+    W = wl.random_triangles(n_tri=64, n_rays=16, k=303, half=0.2)
+    m = W.scene.meshes[0]
+    acc = api.Accel(ctx, [(torch.from_numpy(m.vertices).cuda(), torch.from_numpy(m.indices.view(np.int32)).cuda())],
+                    inst_mesh=np.zeros(2, np.uint32),
+                    inst_srt=np.array([[1, 1, 1, 0, 0, 0, 1, 0, 0, 0], [1, 1, 1, 0, 0, 0, 1, 3, 0, 0]], np.float32))
+    rays = torch.from_numpy(W.rays).cuda()
+    hits, _ = api.trace_closest(acc, rays)
+    dV = torch.zeros((m.vertices.shape[0], 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(_capi.RtError) as e:
+        api.trace_backward(acc, rays, hits, torch.zeros((16, 3), dtype=torch.float32, device="cuda"), dV)
+    assert e.value.status == _capi.RT_ERROR_UNSUPPORTED
+    acc.close()

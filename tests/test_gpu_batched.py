@@ -1,0 +1,114 @@
+"""Batched plans: one persistent launch (and its HIP graph) over many meshes
+equals separate per-mesh launches bit for bit, and matches the oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from helpers import check_closest, to_gpu_scene
+from paper_2603_00292_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    from paper_2603_00292_amd import api
+
+    torch.cuda.set_device(0)
+    ctx = api.Context(0)
+    yield torch, api, ctx
+    torch.cuda.synchronize()
+
+
+def _setup(gpu, works):
+    torch, api, ctx = gpu
+    accs = [to_gpu_scene(api, torch, ctx, w.scene) for w in works]
+    rays = [torch.from_numpy(w.rays).cuda() for w in works]
+    return accs, rays
+
+
+def _per_mesh(gpu, accs, rays):
+    torch, api, _ = gpu
+    out = [api.trace_closest(a, r)[0] for a, r in zip(accs, rays)]
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in out]
+
+
+def _check_equal(batched, per):
+    for b, p in zip(batched, per):
+        assert np.array_equal(b.view(np.uint32), p.view(np.uint32))
+
+
+def test_batched_small_uneven(gpu, orc):
+    """Twelve meshes (0 to 60k triangles) with uneven ray counts, including
+    empty batches: plan launch and graph replays equal per-mesh launches."""
+    torch, api, ctx = gpu
+    rng = wl.rng_for(500)
+    works = []
+    for m, (nt, nr) in enumerate([(1000, 1), (60000, 50000), (0, 100), (5000, 0), (2000, 7777),
+                                  (30000, 64), (1, 65), (12345, 30000), (800, 1000), (40000, 3),
+                                  (7000, 20000), (3, 1)]):
+        half = 0.025 * np.sqrt(4096.0 / max(nt, 1))
+        V, I = wl.random_triangle_soup(rng, nt, half)
+        works.append(wl.Workload(f"b{m}", wl.Scene([wl.Mesh(V, I)]), wl.box_rays(rng, nr, -1, 2)))
+    accs, rays = _setup(gpu, works)
+    per = _per_mesh(gpu, accs, rays)
+    plan = api.BatchPlan(ctx, accs, rays)
+    plan.launch()
+    torch.cuda.synchronize()
+    _check_equal([h.cpu().numpy() for h in plan.hits], per)
+    # graph: capture once, replay several times with eager work in between
+    s = torch.cuda.Stream()
+    g = plan.graph_exec(s)
+    for rep in range(3):
+        for h in plan.hits:
+            h.fill_(-1.0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            api.graph_launch(g, s)
+        s.synchronize()
+        _check_equal([h.cpu().numpy() for h in plan.hits], per)
+        _ = (rays[1] * 2).sum().item()  # unrelated eager work between replays
+    # oracle on a few batches
+    for b in (1, 4, 7, 10):
+        if works[b].rays.shape[0] == 0:
+            continue
+        k = min(256, works[b].rays.shape[0])
+        S = orc.OracleScene.from_scene(works[b].scene)
+        check_closest(per[b][:k], orc.accept(S, works[b].rays[:k]), label=f"batch {b}")
+    plan.close()
+    for a in accs:
+        a.close()
+
+
+def test_batched_full_size(gpu, orc):
+    """256 meshes with log-uniform triangle (1k-500k) and ray (1k-1M) counts,
+    all traced in one persistent launch and by 256 per-mesh launches; every
+    ray compared bit for bit, 4 meshes x 64 rays against the oracle."""
+    torch, api, ctx = gpu
+    works = wl.batched_meshes()
+    say("triangles", sum(w.scene.meshes[0].n_tri for w in works), "rays", sum(w.rays.shape[0] for w in works))
+    accs, rays = _setup(gpu, works)
+    per = _per_mesh(gpu, accs, rays)
+    plan = api.BatchPlan(ctx, accs, rays)
+    s = torch.cuda.Stream()
+    g = plan.graph_exec(s)
+    with torch.cuda.stream(s):
+        api.graph_launch(g, s)
+    s.synchronize()
+    _check_equal([h.cpu().numpy() for h in plan.hits], per)
+    rng = wl.rng_for(501)
+    for b in rng.choice(len(works), 4, replace=False):
+        idx = np.sort(rng.choice(works[b].rays.shape[0], 64, replace=False))
+        S = orc.OracleScene.from_scene(works[b].scene)
+        check_closest(per[b][idx], orc.accept(S, works[b].rays[idx]), label=f"batch {b}")
+    plan.close()
+    for a in accs:
+        a.close()
