@@ -92,7 +92,9 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 512 MiB device copy first (for HBM counter calibration)")
-    ap.add_argument("--width", type=int, default=4)
+    ap.add_argument("--width", type=int, default=4, help="node width when not autotuning")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--probe", type=int, default=262144, help="rays the autotuner times")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the ray-query path is built and measured on a single "
@@ -126,11 +128,22 @@ def main():
     ctx = api.Context(0)
     V = torch.from_numpy(mesh.vertices).to(dev)
     I = torch.from_numpy(mesh.indices.view(np.int32)).to(dev)
+    rays = torch.from_numpy(W.rays).to(dev)
+    tuned = None
+    width = args.width
+    if not args.no_autotune:
+        # untimed: pick node width, stack entries and workgroup on a probe of
+        # the workload's own rays (rt_autotune)
+        from paper_2603_00292_amd import autotune
+
+        t0 = time.time()
+        tuned, _ = autotune.autotune(ctx, V, I, rays[: args.probe].contiguous())
+        width = tuned["node_width"]
+        log(f"autotune {time.time() - t0:.1f}s: {tuned}")
     t0 = time.time()
-    acc = api.Accel(ctx, [(V, I)], node_width=args.width)
+    acc = api.Accel(ctx, [(V, I)], node_width=width)
     info = acc.info
     log(f"build {time.time() - t0:.1f}s: {info}")
-    rays = torch.from_numpy(W.rays).to(dev)
     hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
@@ -211,7 +224,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "icosphere_incoherent", "triangles": int(mesh.n_tri), "rays": int(n),
                    "origins": "U[-1,1]^3", "directions": "uniform sphere", "node_width": info["node_width"],
-                   "variant": list(ctx.variant), "query": "closest"},
+                   "variant": list(ctx.variant), "autotuned": tuned is not None, "query": "closest"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_ray": round(bytes_per_launch / n, 1), "kernel_ms": round(mean_launch_ms, 4)},

@@ -107,10 +107,10 @@ typedef struct rt_build_options {
 } rt_build_options;
 
 /* Trace variant (launch configuration of the traversal kernels):
- * stack_entries = per-lane traversal stack kept in LDS (4, 8, 16, 32; deeper
+ * stack_entries = per-lane traversal stack kept in LDS (8, 16, 32; deeper
  * entries spill to a global stack), workgroup = threads per workgroup (64,
- * 128, 256, 512).  The defaults are 16 and 256.  Results do not depend on the
- * variant. */
+ * 128, 256).  The defaults are 16 and 256.  Results do not depend on the
+ * variant (§7.5 notes that stack and block sizes are compile-time choices). */
 typedef struct rt_variant {
   uint32_t stack_entries;
   uint32_t workgroup;
@@ -225,6 +225,29 @@ rt_status rt_batch_plan_launch(rt_batch_plan plan, void* stream);
  * plan (freed by rt_batch_plan_destroy).  Replay it with hipGraphLaunch. */
 rt_status rt_batch_plan_graph(rt_batch_plan plan, void* stream, void** out_graph_exec);
 rt_status rt_batch_plan_destroy(rt_batch_plan plan);
+
+/* ---- autotuning ---------------------------------------------------------- */
+
+/* One measured configuration. */
+typedef struct rt_tune_entry {
+  uint32_t node_width;
+  uint32_t stack_entries;
+  uint32_t workgroup;
+  float ms;                   /* median of the timed closest-hit launches */
+} rt_tune_entry;
+
+/* Picks node width, stack entries and workgroup size for closest-hit
+ * queries on `mesh` by measurement: the mesh is built at each candidate
+ * node width (2, 4, 8) and every variant is timed with HIP events on
+ * `stream` on the n_probe probe rays (device), median of `repeats` launches
+ * after one warm-up.  On return *best holds the fastest configuration, the
+ * context's variant is set to it, and table (HOST, capacity table_cap,
+ * nullable) receives up to table_cap measured entries (*table_len = how many
+ * were measured).  The caller builds its accel with best->node_width.
+ * Synchronises the stream.  Errors as rt_build and rt_trace_closest. */
+rt_status rt_autotune(rt_context ctx, const rt_mesh_desc* mesh, const rt_ray* probe_rays,
+                      uint32_t n_probe, uint32_t repeats, void* stream, rt_tune_entry* best,
+                      rt_tune_entry* table, uint32_t table_cap, uint32_t* table_len);
 
 /* ---- diagnostics -------------------------------------------------------- */
 

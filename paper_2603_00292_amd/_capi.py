@@ -25,6 +25,7 @@ EXPORTS = [
     "rt_context_create", "rt_context_destroy", "rt_context_set_variant", "rt_context_get_variant",
     "rt_build", "rt_accel_destroy", "rt_accel_get_info",
     "rt_trace_closest", "rt_trace_any", "rt_trace_backward", "rt_trace_counters",
+    "rt_autotune",
     "rt_batch_plan_create", "rt_batch_plan_launch", "rt_batch_plan_graph", "rt_batch_plan_destroy",
     "rt_status_string", "rt_last_error_message", "rt_version",
 ]
@@ -55,6 +56,11 @@ class rt_build_options(C.Structure):
 
 class rt_variant(C.Structure):
     _fields_ = [("stack_entries", C.c_uint32), ("workgroup", C.c_uint32)]
+
+
+class rt_tune_entry(C.Structure):
+    _fields_ = [("node_width", C.c_uint32), ("stack_entries", C.c_uint32), ("workgroup", C.c_uint32),
+                ("ms", C.c_float)]
 
 
 class rt_accel_info(C.Structure):
@@ -93,6 +99,7 @@ def load():
             "rt_trace_any": [P, P, U32, P, P],
             "rt_trace_backward": [P, P, P, P, U32, P, P, P, P],
             "rt_trace_counters": [P, P, U32, I32, P, P, P, P],
+            "rt_autotune": [P, P, P, U32, U32, P, P, P, U32, P],
             "rt_batch_plan_create": [P, P, P, P, P, U32, P],
             "rt_batch_plan_launch": [P, P],
             "rt_batch_plan_graph": [P, P, P],

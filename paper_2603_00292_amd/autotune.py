@@ -1,0 +1,102 @@
+"""Autotuner front end: picks node width, stack entries and workgroup size by
+measurement (rt_autotune in librtq) and caches the choice per device and
+scene class.
+
+    python -m paper_2603_00292_amd.autotune --workload icosphere_incoherent
+
+The measurement itself (builds at each node width, HIP-event timing of every
+variant on a probe batch) runs in the library; this module marshals tensors,
+keys the cache and reads/writes it as JSON.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import math
+import os
+
+import torch
+
+from . import _capi as capi
+from . import api
+
+CACHE = os.environ.get("RTQ_AUTOTUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "rtq", "autotune.json"))
+
+
+def scene_class(n_triangles: int, n_rays: int) -> str:
+    """Cache key part: triangle and ray counts by power-of-four bucket."""
+    tb = int(math.log(max(n_triangles, 1), 4))
+    rb = int(math.log(max(n_rays, 1), 4))
+    return f"tri4^{tb}_ray4^{rb}"
+
+
+def device_key(device: int) -> str:
+    p = torch.cuda.get_device_properties(device)
+    arch = getattr(p, "gcnArchName", "unknown").split(":")[0]
+    return f"{arch}_cu{p.multi_processor_count}"
+
+
+def autotune(ctx: api.Context, vertices: torch.Tensor, indices: torch.Tensor, probe_rays: torch.Tensor,
+             repeats: int = 3):
+    """Runs rt_autotune; returns (best, table) as dicts.  The context's
+    variant is set to the best one; build the accel with best['node_width']."""
+    api._require(vertices, "vertices", torch.float32, 3)
+    api._require(probe_rays, "probe_rays", torch.float32, 8)
+    desc = capi.rt_mesh_desc(vertices.data_ptr(), vertices.shape[0], 12, indices.data_ptr(), indices.shape[0], 12)
+    best = capi.rt_tune_entry()
+    cap = 64
+    table = (capi.rt_tune_entry * cap)()
+    n = C.c_uint32(0)
+    capi.call("rt_autotune", ctx.handle, C.byref(desc), C.c_void_p(probe_rays.data_ptr()), probe_rays.shape[0],
+              int(repeats), C.c_void_p(api._stream()), C.byref(best), table, cap, C.byref(n))
+    to = lambda e: {"node_width": e.node_width, "stack_entries": e.stack_entries, "workgroup": e.workgroup,
+                    "ms": round(float(e.ms), 5)}
+    return to(best), [to(table[i]) for i in range(min(n.value, cap))]
+
+
+def load_cache() -> dict:
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def save_choice(device: int, cls: str, best: dict) -> None:
+    c = load_cache()
+    c.setdefault(device_key(device), {})[cls] = best
+    os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+    with open(CACHE, "w") as f:
+        json.dump(c, f, indent=1)
+
+
+def cached_choice(device: int, cls: str):
+    return load_cache().get(device_key(device), {}).get(cls)
+
+
+def main():
+    import numpy as np
+
+    from . import workloads
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="icosphere_incoherent",
+                    choices=["icosphere_incoherent", "random_triangles", "displaced_grid"])
+    ap.add_argument("--probe", type=int, default=262144)
+    args = ap.parse_args()
+    W = getattr(workloads, args.workload)()
+    m = W.scene.meshes[0]
+    torch.cuda.set_device(0)
+    ctx = api.Context(0)
+    V = torch.from_numpy(m.vertices).cuda()
+    I = torch.from_numpy(m.indices.view(np.int32)).cuda()
+    probe = torch.from_numpy(W.rays[: args.probe]).cuda()
+    best, table = autotune(ctx, V, I, probe)
+    cls = scene_class(m.n_tri, W.rays.shape[0])
+    save_choice(0, cls, best)
+    print(json.dumps({"class": cls, "best": best, "table": table}))
+
+
+if __name__ == "__main__":
+    main()

@@ -59,11 +59,15 @@ int env_int(const char* name, int dflt) {
   return std::atoi(v);
 }
 
+const uint32_t kStackChoices[] = {8, 16, 32};
+const uint32_t kWorkgroupChoices[] = {64, 128, 256};
+const uint32_t kWidthChoices[] = {2, 4, 8};
+
 bool valid_variant(const rt_variant& v) {
-  bool s_ok = v.stack_entries == 4 || v.stack_entries == 8 || v.stack_entries == 16 ||
-              v.stack_entries == 32;
-  bool wg_ok = v.workgroup == 64 || v.workgroup == 128 || v.workgroup == 256 || v.workgroup == 512;
-  return s_ok && wg_ok && !(v.stack_entries == 32 && v.workgroup == 512);
+  bool s_ok = false, wg_ok = false;
+  for (uint32_t x : kStackChoices) s_ok = s_ok || v.stack_entries == x;
+  for (uint32_t x : kWorkgroupChoices) wg_ok = wg_ok || v.workgroup == x;
+  return s_ok && wg_ok;
 }
 
 // device scratch of one launch: queue counter + global spill stack
@@ -85,7 +89,8 @@ struct rt_context_s {
   int device = 0;
   int cu_count = 0;
   rt_variant variant{16, 256};
-  uint32_t refill_min = 16;
+  uint32_t refill_min = 32;
+  uint32_t blocks_per_cu = 0;  // 0 = the occupancy API's resident count
   std::mutex mu;
   Scratch scratch;
   hipEvent_t last_event = nullptr;
@@ -222,7 +227,8 @@ rt_status rt_context_create(int hip_device, rt_context* out) {
   c->cu_count = prop.multiProcessorCount;
   rt_variant v{(uint32_t)env_int("RT_STACK", 16), (uint32_t)env_int("RT_WG", 256)};
   if (valid_variant(v)) c->variant = v;
-  c->refill_min = (uint32_t)std::min(64, std::max(1, env_int("RT_REFILL", 16)));
+  c->refill_min = (uint32_t)std::min(64, std::max(1, env_int("RT_REFILL", 32)));
+  c->blocks_per_cu = (uint32_t)std::min(64, std::max(0, env_int("RT_BLOCKS_PER_CU", 0)));
   if (hipEventCreateWithFlags(&c->last_event, hipEventDisableTiming) != hipSuccess) {
     delete c;
     return fail(RT_ERROR_HIP, "rt_context_create: hipEventCreate failed");
@@ -245,8 +251,8 @@ rt_status rt_context_set_variant(rt_context ctx, const rt_variant* v) {
   if (!ctx || !v) return fail(RT_ERROR_INVALID_VALUE, "rt_context_set_variant: NULL argument");
   if (!valid_variant(*v))
     return fail(RT_ERROR_INVALID_VALUE,
-                "rt_context_set_variant: stack_entries must be 4/8/16/32 and workgroup "
-                "64/128/256/512 (not 32 with 512)");
+                "rt_context_set_variant: stack_entries must be 8/16/32 and workgroup "
+                "64/128/256");
   std::lock_guard<std::mutex> lk(ctx->mu);
   ctx->variant = *v;
   return ok();
@@ -569,6 +575,7 @@ rt_status rt_accel_get_info(rt_accel accel, rt_accel_info* out) {
 // ---------------------------------------------------------------------------
 
 static uint32_t cached_resident(rt_context ctx, const void* kern, int wg) {
+  if (ctx->blocks_per_cu) return ctx->blocks_per_cu * (uint32_t)std::max(ctx->cu_count, 1);
   for (auto& e : ctx->occupancy)
     if (e.first == kern) return e.second;
   uint32_t b = resident_blocks(kern, wg, ctx->cu_count);
@@ -682,6 +689,79 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
   p.d_origins = d_origins;
   p.d_directions = d_directions;
   RT_HIP(rtk_launch_backward(p, static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// autotuning
+// ---------------------------------------------------------------------------
+
+rt_status rt_autotune(rt_context ctx, const rt_mesh_desc* mesh, const rt_ray* probe_rays,
+                      uint32_t n_probe, uint32_t repeats, void* stream, rt_tune_entry* best,
+                      rt_tune_entry* table, uint32_t table_cap, uint32_t* table_len) {
+  if (!ctx || !mesh || !best) return fail(RT_ERROR_INVALID_VALUE, "rt_autotune: NULL argument");
+  if (n_probe == 0 || !probe_rays)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_autotune: no probe rays");
+  if (table_cap > 0 && !table) return fail(RT_ERROR_INVALID_VALUE, "rt_autotune: NULL table");
+  if (repeats == 0) repeats = 3;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rt_status st = check_device(ctx->device);
+  if (st != RT_SUCCESS) return st;
+  rt_hit* hits = nullptr;
+  RT_HIP(hipMalloc(&hits, (size_t)n_probe * sizeof(rt_hit)));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipFree(hits);
+    return fail(RT_ERROR_HIP, "rt_autotune: hipEventCreate failed");
+  }
+  rt_variant saved = ctx->variant;
+  rt_tune_entry win{0, 0, 0, INFINITY};
+  uint32_t count = 0;
+  st = RT_SUCCESS;
+  for (uint32_t w : kWidthChoices) {
+    rt_build_options opt{w, 0, 0};
+    rt_accel a = nullptr;
+    st = rt_build(ctx, mesh, 1, nullptr, nullptr, 0, &opt, stream, &a);
+    if (st != RT_SUCCESS) break;
+    for (uint32_t sn : kStackChoices) {
+      for (uint32_t wg : kWorkgroupChoices) {
+        {
+          std::lock_guard<std::mutex> lk(ctx->mu);
+          ctx->variant = rt_variant{sn, wg};
+        }
+        std::vector<float> ms;
+        for (uint32_t r = 0; r <= repeats && st == RT_SUCCESS; ++r) {
+          if (hipEventRecord(e0, s) != hipSuccess) st = fail(RT_ERROR_HIP, "rt_autotune: event");
+          if (st == RT_SUCCESS) st = launch_trace(a, probe_rays, n_probe, hits, nullptr, nullptr, false, s);
+          if (st == RT_SUCCESS && hipEventRecord(e1, s) != hipSuccess) st = fail(RT_ERROR_HIP, "rt_autotune: event");
+          if (st == RT_SUCCESS && hipEventSynchronize(e1) != hipSuccess) st = fail(RT_ERROR_HIP, "rt_autotune: sync");
+          float t = 0.0f;
+          if (st == RT_SUCCESS && hipEventElapsedTime(&t, e0, e1) != hipSuccess) st = fail(RT_ERROR_HIP, "rt_autotune: timing");
+          if (st == RT_SUCCESS && r > 0) ms.push_back(t);  // the first launch warms up
+        }
+        if (st != RT_SUCCESS) break;
+        std::sort(ms.begin(), ms.end());
+        rt_tune_entry e{w, sn, wg, ms[ms.size() / 2]};
+        if (count < table_cap) table[count] = e;
+        ++count;
+        if (e.ms < win.ms) win = e;
+      }
+      if (st != RT_SUCCESS) break;
+    }
+    rt_accel_destroy(a);
+    if (st != RT_SUCCESS) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(hits);
+  if (table_len) *table_len = count;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  if (st != RT_SUCCESS) {
+    ctx->variant = saved;
+    return st;
+  }
+  ctx->variant = rt_variant{win.stack_entries, win.workgroup};
+  *best = win;
   return ok();
 }
 

@@ -189,7 +189,11 @@ __device__ __forceinline__ void visit_node(const float* nodes, uint32_t idx, con
 // functions of the triangle are F0 = -g(p1,p2), F1 = g(p0,p2), F2 = -g(p0,p1)
 // (F_k is proportional to the weight of p_k); the ray crosses the closed
 // triangle when they share a sign and their sum d.n is non-zero.  Then
-// t = n.(p0 - o) / d.n with n = (p1 - p0) x (p2 - p0) (§3.1, plane solution).
+// t = n.(p0 - o) / n.d with n = (p1 - p0) x (p2 - p0) (§3.1, plane solution).
+// The denominator is n.d from the short edge vectors, not the sum of the
+// edge functions: those are formed against the (possibly distant) origin and
+// their sum carries a cancellation error of order u |e| |p - o| |d|, which for
+// grazing rays from afar would reach 1e-4 of t.
 __device__ __forceinline__ bool tri_test(const float4& A, const float4& B, const float4& C,
                                          const RayState& r, float& t_out) {
   float w0x = A.x - r.ox, w0y = A.y - r.oy, w0z = A.z - r.oz;
@@ -213,7 +217,9 @@ __device__ __forceinline__ bool tri_test(const float4& A, const float4& B, const
   float ny = e01z * e02x - e01x * e02z;
   float nz = e01x * e02y - e01y * e02x;
   float T = nx * w0x + ny * w0y + nz * w0z;
-  t_out = T / det;
+  float nd = nx * r.dx + ny * r.dy + nz * r.dz;
+  if (nd == 0.0f) return false;
+  t_out = T / nd;
   return true;
 }
 
@@ -594,7 +600,6 @@ const void* pick_wg(int wg, bool any, bool inst, int mode) {
     case 64: return pick_mode<W, S, 64>(any, inst, mode);
     case 128: return pick_mode<W, S, 128>(any, inst, mode);
     case 256: return pick_mode<W, S, 256>(any, inst, mode);
-    case 512: return pick_mode<W, S, 512>(any, inst, mode);
     default: return nullptr;
   }
 }
@@ -602,7 +607,6 @@ const void* pick_wg(int wg, bool any, bool inst, int mode) {
 template <int W>
 const void* pick_s(int s, int wg, bool any, bool inst, int mode) {
   switch (s) {
-    case 4: return pick_wg<W, 4>(wg, any, inst, mode);
     case 8: return pick_wg<W, 8>(wg, any, inst, mode);
     case 16: return pick_wg<W, 16>(wg, any, inst, mode);
     case 32: return pick_wg<W, 32>(wg, any, inst, mode);
@@ -624,7 +628,6 @@ const void* rtk_count_kernel(int width, bool any) {
 }
 
 const void* rtk_trace_kernel(int width, int stack, int wg, bool any, bool inst, int mode) {
-  if (stack == 32 && wg == 512) return nullptr;  // 64 KB of LDS: not offered
   switch (width) {
     case 2: return pick_s<2>(stack, wg, any, inst, mode);
     case 4: return pick_s<4>(stack, wg, any, inst, mode);
