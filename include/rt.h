@@ -208,6 +208,19 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
 rt_status rt_trace_counters(rt_accel accel, const rt_ray* rays, uint32_t n, int any, rt_hit* hits,
                             uint8_t* occluded, uint64_t* counters, void* stream);
 
+/* Refit (§6.2 construction paragraph: keep the topology of the hierarchy and
+ * fit the bounding volumes to the current geometry, bottom-up): replaces the
+ * accel's vertices by `vertices` (device, vertex_count records of 3 float32,
+ * compact) and recomputes every triangle record and child box on `stream`,
+ * without a host round trip.  Single-level accels only (RT_ERROR_UNSUPPORTED
+ * otherwise).  Triangles that were degenerate or non-finite when the accel
+ * was built stay out of it; triangles that become degenerate or non-finite
+ * are disabled (never hit) until a refit makes them valid again.  Query
+ * results after a refit equal those of a fresh build on the same vertices
+ * (up to ties between distinct triangles at equal t); traversal cost grows as
+ * the geometry departs from the one the topology was built for. */
+rt_status rt_refit(rt_accel accel, const float* vertices, void* stream);
+
 /* ---- batched queries (many meshes, one persistent launch) --------------- */
 
 /* Plans closest-hit queries for batch_count (accel, rays, hits, count)

@@ -116,6 +116,14 @@ class Accel:
         capi.call("rt_accel_get_info", self.handle, C.byref(i))
         return {f: getattr(i, f) for f, _ in capi.rt_accel_info._fields_}
 
+    def refit(self, vertices: torch.Tensor) -> None:
+        """Fits the boxes to new vertex positions on the device, keeping the
+        tree topology (rt_refit; single-level accels)."""
+        _require(vertices, "vertices", torch.float32, 3)
+        if vertices.shape[0] != self.vertex_count:
+            raise ValueError(f"refit needs {self.vertex_count} vertices, got {vertices.shape[0]}")
+        capi.call("rt_refit", self.handle, _ptr(vertices), C.c_void_p(_stream()))
+
     def close(self):
         if self.handle:
             capi.call("rt_accel_destroy", self.handle)

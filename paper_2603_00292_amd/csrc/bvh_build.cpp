@@ -204,6 +204,8 @@ void collapse(Collapse& C, uint32_t bi, uint32_t wi, uint32_t depth, uint32_t st
   uint32_t stack_here = stack_above + (uint32_t)kids.size() - 1;
   T.max_stack = std::max(T.max_stack, stack_here + 1);
   T.max_depth = std::max(T.max_depth, depth);
+  if (T.node_depth.size() <= wi) T.node_depth.resize((size_t)wi + 1, 0);
+  T.node_depth[wi] = depth;
   // allocate the internal children consecutively, then fill this node
   std::vector<uint32_t> child_node(kids.size(), RT_CHILD_EMPTY);
   for (size_t i = 0; i < kids.size(); ++i)
@@ -246,6 +248,7 @@ void finish_tree(Binary& B, int width, WideTree& out, const std::function<uint32
   out.node_count = 0;
   out.max_depth = 0;
   out.max_stack = 0;
+  out.node_depth.clear();
   if (B.prims->empty()) {
     out.root = RT_CHILD_EMPTY;
     out.sah_cost = 0.0;

@@ -37,6 +37,7 @@ struct WideTree {
   uint32_t max_stack = 0;            // stack entries a traversal may need
   uint32_t leaf_count = 0;
   uint32_t stored_triangles = 0;
+  std::vector<uint32_t> node_depth;  // depth of each wide node (root = 1)
   double sah_cost = 0.0;             // sum of internal-node areas / root area
   Box bounds{};
 };

@@ -113,6 +113,8 @@ struct rt_accel_s {
   rt_mesh_dev* meshes = nullptr;             // device array of mesh records
   std::vector<void*> owned;                  // every device allocation
   std::vector<rt_mesh_dev> host_meshes;      // device pointers, host copy
+  uint32_t* refit_nodes = nullptr;           // node ids, deepest level first (single level)
+  std::vector<uint32_t> refit_levels;        // level boundaries in refit_nodes
   rt_accel_info info{};
 };
 
@@ -522,6 +524,23 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
     st = dev_alloc(a, &a->meshes, mesh_count);
     if (st != RT_SUCCESS) return bail(st);
     RT_HIP(hipMemcpyAsync(a->meshes, a->host_meshes.data(), mesh_count * sizeof(rt_mesh_dev), hipMemcpyHostToDevice, s));
+    if (!a->two_level && blas[0].node_count > 0) {
+      // node ids grouped by depth, deepest first, for the bottom-up refit
+      const std::vector<uint32_t>& dep = blas[0].node_depth;
+      uint32_t maxd = 0;
+      for (uint32_t d : dep) maxd = std::max(maxd, d);
+      std::vector<uint32_t> order;
+      order.reserve(dep.size());
+      a->refit_levels.assign(1, 0);
+      for (uint32_t d = maxd; d >= 1; --d) {
+        for (uint32_t i = 0; i < (uint32_t)dep.size(); ++i)
+          if (dep[i] == d) order.push_back(i + node_base[0]);
+        a->refit_levels.push_back((uint32_t)order.size());
+      }
+      st = dev_alloc(a, &a->refit_nodes, order.size());
+      if (st != RT_SUCCESS) return bail(st);
+      RT_HIP(hipMemcpyAsync(a->refit_nodes, order.data(), order.size() * 4, hipMemcpyHostToDevice, s));
+    }
     if (a->two_level) {
       std::vector<rt_inst_rec> ir(instance_count);
       std::vector<rt_inst_rec64> ir64(instance_count);
@@ -624,6 +643,7 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   p.counters = counters;
   RT_HIP(rtk_launch_fill(ctx->scratch.counter, 1, 0u, s));
   RT_HIP(rtk_launch_trace(kern, blocks, wg, p, s));
+  if (!any) RT_HIP(rtk_launch_finalize(a->two_level, 0, p, s));
   RT_HIP(hipEventRecord(ctx->last_event, s));
   ctx->last_stream = s;
   ctx->has_last = true;
@@ -689,6 +709,25 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
   p.d_origins = d_origins;
   p.d_directions = d_directions;
   RT_HIP(rtk_launch_backward(p, static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+rt_status rt_refit(rt_accel accel, const float* vertices, void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_refit: NULL accel");
+  if (accel->two_level) return fail(RT_ERROR_UNSUPPORTED, "rt_refit: two-level accels are not supported");
+  const rt_mesh_dev& m = accel->host_meshes[0];
+  if (m.vertex_count > 0 && !vertices) return fail(RT_ERROR_INVALID_VALUE, "rt_refit: vertices is NULL");
+  rt_status st = check_device(accel->device);
+  if (st != RT_SUCCESS) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (m.vertex_count > 0)
+    RT_HIP(hipMemcpyAsync(const_cast<float*>(m.vertices), vertices, (size_t)m.vertex_count * 12,
+                          hipMemcpyDefault, s));
+  RT_HIP(rtk_launch_refit_tris(accel->tris, accel->info.triangle_count, m, s));
+  for (size_t l = 0; l + 1 < accel->refit_levels.size(); ++l) {
+    uint32_t b = accel->refit_levels[l], e = accel->refit_levels[l + 1];
+    RT_HIP(rtk_launch_refit_nodes(accel->width, accel->nodes, accel->tris, accel->refit_nodes + b, e - b, s));
+  }
   return ok();
 }
 
@@ -858,6 +897,7 @@ static rt_status enqueue_plan(rt_batch_plan p, hipStream_t s) {
   q.root = RT_CHILD_EMPTY;
   RT_HIP(rtk_launch_fill(p->scratch.counter, 1, 0u, s));
   RT_HIP(rtk_launch_trace(p->kernel, p->grid, v.workgroup, q, s));
+  RT_HIP(rtk_launch_finalize(false, 1, q, s));
   return RT_SUCCESS;
 }
 

@@ -58,5 +58,11 @@ const void* rtk_trace_kernel(int width, int stack, int wg, bool any, bool inst, 
 const void* rtk_count_kernel(int width, bool any);
 hipError_t rtk_launch_trace(const void* kern, uint32_t grid, uint32_t wg, const TraceParams& p,
                             hipStream_t stream);
+// float64 finalize of closest hits written by a trace launch with the same params
+hipError_t rtk_launch_finalize(bool inst, int mode, const TraceParams& p, hipStream_t stream);
 hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream);
+hipError_t rtk_launch_refit_tris(rt_tri_rec* tris, uint32_t n, const rt_mesh_dev& mesh,
+                                 hipStream_t stream);
+hipError_t rtk_launch_refit_nodes(int width, float* nodes, const rt_tri_rec* tris,
+                                  const uint32_t* node_ids, uint32_t count, hipStream_t stream);
 hipError_t rtk_launch_fill(uint32_t* ptr, uint32_t n, uint32_t value, hipStream_t stream);

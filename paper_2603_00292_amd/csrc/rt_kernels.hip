@@ -315,7 +315,6 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
   float best_t = 0.0f;
   uint32_t best_prim = RT_INVALID_ID, best_inst = RT_INVALID_ID, cur_inst = 0;
   rt_hit* hit_out = P.hits;
-  uint32_t* inst_out = P.inst_ids;
   uint8_t* occ_out = P.occluded;
   const rt_ray* ray_in = P.rays;
   bool live = false, retired = false;
@@ -456,43 +455,17 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
         }
       }
       // ---- finished: write the result --------------------------------------
+      // (the float64 (t, u, v) of a closest hit is computed afterwards by
+      // finalize_kernel, one thread per ray; here: float32 t, the triangle id
+      // and, in the u slot, the instance id)
       if (cur == RT_CHILD_EMPTY) {
         if constexpr (ANY) {
           occ_out[ray_id] = (best_prim != RT_INVALID_ID) ? 1 : 0;
         } else {
-          rt_hit h;
-          h.t = __int_as_float(0x7f800000);
-          h.prim_id = RT_INVALID_ID;
-          h.u = 0.0f;
-          h.v = 0.0f;
-          if (best_prim != RT_INVALID_ID) {
-            h.t = best_t;
-            h.prim_id = best_prim;
-            double ox = wray.ox, oy = wray.oy, oz = wray.oz;
-            double dx = wray.dx, dy = wray.dy, dz = wray.dz;
-            uint32_t mesh = 0;
-            if constexpr (INST) {
-              const rt_inst_rec64& M = g.insts64[best_inst];
-              double a = M.m[0] * ox + M.m[1] * oy + M.m[2] * oz + M.m[3];
-              double b = M.m[4] * ox + M.m[5] * oy + M.m[6] * oz + M.m[7];
-              double c = M.m[8] * ox + M.m[9] * oy + M.m[10] * oz + M.m[11];
-              double e = M.m[0] * dx + M.m[1] * dy + M.m[2] * dz;
-              double f = M.m[4] * dx + M.m[5] * dy + M.m[6] * dz;
-              double gg = M.m[8] * dx + M.m[9] * dy + M.m[10] * dz;
-              ox = a; oy = b; oz = c; dx = e; dy = f; dz = gg;
-              mesh = g.insts[best_inst].mesh;
-            }
-            float t, u, v;
-            if (finalize64(g.meshes[mesh], best_prim, ox, oy, oz, dx, dy, dz, t, u, v)) {
-              h.t = t;
-              h.u = u;
-              h.v = v;
-            }
-          }
+          bool hit = best_prim != RT_INVALID_ID;
           float4* hp = reinterpret_cast<float4*>(hit_out + ray_id);
-          *hp = make_float4(h.t, __uint_as_float(h.prim_id), h.u, h.v);
-          if (MODE == 0 && inst_out)
-            inst_out[ray_id] = (best_prim != RT_INVALID_ID) ? (INST ? best_inst : 0u) : RT_INVALID_ID;
+          *hp = make_float4(hit ? best_t : __int_as_float(0x7f800000), __uint_as_float(best_prim),
+                            __uint_as_float(hit ? (INST ? best_inst : 0u) : 0u), 0.0f);
         }
         live = false;
       }
@@ -562,6 +535,159 @@ __global__ __launch_bounds__(256) void backward_kernel(BackwardParams P) {
     atomicAdd(dv + 0, (float)(-w[k] * lx));
     atomicAdd(dv + 1, (float)(-w[k] * ly));
     atomicAdd(dv + 2, (float)(-w[k] * lz));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// float64 finalize of closest hits (one thread per ray, after the traversal)
+// ---------------------------------------------------------------------------
+// Recomputes (t, u, v) of the winning triangle in float64 from the float32
+// inputs (for instances, the ray is taken to object space with the float64
+// inverse frame) and writes the instance id.  Misses are left as written.
+template <bool INST, int MODE>
+__global__ __launch_bounds__(256) void finalize_kernel(TraceParams P) {
+  uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= P.n) return;
+  const rt_ray* rays = P.rays;
+  rt_hit* hits = P.hits;
+  const rt_mesh_dev* meshes = P.meshes;
+  uint32_t local = i;
+  if constexpr (MODE == 1) {
+    uint32_t lo = 0, hi = P.batch_count;
+    while (hi - lo > 1) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (P.batch_offsets[mid] <= i) lo = mid; else hi = mid;
+    }
+    const BatchDesc& bd = P.batches[lo];
+    local = i - P.batch_offsets[lo];
+    rays = bd.rays;
+    hits = bd.hits;
+    meshes = bd.meshes;
+  }
+  float4* hp = reinterpret_cast<float4*>(hits + local);
+  float4 h = *hp;
+  uint32_t prim = __float_as_uint(h.y);
+  if (prim == RT_INVALID_ID) {
+    if (MODE == 0 && P.inst_ids) P.inst_ids[local] = RT_INVALID_ID;
+    return;
+  }
+  uint32_t inst = __float_as_uint(h.z);
+  rt_ray q = load_ray(rays, local);
+  double ox = q.ox, oy = q.oy, oz = q.oz, dx = q.dx, dy = q.dy, dz = q.dz;
+  uint32_t mesh = 0;
+  if constexpr (INST) {
+    const rt_inst_rec64& M = P.insts64[inst];
+    double a = M.m[0] * ox + M.m[1] * oy + M.m[2] * oz + M.m[3];
+    double b = M.m[4] * ox + M.m[5] * oy + M.m[6] * oz + M.m[7];
+    double c = M.m[8] * ox + M.m[9] * oy + M.m[10] * oz + M.m[11];
+    double e = M.m[0] * dx + M.m[1] * dy + M.m[2] * dz;
+    double f = M.m[4] * dx + M.m[5] * dy + M.m[6] * dz;
+    double gg = M.m[8] * dx + M.m[9] * dy + M.m[10] * dz;
+    ox = a; oy = b; oz = c; dx = e; dy = f; dz = gg;
+    mesh = P.insts[inst].mesh;
+  }
+  float t, u, v;
+  if (finalize64(meshes[mesh], prim, ox, oy, oz, dx, dy, dz, t, u, v)) {
+    *hp = make_float4(t, h.y, u, v);
+  } else {
+    *hp = make_float4(h.x, h.y, 0.0f, 0.0f);
+  }
+  if (MODE == 0 && P.inst_ids) P.inst_ids[local] = INST ? inst : 0u;
+}
+
+// ---------------------------------------------------------------------------
+// refit: triangle records from new vertices, then child boxes bottom-up
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool lex_less3(float ax, float ay, float az, float bx, float by, float bz) {
+  if (ax != bx) return ax < bx;
+  if (ay != by) return ay < by;
+  return az < bz;
+}
+
+__global__ __launch_bounds__(256) void refit_tris_kernel(rt_tri_rec* tris, uint32_t n,
+                                                         rt_mesh_dev mesh) {
+  uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  rt_tri_rec r = tris[i];
+  const uint32_t* ix = mesh.indices + 3 * (size_t)r.prim;
+  float p[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) p[k][a] = mesh.vertices[3 * (size_t)ix[k] + a];
+  // disable the triangle (NaN record: never hit, ignored by the box fit)
+  // when a vertex is not finite or its float64 normal is zero
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) finite = finite && (fabsf(p[k][a]) < __int_as_float(0x7f800000));
+  double e1x = (double)p[1][0] - p[0][0], e1y = (double)p[1][1] - p[0][1], e1z = (double)p[1][2] - p[0][2];
+  double e2x = (double)p[2][0] - p[0][0], e2y = (double)p[2][1] - p[0][1], e2z = (double)p[2][2] - p[0][2];
+  double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+  bool ok = finite && !(nx == 0.0 && ny == 0.0 && nz == 0.0);
+  // sort the vertices lexicographically (three compare-exchanges)
+#define RT_VSWAP(a, b)                                                              \
+  if (lex_less3(p[b][0], p[b][1], p[b][2], p[a][0], p[a][1], p[a][2])) {            \
+    for (int c_ = 0; c_ < 3; ++c_) { float t_ = p[a][c_]; p[a][c_] = p[b][c_]; p[b][c_] = t_; } \
+  }
+  RT_VSWAP(0, 1);
+  RT_VSWAP(1, 2);
+  RT_VSWAP(0, 1);
+#undef RT_VSWAP
+  float nan = __int_as_float(0x7fc00000);
+  r.p0x = ok ? p[0][0] : nan; r.p0y = p[0][1]; r.p0z = p[0][2];
+  r.p1x = p[1][0]; r.p1y = p[1][1]; r.p1z = p[1][2];
+  r.p2x = p[2][0]; r.p2y = p[2][1]; r.p2z = p[2][2];
+  if (!ok) {
+    r.p0y = r.p0z = r.p1x = r.p1y = r.p1z = r.p2x = r.p2y = r.p2z = nan;
+  }
+  tris[i] = r;
+}
+
+// One tree level: for each node, every child slot's box becomes the exact
+// float32 bounds of what lies below it (a leaf's triangle records, or the
+// union of an internal child's child boxes, refitted by the previous launch).
+// fminf/fmaxf skip the NaN coordinates of disabled triangles.
+template <int W>
+__global__ __launch_bounds__(256) void refit_nodes_kernel(float* nodes, const rt_tri_rec* tris,
+                                                          const uint32_t* node_ids, uint32_t count) {
+  uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= count) return;
+  float* nd = nodes + (size_t)node_ids[i] * (8 * W);
+  const float inf = __int_as_float(0x7f800000);
+  for (int c = 0; c < W; ++c) {
+    uint32_t ref = __float_as_uint(nd[6 * W + c]);
+    if (ref == RT_CHILD_EMPTY) continue;
+    float lo[3] = {inf, inf, inf}, hi[3] = {-inf, -inf, -inf};
+    if ((ref & RT_LEAF_BIT) == 0u) {
+      const float* ch = nodes + (size_t)ref * (8 * W);
+      for (int k = 0; k < W; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = fminf(lo[a], ch[(2 * a) * W + k]);
+          hi[a] = fmaxf(hi[a], ch[(2 * a + 1) * W + k]);
+        }
+    } else {
+      uint32_t first = ref & RT_LEAF_FIRST_MASK;
+      uint32_t cnt = (ref >> RT_LEAF_COUNT_SHIFT) & RT_LEAF_COUNT_MASK;
+      for (uint32_t k = 0; k < cnt; ++k) {
+        const rt_tri_rec& t = tris[first + k];
+        const float v[9] = {t.p0x, t.p0y, t.p0z, t.p1x, t.p1y, t.p1z, t.p2x, t.p2y, t.p2z};
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], v[3 * j + a]);
+            hi[a] = fmaxf(hi[a], v[3 * j + a]);
+          }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      nd[(2 * a) * W + c] = lo[a];
+      nd[(2 * a + 1) * W + c] = hi[a];
+    }
   }
 }
 
@@ -649,6 +775,35 @@ hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream) {
   void* args[] = {&q};
   return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::backward_kernel),
                          dim3((p.n + 255) / 256), dim3(256), args, 0, stream);
+}
+
+hipError_t rtk_launch_finalize(bool inst, int mode, const TraceParams& p, hipStream_t stream) {
+  if (p.n == 0) return hipSuccess;
+  const void* k = mode == 1 ? reinterpret_cast<const void*>(&rtk::finalize_kernel<false, 1>)
+                  : inst    ? reinterpret_cast<const void*>(&rtk::finalize_kernel<true, 0>)
+                            : reinterpret_cast<const void*>(&rtk::finalize_kernel<false, 0>);
+  TraceParams q = p;
+  void* args[] = {&q};
+  return hipLaunchKernel(k, dim3((p.n + 255) / 256), dim3(256), args, 0, stream);
+}
+
+hipError_t rtk_launch_refit_tris(rt_tri_rec* tris, uint32_t n, const rt_mesh_dev& mesh,
+                                 hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  rt_mesh_dev m = mesh;
+  void* args[] = {&tris, &n, &m};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::refit_tris_kernel), dim3((n + 255) / 256),
+                         dim3(256), args, 0, stream);
+}
+
+hipError_t rtk_launch_refit_nodes(int width, float* nodes, const rt_tri_rec* tris,
+                                  const uint32_t* node_ids, uint32_t count, hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  const void* k = width == 2   ? reinterpret_cast<const void*>(&rtk::refit_nodes_kernel<2>)
+                  : width == 4 ? reinterpret_cast<const void*>(&rtk::refit_nodes_kernel<4>)
+                               : reinterpret_cast<const void*>(&rtk::refit_nodes_kernel<8>);
+  void* args[] = {&nodes, &tris, &node_ids, &count};
+  return hipLaunchKernel(k, dim3((count + 255) / 256), dim3(256), args, 0, stream);
 }
 
 hipError_t rtk_launch_fill(uint32_t* ptr, uint32_t n, uint32_t value, hipStream_t stream) {
