@@ -65,6 +65,8 @@ def _load():
             "orc_adjoint": [P, P, P, i64, P, P, P, P],
             "orc_fd": [P, P, P, i64, P, C.c_double, P],
             "orc_fixed_tuv": [P, P, P, i64, P],
+            "orc_adjoint_inst": [P, P, P, P, i64, P, P, P, P, P],
+            "orc_fd_inst": [P, P, P, P, i64, P, C.c_double, P],
         }.items():
             f = getattr(lib, name)
             f.argtypes = args
@@ -220,6 +222,37 @@ def fixed_tuv(scene: OracleScene, rays, prim):
     tuv = np.empty((n, 3), np.float64)
     _check(lib.orc_fixed_tuv(scene.ptr, _p(r), _p(prim), n, _p(tuv)), "fixed_tuv")
     return tuv
+
+
+def adjoint_inst(scene: OracleScene, rays, inst, prim, g):
+    """Two-level adjoint.  Returns (list of d_vertices (V_m,3) per mesh,
+    d_srt (n_inst,10), d_orig (n,3), d_dir (n,3)), all float64."""
+    lib = _load()
+    r, n = _rays(rays)
+    inst = np.ascontiguousarray(inst, dtype=np.uint32).reshape(-1)
+    prim = np.ascontiguousarray(prim, dtype=np.uint32).reshape(-1)
+    g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1, 3)
+    dV = [np.zeros((int(nv), 3), np.float64) for nv in scene._nv]
+    ptrs = (C.c_void_p * len(dV))(*[a.ctypes.data if a.size else None for a in dV])
+    dS = np.zeros((scene.n_inst, 10), np.float64)
+    do = np.empty((n, 3), np.float64)
+    dd = np.empty((n, 3), np.float64)
+    _check(lib.orc_adjoint_inst(scene.ptr, _p(r), _p(inst), _p(prim), n, _p(g),
+                                C.cast(ptrs, C.c_void_p), _p(dS), _p(do), _p(dd)), "adjoint_inst")
+    return dV, dS, do, dd
+
+
+def fd_inst(scene: OracleScene, rays, inst, prim, g, h: float = 1e-6):
+    """Central differences: (n,25) = d/d(v0,v1,v2, sx,sy,sz,qx,qy,qz,qw,tx,ty,tz, o,d)."""
+    lib = _load()
+    r, n = _rays(rays)
+    inst = np.ascontiguousarray(inst, dtype=np.uint32).reshape(-1)
+    prim = np.ascontiguousarray(prim, dtype=np.uint32).reshape(-1)
+    g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1, 3)
+    out = np.empty((n, 25), np.float64)
+    _check(lib.orc_fd_inst(scene.ptr, _p(r), _p(inst), _p(prim), n, _p(g), float(h), _p(out)),
+           "fd_inst")
+    return out
 
 
 def num_threads() -> int:

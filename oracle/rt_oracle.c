@@ -87,7 +87,8 @@ typedef struct {
   vec3 S, T;
 } frame64;
 
-static frame64 load_frame(const float* f) {
+/* The frame of ten float64 parameters (sx,sy,sz, qx,qy,qz,qw, tx,ty,tz). */
+static frame64 frame_from(const double* f) {
   frame64 F;
   double qx = f[3], qy = f[4], qz = f[5], qw = f[6];
   double nq = sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
@@ -104,6 +105,20 @@ static frame64 load_frame(const float* f) {
   F.S = mk(f[0], f[1], f[2]);
   F.T = mk(f[7], f[8], f[9]);
   return F;
+}
+
+static frame64 load_frame(const float* f) {
+  double p[10];
+  for (int i = 0; i < 10; ++i) p[i] = f[i];
+  return frame_from(p);
+}
+
+/* world = T + R (S*x) */
+static vec3 to_world(const frame64* F, vec3 x) {
+  vec3 a = mk(F->S.x * x.x, F->S.y * x.y, F->S.z * x.z);
+  return mk(F->T.x + F->R[0][0] * a.x + F->R[0][1] * a.y + F->R[0][2] * a.z,
+            F->T.y + F->R[1][0] * a.x + F->R[1][1] * a.y + F->R[1][2] * a.z,
+            F->T.z + F->R[2][0] * a.x + F->R[2][1] * a.y + F->R[2][2] * a.z);
 }
 
 /* R^T a, then divide by the per-axis scale. */
@@ -619,6 +634,173 @@ int orc_fixed_tuv(const orc_scene* s, const float* rays, const uint32_t* prim, i
     vec3 v0, v1, v2;
     tri(s, 0, prim[r], &v0, &v1, &v2);
     plane_tuv(q.o, q.d, v0, v1, v2, &tuv[3 * r], &tuv[3 * r + 1], &tuv[3 * r + 2]);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* two-level adjoint                                                          */
+/* ------------------------------------------------------------------------- */
+
+/* Partial derivatives of the rotation matrix R(q) of frame_from with respect
+ * to the components (x, y, z, w) of a unit quaternion, read off the matrix
+ * entries one by one: dR[c][i][j] = d R_ij / d q_c. */
+static void rotation_partials(double x, double y, double z, double w, double dR[4][3][3]) {
+  /* d/dx */
+  dR[0][0][0] = 0;      dR[0][0][1] = 2 * y;  dR[0][0][2] = 2 * z;
+  dR[0][1][0] = 2 * y;  dR[0][1][1] = -4 * x; dR[0][1][2] = -2 * w;
+  dR[0][2][0] = 2 * z;  dR[0][2][1] = 2 * w;  dR[0][2][2] = -4 * x;
+  /* d/dy */
+  dR[1][0][0] = -4 * y; dR[1][0][1] = 2 * x;  dR[1][0][2] = 2 * w;
+  dR[1][1][0] = 2 * x;  dR[1][1][1] = 0;      dR[1][1][2] = 2 * z;
+  dR[1][2][0] = -2 * w; dR[1][2][1] = 2 * z;  dR[1][2][2] = -4 * y;
+  /* d/dz */
+  dR[2][0][0] = -4 * z; dR[2][0][1] = -2 * w; dR[2][0][2] = 2 * x;
+  dR[2][1][0] = 2 * w;  dR[2][1][1] = -4 * z; dR[2][1][2] = 2 * y;
+  dR[2][2][0] = 2 * x;  dR[2][2][1] = 2 * y;  dR[2][2][2] = 0;
+  /* d/dw */
+  dR[3][0][0] = 0;      dR[3][0][1] = -2 * z; dR[3][0][2] = 2 * y;
+  dR[3][1][0] = 2 * z;  dR[3][1][1] = 0;      dR[3][1][2] = -2 * x;
+  dR[3][2][0] = -2 * y; dR[3][2][1] = 2 * x;  dR[3][2][2] = 0;
+}
+
+/* The hit of a world ray on instance j, triangle k is the hit of the world
+ * ray on the world-space triangle W_i = T + R (S*v_i) (§6.2: the instance is
+ * the base mesh under an affine map; barycentrics and t do not change under
+ * it).  So the adjoint is the world-space one (lambda = M_w^-T g, grad o =
+ * lambda, grad d = t lambda, grad W_i = -w_i lambda), then the chain rule
+ * through W_i: grad v_i = (R S)^T grad W_i, grad T = sum_i grad W_i, and with
+ * G = sum_i grad W_i v_i^T: grad S_j = sum_i G_ij R_ij, grad R_ij = G_ij S_j,
+ * grad qhat_c = sum_ij grad R_ij dR_ij/dqhat_c, and for the normalisation
+ * qhat = q/|q|: grad q = (grad qhat - qhat (qhat . grad qhat)) / |q|. */
+int orc_adjoint_inst(const orc_scene* s, const float* rays, const uint32_t* inst,
+                     const uint32_t* prim, int64_t nr, const double* g,
+                     double* const* d_vertices, double* d_srt, double* d_orig, double* d_dir) {
+  if (nr < 0 || !scene_valid(s) || s->n_inst < 1) return -1;
+  if (nr > 0 && (!rays || !inst || !prim || !g || !d_orig || !d_dir)) return -1;
+  for (int64_t r = 0; r < nr; ++r) {
+    if (prim[r] == ORC_NONE) continue;
+    if ((int64_t)inst[r] >= s->n_inst) return -1;
+    if ((int64_t)prim[r] >= s->n_triangles[s->inst_mesh[inst[r]]]) return -1;
+  }
+  for (int64_t r = 0; r < nr; ++r) {
+    double* go = d_orig + 3 * r;
+    double* gd = d_dir + 3 * r;
+    go[0] = go[1] = go[2] = 0.0;
+    gd[0] = gd[1] = gd[2] = 0.0;
+    if (prim[r] == ORC_NONE) continue;
+    int64_t j = inst[r];
+    int m = (int)s->inst_mesh[j];
+    const float* f = s->inst_srt + 10 * j;
+    frame64 F = load_frame(f);
+    ray64 q = load_ray(rays + 8 * r);
+    const uint32_t* ix = s->indices[m] + 3 * (int64_t)prim[r];
+    vec3 v[3], W[3];
+    for (int c = 0; c < 3; ++c) {
+      v[c] = vtx(s, m, ix[c]);
+      W[c] = to_world(&F, v[c]);
+    }
+    vec3 e1 = sub(W[1], W[0]), e2 = sub(W[2], W[0]), c0 = scl(q.d, -1.0);
+    vec3 r0 = cross(e1, e2), r1 = cross(e2, c0), r2 = cross(c0, e1);
+    double det = dot(c0, r0);
+    if (det == 0.0) continue;
+    r0 = scl(r0, 1.0 / det);
+    r1 = scl(r1, 1.0 / det);
+    r2 = scl(r2, 1.0 / det);
+    vec3 rhs = sub(q.o, W[0]);
+    double t = dot(r0, rhs), u = dot(r1, rhs), vv = dot(r2, rhs);
+    const double* gr = g + 3 * r;
+    vec3 lam = add(add(scl(r0, gr[0]), scl(r1, gr[1])), scl(r2, gr[2]));
+    go[0] = lam.x; go[1] = lam.y; go[2] = lam.z;
+    gd[0] = t * lam.x; gd[1] = t * lam.y; gd[2] = t * lam.z;
+    double w[3] = {1.0 - u - vv, u, vv};
+    double S[3] = {F.S.x, F.S.y, F.S.z};
+    double G[3][3] = {{0}}, gT[3] = {0, 0, 0};
+    for (int c = 0; c < 3; ++c) {
+      double gW[3] = {-w[c] * lam.x, -w[c] * lam.y, -w[c] * lam.z};
+      double vc[3] = {v[c].x, v[c].y, v[c].z};
+      if (d_vertices && d_vertices[m]) {
+        double* dv = d_vertices[m] + 3 * (int64_t)ix[c];
+        for (int b = 0; b < 3; ++b)  /* (R S)^T gW: column b of R S is S_b R[:, b] */
+          dv[b] += S[b] * (F.R[0][b] * gW[0] + F.R[1][b] * gW[1] + F.R[2][b] * gW[2]);
+      }
+      for (int a = 0; a < 3; ++a) {
+        gT[a] += gW[a];
+        for (int b = 0; b < 3; ++b) G[a][b] += gW[a] * vc[b];
+      }
+    }
+    if (!d_srt) continue;
+    double qn = sqrt((double)f[3] * f[3] + (double)f[4] * f[4] + (double)f[5] * f[5] +
+                     (double)f[6] * f[6]);
+    double qh[4] = {f[3] / qn, f[4] / qn, f[5] / qn, f[6] / qn};
+    double dR[4][3][3];
+    rotation_partials(qh[0], qh[1], qh[2], qh[3], dR);
+    double gS[3] = {0, 0, 0}, gqh[4] = {0, 0, 0, 0};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        gS[b] += G[a][b] * F.R[a][b];
+        double gRab = G[a][b] * S[b];
+        for (int c = 0; c < 4; ++c) gqh[c] += gRab * dR[c][a][b];
+      }
+    double radial = qh[0] * gqh[0] + qh[1] * gqh[1] + qh[2] * gqh[2] + qh[3] * gqh[3];
+    double* out = d_srt + 10 * j;
+    for (int b = 0; b < 3; ++b) out[b] += gS[b];
+    for (int c = 0; c < 4; ++c) out[3 + c] += (gqh[c] - qh[c] * radial) / qn;
+    for (int a = 0; a < 3; ++a) out[7 + a] += gT[a];
+  }
+  return 0;
+}
+
+/* Central differences (step h) of l = g.(t,u,v) of the world ray against the
+ * world-space triangle T + R(q/|q|)(S*v_i) by the plane formula, at the fixed
+ * (inst[r], prim[r]).  Output per ray: 25 derivatives: v0, v1, v2 (object
+ * space, 9), the ten frame parameters of the instance, o (3), d (3). */
+int orc_fd_inst(const orc_scene* s, const float* rays, const uint32_t* inst, const uint32_t* prim,
+                int64_t nr, const double* g, double h, double* out) {
+  if (nr < 0 || !scene_valid(s) || s->n_inst < 1 || !(h > 0.0)) return -1;
+  if (nr > 0 && (!rays || !inst || !prim || !g || !out)) return -1;
+  for (int64_t r = 0; r < nr; ++r) {
+    if (prim[r] == ORC_NONE) continue;
+    if ((int64_t)inst[r] >= s->n_inst) return -1;
+    if ((int64_t)prim[r] >= s->n_triangles[s->inst_mesh[inst[r]]]) return -1;
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t r = 0; r < nr; ++r) {
+    double* res = out + 25 * r;
+    if (prim[r] == ORC_NONE) {
+      for (int i = 0; i < 25; ++i) res[i] = 0.0;
+      continue;
+    }
+    int64_t j = inst[r];
+    int m = (int)s->inst_mesh[j];
+    ray64 q = load_ray(rays + 8 * r);
+    /* x: v0, v1, v2 (9), frame (10), o (3), d (3) */
+    double x[25];
+    const uint32_t* ix = s->indices[m] + 3 * (int64_t)prim[r];
+    for (int c = 0; c < 3; ++c) {
+      vec3 p = vtx(s, m, ix[c]);
+      x[3 * c] = p.x; x[3 * c + 1] = p.y; x[3 * c + 2] = p.z;
+    }
+    for (int i = 0; i < 10; ++i) x[9 + i] = s->inst_srt[10 * j + i];
+    x[19] = q.o.x; x[20] = q.o.y; x[21] = q.o.z;
+    x[22] = q.d.x; x[23] = q.d.y; x[24] = q.d.z;
+    const double* gr = g + 3 * r;
+    for (int i = 0; i < 25; ++i) {
+      double l[2];
+      for (int side = 0; side < 2; ++side) {
+        double y[25];
+        memcpy(y, x, sizeof y);
+        y[i] += side == 0 ? h : -h;
+        frame64 F = frame_from(y + 9);
+        vec3 W0 = to_world(&F, mk(y[0], y[1], y[2]));
+        vec3 W1 = to_world(&F, mk(y[3], y[4], y[5]));
+        vec3 W2 = to_world(&F, mk(y[6], y[7], y[8]));
+        double t, u, v;
+        plane_tuv(mk(y[19], y[20], y[21]), mk(y[22], y[23], y[24]), W0, W1, W2, &t, &u, &v);
+        l[side] = gr[0] * t + gr[1] * u + gr[2] * v;
+      }
+      res[i] = (l[0] - l[1]) / (2.0 * h);
+    }
   }
   return 0;
 }

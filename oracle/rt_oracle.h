@@ -78,6 +78,22 @@ int orc_fd(const orc_scene* s, const float* rays, const uint32_t* prim, int64_t 
 int orc_fixed_tuv(const orc_scene* s, const float* rays, const uint32_t* prim, int64_t nr,
                   double* tuv);
 
+/* Adjoint of (t,u,v) of two-level hits at fixed (inst[r], prim[r]): the
+ * gradients reach the base mesh's object-space vertices and the instance's
+ * ten frame parameters.  d_vertices: n_mesh pointers (the array or an entry
+ * may be NULL: not wanted), mesh m holding nv_m*3 doubles, ACCUMULATED;
+ * d_srt (n_inst*10, may be NULL) ACCUMULATED; d_orig / d_dir (nr*3)
+ * overwritten.  prim[r] = ORC_NONE contributes nothing. */
+int orc_adjoint_inst(const orc_scene* s, const float* rays, const uint32_t* inst,
+                     const uint32_t* prim, int64_t nr, const double* g,
+                     double* const* d_vertices, double* d_srt, double* d_orig, double* d_dir);
+
+/* Central finite differences for two-level hits.  Output per ray: 25
+ * derivatives: v0, v1, v2 (object space), the frame (sx,sy,sz, qx,qy,qz,qw,
+ * tx,ty,tz), o.xyz, d.xyz. */
+int orc_fd_inst(const orc_scene* s, const float* rays, const uint32_t* inst, const uint32_t* prim,
+                int64_t nr, const double* g, double h, double* out /* nr*25 */);
+
 int orc_num_threads(void);
 void orc_set_num_threads(int n);
 
