@@ -194,10 +194,42 @@ rt_status rt_trace_any(rt_accel accel, const rt_ray* rays, uint32_t n, uint8_t* 
  * summation order is not deterministic); d_origins / d_directions (device,
  * n*3 float32) are overwritten (zero for misses).  t, u, v are recomputed in
  * float64 from the triangle, so `hits` contributes only the triangle id.
- * Errors: RT_ERROR_UNSUPPORTED on a two-level accel. */
+ * Errors: RT_ERROR_UNSUPPORTED on a two-level accel (use
+ * rt_trace_backward_instances). */
 rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hits,
                             const float* d_tuv, uint32_t n, float* d_vertices, float* d_origins,
                             float* d_directions, void* stream);
+
+/* Adjoint of two-level closest hits (§6.2 two-level hierarchy: a hit on an
+ * instance is the hit of the ray taken to object space by the inverse of
+ * the instance frame, so t, u, v are those of the world ray against the
+ * world-space triangle T + R(q/|q|)(S v_k)).  For ray i with
+ * hits[i].prim_id != RT_INVALID_ID on instance inst_ids[i] (the ids written
+ * by rt_trace_closest) and g = d_tuv[3i..3i+2] = dL/d(t,u,v), with lambda =
+ * M^-T g for the world-space M = [-d | W1-W0 | W2-W0]:
+ *   d_origins[i] = lambda, d_directions[i] = t lambda (world space,
+ *     device, n*3 float32, OVERWRITTEN; zero for misses);
+ *   d_vertices (device, float32, nullable): gradients of the base meshes'
+ *     object-space vertices, ACCUMULATED; mesh m's rows start at the sum of
+ *     the vertex counts of meshes 0..m-1 (the mesh order of rt_build), so
+ *     the buffer holds 3 * (total vertex count) floats;
+ *   d_srt (device, instance_count*10 float32, nullable): gradients of each
+ *     instance's (sx,sy,sz, qx,qy,qz,qw, tx,ty,tz) as given to rt_build,
+ *     ACCUMULATED; the quaternion part is the gradient with respect to the
+ *     unnormalised q (orthogonal to q).
+ * Accumulation uses float32 atomics (the summation order is not
+ * deterministic).  t, u, v are recomputed in float64 with the accel's copies
+ * of the meshes and frames.  A hit whose instance id is not an instance of
+ * the accel, or whose prim_id is not a triangle of that instance's mesh,
+ * contributes nothing (zero ray gradients).
+ * Errors: RT_ERROR_UNSUPPORTED on a single-level accel (use
+ * rt_trace_backward); RT_ERROR_INVALID_VALUE for NULL rays, hits, inst_ids,
+ * d_tuv, d_origins or d_directions with n > 0, or rays/hits not 16-byte
+ * aligned. */
+rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const rt_hit* hits,
+                                      const uint32_t* inst_ids, const float* d_tuv, uint32_t n,
+                                      float* d_vertices, float* d_srt, float* d_origins,
+                                      float* d_directions, void* stream);
 
 /* Diagnostics: the query of rt_trace_closest (any == 0, into hits) or
  * rt_trace_any (any != 0, into occluded) run with a counting kernel variant

@@ -24,7 +24,8 @@ RT_INVALID_ID = 0xFFFFFFFF
 EXPORTS = [
     "rt_context_create", "rt_context_destroy", "rt_context_set_variant", "rt_context_get_variant",
     "rt_build", "rt_accel_destroy", "rt_accel_get_info",
-    "rt_trace_closest", "rt_trace_any", "rt_trace_backward", "rt_trace_counters", "rt_refit",
+    "rt_trace_closest", "rt_trace_any", "rt_trace_backward", "rt_trace_backward_instances",
+    "rt_trace_counters", "rt_refit",
     "rt_autotune",
     "rt_batch_plan_create", "rt_batch_plan_launch", "rt_batch_plan_graph", "rt_batch_plan_destroy",
     "rt_status_string", "rt_last_error_message", "rt_version",
@@ -98,6 +99,7 @@ def load():
             "rt_trace_closest": [P, P, U32, P, P, P],
             "rt_trace_any": [P, P, U32, P, P],
             "rt_trace_backward": [P, P, P, P, U32, P, P, P, P],
+            "rt_trace_backward_instances": [P, P, P, P, P, U32, P, P, P, P, P],
             "rt_trace_counters": [P, P, U32, I32, P, P, P, P],
             "rt_refit": [P, P, P],
             "rt_autotune": [P, P, P, U32, U32, P, P, P, U32, P],

@@ -91,6 +91,7 @@ class Accel:
                                          f.data_ptr() if f.numel() else None, f.shape[0], 12)
             self._keep += [v, f]
         self.vertex_count = int(meshes[0][0].shape[0])
+        self.vertex_counts = [int(v.shape[0]) for v, _ in meshes]
         n_inst = 0
         im_p = srt_p = None
         if inst_mesh is not None:
@@ -108,6 +109,7 @@ class Accel:
                   C.c_void_p(_stream()), C.byref(h))
         self.handle = h
         self.two_level = n_inst > 0
+        self.instance_count = n_inst
         self._keep = []
 
     @property
@@ -190,6 +192,38 @@ def trace_backward(accel: Accel, rays: torch.Tensor, hits: torch.Tensor, d_tuv: 
     return do, dd
 
 
+def trace_backward_instances(accel: Accel, rays: torch.Tensor, hits: torch.Tensor,
+                             inst_ids: torch.Tensor, d_tuv: torch.Tensor,
+                             d_vertices: torch.Tensor | None = None,
+                             d_srt: torch.Tensor | None = None):
+    """Two-level adjoint (rt_trace_backward_instances).  d_vertices
+    (sum of vertex counts, 3) holds the meshes' object-space vertex gradients
+    one after another in build order; d_srt (instances, 10) the frame
+    gradients; both accumulated in place when given.  Returns (d_origins,
+    d_directions), each (n,3)."""
+    _require(rays, "rays", torch.float32, 8)
+    _require(hits, "hits", torch.float32, 4)
+    _require(d_tuv, "d_tuv", torch.float32, 3)
+    if inst_ids.dtype not in (torch.int32, torch.uint32) or not inst_ids.is_contiguous() \
+            or inst_ids.device.type != "cuda" or inst_ids.shape != (rays.shape[0],):
+        raise ValueError("inst_ids must be a contiguous (n,) int32 cuda tensor")
+    if d_vertices is not None:
+        _require(d_vertices, "d_vertices", torch.float32, 3)
+        if d_vertices.shape[0] != sum(accel.vertex_counts):
+            raise ValueError(f"d_vertices needs {sum(accel.vertex_counts)} rows")
+    if d_srt is not None:
+        _require(d_srt, "d_srt", torch.float32, 10)
+        if d_srt.shape[0] != accel.instance_count:
+            raise ValueError(f"d_srt needs {accel.instance_count} rows")
+    n = rays.shape[0]
+    do = torch.empty((n, 3), dtype=torch.float32, device=rays.device)
+    dd = torch.empty((n, 3), dtype=torch.float32, device=rays.device)
+    capi.call("rt_trace_backward_instances", accel.handle, _ptr(rays), _ptr(hits), _ptr(inst_ids),
+              _ptr(d_tuv), n, _ptr(d_vertices), _ptr(d_srt), _ptr(do), _ptr(dd),
+              C.c_void_p(_stream()))
+    return do, dd
+
+
 class RayQueryFn(torch.autograd.Function):
     """Differentiable closest hit.
 
@@ -224,6 +258,47 @@ class RayQueryFn(torch.autograd.Function):
         dV = torch.zeros(ctx.vshape, dtype=torch.float32, device=rays.device)
         do, dd = trace_backward(ctx.accel, rays, hits, d_tuv, dV)
         return None, dV, do, dd, None, None
+
+
+class InstanceRayQueryFn(torch.autograd.Function):
+    """Differentiable closest hit on a two-level accel.
+
+    forward(accel, vertices, srt, origins, directions, tmin, tmax) ->
+    (t, u, v, prim_id, inst_id).  ``vertices`` (sum of vertex counts, 3) are
+    the meshes' vertices the accel was built from, one mesh after another in
+    build order, and ``srt`` (instances, 10) its frames; gradients flow to
+    them and to the rays through rt_trace_backward_instances."""
+
+    @staticmethod
+    def forward(ctx, accel, vertices, srt, origins, directions, tmin, tmax):
+        n = origins.shape[0]
+        rays = torch.empty((n, 8), dtype=torch.float32, device=origins.device)
+        rays[:, 0:3] = origins
+        rays[:, 3] = tmin
+        rays[:, 4:7] = directions
+        rays[:, 7] = tmax
+        hits, inst = trace_closest(accel, rays, want_inst=True)
+        t, prim, u, v = hit_fields(hits)
+        ctx.accel = accel
+        ctx.save_for_backward(rays, hits, inst)
+        ctx.vshape = vertices.shape
+        ctx.srt_device = srt.device
+        inst64 = inst.to(torch.int64)
+        inst64[prim < 0] = -1
+        ctx.mark_non_differentiable(prim, inst64)
+        return t.clone(), u.clone(), v.clone(), prim, inst64
+
+    @staticmethod
+    def backward(ctx, gt, gu, gv, gprim, ginst):
+        rays, hits, inst = ctx.saved_tensors
+        n = rays.shape[0]
+        z = torch.zeros(n, dtype=torch.float32, device=rays.device)
+        d_tuv = torch.stack([gt if gt is not None else z, gu if gu is not None else z,
+                             gv if gv is not None else z], 1).contiguous().float()
+        dV = torch.zeros(ctx.vshape, dtype=torch.float32, device=rays.device)
+        dS = torch.zeros((ctx.accel.instance_count, 10), dtype=torch.float32, device=rays.device)
+        do, dd = trace_backward_instances(ctx.accel, rays, hits, inst, d_tuv, dV, dS)
+        return None, dV, dS.to(ctx.srt_device), do, dd, None, None
 
 
 class BatchPlan:

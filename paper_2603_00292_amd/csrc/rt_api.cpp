@@ -111,6 +111,9 @@ struct rt_accel_s {
   rt_inst_rec* insts = nullptr;
   rt_inst_rec64* insts64 = nullptr;
   rt_mesh_dev* meshes = nullptr;             // device array of mesh records
+  rt_srt* srts = nullptr;                    // two-level: frames as given to the build
+  uint64_t* vertex_base = nullptr;           // two-level: first gradient row per mesh
+  uint32_t instance_count = 0;
   std::vector<void*> owned;                  // every device allocation
   std::vector<rt_mesh_dev> host_meshes;      // device pointers, host copy
   uint32_t* refit_nodes = nullptr;           // node ids, deepest level first (single level)
@@ -564,6 +567,20 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
       if (st != RT_SUCCESS) return bail(st);
       RT_HIP(hipMemcpyAsync(a->insts, ir.data(), ir.size() * sizeof(rt_inst_rec), hipMemcpyHostToDevice, s));
       RT_HIP(hipMemcpyAsync(a->insts64, ir64.data(), ir64.size() * sizeof(rt_inst_rec64), hipMemcpyHostToDevice, s));
+      // frames and per-mesh gradient rows for the two-level adjoint
+      std::vector<uint64_t> base(mesh_count);
+      uint64_t acc = 0;
+      for (uint32_t m = 0; m < mesh_count; ++m) {
+        base[m] = acc;
+        acc += meshes[m].vertex_count;
+      }
+      st = dev_alloc(a, &a->srts, instance_count);
+      if (st != RT_SUCCESS) return bail(st);
+      st = dev_alloc(a, &a->vertex_base, mesh_count);
+      if (st != RT_SUCCESS) return bail(st);
+      RT_HIP(hipMemcpyAsync(a->srts, instance_srt, instance_count * sizeof(rt_srt), hipMemcpyHostToDevice, s));
+      RT_HIP(hipMemcpyAsync(a->vertex_base, base.data(), mesh_count * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+      a->instance_count = instance_count;
     }
     RT_HIP(hipStreamSynchronize(s));
   } catch (const std::bad_alloc&) {
@@ -709,6 +726,42 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
   p.d_origins = d_origins;
   p.d_directions = d_directions;
   RT_HIP(rtk_launch_backward(p, static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const rt_hit* hits,
+                                      const uint32_t* inst_ids, const float* d_tuv, uint32_t n,
+                                      float* d_vertices, float* d_srt, float* d_origins,
+                                      float* d_directions, void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_backward_instances: NULL accel");
+  if (!accel->two_level)
+    return fail(RT_ERROR_UNSUPPORTED,
+                "rt_trace_backward_instances: single-level accel (use rt_trace_backward)");
+  if (n == 0) return ok();
+  if (!rays || !hits || !inst_ids || !d_tuv || !d_origins || !d_directions)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_backward_instances: NULL buffer with n > 0");
+  if (!aligned16(rays) || !aligned16(hits))
+    return fail(RT_ERROR_INVALID_VALUE,
+                "rt_trace_backward_instances: rays and hits must be 16-byte aligned");
+  rt_status st = check_device(accel->device);
+  if (st != RT_SUCCESS) return st;
+  BackwardInstParams p{};
+  p.meshes = accel->meshes;
+  p.vertex_base = accel->vertex_base;
+  p.insts = accel->insts;
+  p.insts64 = accel->insts64;
+  p.srts = accel->srts;
+  p.inst_count = accel->instance_count;
+  p.rays = rays;
+  p.hits = hits;
+  p.inst_ids = inst_ids;
+  p.d_tuv = d_tuv;
+  p.n = n;
+  p.d_vertices = d_vertices;
+  p.d_srt = d_srt;
+  p.d_origins = d_origins;
+  p.d_directions = d_directions;
+  RT_HIP(rtk_launch_backward_inst(p, static_cast<hipStream_t>(stream)));
   return ok();
 }
 

@@ -52,6 +52,25 @@ struct BackwardParams {
   float* d_directions;
 };
 
+// Adjoint of two-level closest hits (one thread per ray).
+struct BackwardInstParams {
+  const rt_mesh_dev* meshes;      // device mesh records (the accel's copies)
+  const uint64_t* vertex_base;    // first gradient row of each mesh
+  const rt_inst_rec* insts;       // mesh of each instance
+  const rt_inst_rec64* insts64;   // float64 world-to-object maps
+  const rt_srt* srts;             // frames as given to the build
+  uint32_t inst_count;
+  const rt_ray* rays;
+  const rt_hit* hits;
+  const uint32_t* inst_ids;
+  const float* d_tuv;
+  uint32_t n;
+  float* d_vertices;              // may be null
+  float* d_srt;                   // may be null
+  float* d_origins;
+  float* d_directions;
+};
+
 // Kernel handle for a variant (mode 0: one accel, mode 1: batched closest);
 // nullptr when the combination is not compiled.
 const void* rtk_trace_kernel(int width, int stack, int wg, bool any, bool inst, int mode);
@@ -61,6 +80,7 @@ hipError_t rtk_launch_trace(const void* kern, uint32_t grid, uint32_t wg, const 
 // float64 finalize of closest hits written by a trace launch with the same params
 hipError_t rtk_launch_finalize(bool inst, int mode, const TraceParams& p, hipStream_t stream);
 hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream);
+hipError_t rtk_launch_backward_inst(const BackwardInstParams& p, hipStream_t stream);
 hipError_t rtk_launch_refit_tris(rt_tri_rec* tris, uint32_t n, const rt_mesh_dev& mesh,
                                  hipStream_t stream);
 hipError_t rtk_launch_refit_nodes(int width, float* nodes, const rt_tri_rec* tris,

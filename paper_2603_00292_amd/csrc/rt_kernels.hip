@@ -482,6 +482,52 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
 // ---------------------------------------------------------------------------
 // adjoint of the closest hit at fixed triangles (one ray per thread)
 // ---------------------------------------------------------------------------
+// The hit solves o + t d = (1-u-v) v0 + u v1 + v v2, i.e. M (t,u,v)^T = o - v0
+// with M = [-d | v1-v0 | v2-v0].  For L with dL/d(t,u,v) = g the implicit
+// function theorem gives lambda = M^-T g and dL/do = lambda, dL/dd = t lambda,
+// dL/dv_k = -w_k lambda with w = (1-u-v, u, v).
+struct Adjoint64 {
+  double t, u, v;
+  double lx, ly, lz;     // lambda
+  double p[3][3];        // the triangle's vertices (float32 promoted)
+  uint32_t id[3];        // their indices
+};
+
+__device__ __forceinline__ bool adjoint64(const rt_mesh_dev& mesh, uint32_t prim, double ox,
+                                          double oy, double oz, double dx, double dy, double dz,
+                                          double gt, double gu, double gv, Adjoint64& A) {
+  const uint32_t* ix = mesh.indices + 3 * (size_t)prim;
+  const float* V = mesh.vertices;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    A.id[k] = ix[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) A.p[k][c] = V[3 * (size_t)A.id[k] + c];
+  }
+  double v0x = A.p[0][0], v0y = A.p[0][1], v0z = A.p[0][2];
+  double e1x = A.p[1][0] - v0x, e1y = A.p[1][1] - v0y, e1z = A.p[1][2] - v0z;
+  double e2x = A.p[2][0] - v0x, e2y = A.p[2][1] - v0y, e2z = A.p[2][2] - v0z;
+  // rows of M^-1 are (e1 x e2, e2 x c0, c0 x e1) / det with c0 = -d
+  double c0x = -dx, c0y = -dy, c0z = -dz;
+  double r0x = e1y * e2z - e1z * e2y, r0y = e1z * e2x - e1x * e2z, r0z = e1x * e2y - e1y * e2x;
+  double r1x = e2y * c0z - e2z * c0y, r1y = e2z * c0x - e2x * c0z, r1z = e2x * c0y - e2y * c0x;
+  double r2x = c0y * e1z - c0z * e1y, r2y = c0z * e1x - c0x * e1z, r2z = c0x * e1y - c0y * e1x;
+  double det = c0x * r0x + c0y * r0y + c0z * r0z;
+  if (det == 0.0) return false;
+  double inv = 1.0 / det;
+  double sx = ox - v0x, sy = oy - v0y, sz = oz - v0z;
+  A.t = (r0x * sx + r0y * sy + r0z * sz) * inv;
+  A.u = (r1x * sx + r1y * sy + r1z * sz) * inv;
+  A.v = (r2x * sx + r2y * sy + r2z * sz) * inv;
+  // lambda = M^-T g = sum_i g_i row_i(M^-1)
+  A.lx = (gt * r0x + gu * r1x + gv * r2x) * inv;
+  A.ly = (gt * r0y + gu * r1y + gv * r2y) * inv;
+  A.lz = (gt * r0z + gu * r1z + gv * r2z) * inv;
+  return true;
+}
+
+__device__ __forceinline__ void zero3(float* a) { a[0] = a[1] = a[2] = 0.0f; }
+
 __global__ __launch_bounds__(256) void backward_kernel(BackwardParams P) {
   uint32_t i = blockIdx.x * 256u + threadIdx.x;
   if (i >= P.n) return;
@@ -489,53 +535,136 @@ __global__ __launch_bounds__(256) void backward_kernel(BackwardParams P) {
   uint32_t prim = __float_as_uint(hp->y);
   float* go = P.d_origins + 3 * (size_t)i;
   float* gd = P.d_directions + 3 * (size_t)i;
-  if (prim == RT_INVALID_ID || prim >= P.mesh.triangle_count) {
-    go[0] = go[1] = go[2] = 0.0f;
-    gd[0] = gd[1] = gd[2] = 0.0f;
-    return;
-  }
   rt_ray q = load_ray(P.rays, i);
-  const uint32_t* ix = P.mesh.indices + 3 * (size_t)prim;
-  uint32_t id[3] = {ix[0], ix[1], ix[2]};
-  const float* V = P.mesh.vertices;
-  double v0x = V[3 * (size_t)id[0]], v0y = V[3 * (size_t)id[0] + 1], v0z = V[3 * (size_t)id[0] + 2];
-  double e1x = V[3 * (size_t)id[1]] - v0x, e1y = V[3 * (size_t)id[1] + 1] - v0y,
-         e1z = V[3 * (size_t)id[1] + 2] - v0z;
-  double e2x = V[3 * (size_t)id[2]] - v0x, e2y = V[3 * (size_t)id[2] + 1] - v0y,
-         e2z = V[3 * (size_t)id[2] + 2] - v0z;
-  double dx = q.dx, dy = q.dy, dz = q.dz;
-  // M = [c0 | e1 | e2], c0 = -d; rows of M^-1 are (e1 x e2, e2 x c0, c0 x e1) / det
-  double c0x = -dx, c0y = -dy, c0z = -dz;
-  double r0x = e1y * e2z - e1z * e2y, r0y = e1z * e2x - e1x * e2z, r0z = e1x * e2y - e1y * e2x;
-  double r1x = e2y * c0z - e2z * c0y, r1y = e2z * c0x - e2x * c0z, r1z = e2x * c0y - e2y * c0x;
-  double r2x = c0y * e1z - c0z * e1y, r2y = c0z * e1x - c0x * e1z, r2z = c0x * e1y - c0y * e1x;
-  double det = c0x * r0x + c0y * r0y + c0z * r0z;
-  if (det == 0.0) {
-    go[0] = go[1] = go[2] = 0.0f;
-    gd[0] = gd[1] = gd[2] = 0.0f;
+  const float* gr = P.d_tuv + 3 * (size_t)i;
+  Adjoint64 A;
+  if (prim == RT_INVALID_ID || prim >= P.mesh.triangle_count ||
+      !adjoint64(P.mesh, prim, q.ox, q.oy, q.oz, q.dx, q.dy, q.dz, gr[0], gr[1], gr[2], A)) {
+    zero3(go);
+    zero3(gd);
     return;
   }
-  double inv = 1.0 / det;
-  double sx = q.ox - v0x, sy = q.oy - v0y, sz = q.oz - v0z;
-  double t = (r0x * sx + r0y * sy + r0z * sz) * inv;
-  double u = (r1x * sx + r1y * sy + r1z * sz) * inv;
-  double v = (r2x * sx + r2y * sy + r2z * sz) * inv;
-  const float* gr = P.d_tuv + 3 * (size_t)i;
-  double gt = gr[0], gu = gr[1], gv = gr[2];
-  // lambda = M^-T g = sum_i g_i row_i(M^-1)
-  double lx = (gt * r0x + gu * r1x + gv * r2x) * inv;
-  double ly = (gt * r0y + gu * r1y + gv * r2y) * inv;
-  double lz = (gt * r0z + gu * r1z + gv * r2z) * inv;
-  go[0] = (float)lx; go[1] = (float)ly; go[2] = (float)lz;
-  gd[0] = (float)(t * lx); gd[1] = (float)(t * ly); gd[2] = (float)(t * lz);
-  double w[3] = {1.0 - u - v, u, v};
+  go[0] = (float)A.lx; go[1] = (float)A.ly; go[2] = (float)A.lz;
+  gd[0] = (float)(A.t * A.lx); gd[1] = (float)(A.t * A.ly); gd[2] = (float)(A.t * A.lz);
+  double w[3] = {1.0 - A.u - A.v, A.u, A.v};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    float* dv = P.d_vertices + 3 * (size_t)id[k];
-    atomicAdd(dv + 0, (float)(-w[k] * lx));
-    atomicAdd(dv + 1, (float)(-w[k] * ly));
-    atomicAdd(dv + 2, (float)(-w[k] * lz));
+    float* dv = P.d_vertices + 3 * (size_t)A.id[k];
+    atomicAdd(dv + 0, (float)(-w[k] * A.lx));
+    atomicAdd(dv + 1, (float)(-w[k] * A.ly));
+    atomicAdd(dv + 2, (float)(-w[k] * A.lz));
   }
+}
+
+// Two-level hits (§6.2: the hit on an instance is the hit of the object-space
+// ray x = A^-1 (w - T)).  t, u and v are invariant under the affine frame, so
+// the object-space solve gives them and lambda_o; the world-space adjoint is
+// lambda_w = A^-T lambda_o (A^-1 is the float64 map the finalize uses), the
+// object vertices take -w_k lambda_o directly.  For the frame world = T +
+// R(qh) (S x), qh = q/|q|, with the object hit point p and a = S p:
+//   dL/dT = -lambda_w,   dL/dS_j = -(R^T lambda_w)_j p_j,
+//   dL/dqh (through R a = a + 2 w (v x a) + 2 v x (v x a), qh = (v, w)):
+//     w-part  -2 lambda.(v x a),
+//     v-part  -2 [w (a x lambda) + (v x a) x lambda + a x (lambda x v)],
+//   dL/dq = (dL/dqh - qh (qh . dL/dqh)) / |q|.
+__device__ __forceinline__ void cross3(double ax, double ay, double az, double bx, double by,
+                                       double bz, double& cx, double& cy, double& cz) {
+  cx = ay * bz - az * by;
+  cy = az * bx - ax * bz;
+  cz = ax * by - ay * bx;
+}
+
+__global__ __launch_bounds__(256) void backward_inst_kernel(BackwardInstParams P) {
+  uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= P.n) return;
+  const float4* hp = reinterpret_cast<const float4*>(P.hits + i);
+  uint32_t prim = __float_as_uint(hp->y);
+  uint32_t inst = P.inst_ids[i];
+  float* go = P.d_origins + 3 * (size_t)i;
+  float* gd = P.d_directions + 3 * (size_t)i;
+  if (prim == RT_INVALID_ID || inst >= P.inst_count) {
+    zero3(go);
+    zero3(gd);
+    return;
+  }
+  uint32_t mesh = P.insts[inst].mesh;
+  const rt_mesh_dev& md = P.meshes[mesh];
+  const rt_inst_rec64& M = P.insts64[inst];
+  rt_ray q = load_ray(P.rays, i);
+  double ox = q.ox, oy = q.oy, oz = q.oz, dx = q.dx, dy = q.dy, dz = q.dz;
+  double xo = M.m[0] * ox + M.m[1] * oy + M.m[2] * oz + M.m[3];
+  double yo = M.m[4] * ox + M.m[5] * oy + M.m[6] * oz + M.m[7];
+  double zo = M.m[8] * ox + M.m[9] * oy + M.m[10] * oz + M.m[11];
+  double xd = M.m[0] * dx + M.m[1] * dy + M.m[2] * dz;
+  double yd = M.m[4] * dx + M.m[5] * dy + M.m[6] * dz;
+  double zd = M.m[8] * dx + M.m[9] * dy + M.m[10] * dz;
+  const float* gr = P.d_tuv + 3 * (size_t)i;
+  Adjoint64 A;
+  if (prim >= md.triangle_count ||
+      !adjoint64(md, prim, xo, yo, zo, xd, yd, zd, gr[0], gr[1], gr[2], A)) {
+    zero3(go);
+    zero3(gd);
+    return;
+  }
+  // lambda_w = (A^-1)^T lambda_o
+  double lx = M.m[0] * A.lx + M.m[4] * A.ly + M.m[8] * A.lz;
+  double ly = M.m[1] * A.lx + M.m[5] * A.ly + M.m[9] * A.lz;
+  double lz = M.m[2] * A.lx + M.m[6] * A.ly + M.m[10] * A.lz;
+  go[0] = (float)lx; go[1] = (float)ly; go[2] = (float)lz;
+  gd[0] = (float)(A.t * lx); gd[1] = (float)(A.t * ly); gd[2] = (float)(A.t * lz);
+  double w[3] = {1.0 - A.u - A.v, A.u, A.v};
+  if (P.d_vertices) {
+    float* base = P.d_vertices + 3 * P.vertex_base[mesh];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      float* dv = base + 3 * (size_t)A.id[k];
+      atomicAdd(dv + 0, (float)(-w[k] * A.lx));
+      atomicAdd(dv + 1, (float)(-w[k] * A.ly));
+      atomicAdd(dv + 2, (float)(-w[k] * A.lz));
+    }
+  }
+  if (!P.d_srt) return;
+  const rt_srt f = P.srts[inst];
+  double qx = f.qx, qy = f.qy, qz = f.qz, qw = f.qw;
+  double qn = sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
+  double iq = 1.0 / qn;
+  qx *= iq; qy *= iq; qz *= iq; qw *= iq;
+  // object hit point and a = S p
+  double px = w[0] * A.p[0][0] + w[1] * A.p[1][0] + w[2] * A.p[2][0];
+  double py = w[0] * A.p[0][1] + w[1] * A.p[1][1] + w[2] * A.p[2][1];
+  double pz = w[0] * A.p[0][2] + w[1] * A.p[1][2] + w[2] * A.p[2][2];
+  double ax = f.sx * px, ay = f.sy * py, az = f.sz * pz;
+  // R^T lambda = lambda - 2 w (v x lambda) + 2 v x (v x lambda)
+  double cx, cy, cz, ex, ey, ez;
+  cross3(qx, qy, qz, lx, ly, lz, cx, cy, cz);
+  cross3(qx, qy, qz, cx, cy, cz, ex, ey, ez);
+  double rlx = lx - 2.0 * qw * cx + 2.0 * ex;
+  double rly = ly - 2.0 * qw * cy + 2.0 * ey;
+  double rlz = lz - 2.0 * qw * cz + 2.0 * ez;
+  // quaternion part
+  double vax, vay, vaz;           // v x a
+  cross3(qx, qy, qz, ax, ay, az, vax, vay, vaz);
+  double gqw = -2.0 * (lx * vax + ly * vay + lz * vaz);
+  double t1x, t1y, t1z, t2x, t2y, t2z, lvx, lvy, lvz, t3x, t3y, t3z;
+  cross3(ax, ay, az, lx, ly, lz, t1x, t1y, t1z);        // a x lambda
+  cross3(vax, vay, vaz, lx, ly, lz, t2x, t2y, t2z);     // (v x a) x lambda
+  cross3(lx, ly, lz, qx, qy, qz, lvx, lvy, lvz);        // lambda x v
+  cross3(ax, ay, az, lvx, lvy, lvz, t3x, t3y, t3z);     // a x (lambda x v)
+  double gqx = -2.0 * (qw * t1x + t2x + t3x);
+  double gqy = -2.0 * (qw * t1y + t2y + t3y);
+  double gqz = -2.0 * (qw * t1z + t2z + t3z);
+  double radial = qx * gqx + qy * gqy + qz * gqz + qw * gqw;
+  float* out = P.d_srt + 10 * (size_t)inst;
+  atomicAdd(out + 0, (float)(-rlx * px));
+  atomicAdd(out + 1, (float)(-rly * py));
+  atomicAdd(out + 2, (float)(-rlz * pz));
+  atomicAdd(out + 3, (float)((gqx - qx * radial) * iq));
+  atomicAdd(out + 4, (float)((gqy - qy * radial) * iq));
+  atomicAdd(out + 5, (float)((gqz - qz * radial) * iq));
+  atomicAdd(out + 6, (float)((gqw - qw * radial) * iq));
+  atomicAdd(out + 7, (float)(-lx));
+  atomicAdd(out + 8, (float)(-ly));
+  atomicAdd(out + 9, (float)(-lz));
 }
 
 // ---------------------------------------------------------------------------
@@ -774,6 +903,14 @@ hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream) {
   BackwardParams q = p;
   void* args[] = {&q};
   return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::backward_kernel),
+                         dim3((p.n + 255) / 256), dim3(256), args, 0, stream);
+}
+
+hipError_t rtk_launch_backward_inst(const BackwardInstParams& p, hipStream_t stream) {
+  if (p.n == 0) return hipSuccess;
+  BackwardInstParams q = p;
+  void* args[] = {&q};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::backward_inst_kernel),
                          dim3((p.n + 255) / 256), dim3(256), args, 0, stream);
 }
 

@@ -369,6 +369,37 @@ def instanced_grids(n_inst: int = 1024, n_rays: int = 8388608, k: int = 2) -> Wo
     return Workload("instanced_grids", Scene(meshes, inst_mesh, srt), rays)
 
 
+def aimed_instances(n_inst: int = 8, n_rays: int = 4096, k: int = 130) -> Workload:
+    """Small two-level scene for gradient checks: three 12x8-quad displaced
+    grids (heights N(0, sigma), sigma in {0.02, 0.05, 0.1}) instanced
+    ``n_inst`` times (instance m uses mesh m mod 3) with scale U[0.5,2]^3
+    (instance 1 mirrored in z), uniform rotations given as quaternions of
+    norm U[0.6,1.8] (the frame normalises them) and translation U[-6,6]^3.
+    Rays start uniformly in [-9,9]^3 and aim at uniformly chosen points of
+    uniformly chosen instances."""
+    rng = rng_for(k)
+    meshes = []
+    for s in (0.02, 0.05, 0.1):
+        mv, mf = grid_mesh(12, 8, -1.0, 1.0, -0.5, 0.5, rng.normal(0, s, 13 * 9))
+        meshes.append(Mesh(mv, mf))
+    inst_mesh = (np.arange(n_inst) % 3).astype(np.uint32)
+    S = rng.uniform(0.5, 2.0, (n_inst, 3))
+    if n_inst > 1:
+        S[1, 2] *= -1.0
+    q = uniform_quaternions(rng, n_inst) * rng.uniform(0.6, 1.8, (n_inst, 1))
+    T = rng.uniform(-6, 6, (n_inst, 3))
+    srt = _f32(np.concatenate([S, q, T], 1))
+    R = quat_matrix(srt[:, 3:7].astype(np.float64))
+    j = rng.integers(0, n_inst, n_rays)
+    p_obj = np.stack([rng.uniform(-0.9, 0.9, n_rays), np.zeros(n_rays),
+                      rng.uniform(-0.4, 0.4, n_rays)], 1)
+    tgt = np.einsum("nij,nj->ni", R[j], srt[j, 0:3].astype(np.float64) * p_obj) + srt[j, 7:10]
+    o = rng.uniform(-9, 9, (n_rays, 3))
+    d = tgt - o
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return Workload("aimed_instances", Scene(meshes, inst_mesh, srt), pack_rays(o, d))
+
+
 def batched_meshes(n_mesh: int = 256, tri_range=(1e3, 5e5), ray_range=(1e3, 1e6), k: int = 3):
     """Independent meshes with log-uniform triangle counts and log-uniform ray
     counts. Mesh m: the random-triangle recipe with offset half-width

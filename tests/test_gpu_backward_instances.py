@@ -1,0 +1,261 @@
+"""GPU parity of the two-level adjoint (rt_trace_backward_instances) and of
+the autograd Function over it, against the FP64 oracle's two-level adjoint
+and FP64 finite differences of all 25 inputs of a hit.
+
+Accumulated gradients (vertices, frames) are sums of float32 atomics of
+float64-computed contributions; each entry must lie within the rounding
+bound of such a sum: n * 2^-24 * (sum of |contributions|) for n terms, plus
+the float64 differences between the object-space (library) and world-space
+(oracle) routes, far below that."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from helpers import NONE, check_closest, to_gpu_scene
+from paper_2603_00292_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+GRAD_REL = 1e-4   # per-ray world-space ray gradients (float32 outputs of float64 math)
+EPS32 = 2.0 ** -24
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    from paper_2603_00292_amd import api
+
+    torch.cuda.set_device(0)
+    ctx = api.Context(0)
+    yield torch, api, ctx
+    torch.cuda.synchronize()
+
+
+def _forward(gpu, acc, rays_np):
+    torch, api, _ = gpu
+    rays = torch.from_numpy(np.ascontiguousarray(rays_np)).cuda()
+    hits, inst = api.trace_closest(acc, rays, want_inst=True)
+    return rays, hits, inst
+
+
+def _backward(gpu, acc, rays, hits, inst, g, n_vert, n_inst):
+    torch, api, _ = gpu
+    gt = torch.from_numpy(np.ascontiguousarray(g, dtype=np.float32)).cuda()
+    dV = torch.zeros((n_vert, 3), dtype=torch.float32, device="cuda")
+    dS = torch.zeros((n_inst, 10), dtype=torch.float32, device="cuda")
+    do, dd = api.trace_backward_instances(acc, rays, hits, inst, gt, dV, dS)
+    torch.cuda.synchronize()
+    return (dV.cpu().numpy().astype(np.float64), dS.cpu().numpy().astype(np.float64),
+            do.cpu().numpy().astype(np.float64), dd.cpu().numpy().astype(np.float64))
+
+
+def _bases(scene):
+    return np.concatenate([[0], np.cumsum([m.vertices.shape[0] for m in scene.meshes])])
+
+
+def test_backward_instances_small_full_check(gpu, orc):
+    """8 frames (one mirrored, unnormalised quaternions) of 3 meshes, 8,192
+    aimed rays: every pinned hit's ray gradients, and every accumulated vertex
+    and frame gradient within the float32 summation bound."""
+    torch, api, ctx = gpu
+    W = wl.aimed_instances(n_inst=8, n_rays=8192, k=310)
+    scene = W.scene
+    acc = to_gpu_scene(api, torch, ctx, scene)
+    rays, hits, inst = _forward(gpu, acc, W.rays)
+    h = hits.cpu().numpy()
+    ii = inst.cpu().numpy().view(np.uint32)
+    S = orc.OracleScene.from_scene(scene)
+    A = orc.accept(S, W.rays)
+    check_closest(h, A, inst=ii, label="aimed instances")
+    oinst, oprim, _ = orc.closest(S, W.rays)
+    prim = h[:, 1].copy().view(np.uint32)
+    keep = A.pinned & (oprim != NONE)
+    assert (prim[keep] == oprim[keep]).all() and (ii[keep] == oinst[keep]).all()
+    assert keep.sum() > 3000
+    # float32-representable cotangents: both sides see the same g
+    g = wl.rng_for(311).standard_normal((W.rays.shape[0], 3)).astype(np.float32).astype(np.float64)
+    g *= keep[:, None]
+    base = _bases(scene)
+    dV, dS, do, dd = _backward(gpu, acc, rays, hits, inst, g, base[-1], 8)
+    # reference: per-ray oracle contributions, their sums and absolute sums
+    p_ref = np.where(keep, oprim, NONE).astype(np.uint32)
+    rV, rS, ro, rd = orc.adjoint_inst(S, W.rays, oinst, p_ref, g)
+    rV = np.concatenate(rV)
+    absV = np.zeros_like(rV)
+    absS = np.zeros_like(rS)
+    cntV = np.zeros(rV.shape[0])
+    cntS = np.zeros(8)
+    for r in np.flatnonzero(keep):
+        v1, s1, _, _ = orc.adjoint_inst(S, W.rays[r:r + 1], oinst[r:r + 1], p_ref[r:r + 1], g[r:r + 1])
+        m = int(scene.inst_mesh[oinst[r]])
+        tri = scene.meshes[m].indices[oprim[r]].astype(np.int64) + base[m]
+        absV[tri] += np.abs(np.concatenate(v1)[tri])
+        cntV[tri] += 1
+        absS[oinst[r]] += np.abs(s1[oinst[r]])
+        cntS[oinst[r]] += 1
+    r = np.flatnonzero(keep)
+    eo = np.linalg.norm(do[r] - ro[r], axis=1) / np.linalg.norm(ro[r], axis=1)
+    ed = np.linalg.norm(dd[r] - rd[r], axis=1) / np.linalg.norm(rd[r], axis=1)
+    say("max rel err d_origin", eo.max(), "d_direction", ed.max())
+    assert eo.max() <= GRAD_REL and ed.max() <= GRAD_REL
+    assert np.abs(do[~keep]).max() == 0 and np.abs(dd[~keep]).max() == 0
+    boundV = (cntV[:, None] + 1) * EPS32 * absV + 1e-12
+    boundS = (cntS[:, None] + 1) * EPS32 * absS + 1e-12
+    say("vertex err / bound", (np.abs(dV - rV) / boundV).max(),
+        "frame err / bound", (np.abs(dS - rS) / boundS).max())
+    assert (np.abs(dV - rV) <= boundV).all()
+    assert (np.abs(dS - rS) <= boundS).all()
+    say("frob rel: vertices", np.linalg.norm(dV - rV) / np.linalg.norm(rV),
+        "frames", np.linalg.norm(dS - rS) / np.linalg.norm(rS))
+    acc.close()
+
+
+def test_backward_instances_single_rays_vs_finite_differences(gpu, orc):
+    """All 25 derivatives of single hits (object vertices, ten frame
+    parameters, origin, direction) against FP64 central differences."""
+    torch, api, ctx = gpu
+    W = wl.aimed_instances(n_inst=8, n_rays=2048, k=312)
+    scene = W.scene
+    acc = to_gpu_scene(api, torch, ctx, scene)
+    rays, hits, inst = _forward(gpu, acc, W.rays)
+    S = orc.OracleScene.from_scene(scene)
+    A = orc.accept(S, W.rays)
+    oinst, oprim, _ = orc.closest(S, W.rays)
+    sel = np.flatnonzero(A.pinned & (oprim != NONE))[:40]
+    assert sel.size == 40
+    g = wl.rng_for(313).standard_normal((W.rays.shape[0], 3)).astype(np.float32).astype(np.float64)
+    fd = orc.fd_inst(S, W.rays[sel], oinst[sel], oprim[sel], g[sel], h=1e-6)
+    base = _bases(scene)
+    for i, r in enumerate(sel):
+        dV, dS, do, dd = _backward(gpu, acc, rays[r:r + 1].contiguous(), hits[r:r + 1].contiguous(),
+                                   inst[r:r + 1].contiguous(), g[r:r + 1], base[-1], 8)
+        m = int(scene.inst_mesh[oinst[r]])
+        tri = scene.meshes[m].indices[oprim[r]].astype(np.int64) + base[m]
+        got = np.concatenate([dV[tri[0]], dV[tri[1]], dV[tri[2]], dS[oinst[r]], do[0], dd[0]])
+        scale = np.abs(fd[i]).max()
+        assert np.abs(got - fd[i]).max() <= GRAD_REL * scale, (r, got, fd[i])
+    acc.close()
+
+
+def test_backward_instances_full_size(gpu, orc):
+    """1,024 frames, 8,388,608 secondary rays: forward and backward on all
+    rays; 256 sampled hits against the oracle's adjoint at the same ids;
+    per frame, the translation gradient equals minus the summed origin
+    gradients of its rays, and the quaternion gradient is orthogonal to q."""
+    torch, api, ctx = gpu
+    W = wl.instanced_grids()
+    scene = W.scene
+    acc = to_gpu_scene(api, torch, ctx, scene)
+    rays, hits, inst = _forward(gpu, acc, W.rays)
+    h = hits.cpu().numpy()
+    ii = inst.cpu().numpy().view(np.uint32)
+    prim = h[:, 1].copy().view(np.uint32)
+    hit = prim != NONE
+    say("hit fraction", hit.mean())
+    g = wl.rng_for(314).standard_normal((W.rays.shape[0], 3)).astype(np.float32)
+    base = _bases(scene)
+    dV, dS, do, dd = _backward(gpu, acc, rays, hits, inst, g, base[-1], 1024)
+    cand = np.sort(wl.rng_for(315).choice(W.rays.shape[0], 400, replace=False))
+    S = orc.OracleScene.from_scene(scene)
+    A = orc.accept(S, W.rays[cand])
+    check_closest(h[cand], A, inst=ii[cand], label="instanced sampled")
+    # the adjoint is taken at the library's own hit ids (surface-leaving rays
+    # are rarely pinned: their origin sits 1e-4 off a triangle)
+    idx = cand[hit[cand]][:256]
+    assert idx.size >= 200
+    _, _, ro, rd = orc.adjoint_inst(S, W.rays[idx], ii[idx], prim[idx], g[idx].astype(np.float64))
+    eo = np.linalg.norm(do[idx] - ro, axis=1) / np.linalg.norm(ro, axis=1)
+    ed = np.linalg.norm(dd[idx] - rd, axis=1) / np.linalg.norm(rd, axis=1)
+    say("sampled max rel err d_origin", eo.max(), "d_direction", ed.max())
+    assert eo.max() <= GRAD_REL and ed.max() <= GRAD_REL
+    # frame relations on all rays (float64 sums of the float32 ray gradients)
+    sum_o = np.zeros((1024, 3))
+    abs_o = np.zeros((1024, 3))
+    cnt = np.bincount(ii[hit], minlength=1024).astype(np.float64)
+    for c in range(3):
+        sum_o[:, c] = np.bincount(ii[hit], weights=do[hit, c], minlength=1024)
+        abs_o[:, c] = np.bincount(ii[hit], weights=np.abs(do[hit, c]), minlength=1024)
+    bound = (cnt[:, None] + 2) * EPS32 * abs_o * 2 + 1e-9
+    err = np.abs(dS[:, 7:10] + sum_o)
+    say("translation relation err / bound", (err / bound).max())
+    assert (err <= bound).all()
+    q = scene.inst_srt[:, 3:7].astype(np.float64)
+    radial = np.abs((q * dS[:, 3:7]).sum(1)) / np.linalg.norm(q, axis=1)
+    assert (radial <= 1e-3 * np.linalg.norm(dS[:, 3:7], axis=1) + 1e-6).all()
+    acc.close()
+
+
+def test_instance_autograd_function(gpu, orc):
+    """InstanceRayQueryFn: gradients of a masked loss equal the direct call's."""
+    torch, api, ctx = gpu
+    W = wl.aimed_instances(n_inst=8, n_rays=4096, k=316)
+    scene = W.scene
+    Vs = [torch.from_numpy(m.vertices).cuda() for m in scene.meshes]
+    Is = [torch.from_numpy(m.indices.view(np.int32)).cuda() for m in scene.meshes]
+    acc = api.Accel(ctx, list(zip(Vs, Is)), inst_mesh=scene.inst_mesh, inst_srt=scene.inst_srt)
+    V = torch.cat(Vs).requires_grad_(True)
+    srt = torch.from_numpy(scene.inst_srt.copy()).requires_grad_(True)
+    rays = torch.from_numpy(W.rays).cuda()
+    o = rays[:, 0:3].clone().requires_grad_(True)
+    d = rays[:, 4:7].clone().requires_grad_(True)
+    t, u, v, prim, ins = api.InstanceRayQueryFn.apply(acc, V, srt, o, d, 0.0, float("inf"))
+    abc = torch.from_numpy(wl.rng_for(317).standard_normal((4096, 3)).astype(np.float32)).cuda()
+    hit = prim >= 0
+    assert int(hit.sum()) > 1500
+    loss = (abc[hit, 0] * t[hit] + abc[hit, 1] * u[hit] + abc[hit, 2] * v[hit]).sum()
+    loss.backward()
+    hits, inst = api.trace_closest(acc, rays, want_inst=True)
+    g = torch.zeros((4096, 3), dtype=torch.float32, device="cuda")
+    g[hit] = abc[hit]
+    dV = torch.zeros_like(V)
+    dS = torch.zeros((8, 10), dtype=torch.float32, device="cuda")
+    do, dd = api.trace_backward_instances(acc, rays, hits, inst, g.contiguous(), dV, dS)
+    torch.cuda.synchronize()
+    assert srt.grad.device.type == "cpu"
+    assert torch.allclose(o.grad, do, rtol=1e-6, atol=1e-6)
+    assert torch.allclose(d.grad, dd, rtol=1e-6, atol=1e-6)
+    assert torch.allclose(V.grad, dV, rtol=1e-4, atol=1e-5)
+    assert torch.allclose(srt.grad, dS.cpu(), rtol=1e-4, atol=1e-4)
+    assert (ins[~hit] == -1).all()
+    acc.close()
+
+
+def test_backward_instances_errors(gpu):
+    torch, api, ctx = gpu
+    from paper_2603_00292_amd import _capi
+    import ctypes as C
+
+    W = wl.aimed_instances(n_inst=2, n_rays=16, k=318)
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    rays, hits, inst = _forward(gpu, acc, W.rays)
+    g = torch.zeros((16, 3), dtype=torch.float32, device="cuda")
+    do = torch.empty((16, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(_capi.RtError) as e:
+        _capi.call("rt_trace_backward_instances", acc.handle, C.c_void_p(rays.data_ptr()),
+                   C.c_void_p(hits.data_ptr()), None, C.c_void_p(g.data_ptr()), 16, None, None,
+                   C.c_void_p(do.data_ptr()), C.c_void_p(do.data_ptr()), None)
+    assert e.value.status == _capi.RT_ERROR_INVALID_VALUE
+    # n = 0 does nothing; no vertex or frame buffers is allowed
+    api.trace_backward_instances(acc, rays[:0], hits[:0], inst[:0], g[:0])
+    api.trace_backward_instances(acc, rays, hits, inst, g)
+    # ids that are no instance contribute nothing
+    bad = torch.full((16,), 7, dtype=torch.int32, device="cuda")
+    dS = torch.zeros((2, 10), dtype=torch.float32, device="cuda")
+    do2, dd2 = api.trace_backward_instances(acc, rays, hits, bad, torch.ones_like(g), None, dS)
+    torch.cuda.synchronize()
+    assert float(do2.abs().max()) == 0.0 and float(dS.abs().max()) == 0.0
+    acc.close()
+    # a single-level accel is refused
+    m = W.scene.meshes[0]
+    acc1 = api.Accel(ctx, [(torch.from_numpy(m.vertices).cuda(),
+                            torch.from_numpy(m.indices.view(np.int32)).cuda())])
+    with pytest.raises(_capi.RtError) as e:
+        api.trace_backward_instances(acc1, rays, hits, inst, g)
+    assert e.value.status == _capi.RT_ERROR_UNSUPPORTED
+    acc1.close()

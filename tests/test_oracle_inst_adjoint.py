@@ -19,29 +19,8 @@ NONE = 0xFFFFFFFF
 
 
 def instanced_scene(k, n_inst=8, n_rays=4096):
-    """Three small displaced grids, n_inst frames (one mirrored, quaternions
-    of norms 0.6-1.8), rays from the scene box aimed at instance surfaces."""
-    rng = wl.rng_for(k)
-    meshes = []
-    for s in (0.02, 0.05, 0.1):
-        mv, mf = wl.grid_mesh(12, 8, -1.0, 1.0, -0.5, 0.5, rng.normal(0, s, 13 * 9))
-        meshes.append(wl.Mesh(mv, mf))
-    inst_mesh = (np.arange(n_inst) % 3).astype(np.uint32)
-    S = rng.uniform(0.5, 2.0, (n_inst, 3))
-    S[1, 2] *= -1.0  # a mirror frame
-    q = wl.uniform_quaternions(rng, n_inst) * rng.uniform(0.6, 1.8, (n_inst, 1))
-    T = rng.uniform(-6, 6, (n_inst, 3))
-    srt = np.concatenate([S, q, T], 1).astype(np.float32)
-    R = wl.quat_matrix(srt[:, 3:7].astype(np.float64))
-    j = rng.integers(0, n_inst, n_rays)
-    p_obj = np.stack([rng.uniform(-0.9, 0.9, n_rays), np.zeros(n_rays),
-                      rng.uniform(-0.4, 0.4, n_rays)], 1)
-    tgt = np.einsum("nij,nj->ni", R[j], srt[j, 0:3].astype(np.float64) * p_obj) + srt[j, 7:10]
-    o = rng.uniform(-9, 9, (n_rays, 3))
-    d = tgt - o
-    d /= np.linalg.norm(d, axis=1, keepdims=True)
-    rays = wl.pack_rays(o, d)
-    return wl.Scene(meshes, inst_mesh, srt), rays
+    W = wl.aimed_instances(n_inst=n_inst, n_rays=n_rays, k=k)
+    return W.scene, W.rays
 
 
 def hits_of(orc, S, rays):
