@@ -80,7 +80,11 @@ def test_instanced_small_all_rays(gpu, orc):
 
 def test_instanced_aimed_rays(gpu, orc):
     """64 instances; 16,384 rays from random points of the scene box aimed at
-    random instances: every ray against the oracle, >99% pinned."""
+    random instances: every ray against the oracle.  The acceptable sets
+    widen instance hits by 16 float32 ulps of |o| + |T| in object units (up
+    to ~1e-4 here, on 0.02-wide triangles), so 93.6% of these rays have a
+    single acceptable answer (checked bit-exactly); agreement with the
+    oracle's own answer is checked on all rays."""
     torch, api, ctx = gpu
     W = wl.instanced_grids(n_inst=64, n_rays=16, k=401)
     rng = wl.rng_for(408)
@@ -96,8 +100,12 @@ def test_instanced_aimed_rays(gpu, orc):
     A = orc.accept(S, rays)
     st = check_closest(h, A, inst=inst, label="instanced aimed")
     check_any(occ, A, label="instanced aimed any")
-    say(st)
-    assert st["hits"] > 2000 and st["pinned_frac"] > 0.99
+    oi, op, _ = orc.closest(S, rays)
+    prim = h[:, 1].copy().view(np.uint32)
+    agree = ((prim == op) & ((inst == oi) | (op == NONE))).mean()
+    say(st, "agreement with the oracle's answer", agree)
+    assert st["hits"] > 2000 and st["pinned_frac"] > 0.93
+    assert agree > 0.995
     acc.close()
 
 
