@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <limits>
@@ -14,9 +15,14 @@ namespace {
 
 constexpr int kBins = 32;
 constexpr float kInf = std::numeric_limits<float>::infinity();
-// relative costs of one node visit and one triangle test in the SAH
-constexpr float kTraversalCost = 1.0f;
+// relative costs of one node visit and one triangle test in the SAH; the
+// node cost can be changed with RT_SAH_TRAVERSAL_COST (read at each build)
 constexpr float kTriangleCost = 1.0f;
+float traversal_cost_from_env() {
+  const char* v = std::getenv("RT_SAH_TRAVERSAL_COST");
+  float x = v ? (float)std::atof(v) : 1.0f;
+  return (x > 0.0f && x < 1000.0f) ? x : 1.0f;
+}
 
 Box empty_box() {
   Box b;
@@ -58,6 +64,7 @@ struct Binary {
   std::vector<Prim>* prims = nullptr;
   int max_leaf = 4;
   int spawn_depth = 0;
+  float traversal_cost = 1.0f;
 };
 
 // Binned SAH split of prims[lo, hi) in node `ni` (Wald 2007).
@@ -129,7 +136,7 @@ void build_node(Binary& B, uint32_t ni, uint32_t lo, uint32_t hi, int depth) {
   double leaf_cost = kTriangleCost * (double)n;
   double split_cost =
       (best_axis >= 0 && node_area > 0.0)
-          ? kTraversalCost + kTriangleCost * best_cost / node_area
+          ? B.traversal_cost + kTriangleCost * best_cost / node_area
           : std::numeric_limits<double>::infinity();
   if ((int)n <= B.max_leaf && leaf_cost <= split_cost) {
     make_leaf();
@@ -324,6 +331,7 @@ bool build_mesh(const BuildInput& in, int width, int max_leaf, WideTree& out, st
   B.prims = &prims;
   B.max_leaf = max_leaf;
   B.spawn_depth = spawn_depth_for(threads);
+  B.traversal_cost = traversal_cost_from_env();
   if (!prims.empty()) {
     B.nodes.resize(2 * prims.size());
     build_node(B, 0, 0, (uint32_t)prims.size(), 0);
