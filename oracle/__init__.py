@@ -61,6 +61,11 @@ def _load():
         for name, args in {
             "orc_closest": [P, P, i64, P, P, P],
             "orc_any": [P, P, i64, P],
+            "orc_closest_ex": [P, P, i64, P, P, P, P],
+            "orc_any_ex": [P, P, i64, P, P],
+            "orc_all": [P, P, i64, P, C.c_int32, P, P, P, P],
+            "orc_accept_ex": [P, P, i64, P, C.c_double, C.c_int32, P, P, P, P, P, P, P],
+            "orc_classify_all": [P, P, i64, P, C.c_double, C.c_int32, P, P, P, P, P, P, P, P, P],
             "orc_accept": [P, P, i64, C.c_double, C.c_int32, P, P, P, P, P, P, P],
             "orc_adjoint": [P, P, P, i64, P, P, P, P],
             "orc_fd": [P, P, P, i64, P, C.c_double, P],
@@ -140,23 +145,105 @@ def _check(rc, name):
         raise ValueError(f"oracle {name}: invalid arguments")
 
 
-def closest(scene: OracleScene, rays):
+class _OptsC(C.Structure):
+    _fields_ = [("inst_mask", C.c_void_p), ("ray_mask", C.c_void_p), ("skip_inst", C.c_void_p),
+                ("skip_prim", C.c_void_p)]
+
+
+class Opts:
+    """Query options: instance masks (n_inst,), ray masks (n,) and the
+    per-ray skipped triangle (skip_inst, skip_prim) (n,) each; any may be
+    None.  See ``orc_opts`` in ``rt_oracle.h`` for the semantics."""
+
+    def __init__(self, inst_mask=None, ray_mask=None, skip_inst=None, skip_prim=None):
+        def u32(a):
+            return None if a is None else np.ascontiguousarray(a, dtype=np.uint32).reshape(-1)
+        self._a = [u32(inst_mask), u32(ray_mask), u32(skip_inst), u32(skip_prim)]
+        self.desc = _OptsC(*[a.ctypes.data if a is not None and a.size else None for a in self._a])
+
+    @property
+    def ptr(self):
+        return C.addressof(self.desc)
+
+    def check(self, n):
+        for a in self._a[1:]:
+            if a is not None and a.shape[0] != n:
+                raise ValueError("per-ray option arrays need one entry per ray")
+
+
+def _optp(opts, n):
+    if opts is None:
+        return None
+    opts.check(n)
+    return opts.ptr
+
+
+def closest(scene: OracleScene, rays, opts: Opts | None = None):
     """Returns (inst (n,) uint32, prim (n,) uint32, tuv (n,3) float64)."""
     lib = _load()
     r, n = _rays(rays)
     inst = np.empty(n, np.uint32)
     prim = np.empty(n, np.uint32)
     tuv = np.empty((n, 3), np.float64)
-    _check(lib.orc_closest(scene.ptr, _p(r), n, _p(inst), _p(prim), _p(tuv)), "closest")
+    if opts is None:
+        _check(lib.orc_closest(scene.ptr, _p(r), n, _p(inst), _p(prim), _p(tuv)), "closest")
+    else:
+        _check(lib.orc_closest_ex(scene.ptr, _p(r), n, _optp(opts, n), _p(inst), _p(prim), _p(tuv)),
+               "closest_ex")
     return inst, prim, tuv
 
 
-def any_hit(scene: OracleScene, rays):
+def any_hit(scene: OracleScene, rays, opts: Opts | None = None):
     lib = _load()
     r, n = _rays(rays)
     occ = np.empty(n, np.uint8)
-    _check(lib.orc_any(scene.ptr, _p(r), n, _p(occ)), "any")
+    if opts is None:
+        _check(lib.orc_any(scene.ptr, _p(r), n, _p(occ)), "any")
+    else:
+        _check(lib.orc_any_ex(scene.ptr, _p(r), n, _optp(opts, n), _p(occ)), "any_ex")
     return occ
+
+
+def all_hits(scene: OracleScene, rays, K: int, opts: Opts | None = None):
+    """All hits sorted by (t, inst, prim): (count (n,) int64, inst (n,K),
+    prim (n,K) uint32, tuv (n,K,3) float64), the first K stored."""
+    lib = _load()
+    r, n = _rays(rays)
+    count = np.empty(n, np.int64)
+    inst = np.empty((n, K), np.uint32)
+    prim = np.empty((n, K), np.uint32)
+    tuv = np.empty((n, K, 3), np.float64)
+    _check(lib.orc_all(scene.ptr, _p(r), n, _optp(opts, n), int(K), _p(count), _p(inst), _p(prim),
+                       _p(tuv)), "all")
+    return count, inst, prim, tuv
+
+
+class Candidates:
+    """Every sure-or-maybe pair per ray for all-hit queries, sorted by
+    (t, inst, prim), with the range [lo, hi] of its float32 t."""
+
+    def __init__(self, count, n_sure, inst, prim, tuv, scale, lo, hi, sure, K):
+        self.count, self.n_sure, self.inst, self.prim = count, n_sure, inst, prim
+        self.tuv, self.scale, self.lo, self.hi, self.sure, self.K = tuv, scale, lo, hi, sure, K
+
+
+def classify_all(scene: OracleScene, rays, K: int, opts: Opts | None = None,
+                 delta: float = DELTA) -> Candidates:
+    lib = _load()
+    r, n = _rays(rays)
+    count = np.empty(n, np.int32)
+    n_sure = np.empty(n, np.int32)
+    ai = np.empty((n, K), np.uint32)
+    ap = np.empty((n, K), np.uint32)
+    at = np.empty((n, K, 3), np.float64)
+    asc = np.empty((n, K), np.float64)
+    lo = np.empty((n, K), np.float64)
+    hi = np.empty((n, K), np.float64)
+    su = np.empty((n, K), np.uint8)
+    _check(lib.orc_classify_all(scene.ptr, _p(r), n, _optp(opts, n), float(delta), int(K), _p(count),
+                                _p(n_sure), _p(ai), _p(ap), _p(at), _p(asc), _p(lo), _p(hi), _p(su)),
+           "classify_all")
+    return Candidates(count, n_sure, ai, ap, at, asc, lo, hi, su.astype(bool), K)
 
 
 class Accept:
@@ -175,7 +262,8 @@ class Accept:
         return self.count > self.K
 
 
-def accept(scene: OracleScene, rays, delta: float = DELTA, K: int = 8) -> Accept:
+def accept(scene: OracleScene, rays, delta: float = DELTA, K: int = 8,
+           opts: Opts | None = None) -> Accept:
     lib = _load()
     r, n = _rays(rays)
     miss_ok = np.empty(n, np.uint8)
@@ -185,8 +273,13 @@ def accept(scene: OracleScene, rays, delta: float = DELTA, K: int = 8) -> Accept
     at = np.empty((n, K, 3), np.float64)
     asc = np.empty((n, K), np.float64)
     ac = np.empty(n, np.uint8)
-    _check(lib.orc_accept(scene.ptr, _p(r), n, float(delta), int(K), _p(miss_ok), _p(count),
-                          _p(ai), _p(ap), _p(at), _p(asc), _p(ac)), "accept")
+    if opts is None:
+        _check(lib.orc_accept(scene.ptr, _p(r), n, float(delta), int(K), _p(miss_ok), _p(count),
+                              _p(ai), _p(ap), _p(at), _p(asc), _p(ac)), "accept")
+    else:
+        _check(lib.orc_accept_ex(scene.ptr, _p(r), n, _optp(opts, n), float(delta), int(K),
+                                 _p(miss_ok), _p(count), _p(ai), _p(ap), _p(at), _p(asc), _p(ac)),
+               "accept_ex")
     return Accept(miss_ok.astype(bool), count, ai, ap, at, asc, ac, K)
 
 

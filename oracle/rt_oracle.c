@@ -243,8 +243,22 @@ static void plane_tuv(vec3 o, vec3 d, vec3 v0, vec3 v1, vec3 v2, double* t_out, 
 
 static int64_t n_units(const orc_scene* s) { return s->n_inst > 0 ? s->n_inst : 1; }
 
-int orc_closest(const orc_scene* s, const float* rays, int64_t nr, uint32_t* inst_out,
-                uint32_t* prim_out, double* tuv_out) {
+/* Query options (masks and the self-intersection filter); see the header. */
+static int unit_enabled(const orc_scene* s, const orc_opts* o, int64_t r, int64_t j) {
+  if (!o || !o->ray_mask) return 1;
+  uint32_t m = (s->n_inst > 0 && o->inst_mask) ? o->inst_mask[j] : 0xFFFFFFFFu;
+  return (m & o->ray_mask[r]) != 0u;
+}
+
+static int skipped(const orc_scene* s, const orc_opts* o, int64_t r, int64_t j, int64_t k) {
+  if (!o || !o->skip_prim || o->skip_prim[r] == ORC_NONE) return 0;
+  if ((uint32_t)k != o->skip_prim[r]) return 0;
+  if (s->n_inst > 0 && o->skip_inst && (uint32_t)j != o->skip_inst[r]) return 0;
+  return 1;
+}
+
+int orc_closest_ex(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts,
+                   uint32_t* inst_out, uint32_t* prim_out, double* tuv_out) {
   if (nr < 0 || (nr > 0 && (!rays || !prim_out || !tuv_out)) || !scene_valid(s)) return -1;
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t r = 0; r < nr; ++r) {
@@ -253,6 +267,7 @@ int orc_closest(const orc_scene* s, const float* rays, int64_t nr, uint32_t* ins
     uint32_t bi = ORC_NONE, bp = ORC_NONE;
     if (!ray_is_void(&w)) {
       for (int64_t j = 0; j < n_units(s); ++j) {
+        if (!unit_enabled(s, opts, r, j)) continue;
         ray64 q;
         int m;
         double xs, xd;
@@ -260,6 +275,7 @@ int orc_closest(const orc_scene* s, const float* rays, int64_t nr, uint32_t* ins
         for (int64_t k = 0; k < s->n_triangles[m]; ++k) {
           vec3 v0, v1, v2;
           double t, u, v;
+          if (skipped(s, opts, r, j, k)) continue;
           tri(s, m, k, &v0, &v1, &v2);
           if (intersect_paper(&q, v0, v1, v2, &t, &u, &v) && t < minT) {
             minT = t; bu = u; bv = v;
@@ -277,7 +293,13 @@ int orc_closest(const orc_scene* s, const float* rays, int64_t nr, uint32_t* ins
   return 0;
 }
 
-int orc_any(const orc_scene* s, const float* rays, int64_t nr, uint8_t* occluded) {
+int orc_closest(const orc_scene* s, const float* rays, int64_t nr, uint32_t* inst_out,
+                uint32_t* prim_out, double* tuv_out) {
+  return orc_closest_ex(s, rays, nr, NULL, inst_out, prim_out, tuv_out);
+}
+
+int orc_any_ex(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts,
+               uint8_t* occluded) {
   if (nr < 0 || (nr > 0 && (!rays || !occluded)) || !scene_valid(s)) return -1;
 #pragma omp parallel for schedule(dynamic, 16)
   for (int64_t r = 0; r < nr; ++r) {
@@ -285,6 +307,7 @@ int orc_any(const orc_scene* s, const float* rays, int64_t nr, uint8_t* occluded
     int hit = 0;
     if (!ray_is_void(&w)) {
       for (int64_t j = 0; j < n_units(s) && !hit; ++j) {
+        if (!unit_enabled(s, opts, r, j)) continue;
         ray64 q;
         int m;
         double xs, xd;
@@ -292,6 +315,7 @@ int orc_any(const orc_scene* s, const float* rays, int64_t nr, uint8_t* occluded
         for (int64_t k = 0; k < s->n_triangles[m]; ++k) {
           vec3 v0, v1, v2;
           double t, u, v;
+          if (skipped(s, opts, r, j, k)) continue;
           tri(s, m, k, &v0, &v1, &v2);
           if (intersect_paper(&q, v0, v1, v2, &t, &u, &v)) { hit = 1; break; }
         }
@@ -300,6 +324,92 @@ int orc_any(const orc_scene* s, const float* rays, int64_t nr, uint8_t* occluded
     occluded[r] = (uint8_t)hit;
   }
   return 0;
+}
+
+int orc_any(const orc_scene* s, const float* rays, int64_t nr, uint8_t* occluded) {
+  return orc_any_ex(s, rays, nr, NULL, occluded);
+}
+
+/* All hits of §6.2's enumeration ("all intersections"): every pair the §3.1
+ * test accepts within [tmin, tmax], sorted by (t, inst, prim). */
+typedef struct {
+  double t, u, v;
+  uint32_t inst, prim;
+} hit64;
+
+static int hit_less(const hit64* a, const hit64* b) {
+  if (a->t != b->t) return a->t < b->t;
+  if (a->inst != b->inst) return a->inst < b->inst;
+  return a->prim < b->prim;
+}
+
+int orc_all(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts, int32_t K,
+            int64_t* count, uint32_t* inst_out, uint32_t* prim_out, double* tuv_out) {
+  if (nr < 0 || K < 1 || !scene_valid(s)) return -1;
+  if (nr > 0 && (!rays || !count || !prim_out || !tuv_out)) return -1;
+  int bad = 0;
+#pragma omp parallel
+  {
+    int64_t cap = 64;
+    hit64* buf = (hit64*)malloc(sizeof(hit64) * cap);
+    if (!buf) {
+#pragma omp atomic write
+      bad = 1;
+    }
+#pragma omp for schedule(dynamic, 8)
+    for (int64_t r = 0; r < nr; ++r) {
+      if (!buf) continue;
+      int64_t n = 0;
+      ray64 w = load_ray(rays + 8 * r);
+      if (!ray_is_void(&w)) {
+        for (int64_t j = 0; j < n_units(s); ++j) {
+          if (!unit_enabled(s, opts, r, j)) continue;
+          ray64 q;
+          int m;
+          double xs, xd;
+          object_ray(s, &w, j, &q, &m, &xs, &xd);
+          for (int64_t k = 0; k < s->n_triangles[m]; ++k) {
+            vec3 v0, v1, v2;
+            hit64 h;
+            if (skipped(s, opts, r, j, k)) continue;
+            tri(s, m, k, &v0, &v1, &v2);
+            if (!intersect_paper(&q, v0, v1, v2, &h.t, &h.u, &h.v)) continue;
+            h.inst = s->n_inst > 0 ? (uint32_t)j : 0u;
+            h.prim = (uint32_t)k;
+            if (n == cap) {
+              hit64* nb = (hit64*)realloc(buf, sizeof(hit64) * cap * 2);
+              if (!nb) {
+#pragma omp atomic write
+                bad = 1;
+                continue;
+              }
+              buf = nb;
+              cap *= 2;
+            }
+            buf[n++] = h;
+          }
+        }
+      }
+      for (int64_t i = 1; i < n; ++i) {
+        hit64 x = buf[i];
+        int64_t jj = i - 1;
+        while (jj >= 0 && hit_less(&x, &buf[jj])) { buf[jj + 1] = buf[jj]; --jj; }
+        buf[jj + 1] = x;
+      }
+      count[r] = n;
+      for (int64_t i = 0; i < K; ++i) {
+        int64_t o = r * K + i;
+        int in = i < n;
+        if (inst_out) inst_out[o] = in ? buf[i].inst : ORC_NONE;
+        prim_out[o] = in ? buf[i].prim : ORC_NONE;
+        tuv_out[3 * o + 0] = in ? buf[i].t : INFINITY;
+        tuv_out[3 * o + 1] = in ? buf[i].u : 0.0;
+        tuv_out[3 * o + 2] = in ? buf[i].v : 0.0;
+      }
+    }
+    free(buf);
+  }
+  return bad ? -1 : 0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -333,7 +443,7 @@ int orc_any(const orc_scene* s, const float* rays, int64_t nr, uint8_t* occluded
  * when there is no sure hit. */
 
 typedef struct {
-  double t, u, v, lo, scale;
+  double t, u, v, lo, hi, scale;
   uint32_t inst, prim;
   int sure;
 } cand;
@@ -424,7 +534,7 @@ static int classify(const ray64* q, vec3 v0, vec3 v1, vec3 v2, double delta, dou
   c->v = v;
   c->scale = s;
   c->lo = tlo;
-  *hi = INFINITY;
+  *hi = thi;
   if (crosses && isfinite(rt)) {
     double need = eta / cs + eta;
     vec3 p = add(q->o, scl(q->d, t));
@@ -441,13 +551,20 @@ static int classify(const ray64* q, vec3 v0, vec3 v1, vec3 v2, double delta, dou
   return 1;
 }
 
-int orc_accept(const orc_scene* s, const float* rays, int64_t nr, double delta, int32_t K,
-               uint8_t* miss_ok, int32_t* count, uint32_t* acc_inst, uint32_t* acc_prim,
-               double* acc_tuv, double* acc_scale, uint8_t* any_class) {
+/* The candidates (sure and maybe pairs) of every ray, with the range
+ * [lo, hi] their float32 t may take.  mode 0: the acceptable closest answers
+ * (pairs whose lowest possible t does not exceed t*); mode 1: every
+ * candidate (all-hit queries). */
+static int accept_impl(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts,
+                       double delta, int32_t K, int mode, uint8_t* miss_ok, int32_t* count,
+                       int32_t* n_sure, uint32_t* acc_inst, uint32_t* acc_prim, double* acc_tuv,
+                       double* acc_scale, double* acc_lo, double* acc_hi, uint8_t* acc_sure,
+                       uint8_t* any_class) {
   if (nr < 0 || K < 1 || !scene_valid(s)) return -1;
   if (nr > 0 && (!rays || !miss_ok || !count || !acc_inst || !acc_prim || !acc_tuv ||
                  !acc_scale || !any_class))
     return -1;
+  if (mode != 0 && mode != 1) return -1;
   int bad = 0;
 #pragma omp parallel
   {
@@ -462,10 +579,11 @@ int orc_accept(const orc_scene* s, const float* rays, int64_t nr, double delta, 
       if (!buf) continue;
       ray64 w = load_ray(rays + 8 * r);
       double tstar = INFINITY;
-      int any_sure = 0;
+      int any_sure = 0, sures = 0;
       n = 0;
       if (!ray_is_void(&w)) {
         for (int64_t j = 0; j < n_units(s); ++j) {
+          if (!unit_enabled(s, opts, r, j)) continue;
           ray64 q;
           int m;
           double xs, xd;
@@ -473,6 +591,7 @@ int orc_accept(const orc_scene* s, const float* rays, int64_t nr, double delta, 
           for (int64_t k = 0; k < s->n_triangles[m]; ++k) {
             vec3 v0, v1, v2;
             cand c;
+            if (skipped(s, opts, r, j, k)) continue;
             tri(s, m, k, &v0, &v1, &v2);
             double hi;
             int cls = classify(&q, v0, v1, v2, delta, xs, xd, &c, &hi);
@@ -480,8 +599,10 @@ int orc_accept(const orc_scene* s, const float* rays, int64_t nr, double delta, 
             c.inst = s->n_inst > 0 ? (uint32_t)j : 0u;
             c.prim = (uint32_t)k;
             c.sure = (cls == 2);
+            c.hi = hi;
             if (c.sure) {
               any_sure = 1;
+              ++sures;
               if (hi < tstar) tstar = hi;
             }
             if (n == cap) {
@@ -497,7 +618,7 @@ int orc_accept(const orc_scene* s, const float* rays, int64_t nr, double delta, 
       /* keep the candidates that can still be the closest, sorted by (t, inst, prim) */
       int64_t kept = 0;
       for (int64_t i = 0; i < n; ++i)
-        if (!(buf[i].lo > tstar)) buf[kept++] = buf[i];
+        if (mode == 1 || !(buf[i].lo > tstar)) buf[kept++] = buf[i];
       for (int64_t i = 1; i < kept; ++i) {
         cand x = buf[i];
         int64_t jj = i - 1;
@@ -506,6 +627,7 @@ int orc_accept(const orc_scene* s, const float* rays, int64_t nr, double delta, 
       }
       miss_ok[r] = (uint8_t)(!any_sure);
       count[r] = (int32_t)kept;
+      if (n_sure) n_sure[r] = sures;
       any_class[r] = any_sure ? 1 : (n == 0 ? 0 : 2);
       for (int64_t i = 0; i < K; ++i) {
         int64_t o = r * K + i;
@@ -516,6 +638,9 @@ int orc_accept(const orc_scene* s, const float* rays, int64_t nr, double delta, 
           acc_tuv[3 * o + 1] = buf[i].u;
           acc_tuv[3 * o + 2] = buf[i].v;
           acc_scale[o] = buf[i].scale;
+          if (acc_lo) acc_lo[o] = buf[i].lo;
+          if (acc_hi) acc_hi[o] = buf[i].hi;
+          if (acc_sure) acc_sure[o] = (uint8_t)buf[i].sure;
         } else {
           acc_inst[o] = ORC_NONE;
           acc_prim[o] = ORC_NONE;
@@ -523,12 +648,50 @@ int orc_accept(const orc_scene* s, const float* rays, int64_t nr, double delta, 
           acc_tuv[3 * o + 1] = 0.0;
           acc_tuv[3 * o + 2] = 0.0;
           acc_scale[o] = 0.0;
+          if (acc_lo) acc_lo[o] = INFINITY;
+          if (acc_hi) acc_hi[o] = INFINITY;
+          if (acc_sure) acc_sure[o] = 0;
         }
       }
     }
     free(buf);
   }
   return bad ? -1 : 0;
+}
+
+
+int orc_accept(const orc_scene* s, const float* rays, int64_t nr, double delta, int32_t K,
+               uint8_t* miss_ok, int32_t* count, uint32_t* acc_inst, uint32_t* acc_prim,
+               double* acc_tuv, double* acc_scale, uint8_t* any_class) {
+  return accept_impl(s, rays, nr, NULL, delta, K, 0, miss_ok, count, NULL, acc_inst, acc_prim,
+                     acc_tuv, acc_scale, NULL, NULL, NULL, any_class);
+}
+
+int orc_accept_ex(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts,
+                  double delta, int32_t K, uint8_t* miss_ok, int32_t* count,
+                  uint32_t* acc_inst, uint32_t* acc_prim, double* acc_tuv, double* acc_scale,
+                  uint8_t* any_class) {
+  return accept_impl(s, rays, nr, opts, delta, K, 0, miss_ok, count, NULL, acc_inst, acc_prim,
+                     acc_tuv, acc_scale, NULL, NULL, NULL, any_class);
+}
+
+int orc_classify_all(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts,
+                     double delta, int32_t K, int32_t* count, int32_t* n_sure, uint32_t* acc_inst,
+                     uint32_t* acc_prim, double* acc_tuv, double* acc_scale, double* acc_lo,
+                     double* acc_hi, uint8_t* acc_sure) {
+  if (nr > 0 && (!n_sure || !acc_lo || !acc_hi || !acc_sure)) return -1;
+  uint8_t* miss_ok = nr > 0 ? (uint8_t*)malloc((size_t)nr) : NULL;
+  uint8_t* any_class = nr > 0 ? (uint8_t*)malloc((size_t)nr) : NULL;
+  if (nr > 0 && (!miss_ok || !any_class)) {
+    free(miss_ok);
+    free(any_class);
+    return -1;
+  }
+  int rc = accept_impl(s, rays, nr, opts, delta, K, 1, miss_ok, count, n_sure, acc_inst, acc_prim,
+                       acc_tuv, acc_scale, acc_lo, acc_hi, acc_sure, any_class);
+  free(miss_ok);
+  free(any_class);
+  return rc;
 }
 
 /* ------------------------------------------------------------------------- */

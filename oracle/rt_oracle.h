@@ -43,13 +43,42 @@ typedef struct {
   const float* inst_srt;          /* [n_inst*10] */
 } orc_scene;
 
+/* Query options.  §7.5 names ray masks and intersection filters as options
+ * of a traversal without fixing their semantics; the readings here:
+ *   ray r may hit instance j only when ray_mask[r] & inst_mask[j] != 0 (a
+ *     single-level scene is one geometry of mask 0xFFFFFFFF, so a zero ray
+ *     mask hits nothing);
+ *   ray r ignores the one triangle (skip_inst[r], skip_prim[r]) (the
+ *     self-intersection filter of a ray leaving a surface); skip_prim[r] =
+ *     ORC_NONE filters nothing and skip_inst is not used in single-level
+ *     scenes.
+ * Any pointer may be NULL (no masks, no filter). */
+typedef struct {
+  const uint32_t* inst_mask;  /* [n_inst] */
+  const uint32_t* ray_mask;   /* [nr] */
+  const uint32_t* skip_inst;  /* [nr] */
+  const uint32_t* skip_prim;  /* [nr] */
+} orc_opts;
+
 /* Closest hit: lexicographic minimum of (t, inst, prim) over all hits.
  * Miss: inst = prim = ORC_NONE, t = +inf, u = v = 0.  inst_out may be NULL. */
 int orc_closest(const orc_scene* s, const float* rays, int64_t nr,
                 uint32_t* inst_out, uint32_t* prim_out, double* tuv_out /* nr*3 */);
 
+int orc_closest_ex(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts,
+                   uint32_t* inst_out, uint32_t* prim_out, double* tuv_out);
+
 /* Any hit: 1 when some triangle is hit with t in [tmin, tmax]. */
 int orc_any(const orc_scene* s, const float* rays, int64_t nr, uint8_t* occluded);
+int orc_any_ex(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts,
+               uint8_t* occluded);
+
+/* All hits (§6.2: the stack traversal finds the nearest, any or all
+ * intersections): every (inst, prim) hit within [tmin, tmax], sorted by
+ * (t, inst, prim).  count[r] = number of hits; the first K are stored
+ * (inst/prim ORC_NONE, t = +inf beyond the count).  inst_out may be NULL. */
+int orc_all(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts, int32_t K,
+            int64_t* count, uint32_t* inst_out, uint32_t* prim_out, double* tuv_out /* nr*K*3 */);
 
 /* Acceptable sets of the FP32 tolerance model (delta = relative slack).
  * For each ray: miss_ok (1 when no pair is a sure hit), count (number of
@@ -61,6 +90,20 @@ int orc_accept(const orc_scene* s, const float* rays, int64_t nr, double delta, 
                uint8_t* miss_ok, int32_t* count, uint32_t* acc_inst /* nr*K */,
                uint32_t* acc_prim /* nr*K */, double* acc_tuv /* nr*K*3 */,
                double* acc_scale /* nr*K */, uint8_t* any_class);
+
+int orc_accept_ex(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts,
+                  double delta, int32_t K, uint8_t* miss_ok, int32_t* count,
+                  uint32_t* acc_inst, uint32_t* acc_prim, double* acc_tuv, double* acc_scale,
+                  uint8_t* any_class);
+
+/* Every candidate of the tolerance model for all-hit queries: count[r]
+ * sure-or-maybe pairs (n_sure[r] of them sure), sorted by (t, inst, prim),
+ * with the range [lo, hi] a float32 t of the pair may take; the first K are
+ * stored. */
+int orc_classify_all(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts,
+                     double delta, int32_t K, int32_t* count, int32_t* n_sure, uint32_t* acc_inst,
+                     uint32_t* acc_prim, double* acc_tuv, double* acc_scale, double* acc_lo,
+                     double* acc_hi, uint8_t* acc_sure);
 
 /* Adjoint of (t,u,v) at fixed triangles, single-level scenes only.
  * prim[r] = ORC_NONE contributes nothing.  g = dL/d(t,u,v) per ray (nr*3).
