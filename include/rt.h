@@ -184,6 +184,61 @@ rt_status rt_trace_closest(rt_accel accel, const rt_ray* rays, uint32_t n, rt_hi
 rt_status rt_trace_any(rt_accel accel, const rt_ray* rays, uint32_t n, uint8_t* occluded,
                        void* stream);
 
+/* ---- query variants (§6.2: a stack traversal finds the nearest, any or
+ * all intersections; §7.5 names ray masks and intersection filters) ------- */
+
+/* Options of the _ex and all-hit queries (all DEVICE arrays of n entries;
+ * each may be NULL):
+ *   ray_masks: ray i may hit instance j only when ray_masks[i] & mask_j != 0
+ *     (instance masks default to 0xFFFFFFFF, see
+ *     rt_accel_set_instance_masks; a single-level accel is one geometry of
+ *     mask 0xFFFFFFFF, so a zero ray mask hits nothing).  NULL: all ones.
+ *   skip_prim / skip_inst: ray i ignores the one triangle
+ *     (skip_inst[i], skip_prim[i]), e.g. the triangle a secondary ray leaves
+ *     (self-intersection filter).  skip_prim[i] = RT_INVALID_ID filters
+ *     nothing; skip_inst is not read for single-level accels and may be NULL
+ *     for them.  For a two-level accel with skip_prim set, skip_inst is
+ *     required. */
+typedef struct rt_query_options {
+  const uint32_t* ray_masks;
+  const uint32_t* skip_inst;
+  const uint32_t* skip_prim;
+} rt_query_options;
+
+/* Largest list length of rt_trace_all. */
+#define RT_MAX_HIT_CAPACITY 64u
+
+/* Sets the visibility masks of a two-level accel's instances (masks: HOST
+ * array of instance_count entries).  Returns after the update is visible to
+ * later queries on any stream.  Errors: RT_ERROR_UNSUPPORTED on a
+ * single-level accel; RT_ERROR_INVALID_VALUE for NULL masks. */
+rt_status rt_accel_set_instance_masks(rt_accel accel, const uint32_t* masks, void* stream);
+
+/* rt_trace_closest / rt_trace_any with options (NULL options: none).  These
+ * queries run the stack-16 / workgroup-256 variant of the context's node
+ * width whatever the context's variant is. */
+rt_status rt_trace_closest_ex(rt_accel accel, const rt_ray* rays, uint32_t n,
+                              const rt_query_options* options, rt_hit* hits, uint32_t* inst_ids,
+                              void* stream);
+rt_status rt_trace_any_ex(rt_accel accel, const rt_ray* rays, uint32_t n,
+                          const rt_query_options* options, uint8_t* occluded, void* stream);
+
+/* All hits: for each ray, every triangle hit with t in [tmin, tmax] (after
+ * masks and the filter) is counted in counts[i] (DEVICE, n uint32), and the
+ * `capacity` nearest, sorted by (t, instance, prim_id), are written to
+ * hits[i * capacity + k] (DEVICE, n * capacity records; entries past
+ * min(counts[i], capacity) are misses: t = +inf, prim_id = RT_INVALID_ID)
+ * with t, u, v as for rt_trace_closest; inst_ids (DEVICE, n * capacity,
+ * nullable) gets the instance of each entry.  The traversal does not stop
+ * at the nearest hit: its cost grows with the number of boxes the whole ray
+ * crosses.  Runs the stack-16 / workgroup-256 variant.
+ * Errors: RT_ERROR_INVALID_VALUE for capacity outside
+ * [1, RT_MAX_HIT_CAPACITY], n * capacity >= 2^31, NULL buffers with n > 0,
+ * rays/hits not 16-byte aligned. */
+rt_status rt_trace_all(rt_accel accel, const rt_ray* rays, uint32_t n,
+                       const rt_query_options* options, uint32_t capacity, rt_hit* hits,
+                       uint32_t* inst_ids, uint32_t* counts, void* stream);
+
 /* Adjoint of the closest hit at fixed triangles (single-level accels).
  * For each ray with hits[i].prim_id != RT_INVALID_ID and g = d_tuv[3i..3i+2]
  * = dL/d(t,u,v): with M = [-d | v1-v0 | v2-v0] and lambda = M^-T g,

@@ -25,6 +25,7 @@ EXPORTS = [
     "rt_context_create", "rt_context_destroy", "rt_context_set_variant", "rt_context_get_variant",
     "rt_build", "rt_accel_destroy", "rt_accel_get_info",
     "rt_trace_closest", "rt_trace_any", "rt_trace_backward", "rt_trace_backward_instances",
+    "rt_trace_closest_ex", "rt_trace_any_ex", "rt_trace_all", "rt_accel_set_instance_masks",
     "rt_trace_counters", "rt_refit",
     "rt_autotune",
     "rt_batch_plan_create", "rt_batch_plan_launch", "rt_batch_plan_graph", "rt_batch_plan_destroy",
@@ -57,6 +58,13 @@ class rt_build_options(C.Structure):
 
 class rt_variant(C.Structure):
     _fields_ = [("stack_entries", C.c_uint32), ("workgroup", C.c_uint32)]
+
+
+class rt_query_options(C.Structure):
+    _fields_ = [("ray_masks", C.c_void_p), ("skip_inst", C.c_void_p), ("skip_prim", C.c_void_p)]
+
+
+RT_MAX_HIT_CAPACITY = 64
 
 
 class rt_tune_entry(C.Structure):
@@ -101,6 +109,10 @@ def load():
             "rt_trace_backward": [P, P, P, P, U32, P, P, P, P],
             "rt_trace_backward_instances": [P, P, P, P, P, U32, P, P, P, P, P],
             "rt_trace_counters": [P, P, U32, I32, P, P, P, P],
+            "rt_trace_closest_ex": [P, P, U32, P, P, P, P],
+            "rt_trace_any_ex": [P, P, U32, P, P, P],
+            "rt_trace_all": [P, P, U32, P, U32, P, P, P, P],
+            "rt_accel_set_instance_masks": [P, P, P],
             "rt_refit": [P, P, P],
             "rt_autotune": [P, P, P, U32, U32, P, P, P, U32, P],
             "rt_batch_plan_create": [P, P, P, P, P, U32, P],

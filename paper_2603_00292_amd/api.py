@@ -60,6 +60,17 @@ class Context:
         v = capi.rt_variant(int(stack_entries), int(workgroup))
         capi.call("rt_context_set_variant", self.handle, C.byref(v))
 
+    def set_instance_masks(self, masks) -> None:
+        """Visibility masks of the instances (host array, one uint32 each),
+        ANDed with the ray masks of the _ex and all-hit queries."""
+        import numpy as np
+
+        m = np.ascontiguousarray(np.asarray(masks), dtype=np.uint32).reshape(-1)
+        if m.shape[0] != self.instance_count:
+            raise ValueError(f"need {self.instance_count} masks, got {m.shape[0]}")
+        capi.call("rt_accel_set_instance_masks", self.handle, C.c_void_p(m.ctypes.data),
+                  C.c_void_p(_stream()))
+
     def close(self):
         if self.handle:
             capi.call("rt_context_destroy", self.handle)
@@ -126,6 +137,17 @@ class Accel:
             raise ValueError(f"refit needs {self.vertex_count} vertices, got {vertices.shape[0]}")
         capi.call("rt_refit", self.handle, _ptr(vertices), C.c_void_p(_stream()))
 
+    def set_instance_masks(self, masks) -> None:
+        """Visibility masks of the instances (host array, one uint32 each),
+        ANDed with the ray masks of the _ex and all-hit queries."""
+        import numpy as np
+
+        m = np.ascontiguousarray(np.asarray(masks), dtype=np.uint32).reshape(-1)
+        if m.shape[0] != self.instance_count:
+            raise ValueError(f"need {self.instance_count} masks, got {m.shape[0]}")
+        capi.call("rt_accel_set_instance_masks", self.handle, C.c_void_p(m.ctypes.data),
+                  C.c_void_p(_stream()))
+
     def close(self):
         if self.handle:
             capi.call("rt_accel_destroy", self.handle)
@@ -142,6 +164,66 @@ def trace_closest(accel: Accel, rays: torch.Tensor, want_inst: bool = False):
     capi.call("rt_trace_closest", accel.handle, _ptr(rays), n, _ptr(hits), _ptr(inst),
               C.c_void_p(_stream()))
     return hits, inst
+
+
+def _u32_vec(t, n, name):
+    if t is None:
+        return None
+    if t.dtype not in (torch.int32, torch.uint32) or not t.is_contiguous() or t.device.type != "cuda" \
+            or t.shape != (n,):
+        raise ValueError(f"{name} must be a contiguous ({n},) int32 cuda tensor")
+    return t
+
+
+def _options(n, ray_masks, skip_inst, skip_prim):
+    """rt_query_options for per-ray tensors (kept alive by the caller)."""
+    if ray_masks is None and skip_inst is None and skip_prim is None:
+        return None
+    o = capi.rt_query_options()
+    for f, t in (("ray_masks", ray_masks), ("skip_inst", skip_inst), ("skip_prim", skip_prim)):
+        t = _u32_vec(t, n, f)
+        setattr(o, f, t.data_ptr() if t is not None and t.numel() else None)
+    return o
+
+
+def trace_closest_ex(accel: Accel, rays: torch.Tensor, ray_masks=None, skip_inst=None,
+                     skip_prim=None, want_inst: bool = False):
+    """rt_trace_closest_ex: closest hits under ray masks and the per-ray
+    skipped triangle; returns (hits (n,4), inst_ids (n,) or None)."""
+    _require(rays, "rays", torch.float32, 8)
+    n = rays.shape[0]
+    opts = _options(n, ray_masks, skip_inst, skip_prim)
+    hits = torch.empty((n, 4), dtype=torch.float32, device=rays.device)
+    inst = torch.empty((n,), dtype=torch.int32, device=rays.device) if want_inst else None
+    capi.call("rt_trace_closest_ex", accel.handle, _ptr(rays), n, C.byref(opts) if opts else None,
+              _ptr(hits), _ptr(inst), C.c_void_p(_stream()))
+    return hits, inst
+
+
+def trace_any_ex(accel: Accel, rays: torch.Tensor, ray_masks=None, skip_inst=None, skip_prim=None):
+    _require(rays, "rays", torch.float32, 8)
+    n = rays.shape[0]
+    opts = _options(n, ray_masks, skip_inst, skip_prim)
+    occ = torch.empty((n,), dtype=torch.uint8, device=rays.device)
+    capi.call("rt_trace_any_ex", accel.handle, _ptr(rays), n, C.byref(opts) if opts else None,
+              _ptr(occ), C.c_void_p(_stream()))
+    return occ
+
+
+def trace_all(accel: Accel, rays: torch.Tensor, capacity: int, ray_masks=None, skip_inst=None,
+              skip_prim=None, want_inst: bool = False):
+    """rt_trace_all: per ray, the number of hits and the `capacity` nearest
+    sorted by (t, instance, prim).  Returns (hits (n, capacity, 4),
+    inst_ids (n, capacity) or None, counts (n,) int32)."""
+    _require(rays, "rays", torch.float32, 8)
+    n = rays.shape[0]
+    opts = _options(n, ray_masks, skip_inst, skip_prim)
+    hits = torch.empty((n, capacity, 4), dtype=torch.float32, device=rays.device)
+    inst = torch.empty((n, capacity), dtype=torch.int32, device=rays.device) if want_inst else None
+    counts = torch.empty((n,), dtype=torch.int32, device=rays.device)
+    capi.call("rt_trace_all", accel.handle, _ptr(rays), n, C.byref(opts) if opts else None,
+              int(capacity), _ptr(hits), _ptr(inst), _ptr(counts), C.c_void_p(_stream()))
+    return hits, inst, counts
 
 
 def hit_fields(hits: torch.Tensor):
@@ -331,6 +413,17 @@ class BatchPlan:
         g = C.c_void_p()
         capi.call("rt_batch_plan_graph", self.handle, C.c_void_p(int(stream.cuda_stream)), C.byref(g))
         return int(g.value)
+
+    def set_instance_masks(self, masks) -> None:
+        """Visibility masks of the instances (host array, one uint32 each),
+        ANDed with the ray masks of the _ex and all-hit queries."""
+        import numpy as np
+
+        m = np.ascontiguousarray(np.asarray(masks), dtype=np.uint32).reshape(-1)
+        if m.shape[0] != self.instance_count:
+            raise ValueError(f"need {self.instance_count} masks, got {m.shape[0]}")
+        capi.call("rt_accel_set_instance_masks", self.handle, C.c_void_p(m.ctypes.data),
+                  C.c_void_p(_stream()))
 
     def close(self):
         if self.handle:

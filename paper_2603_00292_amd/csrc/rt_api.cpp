@@ -116,6 +116,7 @@ struct rt_accel_s {
   uint32_t instance_count = 0;
   std::vector<void*> owned;                  // every device allocation
   std::vector<rt_mesh_dev> host_meshes;      // device pointers, host copy
+  std::vector<rt_inst_rec> host_insts;       // two-level: host copy of the instance records
   uint32_t* refit_nodes = nullptr;           // node ids, deepest level first (single level)
   std::vector<uint32_t> refit_levels;        // level boundaries in refit_nodes
   rt_accel_info info{};
@@ -559,13 +560,15 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
         uint32_t mm = instance_mesh[j];
         ir[j].root = blas[mm].root == RT_CHILD_EMPTY ? RT_CHILD_EMPTY : node_base[mm];
         ir[j].mesh = mm;
-        ir[j].pad[0] = ir[j].pad[1] = 0;
+        ir[j].mask = 0xFFFFFFFFu;
+        ir[j].pad = 0;
       }
       st = dev_alloc(a, &a->insts, ir.size());
       if (st != RT_SUCCESS) return bail(st);
       st = dev_alloc(a, &a->insts64, ir64.size());
       if (st != RT_SUCCESS) return bail(st);
       RT_HIP(hipMemcpyAsync(a->insts, ir.data(), ir.size() * sizeof(rt_inst_rec), hipMemcpyHostToDevice, s));
+      a->host_insts = ir;
       RT_HIP(hipMemcpyAsync(a->insts64, ir64.data(), ir64.size() * sizeof(rt_inst_rec64), hipMemcpyHostToDevice, s));
       // frames and per-mesh gradient rows for the two-level adjoint
       std::vector<uint64_t> base(mesh_count);
@@ -619,18 +622,22 @@ static uint32_t cached_resident(rt_context ctx, const void* kern, int wg) {
   return b;
 }
 
+// mode 0: plain query; 2: with query options; 3: all hits (options, lists of
+// `cap` entries and per-ray counts)
 static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit* hits,
                               uint32_t* inst_ids, uint8_t* occ, bool any, hipStream_t s,
-                              uint64_t* counters = nullptr) {
+                              uint64_t* counters = nullptr, int mode = 0,
+                              const rt_query_options* opts = nullptr, uint32_t* counts = nullptr,
+                              uint32_t cap = 0) {
   rt_context ctx = a->ctx;
   rt_status st = check_device(a->device);
   if (st != RT_SUCCESS) return st;
   std::lock_guard<std::mutex> lk(ctx->mu);
   rt_variant v = ctx->variant;
-  if (counters) v = rt_variant{16, 256};
+  if (counters || mode >= 2) v = rt_variant{16, 256};
   const void* kern = counters ? rtk_count_kernel(a->width, any)
                               : rtk_trace_kernel(a->width, (int)v.stack_entries, (int)v.workgroup,
-                                                 any, a->two_level, 0);
+                                                 any, a->two_level, mode);
   if (!kern) return fail(RT_ERROR_UNSUPPORTED, "trace: variant not compiled");
   uint32_t wg = v.workgroup;
   uint32_t blocks = std::min<uint32_t>((n + wg - 1) / wg, cached_resident(ctx, kern, (int)wg));
@@ -658,9 +665,20 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   p.gstride = gstride;
   p.refill_min = ctx->refill_min;
   p.counters = counters;
+  if (opts) {
+    p.ray_masks = opts->ray_masks;
+    p.skip_inst = opts->skip_inst;
+    p.skip_prim = opts->skip_prim;
+  }
+  p.counts = counts;
+  p.cap = cap;
   RT_HIP(rtk_launch_fill(ctx->scratch.counter, 1, 0u, s));
   RT_HIP(rtk_launch_trace(kern, blocks, wg, p, s));
-  if (!any) RT_HIP(rtk_launch_finalize(a->two_level, 0, p, s));
+  if (mode == 3) {
+    RT_HIP(rtk_launch_finalize_all(a->two_level, p, s));
+  } else if (!any) {
+    RT_HIP(rtk_launch_finalize(a->two_level, 0, p, s));
+  }
   RT_HIP(hipEventRecord(ctx->last_event, s));
   ctx->last_stream = s;
   ctx->has_last = true;
@@ -686,6 +704,72 @@ rt_status rt_trace_any(rt_accel accel, const rt_ray* rays, uint32_t n, uint8_t* 
   if (n > 0x7FFFFFFFu) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_any: n >= 2^31");
   if (!aligned16(rays)) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_any: rays must be 16-byte aligned");
   return launch_trace(accel, rays, n, nullptr, nullptr, occluded, true, static_cast<hipStream_t>(stream));
+}
+
+static bool options_ok(rt_accel a, const rt_query_options* o) {
+  return !(o && a->two_level && o->skip_prim && !o->skip_inst);
+}
+
+rt_status rt_trace_closest_ex(rt_accel accel, const rt_ray* rays, uint32_t n,
+                              const rt_query_options* options, rt_hit* hits, uint32_t* inst_ids,
+                              void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest_ex: NULL accel");
+  if (!options_ok(accel, options))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest_ex: skip_prim without skip_inst on a two-level accel");
+  if (n == 0) return ok();
+  if (!rays || !hits) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest_ex: NULL buffer with n > 0");
+  if (n > 0x7FFFFFFFu) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest_ex: n >= 2^31");
+  if (!aligned16(rays) || !aligned16(hits))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest_ex: rays and hits must be 16-byte aligned");
+  return launch_trace(accel, rays, n, hits, inst_ids, nullptr, false, static_cast<hipStream_t>(stream),
+                      nullptr, 2, options);
+}
+
+rt_status rt_trace_any_ex(rt_accel accel, const rt_ray* rays, uint32_t n,
+                          const rt_query_options* options, uint8_t* occluded, void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_any_ex: NULL accel");
+  if (!options_ok(accel, options))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_any_ex: skip_prim without skip_inst on a two-level accel");
+  if (n == 0) return ok();
+  if (!rays || !occluded) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_any_ex: NULL buffer with n > 0");
+  if (n > 0x7FFFFFFFu) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_any_ex: n >= 2^31");
+  if (!aligned16(rays)) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_any_ex: rays must be 16-byte aligned");
+  return launch_trace(accel, rays, n, nullptr, nullptr, occluded, true, static_cast<hipStream_t>(stream),
+                      nullptr, 2, options);
+}
+
+rt_status rt_trace_all(rt_accel accel, const rt_ray* rays, uint32_t n,
+                       const rt_query_options* options, uint32_t capacity, rt_hit* hits,
+                       uint32_t* inst_ids, uint32_t* counts, void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_all: NULL accel");
+  if (!options_ok(accel, options))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_all: skip_prim without skip_inst on a two-level accel");
+  if (capacity < 1 || capacity > RT_MAX_HIT_CAPACITY)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_all: capacity %u outside [1, %u]", capacity,
+                (unsigned)RT_MAX_HIT_CAPACITY);
+  if (n == 0) return ok();
+  if (!rays || !hits || !counts) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_all: NULL buffer with n > 0");
+  if ((uint64_t)n * capacity > 0x7FFFFFFFull)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_all: n * capacity >= 2^31");
+  if (!aligned16(rays) || !aligned16(hits))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_all: rays and hits must be 16-byte aligned");
+  return launch_trace(accel, rays, n, hits, inst_ids, nullptr, false, static_cast<hipStream_t>(stream),
+                      nullptr, 3, options, counts, capacity);
+}
+
+rt_status rt_accel_set_instance_masks(rt_accel accel, const uint32_t* masks, void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_accel_set_instance_masks: NULL accel");
+  if (!accel->two_level)
+    return fail(RT_ERROR_UNSUPPORTED, "rt_accel_set_instance_masks: single-level accel (no instances)");
+  if (!masks) return fail(RT_ERROR_INVALID_VALUE, "rt_accel_set_instance_masks: masks is NULL");
+  rt_status st = check_device(accel->device);
+  if (st != RT_SUCCESS) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (uint32_t j = 0; j < accel->instance_count; ++j) accel->host_insts[j].mask = masks[j];
+  RT_HIP(hipMemcpyAsync(accel->insts, accel->host_insts.data(),
+                        accel->host_insts.size() * sizeof(rt_inst_rec), hipMemcpyHostToDevice, s));
+  RT_HIP(hipStreamSynchronize(s));
+  return ok();
 }
 
 rt_status rt_trace_counters(rt_accel accel, const rt_ray* rays, uint32_t n, int any, rt_hit* hits,

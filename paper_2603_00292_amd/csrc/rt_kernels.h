@@ -39,6 +39,12 @@ struct TraceParams {
   uint32_t gstride;      // threads in the grid
   uint32_t refill_min;   // refill a wave once this many lanes are idle
   uint64_t* counters;    // counting variants: node visits, triangle tests, spills
+  // query options (modes 2 and 3; each may be null)
+  const uint32_t* ray_masks;
+  const uint32_t* skip_inst;
+  const uint32_t* skip_prim;
+  uint32_t* counts;      // mode 3: hits per ray
+  uint32_t cap;          // mode 3: list entries per ray
 };
 
 struct BackwardParams {
@@ -71,14 +77,18 @@ struct BackwardInstParams {
   float* d_directions;
 };
 
-// Kernel handle for a variant (mode 0: one accel, mode 1: batched closest);
-// nullptr when the combination is not compiled.
+// Kernel handle for a variant (mode 0: one accel, mode 1: batched closest,
+// mode 2: one accel with query options, mode 3: all hits with query options;
+// modes 2 and 3 exist for stack 16 / workgroup 256 only); nullptr when the
+// combination is not compiled.
 const void* rtk_trace_kernel(int width, int stack, int wg, bool any, bool inst, int mode);
 const void* rtk_count_kernel(int width, bool any);
 hipError_t rtk_launch_trace(const void* kern, uint32_t grid, uint32_t wg, const TraceParams& p,
                             hipStream_t stream);
 // float64 finalize of closest hits written by a trace launch with the same params
 hipError_t rtk_launch_finalize(bool inst, int mode, const TraceParams& p, hipStream_t stream);
+// float64 finalize of the hit lists of an all-hits launch (n * cap entries)
+hipError_t rtk_launch_finalize_all(bool inst, const TraceParams& p, hipStream_t stream);
 hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream);
 hipError_t rtk_launch_backward_inst(const BackwardInstParams& p, hipStream_t stream);
 hipError_t rtk_launch_refit_tris(rt_tri_rec* tris, uint32_t n, const rt_mesh_dev& mesh,

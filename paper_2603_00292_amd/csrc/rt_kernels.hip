@@ -279,11 +279,31 @@ __device__ __forceinline__ bool is_tri_leaf(uint32_t ref) {
   return (ref & (RT_LEAF_BIT | RT_INST_BIT)) == RT_LEAF_BIT;
 }
 
+// Inserts the hit (t, inst, prim) into a lane's list of the `cap` nearest
+// hits, kept sorted by (t, inst, prim) in its output records (t, prim, inst
+// bits, 0); `found` hits were seen before this one.
+__device__ __forceinline__ void list_insert(float4* L, uint32_t found, uint32_t cap, float t,
+                                            uint32_t inst, uint32_t prim) {
+  uint32_t pos = min(found, cap);
+  while (pos > 0) {
+    float4 e = L[pos - 1];
+    uint32_t ei = __float_as_uint(e.z), ep = __float_as_uint(e.y);
+    bool greater = (e.x > t) || (e.x == t && (ei > inst || (ei == inst && ep > prim)));
+    if (!greater) break;
+    if (pos < cap) L[pos] = e;
+    --pos;
+  }
+  if (pos < cap) L[pos] = make_float4(t, __uint_as_float(prim), __uint_as_float(inst), 0.0f);
+}
+
 // ---------------------------------------------------------------------------
 // the persistent traversal kernel
 // ---------------------------------------------------------------------------
 // MODE 0: one accel (uniform geometry); MODE 1: batched (geometry per lane
-// from the batch descriptor of the lane's ray).
+// from the batch descriptor of the lane's ray); MODE 2: one accel with the
+// query options (ray masks against instance masks, a skipped triangle per
+// ray); MODE 3: as MODE 2, enumerating all hits within [tmin, tmax] (no
+// culling by the nearest hit) into per-ray lists of the `cap` nearest.
 template <int W, int S, int WG, bool ANY, bool INST, int MODE, bool COUNT = false>
 __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
   __shared__ uint32_t lds_stack[S * WG];
@@ -319,6 +339,7 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
   const rt_ray* ray_in = P.rays;
   bool live = false, retired = false;
   uint32_t batch = 0;
+  uint32_t rmask = 0xFFFFFFFFu, skip_i = RT_INVALID_ID, skip_p = RT_INVALID_ID, found = 0;
   uint64_t n_nodes = 0, n_tris = 0, n_spill = 0;
 
   while (true) {
@@ -363,6 +384,14 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
           cur_inst = 0;
           st.sp = 0;
           cur = ray_void(wray) ? RT_CHILD_EMPTY : g.root;
+          if constexpr (MODE >= 2) {
+            rmask = P.ray_masks ? P.ray_masks[local] : 0xFFFFFFFFu;
+            skip_p = P.skip_prim ? P.skip_prim[local] : RT_INVALID_ID;
+            skip_i = P.skip_inst ? P.skip_inst[local] : RT_INVALID_ID;
+            found = 0;
+            // a single-level accel is one geometry of mask 0xFFFFFFFF
+            if (!INST && rmask == 0u) cur = RT_CHILD_EMPTY;
+          }
           live = true;
         } else {
           retired = true;
@@ -387,6 +416,12 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
           if (is_inst(cur)) {
             uint32_t j = cur & RT_INST_INDEX_MASK;
             const rt_inst_rec& I = g.insts[j];
+            if constexpr (MODE >= 2) {
+              if ((I.mask & rmask) == 0u) {
+                cur = st.pop();
+                continue;
+              }
+            }
             to_object(I, wray, r);
             r.tmin = wray.tmin;
             cur_inst = j;
@@ -423,6 +458,15 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
           float t;
           if (tri_test(A, B, C, r, t) && t >= r.tmin && t <= best_t) {
             uint32_t prim = __float_as_uint(A.w);
+            if constexpr (MODE >= 2) {
+              if (prim == skip_p && (!INST || cur_inst == skip_i)) continue;
+            }
+            if constexpr (MODE == 3) {
+              list_insert(reinterpret_cast<float4*>(hit_out) + (size_t)ray_id * P.cap, found, P.cap, t,
+                          INST ? cur_inst : 0u, prim);
+              ++found;
+              continue;
+            }
             if constexpr (ANY) {
               best_prim = prim;
               stop = true;
@@ -459,7 +503,9 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
       // finalize_kernel, one thread per ray; here: float32 t, the triangle id
       // and, in the u slot, the instance id)
       if (cur == RT_CHILD_EMPTY) {
-        if constexpr (ANY) {
+        if constexpr (MODE == 3) {
+          P.counts[ray_id] = found;
+        } else if constexpr (ANY) {
           occ_out[ray_id] = (best_prim != RT_INVALID_ID) ? 1 : 0;
         } else {
           bool hit = best_prim != RT_INVALID_ID;
@@ -724,6 +770,45 @@ __global__ __launch_bounds__(256) void finalize_kernel(TraceParams P) {
   if (MODE == 0 && P.inst_ids) P.inst_ids[local] = INST ? inst : 0u;
 }
 
+// float64 finalize of all-hit lists: one thread per list entry; entries past
+// a ray's stored hits become misses (t = +inf, prim and instance invalid).
+template <bool INST>
+__global__ __launch_bounds__(256) void finalize_all_kernel(TraceParams P) {
+  uint32_t e = blockIdx.x * 256u + threadIdx.x;
+  if (e >= P.n * P.cap) return;
+  uint32_t ray = e / P.cap, j = e - ray * P.cap;
+  float4* hp = reinterpret_cast<float4*>(P.hits + e);
+  if (j >= min(P.counts[ray], P.cap)) {
+    *hp = make_float4(__int_as_float(0x7f800000), __uint_as_float(RT_INVALID_ID), 0.0f, 0.0f);
+    if (P.inst_ids) P.inst_ids[e] = RT_INVALID_ID;
+    return;
+  }
+  float4 h = *hp;
+  uint32_t prim = __float_as_uint(h.y);
+  uint32_t inst = __float_as_uint(h.z);
+  rt_ray q = load_ray(P.rays, ray);
+  double ox = q.ox, oy = q.oy, oz = q.oz, dx = q.dx, dy = q.dy, dz = q.dz;
+  uint32_t mesh = 0;
+  if constexpr (INST) {
+    const rt_inst_rec64& M = P.insts64[inst];
+    double a = M.m[0] * ox + M.m[1] * oy + M.m[2] * oz + M.m[3];
+    double b = M.m[4] * ox + M.m[5] * oy + M.m[6] * oz + M.m[7];
+    double c = M.m[8] * ox + M.m[9] * oy + M.m[10] * oz + M.m[11];
+    double f = M.m[0] * dx + M.m[1] * dy + M.m[2] * dz;
+    double g = M.m[4] * dx + M.m[5] * dy + M.m[6] * dz;
+    double k = M.m[8] * dx + M.m[9] * dy + M.m[10] * dz;
+    ox = a; oy = b; oz = c; dx = f; dy = g; dz = k;
+    mesh = P.insts[inst].mesh;
+  }
+  float t, u, v;
+  if (finalize64(P.meshes[mesh], prim, ox, oy, oz, dx, dy, dz, t, u, v)) {
+    *hp = make_float4(t, h.y, u, v);
+  } else {
+    *hp = make_float4(h.x, h.y, 0.0f, 0.0f);
+  }
+  if (P.inst_ids) P.inst_ids[e] = INST ? inst : 0u;
+}
+
 // ---------------------------------------------------------------------------
 // refit: triangle records from new vertices, then child boxes bottom-up
 // ---------------------------------------------------------------------------
@@ -837,6 +922,13 @@ const void* kernel_ptr() {
   return reinterpret_cast<const void*>(&rtk::trace_kernel<W, S, WG, ANY, INST, MODE>);
 }
 
+template <int W>
+const void* pick_query(bool any, bool inst, int mode) {
+  if (mode == 3) return inst ? kernel_ptr<W, 16, 256, false, true, 3>() : kernel_ptr<W, 16, 256, false, false, 3>();
+  if (any) return inst ? kernel_ptr<W, 16, 256, true, true, 2>() : kernel_ptr<W, 16, 256, true, false, 2>();
+  return inst ? kernel_ptr<W, 16, 256, false, true, 2>() : kernel_ptr<W, 16, 256, false, false, 2>();
+}
+
 template <int W, bool ANY>
 const void* kernel_ptr_c() {
   return reinterpret_cast<const void*>(&rtk::trace_kernel<W, 16, 256, ANY, false, 0, true>);
@@ -883,6 +975,15 @@ const void* rtk_count_kernel(int width, bool any) {
 }
 
 const void* rtk_trace_kernel(int width, int stack, int wg, bool any, bool inst, int mode) {
+  if (mode >= 2) {
+    if (stack != 16 || wg != 256 || (mode == 3 && any)) return nullptr;
+    switch (width) {
+      case 2: return pick_query<2>(any, inst, mode);
+      case 4: return pick_query<4>(any, inst, mode);
+      case 8: return pick_query<8>(any, inst, mode);
+      default: return nullptr;
+    }
+  }
   switch (width) {
     case 2: return pick_s<2>(stack, wg, any, inst, mode);
     case 4: return pick_s<4>(stack, wg, any, inst, mode);
@@ -922,6 +1023,16 @@ hipError_t rtk_launch_finalize(bool inst, int mode, const TraceParams& p, hipStr
   TraceParams q = p;
   void* args[] = {&q};
   return hipLaunchKernel(k, dim3((p.n + 255) / 256), dim3(256), args, 0, stream);
+}
+
+hipError_t rtk_launch_finalize_all(bool inst, const TraceParams& p, hipStream_t stream) {
+  uint64_t total = (uint64_t)p.n * p.cap;
+  if (total == 0) return hipSuccess;
+  const void* k = inst ? reinterpret_cast<const void*>(&rtk::finalize_all_kernel<true>)
+                       : reinterpret_cast<const void*>(&rtk::finalize_all_kernel<false>);
+  TraceParams q = p;
+  void* args[] = {&q};
+  return hipLaunchKernel(k, dim3((uint32_t)((total + 255) / 256)), dim3(256), args, 0, stream);
 }
 
 hipError_t rtk_launch_refit_tris(rt_tri_rec* tris, uint32_t n, const rt_mesh_dev& mesh,

@@ -61,7 +61,8 @@ struct rt_inst_rec {
   float r2[4];
   uint32_t root;
   uint32_t mesh;
-  uint32_t pad[2];
+  uint32_t mask;   // visibility mask, ANDed with a ray's mask (all ones by default)
+  uint32_t pad;
 };
 
 // float64 world->object map of an instance, used by the float64 finalize

@@ -366,7 +366,8 @@ def instanced_grids(n_inst: int = 1024, n_rays: int = 8388608, k: int = 2) -> Wo
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     o = o + 1e-4 * nrm
     rays = pack_rays(o, d)
-    return Workload("instanced_grids", Scene(meshes, inst_mesh, srt), rays)
+    extra = {"src_inst": inst.astype(np.uint32), "src_prim": tri.astype(np.uint32)}
+    return Workload("instanced_grids", Scene(meshes, inst_mesh, srt), rays, extra)
 
 
 def aimed_instances(n_inst: int = 8, n_rays: int = 4096, k: int = 130) -> Workload:

@@ -78,3 +78,54 @@ def check_any(occ: np.ndarray, A, label: str = ""):
                              f"(rays {i.tolist()}, class {A.any_class[i].tolist()}, gpu {occ[i].tolist()})")
     assert set(np.unique(occ).tolist()) <= {0, 1}
     return {"rays": len(occ), "occluded": int(occ.sum()), "decided": float((A.any_class != 2).mean())}
+
+
+def check_all(hits: np.ndarray, inst: np.ndarray | None, counts: np.ndarray, C, label: str = ""):
+    """All-hit lists from the GPU: hits (n,cap,4), inst (n,cap) or None,
+    counts (n,); C = oracle.classify_all(...) with K at least every ray's
+    candidate count.  Per ray: every listed pair is a candidate, with t, u, v
+    within the value tolerance and no repeats; n_sure <= count <= candidates;
+    the list holds every sure candidate (when count <= cap), or every sure
+    candidate that must precede its last entry (when it is full); entries are
+    ordered up to the candidates' t ranges; entries past the list are misses.
+    Returns a stats dict."""
+    n, cap = hits.shape[0], hits.shape[1]
+    assert (C.count <= C.K).all(), f"{label}: oracle candidate lists overflow K={C.K}"
+    prim = hits[:, :, 1].copy().view(np.uint32)
+    ins = np.zeros_like(prim) if inst is None else inst.astype(np.uint32)
+    counts = counts.astype(np.int64)
+    assert ((C.n_sure <= counts) & (counts <= C.count)).all(), (
+        f"{label}: counts outside [sure, candidates] for rays "
+        f"{np.flatnonzero((C.n_sure > counts) | (counts > C.count))[:5].tolist()}")
+    exact = 0
+    for r in range(n):
+        m = int(min(counts[r], cap))
+        assert (prim[r, m:] == NONE).all() and np.isinf(hits[r, m:, 0]).all(), f"{label}: ray {r} tail"
+        idx = {}
+        for i in range(int(C.count[r])):
+            idx[(int(C.inst[r, i]), int(C.prim[r, i]))] = i
+        pos = []
+        for k in range(m):
+            key = (int(ins[r, k]), int(prim[r, k]))
+            assert key in idx, f"{label}: ray {r} entry {k} {key} is no candidate {sorted(idx)}"
+            pos.append(idx[key])
+        assert len(set(pos)) == m, f"{label}: ray {r} repeats a pair"
+        for k, i in enumerate(pos):
+            ref = C.tuv[r, i]
+            if np.isfinite(ref).all():
+                g = hits[r, k, [0, 2, 3]].astype(np.float64)
+                assert abs(g[0] - ref[0]) <= T_REL * abs(ref[0]) + T_ABS * C.scale[r, i], (label, r, k)
+                assert abs(g[1] - ref[1]) <= UV_ABS and abs(g[2] - ref[2]) <= UV_ABS, (label, r, k)
+        for a, b in zip(pos, pos[1:]):
+            assert C.lo[r, a] <= C.hi[r, b], f"{label}: ray {r} out of order"
+        listed = set(pos)
+        sure = [i for i in range(int(C.count[r])) if C.sure[r, i]]
+        if counts[r] <= cap:
+            missing = [i for i in sure if i not in listed]
+        else:
+            last_lo = C.lo[r, pos[-1]]
+            missing = [i for i in sure if i not in listed and C.hi[r, i] < last_lo]
+        assert not missing, f"{label}: ray {r} lacks sure hits {missing}"
+        exact += int(C.n_sure[r] == C.count[r])
+    return {"rays": n, "hits": int(counts.sum()), "max_count": int(counts.max()) if n else 0,
+            "all_sure_frac": exact / max(n, 1)}
