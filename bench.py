@@ -35,7 +35,6 @@ FINALIZE_BYTES = 12 + 36  # indices + vertices of the winning triangle
 BACKWARD_HIT_BYTES = 32 + 16 + 12 + 12 + 36 + 24 + 36  # per hit ray
 BACKWARD_MISS_BYTES = 32 + 16 + 12 + 24
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_closest_icosphere_incoherent_pmc_traffic.txt")
-TRAFFIC_KERNEL = "trace_kernel<4, 16, 256, false, false, 0, false>"
 KERNEL_SRC = os.path.join(ROOT, "paper_2603_00292_amd", "csrc", "rt_kernels.hip")
 
 
@@ -52,14 +51,16 @@ def measured_traffic(info, variant):
     """HBM-side bytes per launch of the closest-hit kernel from the committed
     rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE, calibrated on a copy of
     known size), or None when the kernel source or configuration differs."""
-    if not os.path.exists(TRAFFIC_FILE) or info["node_width"] != 4 or tuple(variant) != (16, 256):
+    if not os.path.exists(TRAFFIC_FILE):
         return None
+    name = "trace_kernel<%d, %d, %d, false, false, 0, false>" % (
+        info["node_width"], variant[0], variant[1])
     sha, val = None, None
     with open(TRAFFIC_FILE) as f:
         for line in f:
             if "rt_kernels.hip sha256[:16] =" in line:
                 sha = line.split("=")[-1].strip()
-            elif TRAFFIC_KERNEL in line:
+            elif name in line:
                 val = int(line.split()[-1])
     return val if sha == kernel_sha() else None
 
@@ -94,7 +95,7 @@ def main():
                     help="run a 512 MiB device copy first (for HBM counter calibration)")
     ap.add_argument("--width", type=int, default=4, help="node width when not autotuning")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--probe", type=int, default=262144, help="rays the autotuner times")
+    ap.add_argument("--probe", type=int, default=1048576, help="rays the autotuner times")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the ray-query path is built and measured on a single "
@@ -137,7 +138,7 @@ def main():
         from paper_2603_00292_amd import autotune
 
         t0 = time.time()
-        tuned, _ = autotune.autotune(ctx, V, I, rays[: args.probe].contiguous())
+        tuned, _ = autotune.autotune(ctx, V, I, rays[: args.probe].contiguous(), repeats=5)
         width = tuned["node_width"]
         log(f"autotune {time.time() - t0:.1f}s: {tuned}")
     t0 = time.time()

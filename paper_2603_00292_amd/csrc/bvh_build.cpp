@@ -344,15 +344,22 @@ bool build_mesh(const BuildInput& in, int width, int max_leaf, WideTree& out, st
     for (uint32_t i = k.first; i < k.first + k.count; ++i) {
       uint32_t id = prims[i].id;
       const uint32_t* ix = in.indices + 3 * (size_t)id;
-      const float* p[3] = {in.vertices + 3 * (size_t)ix[0], in.vertices + 3 * (size_t)ix[1],
-                           in.vertices + 3 * (size_t)ix[2]};
+      const float* corner[3] = {in.vertices + 3 * (size_t)ix[0], in.vertices + 3 * (size_t)ix[1],
+                                in.vertices + 3 * (size_t)ix[2]};
+      const float* p[3] = {corner[0], corner[1], corner[2]};
       std::sort(p, p + 3, [](const float* a, const float* b) { return lex_less(a, b); });
       rt_tri_rec r;
+      r.order = 0;
+      for (uint32_t c = 0; c < 3; ++c)
+        for (uint32_t slot = 0; slot < 3; ++slot)
+          if (p[slot] == corner[c]) {
+            r.order |= slot << (2 * c);
+            break;
+          }
       r.p0x = p[0][0]; r.p0y = p[0][1]; r.p0z = p[0][2];
       r.p1x = p[1][0]; r.p1y = p[1][1]; r.p1z = p[1][2];
       r.p2x = p[2][0]; r.p2y = p[2][1]; r.p2z = p[2][2];
       r.prim = id;
-      r.pad1 = 0;
       r.pad2 = 0;
       out.tris.push_back(r);
     }

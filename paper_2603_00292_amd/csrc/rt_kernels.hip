@@ -223,19 +223,20 @@ __device__ __forceinline__ bool tri_test(const float4& A, const float4& B, const
   return true;
 }
 
-// float64 (t, u, v) of a triangle in its original vertex order
-// (Moeller-Trumbore solution of o + t d = (1-u-v) v0 + u v1 + v v2).
-__device__ __forceinline__ bool finalize64(const rt_mesh_dev& m, uint32_t prim, double ox,
-                                           double oy, double oz, double dx, double dy, double dz,
-                                           float& t, float& u, float& v) {
-  const uint32_t* ix = m.indices + 3 * (size_t)prim;
-  uint32_t i0 = ix[0], i1 = ix[1], i2 = ix[2];
-  const float* V = m.vertices;
-  double v0x = V[3 * (size_t)i0], v0y = V[3 * (size_t)i0 + 1], v0z = V[3 * (size_t)i0 + 2];
-  double e1x = V[3 * (size_t)i1] - v0x, e1y = V[3 * (size_t)i1 + 1] - v0y,
-         e1z = V[3 * (size_t)i1 + 2] - v0z;
-  double e2x = V[3 * (size_t)i2] - v0x, e2y = V[3 * (size_t)i2 + 1] - v0y,
-         e2z = V[3 * (size_t)i2 + 2] - v0z;
+// float64 (t, u, v) of the triangle of record `rec` in its original vertex
+// order (Moeller-Trumbore solution of o + t d = (1-u-v) v0 + u v1 + v v2);
+// the record holds the float32 vertices sorted and the slot of each corner.
+__device__ __forceinline__ bool finalize64(const float4* tris, uint32_t rec, double ox, double oy,
+                                           double oz, double dx, double dy, double dz, float& t,
+                                           float& u, float& v) {
+  const float4* tp = tris + 3 * (size_t)rec;
+  float4 P0 = tp[0], P1 = tp[1], P2 = tp[2];
+  uint32_t order = __float_as_uint(P1.w);
+  auto slot = [&](uint32_t k) -> float4 { return k == 0u ? P0 : (k == 1u ? P1 : P2); };
+  float4 C0 = slot(order & 3u), C1 = slot((order >> 2) & 3u), C2 = slot((order >> 4) & 3u);
+  double v0x = C0.x, v0y = C0.y, v0z = C0.z;
+  double e1x = C1.x - v0x, e1y = C1.y - v0y, e1z = C1.z - v0z;
+  double e2x = C2.x - v0x, e2y = C2.y - v0y, e2z = C2.z - v0z;
   double px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
   double det = e1x * px + e1y * py + e1z * pz;
   if (det == 0.0) return false;
@@ -281,9 +282,9 @@ __device__ __forceinline__ bool is_tri_leaf(uint32_t ref) {
 
 // Inserts the hit (t, inst, prim) into a lane's list of the `cap` nearest
 // hits, kept sorted by (t, inst, prim) in its output records (t, prim, inst
-// bits, 0); `found` hits were seen before this one.
+// bits, triangle record bits); `found` hits were seen before this one.
 __device__ __forceinline__ void list_insert(float4* L, uint32_t found, uint32_t cap, float t,
-                                            uint32_t inst, uint32_t prim) {
+                                            uint32_t inst, uint32_t prim, uint32_t rec) {
   uint32_t pos = min(found, cap);
   while (pos > 0) {
     float4 e = L[pos - 1];
@@ -293,7 +294,7 @@ __device__ __forceinline__ void list_insert(float4* L, uint32_t found, uint32_t 
     if (pos < cap) L[pos] = e;
     --pos;
   }
-  if (pos < cap) L[pos] = make_float4(t, __uint_as_float(prim), __uint_as_float(inst), 0.0f);
+  if (pos < cap) L[pos] = make_float4(t, __uint_as_float(prim), __uint_as_float(inst), __uint_as_float(rec));
 }
 
 // ---------------------------------------------------------------------------
@@ -304,8 +305,13 @@ __device__ __forceinline__ void list_insert(float4* L, uint32_t found, uint32_t 
 // query options (ray masks against instance masks, a skipped triangle per
 // ray); MODE 3: as MODE 2, enumerating all hits within [tmin, tmax] (no
 // culling by the nearest hit) into per-ray lists of the `cap` nearest.
+// Single-level variants of width 2 and 4 fit 64 VGPRs (8 waves per SIMD)
+// without spilling; the hint keeps the compiler there.
+template <int W, bool INST, bool COUNT>
+constexpr int trace_min_waves() { return (!INST && !COUNT && W <= 4) ? 8 : 1; }
+
 template <int W, int S, int WG, bool ANY, bool INST, int MODE, bool COUNT = false>
-__global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
+__global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT>())) void trace_kernel(TraceParams P) {
   __shared__ uint32_t lds_stack[S * WG];
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63u;
@@ -332,8 +338,12 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
   rt_ray wray;
   uint32_t ray_id = 0;
   uint32_t cur = RT_CHILD_EMPTY;
+  uint32_t pend = RT_CHILD_EMPTY;  // postponed triangle leaf (single level)
   float best_t = 0.0f;
-  uint32_t best_prim = RT_INVALID_ID, best_inst = RT_INVALID_ID, cur_inst = 0;
+  // the nearest hit so far: its triangle record (RT_INVALID_ID: none yet;
+  // the prim id is read from the record where a tie needs it and by the
+  // finalize) and instance
+  uint32_t best_rec = RT_INVALID_ID, best_inst = RT_INVALID_ID, cur_inst = 0;
   rt_hit* hit_out = P.hits;
   uint8_t* occ_out = P.occluded;
   const rt_ray* ray_in = P.rays;
@@ -379,10 +389,11 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
           ray_id = local;
           world_state(wray, r);
           best_t = r.tmax;
-          best_prim = RT_INVALID_ID;
+          best_rec = RT_INVALID_ID;
           best_inst = RT_INVALID_ID;
           cur_inst = 0;
           st.sp = 0;
+          pend = RT_CHILD_EMPTY;
           cur = ray_void(wray) ? RT_CHILD_EMPTY : g.root;
           if constexpr (MODE >= 2) {
             rmask = P.ray_masks ? P.ray_masks[local] : 0xFFFFFFFFu;
@@ -404,9 +415,98 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
     }
     if (live) {
       float tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
-      // ---- internal nodes until this lane holds a leaf or is done ------
-      while (cur != RT_CHILD_EMPTY && !is_tri_leaf(cur)) {
-        if constexpr (INST) {
+      // Tests the triangles of one leaf; true when an any-hit query may stop.
+      auto test_leaf = [&](uint32_t ref) -> bool {
+        uint32_t first = ref & RT_LEAF_FIRST_MASK;
+        uint32_t count = (ref >> RT_LEAF_COUNT_SHIFT) & RT_LEAF_COUNT_MASK;
+        for (uint32_t k = 0; k < count; ++k) {
+          const float4* tp = g.tris + 3 * (size_t)(first + k);
+          if constexpr (COUNT) n_tris++;
+          float4 A = tp[0], B = tp[1], C = tp[2];
+          float t;
+          if (tri_test(A, B, C, r, t) && t >= r.tmin && t <= best_t) {
+            uint32_t prim = __float_as_uint(A.w);
+            if constexpr (MODE >= 2) {
+              if (prim == skip_p && (!INST || cur_inst == skip_i)) continue;
+            }
+            if constexpr (MODE == 3) {
+              list_insert(reinterpret_cast<float4*>(hit_out) + (size_t)ray_id * P.cap, found, P.cap, t,
+                          INST ? cur_inst : 0u, prim, first + k);
+              ++found;
+              continue;
+            }
+            if constexpr (ANY) {
+              best_rec = first + k;
+              return true;
+            } else {
+              // lexicographic (t, inst, prim); t <= best_t here
+              uint32_t inst = INST ? cur_inst : 0u;
+              bool better = (t < best_t) || (inst < best_inst);
+              if (!better && inst == best_inst)
+                better = prim < __float_as_uint(g.tris[3 * (size_t)best_rec].w);
+              if (better) {
+                best_t = t;
+                best_inst = inst;
+                best_rec = first + k;
+              }
+            }
+          }
+        }
+        return false;
+      };
+      // Visits internal node `cur`: continues with the nearest child hit and
+      // pushes the others, farthest first.
+      auto step_node = [&]() {
+        uint32_t refs[W];
+        int nh;
+        if constexpr (COUNT) n_nodes++;
+        visit_node<W>(g.nodes, cur, r, tcull, refs, nh);
+        if (nh == 0) {
+          cur = st.pop();
+        } else {
+          cur = refs[0];
+#pragma unroll
+          for (int i = W - 1; i >= 1; --i)
+            if (i < nh) {
+              if constexpr (COUNT) n_spill += (st.sp >= S) ? 1 : 0;
+              st.push(refs[i]);
+            }
+        }
+      };
+      if constexpr (!INST) {
+        // ---- internal nodes, one leaf postponed ----------------------------
+        // A lane that reaches a leaf sets it aside and keeps traversing until
+        // it meets a second leaf or every lane of the wave holds a leaf, so
+        // that the wave enters the triangle loop together (leaf postponing,
+        // Aila & Laine 2009).
+        while (cur != RT_CHILD_EMPTY) {
+          if (is_tri_leaf(cur)) {
+            if (pend != RT_CHILD_EMPTY) break;
+            pend = cur;
+            cur = st.pop();
+          } else {
+            step_node();
+          }
+          if (__ballot(pend == RT_CHILD_EMPTY) == 0) break;
+        }
+        // ---- triangle leaves: the postponed one, then those on the stack top
+        while (pend != RT_CHILD_EMPTY) {
+          bool stop = test_leaf(pend);
+          pend = RT_CHILD_EMPTY;
+          if (ANY && stop) {
+            cur = RT_CHILD_EMPTY;
+            st.sp = 0;
+            break;
+          }
+          tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
+          if (cur != RT_CHILD_EMPTY && is_tri_leaf(cur)) {
+            pend = cur;
+            cur = st.pop();
+          }
+        }
+      } else {
+        // ---- internal nodes until this lane holds a leaf or is done --------
+        while (cur != RT_CHILD_EMPTY && !is_tri_leaf(cur)) {
           if (cur == RT_STACK_MARKER) {
             world_state(wray, r);
             r.tmax = best_t;
@@ -429,68 +529,18 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
             cur = I.root;
             continue;
           }
+          step_node();
         }
-        uint32_t refs[W];
-        int nh;
-        if constexpr (COUNT) n_nodes++;
-        visit_node<W>(g.nodes, cur, r, tcull, refs, nh);
-        if (nh == 0) {
-          cur = st.pop();
-        } else {
-          cur = refs[0];
-#pragma unroll
-          for (int i = W - 1; i >= 1; --i)
-            if (i < nh) {
-              if constexpr (COUNT) n_spill += (st.sp >= S) ? 1 : 0;
-              st.push(refs[i]);
-            }
-        }
-      }
-      // ---- triangle leaves ------------------------------------------------
-      while (cur != RT_CHILD_EMPTY && is_tri_leaf(cur)) {
-        uint32_t first = cur & RT_LEAF_FIRST_MASK;
-        uint32_t count = (cur >> RT_LEAF_COUNT_SHIFT) & RT_LEAF_COUNT_MASK;
-        bool stop = false;
-        for (uint32_t k = 0; k < count; ++k) {
-          const float4* tp = g.tris + 3 * (size_t)(first + k);
-          if constexpr (COUNT) n_tris++;
-          float4 A = tp[0], B = tp[1], C = tp[2];
-          float t;
-          if (tri_test(A, B, C, r, t) && t >= r.tmin && t <= best_t) {
-            uint32_t prim = __float_as_uint(A.w);
-            if constexpr (MODE >= 2) {
-              if (prim == skip_p && (!INST || cur_inst == skip_i)) continue;
-            }
-            if constexpr (MODE == 3) {
-              list_insert(reinterpret_cast<float4*>(hit_out) + (size_t)ray_id * P.cap, found, P.cap, t,
-                          INST ? cur_inst : 0u, prim);
-              ++found;
-              continue;
-            }
-            if constexpr (ANY) {
-              best_prim = prim;
-              stop = true;
-              break;
-            } else {
-              uint32_t inst = INST ? cur_inst : 0u;
-              bool better = (t < best_t) || (inst < best_inst) ||
-                            (inst == best_inst && prim < best_prim);
-              if (better) {
-                best_t = t;
-                best_prim = prim;
-                best_inst = inst;
-              }
-            }
+        // ---- triangle leaves ----------------------------------------------
+        while (cur != RT_CHILD_EMPTY && is_tri_leaf(cur)) {
+          bool stop = test_leaf(cur);
+          if (ANY && stop) {
+            cur = RT_CHILD_EMPTY;
+            st.sp = 0;
+            break;
           }
-        }
-        if (ANY && stop) {
-          cur = RT_CHILD_EMPTY;
-          st.sp = 0;
-          break;
-        }
-        tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
-        cur = st.pop();
-        if constexpr (INST) {
+          tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
+          cur = st.pop();
           // a marker ends the instance: restore the world ray
           while (cur == RT_STACK_MARKER) {
             world_state(wray, r);
@@ -499,18 +549,18 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
         }
       }
       // ---- finished: write the result --------------------------------------
-      // (the float64 (t, u, v) of a closest hit is computed afterwards by
-      // finalize_kernel, one thread per ray; here: float32 t, the triangle id
-      // and, in the u slot, the instance id)
-      if (cur == RT_CHILD_EMPTY) {
+      // (the float64 (t, u, v) and the prim id of a closest hit are written
+      // afterwards by finalize_kernel, one thread per ray; here: float32 t,
+      // the triangle record in the prim slot and the instance in the u slot)
+      if (cur == RT_CHILD_EMPTY && pend == RT_CHILD_EMPTY) {
         if constexpr (MODE == 3) {
           P.counts[ray_id] = found;
         } else if constexpr (ANY) {
-          occ_out[ray_id] = (best_prim != RT_INVALID_ID) ? 1 : 0;
+          occ_out[ray_id] = (best_rec != RT_INVALID_ID) ? 1 : 0;
         } else {
-          bool hit = best_prim != RT_INVALID_ID;
+          bool hit = best_rec != RT_INVALID_ID;
           float4* hp = reinterpret_cast<float4*>(hit_out + ray_id);
-          *hp = make_float4(hit ? best_t : __int_as_float(0x7f800000), __uint_as_float(best_prim),
+          *hp = make_float4(hit ? best_t : __int_as_float(0x7f800000), __uint_as_float(best_rec),
                             __uint_as_float(hit ? (INST ? best_inst : 0u) : 0u), 0.0f);
         }
         live = false;
@@ -717,15 +767,16 @@ __global__ __launch_bounds__(256) void backward_inst_kernel(BackwardInstParams P
 // float64 finalize of closest hits (one thread per ray, after the traversal)
 // ---------------------------------------------------------------------------
 // Recomputes (t, u, v) of the winning triangle in float64 from the float32
-// inputs (for instances, the ray is taken to object space with the float64
-// inverse frame) and writes the instance id.  Misses are left as written.
+// vertices of its record (for instances, the ray is taken to object space
+// with the float64 inverse frame) and writes the instance id.  Misses are
+// left as written.
 template <bool INST, int MODE>
 __global__ __launch_bounds__(256) void finalize_kernel(TraceParams P) {
   uint32_t i = blockIdx.x * 256u + threadIdx.x;
   if (i >= P.n) return;
   const rt_ray* rays = P.rays;
   rt_hit* hits = P.hits;
-  const rt_mesh_dev* meshes = P.meshes;
+  const float4* tris = reinterpret_cast<const float4*>(P.tris);
   uint32_t local = i;
   if constexpr (MODE == 1) {
     uint32_t lo = 0, hi = P.batch_count;
@@ -737,19 +788,18 @@ __global__ __launch_bounds__(256) void finalize_kernel(TraceParams P) {
     local = i - P.batch_offsets[lo];
     rays = bd.rays;
     hits = bd.hits;
-    meshes = bd.meshes;
+    tris = reinterpret_cast<const float4*>(bd.tris);
   }
   float4* hp = reinterpret_cast<float4*>(hits + local);
   float4 h = *hp;
-  uint32_t prim = __float_as_uint(h.y);
-  if (prim == RT_INVALID_ID) {
+  uint32_t rec = __float_as_uint(h.y);
+  if (rec == RT_INVALID_ID) {
     if (MODE == 0 && P.inst_ids) P.inst_ids[local] = RT_INVALID_ID;
     return;
   }
   uint32_t inst = __float_as_uint(h.z);
   rt_ray q = load_ray(rays, local);
   double ox = q.ox, oy = q.oy, oz = q.oz, dx = q.dx, dy = q.dy, dz = q.dz;
-  uint32_t mesh = 0;
   if constexpr (INST) {
     const rt_inst_rec64& M = P.insts64[inst];
     double a = M.m[0] * ox + M.m[1] * oy + M.m[2] * oz + M.m[3];
@@ -759,13 +809,13 @@ __global__ __launch_bounds__(256) void finalize_kernel(TraceParams P) {
     double f = M.m[4] * dx + M.m[5] * dy + M.m[6] * dz;
     double gg = M.m[8] * dx + M.m[9] * dy + M.m[10] * dz;
     ox = a; oy = b; oz = c; dx = e; dy = f; dz = gg;
-    mesh = P.insts[inst].mesh;
   }
   float t, u, v;
-  if (finalize64(meshes[mesh], prim, ox, oy, oz, dx, dy, dz, t, u, v)) {
-    *hp = make_float4(t, h.y, u, v);
+  float prim = tris[3 * (size_t)rec].w;
+  if (finalize64(tris, rec, ox, oy, oz, dx, dy, dz, t, u, v)) {
+    *hp = make_float4(t, prim, u, v);
   } else {
-    *hp = make_float4(h.x, h.y, 0.0f, 0.0f);
+    *hp = make_float4(h.x, prim, 0.0f, 0.0f);
   }
   if (MODE == 0 && P.inst_ids) P.inst_ids[local] = INST ? inst : 0u;
 }
@@ -784,11 +834,10 @@ __global__ __launch_bounds__(256) void finalize_all_kernel(TraceParams P) {
     return;
   }
   float4 h = *hp;
-  uint32_t prim = __float_as_uint(h.y);
   uint32_t inst = __float_as_uint(h.z);
+  uint32_t rec = __float_as_uint(h.w);
   rt_ray q = load_ray(P.rays, ray);
   double ox = q.ox, oy = q.oy, oz = q.oz, dx = q.dx, dy = q.dy, dz = q.dz;
-  uint32_t mesh = 0;
   if constexpr (INST) {
     const rt_inst_rec64& M = P.insts64[inst];
     double a = M.m[0] * ox + M.m[1] * oy + M.m[2] * oz + M.m[3];
@@ -798,10 +847,9 @@ __global__ __launch_bounds__(256) void finalize_all_kernel(TraceParams P) {
     double g = M.m[4] * dx + M.m[5] * dy + M.m[6] * dz;
     double k = M.m[8] * dx + M.m[9] * dy + M.m[10] * dz;
     ox = a; oy = b; oz = c; dx = f; dy = g; dz = k;
-    mesh = P.insts[inst].mesh;
   }
   float t, u, v;
-  if (finalize64(P.meshes[mesh], prim, ox, oy, oz, dx, dy, dz, t, u, v)) {
+  if (finalize64(reinterpret_cast<const float4*>(P.tris), rec, ox, oy, oz, dx, dy, dz, t, u, v)) {
     *hp = make_float4(t, h.y, u, v);
   } else {
     *hp = make_float4(h.x, h.y, 0.0f, 0.0f);
@@ -840,15 +888,19 @@ __global__ __launch_bounds__(256) void refit_tris_kernel(rt_tri_rec* tris, uint3
   double e2x = (double)p[2][0] - p[0][0], e2y = (double)p[2][1] - p[0][1], e2z = (double)p[2][2] - p[0][2];
   double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
   bool ok = finite && !(nx == 0.0 && ny == 0.0 && nz == 0.0);
-  // sort the vertices lexicographically (three compare-exchanges)
+  // sort the vertices lexicographically (three compare-exchanges), keeping
+  // the original corner of each slot
+  uint32_t corner[3] = {0u, 1u, 2u};
 #define RT_VSWAP(a, b)                                                              \
   if (lex_less3(p[b][0], p[b][1], p[b][2], p[a][0], p[a][1], p[a][2])) {            \
     for (int c_ = 0; c_ < 3; ++c_) { float t_ = p[a][c_]; p[a][c_] = p[b][c_]; p[b][c_] = t_; } \
+    uint32_t k_ = corner[a]; corner[a] = corner[b]; corner[b] = k_;                 \
   }
   RT_VSWAP(0, 1);
   RT_VSWAP(1, 2);
   RT_VSWAP(0, 1);
 #undef RT_VSWAP
+  r.order = (0u << (2 * corner[0])) | (1u << (2 * corner[1])) | (2u << (2 * corner[2]));
   float nan = __int_as_float(0x7fc00000);
   r.p0x = ok ? p[0][0] : nan; r.p0y = p[0][1]; r.p0z = p[0][2];
   r.p1x = p[1][0]; r.p1y = p[1][1]; r.p1z = p[1][2];

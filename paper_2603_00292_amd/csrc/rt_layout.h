@@ -18,16 +18,17 @@
 //   0xFFFFFFFF               empty slot
 //
 // Triangle record (48 bytes, leaf order): three float4
-//   (p0.xyz, prim id bits), (p1.xyz, 0), (p2.xyz, 0)
+//   (p0.xyz, prim id bits), (p1.xyz, order), (p2.xyz, 0)
 // with the vertices sorted lexicographically (x, then y, then z), p0 < p1 <
 // p2, so every edge is evaluated from its smaller endpoint on both triangles
 // sharing it (bit-identical edge functions, no cracks).  The inside test and
 // t do not depend on the vertex order; u, v are recomputed in float64 from
-// the original vertex order at the end of a query.
+// the original vertex order at the end of a query: bits 2c..2c+1 of `order`
+// give the sorted slot of the triangle's corner c.
 //
 // Instance record (64 bytes): float32 rows of the world->object affine map
 // (3 x float4: r0, r1, r2 with object = R3x3 * world + c in .w), blas root
-// ref, mesh id, 2 pad words.
+// ref, mesh id, visibility mask, 1 pad word.
 #pragma once
 #include <stdint.h>
 
@@ -50,7 +51,7 @@ struct rt_tri_rec {
   float p0x, p0y, p0z;
   uint32_t prim;
   float p1x, p1y, p1z;
-  uint32_t pad1;
+  uint32_t order;  // sorted slot of corner c in bits 2c..2c+1
   float p2x, p2y, p2z;
   uint32_t pad2;
 };
