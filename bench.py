@@ -95,7 +95,8 @@ def main():
                     help="run a 512 MiB device copy first (for HBM counter calibration)")
     ap.add_argument("--width", type=int, default=4, help="node width when not autotuning")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--probe", type=int, default=1048576, help="rays the autotuner times")
+    ap.add_argument("--probe", type=int, default=0,
+                    help="rays the autotuner times (0: all rays of the workload)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the ray-query path is built and measured on a single "
@@ -138,7 +139,8 @@ def main():
         from paper_2603_00292_amd import autotune
 
         t0 = time.time()
-        tuned, _ = autotune.autotune(ctx, V, I, rays[: args.probe].contiguous(), repeats=5)
+        probe = rays if args.probe <= 0 else rays[: args.probe].contiguous()
+        tuned, _ = autotune.autotune(ctx, V, I, probe, repeats=5)
         width = tuned["node_width"]
         log(f"autotune {time.time() - t0:.1f}s: {tuned}")
     t0 = time.time()

@@ -305,13 +305,8 @@ __device__ __forceinline__ void list_insert(float4* L, uint32_t found, uint32_t 
 // query options (ray masks against instance masks, a skipped triangle per
 // ray); MODE 3: as MODE 2, enumerating all hits within [tmin, tmax] (no
 // culling by the nearest hit) into per-ray lists of the `cap` nearest.
-// Single-level variants of width 2 and 4 fit 64 VGPRs (8 waves per SIMD)
-// without spilling; the hint keeps the compiler there.
-template <int W, bool INST, bool COUNT>
-constexpr int trace_min_waves() { return (!INST && !COUNT && W <= 4) ? 8 : 1; }
-
 template <int W, int S, int WG, bool ANY, bool INST, int MODE, bool COUNT = false>
-__global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT>())) void trace_kernel(TraceParams P) {
+__global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
   __shared__ uint32_t lds_stack[S * WG];
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63u;
