@@ -72,6 +72,7 @@ def _load():
             "orc_fixed_tuv": [P, P, P, i64, P],
             "orc_adjoint_inst": [P, P, P, P, i64, P, P, P, P, P],
             "orc_fd_inst": [P, P, P, P, i64, P, C.c_double, P],
+            "orc_ao_rays": [P, P, P, P, i64, C.c_int32, P, C.c_double, C.c_double, P],
         }.items():
             f = getattr(lib, name)
             f.argtypes = args
@@ -345,6 +346,22 @@ def fd_inst(scene: OracleScene, rays, inst, prim, g, h: float = 1e-6):
     out = np.empty((n, 25), np.float64)
     _check(lib.orc_fd_inst(scene.ptr, _p(r), _p(inst), _p(prim), n, _p(g), float(h), _p(out)),
            "fd_inst")
+    return out
+
+
+def ao_rays(scene: OracleScene, rays, prim, tuv, xi, offset: float, radius: float):
+    """Ambient-occlusion rays (§4): (n*N, 8) float32 for the primary rays'
+    closest hits (prim, tuv) and uniforms xi (n, N, 2)."""
+    lib = _load()
+    r, n = _rays(rays)
+    prim = np.ascontiguousarray(prim, dtype=np.uint32).reshape(-1)
+    tuv = np.ascontiguousarray(tuv, dtype=np.float64).reshape(-1, 3)
+    xi = np.ascontiguousarray(xi, dtype=np.float32)
+    N = xi.shape[1]
+    assert xi.shape == (n, N, 2)
+    out = np.empty((n * N, 8), np.float32)
+    _check(lib.orc_ao_rays(scene.ptr, _p(r), _p(prim), _p(tuv), n, int(N), _p(xi), float(offset),
+                           float(radius), _p(out)), "ao_rays")
     return out
 
 

@@ -968,6 +968,68 @@ int orc_fd_inst(const orc_scene* s, const float* rays, const uint32_t* inst, con
   return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* ambient occlusion rays (§4)                                                */
+/* ------------------------------------------------------------------------- */
+/* For primary ray r with closest hit (prim[r], t = tuv[3r]) and sample k:
+ * the shading point p = o + t d; the unit geometric normal n of the triangle,
+ * turned to face the incoming ray; the tangent t0 = (v1 - v0)/|v1 - v0| and
+ * bi-tangent t1 = n x t0 (§4.1: a triangle edge and the cross product of the
+ * normal and the tangent); the cosine-weighted direction of §4.1 from the
+ * uniforms (xi0, xi1): phi = 2 pi xi0, rr = sqrt(xi1), x = rr cos phi,
+ * z = rr sin phi, y = sqrt(max(1 - rr^2, 0)), mapped as t0 x + t1 z + n y;
+ * the origin p + offset n (§4.2 self-intersection offset); t in
+ * [0, radius] (§4.2 limited ray length).  Misses give void rays
+ * (tmin = 1, tmax = 0).  Everything in float64, rounded once to float32. */
+int orc_ao_rays(const orc_scene* s, const float* rays, const uint32_t* prim, const double* tuv,
+                int64_t nr, int32_t N, const float* xi, double offset, double radius,
+                float* out) {
+  if (nr < 0 || N < 1 || !scene_valid(s) || s->n_inst != 0) return -1;
+  if (nr > 0 && (!rays || !prim || !tuv || !xi || !out)) return -1;
+  for (int64_t r = 0; r < nr; ++r)
+    if (prim[r] != ORC_NONE && (int64_t)prim[r] >= s->n_triangles[0]) return -1;
+  const double two_pi = 6.283185307179586476925286766559;
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < nr; ++r) {
+    ray64 q = load_ray(rays + 8 * r);
+    int hit = prim[r] != ORC_NONE;
+    vec3 n = mk(0, 0, 0), t0 = mk(0, 0, 0), t1 = mk(0, 0, 0), org = mk(0, 0, 0);
+    if (hit) {
+      vec3 v0, v1, v2;
+      tri(s, 0, prim[r], &v0, &v1, &v2);
+      n = cross(sub(v1, v0), sub(v2, v0));
+      n = scl(n, 1.0 / norm(n));
+      if (dot(n, q.d) > 0.0) n = scl(n, -1.0);
+      t0 = sub(v1, v0);
+      t0 = scl(t0, 1.0 / norm(t0));
+      t1 = cross(n, t0);
+      vec3 p = add(q.o, scl(q.d, tuv[3 * r]));
+      org = add(p, scl(n, offset));
+    }
+    for (int32_t k = 0; k < N; ++k) {
+      float* o = out + 8 * (r * N + k);
+      if (!hit) {
+        o[0] = o[1] = o[2] = 0.0f;
+        o[3] = 1.0f;
+        o[4] = o[5] = o[6] = 0.0f;
+        o[7] = 0.0f;
+        continue;
+      }
+      const float* u = xi + 2 * (r * N + k);
+      double phi = two_pi * (double)u[0], rr = sqrt((double)u[1]);
+      double x = rr * cos(phi), z = rr * sin(phi);
+      double y = 1.0 - rr * rr;
+      y = sqrt(y > 0.0 ? y : 0.0);
+      vec3 d = add(add(scl(t0, x), scl(t1, z)), scl(n, y));
+      o[0] = (float)org.x; o[1] = (float)org.y; o[2] = (float)org.z;
+      o[3] = 0.0f;
+      o[4] = (float)d.x; o[5] = (float)d.y; o[6] = (float)d.z;
+      o[7] = (float)radius;
+    }
+  }
+  return 0;
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -137,6 +137,16 @@ int orc_adjoint_inst(const orc_scene* s, const float* rays, const uint32_t* inst
 int orc_fd_inst(const orc_scene* s, const float* rays, const uint32_t* inst, const uint32_t* prim,
                 int64_t nr, const double* g, double h, double* out /* nr*25 */);
 
+/* Ambient-occlusion rays of §4 for single-level scenes: N per primary ray
+ * from its closest hit (prim, tuv as returned by orc_closest) and the
+ * uniforms xi (nr*N*2): cosine-weighted about the geometric normal facing
+ * the incoming ray, tangent frame (v1-v0 normalised, n x tangent), origin
+ * offset along the normal, t in [0, radius].  Misses give void rays
+ * (tmin 1 > tmax 0).  out: nr*N*8 floats, ray r's sample k at r*N + k. */
+int orc_ao_rays(const orc_scene* s, const float* rays, const uint32_t* prim, const double* tuv,
+                int64_t nr, int32_t N, const float* xi, double offset, double radius,
+                float* out);
+
 int orc_num_threads(void);
 void orc_set_num_threads(int n);
 

@@ -401,6 +401,43 @@ def aimed_instances(n_inst: int = 8, n_rays: int = 4096, k: int = 130) -> Worklo
     return Workload("aimed_instances", Scene(meshes, inst_mesh, srt), pack_rays(o, d))
 
 
+def ao_terrain(width: int = 1024, height: int = 1024, samples: int = 16, k: int = 6,
+               nq: int = 256) -> Workload:
+    """Ambient-occlusion workload (§4): a terrain of nq x nq quads over
+    [0,16]^2 with heights a sum of six random plane waves (amplitudes
+    U[0.2,0.6], wave numbers U[1,4], random directions and phases), seen by
+    a width x height pinhole camera (§3.2) at (8, 6, -2) looking at (8, 0, 9)
+    with a 60-degree vertical field of view.  ``extra``: ``xi``
+    (width*height, samples, 2) float32 uniforms of the cosine-weighted
+    sampling, ``samples``, ``radius`` = 1 (the AO ray length of §4.2) and
+    ``offset`` = 1e-4 (the self-intersection offset of §4.2)."""
+    rng = rng_for(k)
+    xs = np.linspace(0.0, 16.0, nq + 1)
+    X, Z = np.meshgrid(xs, xs, indexing="xy")
+    H = np.zeros_like(X)
+    for _ in range(6):
+        a = rng.uniform(0.2, 0.6)
+        f = rng.uniform(1.0, 4.0)
+        th = rng.uniform(0.0, 2 * np.pi)
+        ph = rng.uniform(0.0, 2 * np.pi)
+        H += a * np.sin(f * (X * np.cos(th) + Z * np.sin(th)) + ph)
+    v, f = grid_mesh(nq, nq, 0.0, 16.0, 0.0, 16.0, H.reshape(-1))
+    origin = np.array([8.0, 6.0, -2.0])
+    fwd = np.array([8.0, 0.0, 9.0]) - origin
+    fwd /= np.linalg.norm(fwd)
+    right = np.cross(fwd, np.array([0.0, 1.0, 0.0]))
+    right /= np.linalg.norm(right)
+    up = np.cross(right, fwd)
+    half = math.tan(math.radians(30.0))
+    right = right * half * (width / height)
+    up = up * half
+    o, d = pinhole_rays(origin, right, up, width, height)
+    rays = pack_rays(o, d)
+    xi = _f32(rng.random((width * height, samples, 2)))
+    extra = {"xi": xi, "samples": samples, "radius": 1.0, "offset": 1e-4}
+    return Workload(f"ao_terrain_{width}x{height}x{samples}", Scene([Mesh(v, f)]), rays, extra)
+
+
 def batched_meshes(n_mesh: int = 256, tri_range=(1e3, 5e5), ray_range=(1e3, 1e6), k: int = 3):
     """Independent meshes with log-uniform triangle counts and log-uniform ray
     counts. Mesh m: the random-triangle recipe with offset half-width
