@@ -211,6 +211,7 @@ def main():
     if not args.no_secondary:
         secondary.update(backward_bench(args, torch, np, api, workloads, ctx, stream))
         secondary.update(batched_bench(args, torch, np, api, _capi, workloads, ctx, stream))
+        secondary.update(ao_bench(args, torch, np, api, workloads, ctx, stream))
 
     out = {
         "metric": "Mrays/s closest-hit incoherent @1M tris",
@@ -277,6 +278,35 @@ def backward_bench(args, torch, np, api, workloads, ctx, stream):
          "backward_workload": "displaced_grid_512x256 (262144 triangles), 1048576 rays",
          "backward_hbm_frac": round(alg / (mean_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     log(f"backward: {r}")
+    acc.close()
+    return r
+
+
+def ao_bench(args, torch, np, api, workloads, ctx, stream):
+    """The ambient-occlusion workload (§4) on the library: 1024 x 1024 camera
+    rays over a 131,072-triangle terrain, 16 AO samples per pixel; one step =
+    closest hits, AO rays, any-hit queries and the occluded fraction."""
+    W = workloads.ao_terrain()
+    m = W.scene.meshes[0]
+    dev = torch.device("cuda:0")
+    V = torch.from_numpy(m.vertices).to(dev)
+    I = torch.from_numpy(m.indices.view(np.int32)).to(dev)
+    acc = api.Accel(ctx, [(V, I)])
+    rays = torch.from_numpy(W.rays).to(dev)
+    xi = torch.from_numpy(W.extra["xi"]).to(dev)
+    off, rad = W.extra["offset"], W.extra["radius"]
+
+    def step():
+        api.ambient_occlusion(acc, rays, xi, off, rad)
+
+    step()
+    ms, _ = timed(step, args.steps, stream, torch)
+    n_ao = rays.shape[0] * W.extra["samples"]
+    r = {"ao_pipeline_ms": round(ms, 4),
+         "ao_mrays": round((rays.shape[0] + n_ao) / (ms * 1e-3) / 1e6, 3),
+         "ao_workload": f"{W.name}: {m.indices.shape[0]} triangles, {rays.shape[0]} camera rays, "
+                        f"{n_ao} AO rays (closest + AO ray generation + any-hit + resolve)"}
+    log(f"ao: {r}")
     acc.close()
     return r
 

@@ -184,6 +184,31 @@ rt_status rt_trace_closest(rt_accel accel, const rt_ray* rays, uint32_t n, rt_hi
 rt_status rt_trace_any(rt_accel accel, const rt_ray* rays, uint32_t n, uint8_t* occluded,
                        void* stream);
 
+/* ---- ambient occlusion (§4), a workload driving the queries ------------- */
+
+/* Ambient-occlusion rays for the closest hits of a single-level accel.  For
+ * ray i with hit (hits[i], as written by rt_trace_closest) and sample k,
+ * with the uniforms xi[2(i*samples + k) + {0,1}] (DEVICE, float32 in [0,1)):
+ * shading point p = o + t d; unit geometric normal n of the hit triangle
+ * turned toward the incoming ray; tangent t0 = (v1 - v0)/|v1 - v0| and
+ * bi-tangent t1 = n x t0 (§4.1); the cosine-weighted direction of §4.1
+ * (phi = 2 pi xi0, rr = sqrt(xi1); (rr cos phi, sqrt(1 - rr^2), rr sin phi)
+ * in the (t0, n, t1) frame); origin p + offset n (§4.2 self-intersection
+ * offset); t in [0, radius] (§4.2 limited length).  Written to
+ * ao_rays[i*samples + k] (DEVICE); a miss gives void rays (tmin 1 > tmax 0,
+ * never occluded).  Computed in float64, rounded once to float32.
+ * Errors: RT_ERROR_UNSUPPORTED on a two-level accel; RT_ERROR_INVALID_VALUE
+ * for samples < 1, a negative or non-finite offset, a negative radius,
+ * n * samples >= 2^31, NULL buffers with n > 0, misaligned records. */
+rt_status rt_ao_rays(rt_accel accel, const rt_ray* rays, const rt_hit* hits, uint32_t n,
+                     uint32_t samples, const float* xi, float offset, float radius,
+                     rt_ray* ao_rays, void* stream);
+
+/* ao[i] = (number of k < samples with occluded[i*samples + k] != 0) /
+ * samples (DEVICE buffers): the occluded fraction of §4's listing. */
+rt_status rt_ao_resolve(const uint8_t* occluded, uint32_t n, uint32_t samples, float* ao,
+                        void* stream);
+
 /* ---- query variants (§6.2: a stack traversal finds the nearest, any or
  * all intersections; §7.5 names ray masks and intersection filters) ------- */
 

@@ -226,6 +226,44 @@ def trace_all(accel: Accel, rays: torch.Tensor, capacity: int, ray_masks=None, s
     return hits, inst, counts
 
 
+def ao_rays(accel: Accel, rays: torch.Tensor, hits: torch.Tensor, xi: torch.Tensor, offset: float,
+            radius: float) -> torch.Tensor:
+    """rt_ao_rays: (n * samples, 8) ambient-occlusion rays from closest hits;
+    xi (n, samples, 2) float32 uniforms on the device."""
+    _require(rays, "rays", torch.float32, 8)
+    _require(hits, "hits", torch.float32, 4)
+    n = rays.shape[0]
+    if xi.dtype != torch.float32 or not xi.is_contiguous() or xi.dim() != 3 or xi.shape[0] != n \
+            or xi.shape[2] != 2 or xi.device.type != "cuda":
+        raise ValueError("xi must be a contiguous (n, samples, 2) float32 cuda tensor")
+    samples = xi.shape[1]
+    out = torch.empty((n * samples, 8), dtype=torch.float32, device=rays.device)
+    capi.call("rt_ao_rays", accel.handle, _ptr(rays), _ptr(hits), n, samples, _ptr(xi), float(offset),
+              float(radius), _ptr(out), C.c_void_p(_stream()))
+    return out
+
+
+def ao_resolve(occluded: torch.Tensor, samples: int) -> torch.Tensor:
+    """rt_ao_resolve: per-ray occluded fraction of `samples` occlusion bytes."""
+    if occluded.dtype != torch.uint8 or not occluded.is_contiguous() or occluded.device.type != "cuda":
+        raise ValueError("occluded must be a contiguous uint8 cuda tensor")
+    n = occluded.numel() // samples
+    ao = torch.empty((n,), dtype=torch.float32, device=occluded.device)
+    capi.call("rt_ao_resolve", _ptr(occluded), n, int(samples), _ptr(ao), C.c_void_p(_stream()))
+    return ao
+
+
+def ambient_occlusion(accel: Accel, rays: torch.Tensor, xi: torch.Tensor, offset: float,
+                      radius: float):
+    """The ambient-occlusion workload of §4 on the library: closest hits of
+    the primary rays, AO rays from them, any-hit queries, occluded fraction.
+    Returns (ao (n,), hits (n,4), ao_rays (n*samples, 8), occluded)."""
+    hits, _ = trace_closest(accel, rays)
+    ar = ao_rays(accel, rays, hits, xi, offset, radius)
+    occ = trace_any(accel, ar)
+    return ao_resolve(occ, xi.shape[1]), hits, ar, occ
+
+
 def hit_fields(hits: torch.Tensor):
     """(t, prim_id (int64, -1 for a miss), u, v) views of a hit tensor."""
     t = hits[:, 0]

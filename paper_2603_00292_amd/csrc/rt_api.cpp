@@ -849,6 +849,47 @@ rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const 
   return ok();
 }
 
+rt_status rt_ao_rays(rt_accel accel, const rt_ray* rays, const rt_hit* hits, uint32_t n,
+                     uint32_t samples, const float* xi, float offset, float radius,
+                     rt_ray* ao_rays, void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays: NULL accel");
+  if (accel->two_level) return fail(RT_ERROR_UNSUPPORTED, "rt_ao_rays: two-level accels are not supported");
+  if (samples < 1) return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays: samples must be >= 1");
+  if (!(radius >= 0.0f) || !(offset >= 0.0f) || !std::isfinite(offset))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays: offset must be finite and >= 0, radius >= 0");
+  if (n == 0) return ok();
+  if ((uint64_t)n * samples > 0x7FFFFFFFull)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays: n * samples >= 2^31");
+  if (!rays || !hits || !xi || !ao_rays) return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays: NULL buffer with n > 0");
+  if (!aligned16(rays) || !aligned16(hits) || !aligned16(ao_rays))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays: rays, hits and ao_rays must be 16-byte aligned");
+  rt_status st = check_device(accel->device);
+  if (st != RT_SUCCESS) return st;
+  AoParams p{};
+  p.mesh = accel->host_meshes[0];
+  p.rays = rays;
+  p.hits = hits;
+  p.xi = xi;
+  p.out = ao_rays;
+  p.n = n;
+  p.samples = samples;
+  p.offset = offset;
+  p.radius = radius;
+  RT_HIP(rtk_launch_ao_rays(p, static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
+rt_status rt_ao_resolve(const uint8_t* occluded, uint32_t n, uint32_t samples, float* ao,
+                        void* stream) {
+  if (samples < 1) return fail(RT_ERROR_INVALID_VALUE, "rt_ao_resolve: samples must be >= 1");
+  if (n == 0) return ok();
+  if ((uint64_t)n * samples > 0x7FFFFFFFull)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_ao_resolve: n * samples >= 2^31");
+  if (!occluded || !ao) return fail(RT_ERROR_INVALID_VALUE, "rt_ao_resolve: NULL buffer with n > 0");
+  RT_HIP(rtk_launch_ao_resolve(occluded, n, samples, ao, static_cast<hipStream_t>(stream)));
+  return ok();
+}
+
 rt_status rt_refit(rt_accel accel, const float* vertices, void* stream) {
   if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_refit: NULL accel");
   if (accel->two_level) return fail(RT_ERROR_UNSUPPORTED, "rt_refit: two-level accels are not supported");

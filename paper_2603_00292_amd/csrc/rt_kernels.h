@@ -77,6 +77,19 @@ struct BackwardInstParams {
   float* d_directions;
 };
 
+// Ambient-occlusion rays from closest hits (one thread per ray sample).
+struct AoParams {
+  rt_mesh_dev mesh;
+  const rt_ray* rays;
+  const rt_hit* hits;
+  const float* xi;        // n * samples * 2 uniforms
+  rt_ray* out;            // n * samples rays
+  uint32_t n;
+  uint32_t samples;
+  double offset;
+  float radius;
+};
+
 // Kernel handle for a variant (mode 0: one accel, mode 1: batched closest,
 // mode 2: one accel with query options, mode 3: all hits with query options;
 // modes 2 and 3 exist for stack 16 / workgroup 256 only); nullptr when the
@@ -96,3 +109,6 @@ hipError_t rtk_launch_refit_tris(rt_tri_rec* tris, uint32_t n, const rt_mesh_dev
 hipError_t rtk_launch_refit_nodes(int width, float* nodes, const rt_tri_rec* tris,
                                   const uint32_t* node_ids, uint32_t count, hipStream_t stream);
 hipError_t rtk_launch_fill(uint32_t* ptr, uint32_t n, uint32_t value, hipStream_t stream);
+hipError_t rtk_launch_ao_rays(const AoParams& p, hipStream_t stream);
+hipError_t rtk_launch_ao_resolve(const uint8_t* occluded, uint32_t n, uint32_t samples, float* ao,
+                                 hipStream_t stream);

@@ -952,6 +952,72 @@ __global__ __launch_bounds__(256) void refit_nodes_kernel(float* nodes, const rt
   }
 }
 
+// ---------------------------------------------------------------------------
+// ambient occlusion (§4): rays from closest hits, then the occluded fraction
+// ---------------------------------------------------------------------------
+// Sample k of ray r: shading point p = o + t d, unit geometric normal n of
+// the hit triangle turned toward the incoming ray, tangent t0 = (v1 - v0)
+// normalised, bi-tangent t1 = n x t0; the cosine-weighted direction of §4.1
+// (phi = 2 pi xi0, rr = sqrt(xi1), (rr cos phi, sqrt(max(1 - rr^2, 0)),
+// rr sin phi) in the (t0, n, t1) frame); origin p + offset n; t in
+// [0, radius].  Misses give void rays (tmin = 1 > tmax = 0).  float64 math,
+// rounded once to float32.
+__global__ __launch_bounds__(256) void ao_rays_kernel(AoParams P) {
+  uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= P.n * P.samples) return;
+  uint32_t ray = i / P.samples;
+  float4* out = reinterpret_cast<float4*>(P.out + i);
+  float4 h = *reinterpret_cast<const float4*>(P.hits + ray);
+  uint32_t prim = __float_as_uint(h.y);
+  if (prim == RT_INVALID_ID || prim >= P.mesh.triangle_count) {
+    out[0] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+    out[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    return;
+  }
+  rt_ray q = load_ray(P.rays, ray);
+  const uint32_t* ix = P.mesh.indices + 3 * (size_t)prim;
+  double v[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[k][c] = P.mesh.vertices[3 * (size_t)ix[k] + c];
+  double ax = v[1][0] - v[0][0], ay = v[1][1] - v[0][1], az = v[1][2] - v[0][2];
+  double bx = v[2][0] - v[0][0], by = v[2][1] - v[0][1], bz = v[2][2] - v[0][2];
+  double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+  double nl = sqrt(nx * nx + ny * ny + nz * nz);
+  nx /= nl; ny /= nl; nz /= nl;
+  if (nx * q.dx + ny * q.dy + nz * q.dz > 0.0) {
+    nx = -nx; ny = -ny; nz = -nz;
+  }
+  double al = sqrt(ax * ax + ay * ay + az * az);
+  double t0x = ax / al, t0y = ay / al, t0z = az / al;
+  double t1x = ny * t0z - nz * t0y, t1y = nz * t0x - nx * t0z, t1z = nx * t0y - ny * t0x;
+  double t = h.x;
+  double px = q.ox + q.dx * t, py = q.oy + q.dy * t, pz = q.oz + q.dz * t;
+  const float* u = P.xi + 2 * (size_t)i;
+  double phi = 6.283185307179586476925286766559 * (double)u[0];
+  double rr = sqrt((double)u[1]);
+  double x = rr * cos(phi), z = rr * sin(phi);
+  double y = 1.0 - rr * rr;
+  y = sqrt(y > 0.0 ? y : 0.0);
+  double dx = t0x * x + t1x * z + nx * y;
+  double dy = t0y * x + t1y * z + ny * y;
+  double dz = t0z * x + t1z * z + nz * y;
+  out[0] = make_float4((float)(px + nx * P.offset), (float)(py + ny * P.offset),
+                       (float)(pz + nz * P.offset), 0.0f);
+  out[1] = make_float4((float)dx, (float)dy, (float)dz, P.radius);
+}
+
+__global__ __launch_bounds__(256) void ao_resolve_kernel(const uint8_t* occ, uint32_t n,
+                                                         uint32_t samples, float* ao) {
+  uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= n) return;
+  const uint8_t* o = occ + (size_t)i * samples;
+  uint32_t c = 0;
+  for (uint32_t k = 0; k < samples; ++k) c += o[k] ? 1u : 0u;
+  ao[i] = (float)c / (float)samples;
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t n, uint32_t value) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = value;
@@ -1099,6 +1165,23 @@ hipError_t rtk_launch_refit_nodes(int width, float* nodes, const rt_tri_rec* tri
                                : reinterpret_cast<const void*>(&rtk::refit_nodes_kernel<8>);
   void* args[] = {&nodes, &tris, &node_ids, &count};
   return hipLaunchKernel(k, dim3((count + 255) / 256), dim3(256), args, 0, stream);
+}
+
+hipError_t rtk_launch_ao_rays(const AoParams& p, hipStream_t stream) {
+  uint64_t total = (uint64_t)p.n * p.samples;
+  if (total == 0) return hipSuccess;
+  AoParams q = p;
+  void* args[] = {&q};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::ao_rays_kernel),
+                         dim3((uint32_t)((total + 255) / 256)), dim3(256), args, 0, stream);
+}
+
+hipError_t rtk_launch_ao_resolve(const uint8_t* occluded, uint32_t n, uint32_t samples, float* ao,
+                                 hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  void* args[] = {&occluded, &n, &samples, &ao};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::ao_resolve_kernel),
+                         dim3((n + 255) / 256), dim3(256), args, 0, stream);
 }
 
 hipError_t rtk_launch_fill(uint32_t* ptr, uint32_t n, uint32_t value, hipStream_t stream) {

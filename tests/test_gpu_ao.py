@@ -1,0 +1,137 @@
+"""GPU parity of the ambient-occlusion workload (§4) driven through the
+library: closest hits of camera rays (rt_trace_closest), AO rays from them
+(rt_ao_rays), any-hit queries (rt_trace_any) and the occluded fraction
+(rt_ao_resolve), against the oracle's own closest hits, AO rays and any-hit
+acceptable sets on the same seeded camera rays and uniforms."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from helpers import NONE, to_gpu_scene
+from paper_2603_00292_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+# AO rays of the two sides differ only by the rounding of t (float32 on the
+# GPU, float64 in the oracle) and the final float32 rounding
+ORIGIN_REL = 2.0 ** -21   # of (|t| |d| + largest |p| coordinate + 1)
+DIR_ABS = 1e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    from paper_2603_00292_amd import api
+
+    torch.cuda.set_device(0)
+    ctx = api.Context(0)
+    yield torch, api, ctx
+    torch.cuda.synchronize()
+
+
+def _run(gpu, W):
+    torch, api, ctx = gpu
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    rays = torch.from_numpy(W.rays).cuda()
+    xi = torch.from_numpy(W.extra["xi"]).cuda()
+    ao, hits, ar, occ = api.ambient_occlusion(acc, rays, xi, W.extra["offset"], W.extra["radius"])
+    torch.cuda.synchronize()
+    out = (ao.cpu().numpy(), hits.cpu().numpy(), ar.cpu().numpy(), occ.cpu().numpy())
+    return acc, out
+
+
+def _check_pixels(orc, W, S, idx, h, ar, occ, ao, label):
+    """For the pixels idx whose closest hit the oracle pins: AO rays equal the
+    oracle's up to rounding, and each occlusion count lies between the
+    oracle's sure and sure-plus-maybe counts."""
+    N = W.extra["samples"]
+    rays = W.rays[idx]
+    A = orc.accept(S, rays)
+    _, op, otuv = orc.closest(S, rays)
+    prim = h[idx, 1].copy().view(np.uint32)
+    keep = A.pinned
+    assert (prim[keep] == op[keep]).all(), label
+    oar = orc.ao_rays(S, rays, op, otuv, W.extra["xi"][idx], W.extra["offset"], W.extra["radius"])
+    oar = oar.reshape(-1, N, 8)
+    gar = ar.reshape(-1, N, 8)[idx]
+    hit = keep & (op != NONE)
+    t = np.abs(otuv[hit, 0])[:, None]
+    dn = np.linalg.norm(rays[hit, 4:7].astype(np.float64), axis=1)[:, None]
+    scale = t * dn + np.abs(oar[hit, :, 0:3]).max(2) + 1.0
+    do = np.abs(gar[hit, :, 0:3].astype(np.float64) - oar[hit, :, 0:3]).max(2)
+    dd = np.abs(gar[hit, :, 4:7].astype(np.float64) - oar[hit, :, 4:7]).max(2)
+    say(label, "max origin err / scale", (do / scale).max(), "max direction err", dd.max())
+    assert (do <= ORIGIN_REL * scale).all() and (dd <= DIR_ABS).all(), label
+    assert (gar[hit, :, 3] == oar[hit, :, 3]).all() and (gar[hit, :, 7] == oar[hit, :, 7]).all()
+    miss = keep & (op == NONE)
+    assert (gar[miss, :, 3] > gar[miss, :, 7]).all()
+    # occlusion per pixel within the oracle's acceptable range
+    Ao = orc.accept(S, oar[keep].reshape(-1, 8))
+    must = (Ao.any_class == 1).reshape(-1, N).sum(1)
+    may = (Ao.any_class == 2).reshape(-1, N).sum(1)
+    got = occ.reshape(-1, N)[idx][keep].astype(np.int64).sum(1)
+    bad = (got < must) | (got > must + may)
+    assert not bad.any(), f"{label}: {int(bad.sum())} pixels outside [{must[bad][:4]}, +{may[bad][:4]}]"
+    assert np.allclose(ao[idx][keep], got / N)
+    return {"pixels": int(keep.sum()), "hits": int(hit.sum()), "ao_mean": float(ao[idx][keep].mean()),
+            "undecided_samples": int(may.sum())}
+
+
+def test_ao_small_every_pixel(gpu, orc):
+    """128 x 128 pixels, 8 samples each: every pinned pixel checked."""
+    W = wl.ao_terrain(128, 128, 8, k=330)
+    acc, (ao, h, ar, occ) = _run(gpu, W)
+    S = orc.OracleScene.from_scene(W.scene)
+    st = _check_pixels(orc, W, S, np.arange(W.rays.shape[0]), h, ar, occ, ao, "ao small")
+    say(st)
+    assert st["pixels"] > 0.97 * W.rays.shape[0] and st["ao_mean"] > 0.05
+    acc.close()
+
+
+def test_ao_full_size_sampled(gpu, orc):
+    """The benchmark's configuration (1024 x 1024 pixels, 16 samples, 16.8 M
+    AO rays): 256 sampled pixels against the oracle."""
+    W = wl.ao_terrain()
+    acc, (ao, h, ar, occ) = _run(gpu, W)
+    assert ar.shape == (1024 * 1024 * 16, 8)
+    say("image mean AO", float(ao.mean()))
+    idx = np.sort(wl.rng_for(331).choice(W.rays.shape[0], 256, replace=False))
+    S = orc.OracleScene.from_scene(W.scene)
+    st = _check_pixels(orc, W, S, idx, h, ar, occ, ao, "ao full sampled")
+    say(st)
+    assert st["pixels"] > 240
+    acc.close()
+
+
+def test_ao_errors(gpu):
+    torch, api, ctx = gpu
+    from paper_2603_00292_amd import _capi
+
+    W = wl.aimed_instances(n_inst=2, n_rays=64, k=332)
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    rays = torch.from_numpy(W.rays).cuda()
+    hits, _ = api.trace_closest(acc, rays)
+    xi = torch.zeros((64, 4, 2), dtype=torch.float32, device="cuda")
+    with pytest.raises(_capi.RtError) as e:
+        api.ao_rays(acc, rays, hits, xi, 1e-4, 1.0)
+    assert e.value.status == _capi.RT_ERROR_UNSUPPORTED
+    acc.close()
+    m = W.scene.meshes[0]
+    single = api.Accel(ctx, [(torch.from_numpy(m.vertices).cuda(),
+                              torch.from_numpy(m.indices.view(np.int32)).cuda())])
+    hits, _ = api.trace_closest(single, rays)
+    with pytest.raises(_capi.RtError) as e:
+        api.ao_rays(single, rays, hits, xi[:, :0].contiguous(), 1e-4, 1.0)
+    assert e.value.status == _capi.RT_ERROR_INVALID_VALUE
+    with pytest.raises(_capi.RtError) as e:
+        api.ao_rays(single, rays, hits, xi, -1.0, 1.0)
+    assert e.value.status == _capi.RT_ERROR_INVALID_VALUE
+    out = api.ao_rays(single, rays[:0], hits[:0], xi[:0], 1e-4, 1.0)
+    assert out.shape == (0, 8)
+    single.close()
