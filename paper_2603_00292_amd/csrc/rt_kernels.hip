@@ -143,8 +143,12 @@ __device__ __forceinline__ void visit_node(const float* nodes, uint32_t idx, con
     // zero direction component), which is the correct "no constraint".
     float tn = fmaxf(fmaxf(tnx, tny), fmaxf(tnz, r.tmin));
     float tf = fminf(fminf(tfx, tfy), tfz);
-    tf = fmaf(fabsf(tf), kSlabWiden, tf);
+    // cull first, then widen: a far distance of -inf (a zero direction
+    // component with the origin outside that slab) widens to NaN, which
+    // fails the test below; widened first, the NaN would be dropped by the
+    // NaN-ignoring fminf and the box kept
     tf = fminf(tf, tcull);
+    tf = fmaf(fabsf(tf), kSlabWiden, tf);
     bool hit = (tn <= tf) & (tn < __int_as_float(0x7f800000));
     key[i] = hit ? ((__float_as_uint(tn) & ~((1u << SH) - 1u)) | (uint32_t)i) : 0xFFFFFFFFu;
   }

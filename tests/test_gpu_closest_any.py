@@ -257,3 +257,38 @@ def test_grazing_rays_from_afar(gpu, orc):
     say(st)
     assert st["hits"] > 20000
     acc.close()
+
+
+def test_zero_direction_components(gpu, orc):
+    """Rays with exactly zero direction components (a pinhole camera's centre
+    column, axis-aligned rays) against the oracle, and their traversal cost:
+    node visits stay within 1.5x of the same rays with the zero components
+    replaced by 1e-7 (a box on the far side of such a slab must be culled,
+    not kept through a NaN far distance)."""
+    torch, api, ctx = gpu
+    W = wl.ao_terrain(512, 512, 1, k=208)
+    rays = W.rays.copy()
+    rng = wl.rng_for(209)
+    axis = np.zeros((4096, 8), np.float32)
+    axis[:, 0:3] = rng.uniform(0, 16, (4096, 3))
+    axis[:, 1] = rng.uniform(-3, 3, 4096)
+    k = rng.integers(0, 3, 4096)
+    axis[np.arange(4096), 4 + k] = rng.choice([-1.0, 1.0], 4096)
+    axis[:, 7] = np.inf
+    centre = rays[rays[:, 4] == 0]
+    assert centre.shape[0] == 512
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    S = orc.OracleScene.from_scene(W.scene)
+    for name, R in (("camera centre column", centre), ("axis-aligned", axis)):
+        h, _ = trace(gpu, acc, R)
+        occ = any_hit(gpu, acc, R)
+        A = orc.accept(S, R)
+        st = check_closest(h, A, label=name)
+        check_any(occ, A, label=name)
+        P = R.copy()
+        P[:, 4:7] = np.where(P[:, 4:7] == 0, np.float32(1e-7), P[:, 4:7])
+        c0, _ = api.trace_counters(acc, torch.from_numpy(R).cuda())
+        c1, _ = api.trace_counters(acc, torch.from_numpy(P).cuda())
+        say(name, st, "nodes per ray", c0[0] / len(R), "perturbed", c1[0] / len(P))
+        assert c0[0] <= 1.5 * c1[0] + 4 * len(R)
+    acc.close()
