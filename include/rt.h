@@ -99,7 +99,15 @@ typedef struct rt_mesh_desc {
 
 /* Build options.  node_width: 0 = default (4), or 2, 4, 8 (§6.2: wide trees
  * of branching factor 4 or 8).  max_leaf_size: 0 = default (4), at most 15.
- * flags: reserved, must be 0. */
+ * flags: 0 (host binned-SAH build) or RT_BUILD_DEVICE. */
+/* Build the tree on the GPU (§6.2 construction paragraph, the bottom-up
+ * family): Morton order of the triangle centres, a binary radix tree over
+ * the sorted codes, boxes fitted bottom-up, collapse to node_width.  Much
+ * faster to build than the host SAH build, with a tree that traces slower;
+ * single-level builds only (RT_ERROR_UNSUPPORTED with instances); vertex
+ * and index pointers and strides must be multiples of 4 bytes. */
+#define RT_BUILD_DEVICE 0x1u
+
 typedef struct rt_build_options {
   uint32_t node_width;
   uint32_t max_leaf_size;

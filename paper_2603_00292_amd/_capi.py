@@ -66,6 +66,7 @@ class rt_query_options(C.Structure):
 
 
 RT_MAX_HIT_CAPACITY = 64
+RT_BUILD_DEVICE = 0x1
 
 
 class rt_tune_entry(C.Structure):

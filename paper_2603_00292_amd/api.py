@@ -78,7 +78,8 @@ class Context:
 
 
 class Accel:
-    """An acceleration structure built with ``rt_build``.
+    """An acceleration structure built with ``rt_build`` (on the host with
+    binned SAH, or on the GPU with ``device_build=True``).
 
     meshes: list of (vertices (V,3) float32 cuda, indices (N,3) int32/uint32
     cuda).  Single level: one mesh and no instances.  Two-level:
@@ -86,7 +87,7 @@ class Accel:
     tensors) of mesh ids and (sx,sy,sz,qx,qy,qz,qw,tx,ty,tz) frames."""
 
     def __init__(self, ctx: Context, meshes, inst_mesh=None, inst_srt=None, node_width: int = 0,
-                 max_leaf_size: int = 0):
+                 max_leaf_size: int = 0, device_build: bool = False):
         import numpy as np
 
         self.ctx = ctx
@@ -114,7 +115,8 @@ class Accel:
             self._im, self._srt = im, srt
             im_p = C.c_void_p(im.ctypes.data)
             srt_p = C.c_void_p(srt.ctypes.data)
-        opts = capi.rt_build_options(int(node_width), int(max_leaf_size), 0)
+        opts = capi.rt_build_options(int(node_width), int(max_leaf_size),
+                                     capi.RT_BUILD_DEVICE if device_build else 0)
         h = C.c_void_p()
         capi.call("rt_build", ctx.handle, descs, len(meshes), im_p, srt_p, n_inst, C.byref(opts),
                   C.c_void_p(_stream()), C.byref(h))

@@ -21,6 +21,7 @@
 
 #include "../../include/rt.h"
 #include "bvh_build.h"
+#include "bvh_device.h"
 #include "rt_kernels.h"
 #include "rt_layout.h"
 
@@ -351,6 +352,67 @@ static rtb::Box world_box(const rtb::Box& b, const rt_srt& f) {
   return out;
 }
 
+// Single-level accel built on the device (RT_BUILD_DEVICE).
+static rt_status build_on_device(rt_context ctx, const rt_mesh_desc& mesh, int width, int max_leaf,
+                                 hipStream_t s, rt_accel* out) {
+  rt_accel_s* a = new (std::nothrow) rt_accel_s();
+  if (!a) return fail(RT_ERROR_OUT_OF_MEMORY, "rt_build: host allocation");
+  a->ctx = ctx;
+  a->device = ctx->device;
+  a->width = width;
+  a->two_level = false;
+  a->info.node_width = (uint32_t)width;
+  rtd::Input in{static_cast<const float*>(mesh.vertices), mesh.vertex_count, mesh.vertex_stride,
+                static_cast<const uint32_t*>(mesh.indices), mesh.triangle_count, mesh.index_stride,
+                width, max_leaf};
+  rtd::Output o;
+  bool index_error = false;
+  hipError_t e;
+  try {
+    e = rtd::build(in, o, index_error, s);
+  } catch (const std::bad_alloc&) {
+    e = hipErrorOutOfMemory;
+  }
+  for (void* p : o.owned) a->owned.push_back(p);
+  a->info.device_bytes += o.owned_bytes;
+  if (e != hipSuccess) {
+    destroy_accel(a);
+    return fail(e == hipErrorOutOfMemory ? RT_ERROR_OUT_OF_MEMORY : RT_ERROR_HIP,
+                "rt_build (device): %s", hipGetErrorString(e));
+  }
+  if (index_error) {
+    destroy_accel(a);
+    return fail(RT_ERROR_INDEX_OUT_OF_RANGE, "rt_build: a vertex index is >= vertex_count");
+  }
+  a->nodes = o.nodes;
+  a->tris = o.tris;
+  a->root = o.tri_count ? o.root : RT_CHILD_EMPTY;
+  a->max_stack = std::max(o.max_stack, 1u);
+  a->refit_nodes = o.tri_count ? o.refit_nodes : nullptr;
+  a->refit_levels = o.tri_count ? o.refit_levels : std::vector<uint32_t>();
+  a->info.node_count = o.tri_count ? o.node_count : 0;
+  a->info.triangle_count = o.tri_count;
+  a->info.input_triangles = mesh.triangle_count;
+  a->info.max_depth = o.tri_count ? o.max_depth : 0;
+  a->info.max_stack = a->max_stack;
+  a->info.leaf_count = o.leaf_count;
+  a->info.sah_cost = o.sah_cost;
+  a->host_meshes.assign(1, rt_mesh_dev{o.vertices, o.indices, mesh.vertex_count, mesh.triangle_count});
+  rt_status st = dev_alloc(a, &a->meshes, 1);
+  if (st != RT_SUCCESS) {
+    destroy_accel(a);
+    return st;
+  }
+  hipError_t ce = hipMemcpyAsync(a->meshes, a->host_meshes.data(), sizeof(rt_mesh_dev), hipMemcpyHostToDevice, s);
+  if (ce == hipSuccess) ce = hipStreamSynchronize(s);
+  if (ce != hipSuccess) {
+    destroy_accel(a);
+    return fail(RT_ERROR_HIP, "rt_build (device): %s", hipGetErrorString(ce));
+  }
+  *out = a;
+  return ok();
+}
+
 rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_count,
                    const uint32_t* instance_mesh, const rt_srt* instance_srt,
                    uint32_t instance_count, const rt_build_options* options, void* stream,
@@ -368,8 +430,11 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
   if (instance_count > RT_INST_INDEX_MASK)
     return fail(RT_ERROR_INVALID_VALUE, "rt_build: too many instances");
   int width = 4, max_leaf = 4;
+  bool on_device = false;
   if (options) {
-    if (options->flags != 0) return fail(RT_ERROR_INVALID_VALUE, "rt_build: flags must be 0");
+    if ((options->flags & ~RT_BUILD_DEVICE) != 0)
+      return fail(RT_ERROR_INVALID_VALUE, "rt_build: unknown flags");
+    on_device = (options->flags & RT_BUILD_DEVICE) != 0;
     if (options->node_width != 0) width = (int)options->node_width;
     if (options->max_leaf_size != 0) max_leaf = (int)options->max_leaf_size;
   }
@@ -397,9 +462,19 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
     if (f.qx == 0.0f && f.qy == 0.0f && f.qz == 0.0f && f.qw == 0.0f)
       return fail(RT_ERROR_INVALID_VALUE, "rt_build: instance %u has a zero quaternion", j);
   }
+  if (on_device) {
+    if (instance_count > 0)
+      return fail(RT_ERROR_UNSUPPORTED, "rt_build: the device build takes single-level meshes only");
+    const rt_mesh_desc& d = meshes[0];
+    if (((uintptr_t)d.vertices | (uintptr_t)d.indices | d.vertex_stride | d.index_stride) & 3u)
+      return fail(RT_ERROR_INVALID_VALUE, "rt_build: the device build needs 4-byte aligned pointers and strides");
+    if (d.triangle_count > RT_MAX_TRI_RECORDS)
+      return fail(RT_ERROR_INVALID_VALUE, "rt_build: mesh too large for one accel");
+  }
   rt_status st = check_device(ctx->device);
   if (st != RT_SUCCESS) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  if (on_device) return build_on_device(ctx, meshes[0], width, max_leaf, s, out);
   int threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
 
   rt_accel_s* a = new (std::nothrow) rt_accel_s();

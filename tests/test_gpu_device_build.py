@@ -1,0 +1,199 @@
+"""GPU parity of the device-side BVH build (RT_BUILD_DEVICE).
+
+Closest-hit answers do not depend on the tree when box culling is
+conservative (the lexicographic (t, prim) minimum over every triangle the
+float32 test accepts), so an accel built on the GPU must answer bit for bit
+like the host-built accel of the same mesh, and stay inside the oracle's
+acceptable sets."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+
+from helpers import NONE, check_any, check_closest, to_gpu_scene
+from paper_2603_00292_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    from paper_2603_00292_amd import api
+
+    torch.cuda.set_device(0)
+    ctx = api.Context(0)
+    yield torch, api, ctx
+    torch.cuda.synchronize()
+
+
+def both(gpu, scene, rays_np, **build):
+    torch, api, ctx = gpu
+    rays = torch.from_numpy(np.ascontiguousarray(rays_np)).cuda()
+    out = []
+    for dev in (False, True):
+        acc = to_gpu_scene(api, torch, ctx, scene, device_build=dev, **build)
+        h, _ = api.trace_closest(acc, rays)
+        occ = api.trace_any(acc, rays)
+        torch.cuda.synchronize()
+        out.append((h.cpu().numpy(), occ.cpu().numpy(), acc.info))
+        acc.close()
+    return out
+
+
+@pytest.mark.parametrize("width", [4, 2, 8])
+def test_device_build_answers_like_host_build(gpu, orc, width):
+    W = wl.random_triangles()
+    (hh, oh, ih), (hd, od, idv) = both(gpu, W.scene, W.rays, node_width=width)
+    say("host", ih)
+    say("device", idv)
+    assert np.array_equal(hh.view(np.uint32), hd.view(np.uint32))
+    assert np.array_equal(oh, od)
+    assert idv["triangle_count"] == ih["triangle_count"] == 4096
+    assert idv["leaf_count"] > 0 and idv["max_stack"] >= 1 and idv["node_count"] > 0
+    A = orc.accept(orc.OracleScene.from_scene(W.scene), W.rays)
+    check_closest(hd, A, label=f"device build W={width}")
+    check_any(od, A, label=f"device build any W={width}")
+
+
+@pytest.mark.parametrize("leaf", [1, 15])
+def test_device_build_leaf_sizes(gpu, leaf):
+    rng = wl.rng_for(340)
+    V, I = wl.random_triangle_soup(rng, 3001, 0.08)
+    rays = wl.box_rays(rng, 20011, 0.0, 1.0)
+    (hh, oh, _), (hd, od, idv) = both(gpu, wl.Scene([wl.Mesh(V, I)]), rays, max_leaf_size=leaf)
+    assert np.array_equal(hh.view(np.uint32), hd.view(np.uint32)) and np.array_equal(oh, od)
+    say("leaf", leaf, idv)
+
+
+def test_device_build_headline_mesh(gpu):
+    """1,310,720 triangles, 4,194,304 incoherent rays: bit-identical answers;
+    build times and trace times of both trees reported."""
+    torch, api, ctx = gpu
+    W = wl.icosphere_incoherent()
+    m = W.scene.meshes[0]
+    V = torch.from_numpy(m.vertices).cuda()
+    I = torch.from_numpy(m.indices.view(np.int32)).cuda()
+    rays = torch.from_numpy(W.rays).cuda()
+    res = {}
+    for dev in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        acc = api.Accel(ctx, [(V, I)], device_build=dev)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        h, _ = api.trace_closest(acc, rays)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            api.trace_closest(acc, rays)
+        e1.record()
+        torch.cuda.synchronize()
+        res[dev] = (h.cpu().numpy(), t_build, e0.elapsed_time(e1) / 5, acc.info)
+        acc.close()
+    say("host build %.3f s, trace %.3f ms, %s" % (res[False][1], res[False][2], res[False][3]))
+    say("device build %.3f s, trace %.3f ms, %s" % (res[True][1], res[True][2], res[True][3]))
+    assert np.array_equal(res[False][0].view(np.uint32), res[True][0].view(np.uint32))
+    assert res[True][3]["triangle_count"] == 1310720
+
+
+def test_device_build_degenerate_empty_strided_errors(gpu, orc):
+    torch, api, ctx = gpu
+    from paper_2603_00292_amd import _capi
+    import ctypes as C
+
+    rng = wl.rng_for(341)
+    rays = wl.box_rays(rng, 512, -1, 2)
+    # all degenerate
+    V = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0], [0, 0, 0], [0, 0, 0], [1, 1, 0]], np.float32)
+    I = np.array([[0, 1, 2], [3, 4, 5]], np.uint32)
+    acc = to_gpu_scene(api, torch, ctx, wl.Scene([wl.Mesh(V, I)]), device_build=True)
+    assert acc.info["triangle_count"] == 0 and acc.info["input_triangles"] == 2
+    h, _ = api.trace_closest(acc, torch.from_numpy(rays).cuda())
+    assert (h.cpu().numpy()[:, 1].view(np.uint32) == NONE).all()
+    acc.close()
+    # empty mesh
+    E = wl.Scene([wl.Mesh(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.uint32))])
+    acc = to_gpu_scene(api, torch, ctx, E, device_build=True)
+    assert acc.info["node_count"] == 0
+    acc.close()
+    # one triangle
+    W1 = wl.Scene([wl.Mesh(np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32), np.array([[0, 1, 2]], np.uint32))])
+    r1 = np.array([[0.25, 0.25, 1, 0, 0, 0, -1, np.inf]], np.float32)
+    (hh, _, _), (hd, _, idv) = both(gpu, W1, r1)
+    assert np.array_equal(hh.view(np.uint32), hd.view(np.uint32)) and hd[0, 1].view(np.uint32) == 0
+    # strided vertices (16-byte records) and degenerate triangles mixed in
+    W = wl.random_triangles(n_tri=2048, n_rays=8192, k=342, half=0.05)
+    m = W.scene.meshes[0]
+    V4 = np.zeros((m.vertices.shape[0], 4), np.float32)
+    V4[:, :3] = m.vertices
+    I = m.indices.copy()
+    I[::7, 2] = I[::7, 1]  # every 7th triangle degenerate
+    Vt = torch.from_numpy(V4).cuda()
+    It = torch.from_numpy(I.view(np.int32)).cuda()
+    ctxh = ctx.handle
+    outs = []
+    for flags in (0, _capi.RT_BUILD_DEVICE):
+        desc = _capi.rt_mesh_desc(Vt.data_ptr(), V4.shape[0], 16, It.data_ptr(), I.shape[0], 12)
+        opt = _capi.rt_build_options(4, 4, flags)
+        hnd = C.c_void_p()
+        _capi.call("rt_build", ctxh, C.byref(desc), 1, None, None, 0, C.byref(opt), None, C.byref(hnd))
+        acc = api.Accel.__new__(api.Accel)
+        acc.handle, acc.ctx, acc.two_level, acc._keep = hnd, ctx, False, []
+        h, _ = api.trace_closest(acc, torch.from_numpy(W.rays).cuda())
+        torch.cuda.synchronize()
+        outs.append(h.cpu().numpy())
+        acc.close()
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
+    S = orc.OracleScene([(m.vertices, I)])
+    check_closest(outs[1], orc.accept(S, W.rays), label="strided device build")
+    # errors: an index out of range; misaligned stride; instances
+    bad = m.indices.copy()
+    bad[5, 1] = 10 ** 6
+    with pytest.raises(_capi.RtError) as e:
+        to_gpu_scene(api, torch, ctx, wl.Scene([wl.Mesh(m.vertices, bad)]), device_build=True)
+    assert e.value.status == _capi.RT_ERROR_INDEX_OUT_OF_RANGE
+    desc = _capi.rt_mesh_desc(Vt.data_ptr(), V4.shape[0], 14, It.data_ptr(), I.shape[0], 12)
+    opt = _capi.rt_build_options(4, 4, _capi.RT_BUILD_DEVICE)
+    with pytest.raises(_capi.RtError) as e:
+        _capi.call("rt_build", ctxh, C.byref(desc), 1, None, None, 0, C.byref(opt), None, C.byref(C.c_void_p()))
+    assert e.value.status == _capi.RT_ERROR_INVALID_VALUE
+    Wi = wl.aimed_instances(n_inst=2, n_rays=16, k=343)
+    with pytest.raises(_capi.RtError) as e:
+        to_gpu_scene(api, torch, ctx, Wi.scene, device_build=True)
+    assert e.value.status == _capi.RT_ERROR_UNSUPPORTED
+
+
+def test_refit_of_device_built_accel(gpu):
+    """Refit of a device-built accel answers like a fresh device build of
+    the moved mesh, and refitting back restores the first answers."""
+    torch, api, ctx = gpu
+    W = wl.displaced_grid(nx=128, nz=64, n_rays=65536, k=344)
+    m = W.scene.meshes[0]
+    V0 = torch.from_numpy(m.vertices).cuda()
+    I = torch.from_numpy(m.indices.view(np.int32)).cuda()
+    rays = torch.from_numpy(W.rays).cuda()
+    acc = api.Accel(ctx, [(V0, I)], device_build=True)
+    h0, _ = api.trace_closest(acc, rays)
+    V1 = V0.clone()
+    V1[:, 1] += 0.2 * torch.sin(V1[:, 0] * 0.3)
+    acc.refit(V1)
+    h1, _ = api.trace_closest(acc, rays)
+    fresh = api.Accel(ctx, [(V1, I)], device_build=True)
+    hf, _ = api.trace_closest(fresh, rays)
+    acc.refit(V0)
+    h2, _ = api.trace_closest(acc, rays)
+    torch.cuda.synchronize()
+    assert torch.equal(h1.view(torch.int32), hf.view(torch.int32))
+    assert torch.equal(h0.view(torch.int32), h2.view(torch.int32))
+    assert not torch.equal(h0.view(torch.int32), h1.view(torch.int32))
+    acc.close()
+    fresh.close()
