@@ -143,10 +143,12 @@ def main():
         tuned, _ = autotune.autotune(ctx, V, I, probe, repeats=5)
         width = tuned["node_width"]
         log(f"autotune {time.time() - t0:.1f}s: {tuned}")
+    torch.cuda.synchronize()
     t0 = time.time()
     acc = api.Accel(ctx, [(V, I)], node_width=width)
+    build_host_s = time.time() - t0
     info = acc.info
-    log(f"build {time.time() - t0:.1f}s: {info}")
+    log(f"build {build_host_s:.3f}s: {info}")
     hits = torch.empty((n, 4), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
 
@@ -209,6 +211,7 @@ def main():
     del rays, hits, occ
 
     if not args.no_secondary:
+        secondary.update(device_build_bench(args, torch, api, ctx, stream, V, I, W, width, build_host_s))
         secondary.update(backward_bench(args, torch, np, api, workloads, ctx, stream))
         secondary.update(batched_bench(args, torch, np, api, _capi, workloads, ctx, stream))
         secondary.update(ao_bench(args, torch, np, api, workloads, ctx, stream))
@@ -307,6 +310,26 @@ def ao_bench(args, torch, np, api, workloads, ctx, stream):
          "ao_workload": f"{W.name}: {m.indices.shape[0]} triangles, {rays.shape[0]} camera rays, "
                         f"{n_ao} AO rays (closest + AO ray generation + any-hit + resolve)"}
     log(f"ao: {r}")
+    acc.close()
+    return r
+
+
+def device_build_bench(args, torch, api, ctx, stream, V, I, W, width, build_host_s):
+    """Build times of the host SAH build and the device build of the
+    headline mesh (not part of the metric) and closest-hit throughput on the
+    device-built tree."""
+    rays = torch.from_numpy(W.rays).to(V.device)
+    api.Accel(ctx, [(V, I)], node_width=width, device_build=True).close()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.time()
+    acc = api.Accel(ctx, [(V, I)], node_width=width, device_build=True)
+    torch.cuda.synchronize()
+    build_dev_s = time.time() - t0
+    ms, _ = timed(lambda: api.trace_closest(acc, rays), args.steps, stream, torch)
+    r = {"build_host_ms": round(build_host_s * 1e3, 2), "build_device_ms": round(build_dev_s * 1e3, 2),
+         "device_tree_closest_mrays": round(rays.shape[0] / (ms * 1e-3) / 1e6, 3),
+         "device_tree_sah_cost": round(acc.info["sah_cost"], 2)}
+    log(f"device build: {r}")
     acc.close()
     return r
 
