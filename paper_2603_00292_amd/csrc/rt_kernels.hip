@@ -152,13 +152,23 @@ __device__ __forceinline__ void visit_node(const float* nodes, uint32_t idx, con
     bool hit = (tn <= tf) & (tn < __int_as_float(0x7f800000));
     key[i] = hit ? ((__float_as_uint(tn) & ~((1u << SH) - 1u)) | (uint32_t)i) : 0xFFFFFFFFu;
   }
-  // sort keys ascending (nearest first)
-#define RT_CSWAP(a, b)                     \
-  {                                        \
-    uint32_t lo_ = min(key[a], key[b]);    \
-    uint32_t hi_ = max(key[a], key[b]);    \
-    key[a] = lo_;                          \
-    key[b] = hi_;                          \
+  // sort (key, child) pairs by key, nearest first; missed children (key
+  // 0xFFFFFFFF) sort last.  Moving the child reference with its key costs two
+  // selects per exchange and saves looking it up by slot afterwards.
+  uint32_t ref[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) ref[i] = __float_as_uint(nd[6 * W + i]);
+#define RT_CSWAP(a, b)                                  \
+  {                                                     \
+    bool s_ = key[b] < key[a];                          \
+    uint32_t k0_ = s_ ? key[b] : key[a];                \
+    uint32_t k1_ = s_ ? key[a] : key[b];                \
+    uint32_t r0_ = s_ ? ref[b] : ref[a];                \
+    uint32_t r1_ = s_ ? ref[a] : ref[b];                \
+    key[a] = k0_;                                       \
+    key[b] = k1_;                                       \
+    ref[a] = r0_;                                       \
+    ref[b] = r1_;                                       \
   }
   if constexpr (W == 2) {
     RT_CSWAP(0, 1);
@@ -177,11 +187,7 @@ __device__ __forceinline__ void visit_node(const float* nodes, uint32_t idx, con
   n_out = 0;
 #pragma unroll
   for (int i = 0; i < W; ++i) {
-    uint32_t slot = key[i] & ((1u << SH) - 1u);
-    uint32_t ref = RT_CHILD_EMPTY;
-#pragma unroll
-    for (int j = 0; j < W; ++j) ref = (slot == (uint32_t)j) ? __float_as_uint(nd[6 * W + j]) : ref;
-    out_ref[i] = (key[i] == 0xFFFFFFFFu) ? RT_CHILD_EMPTY : ref;
+    out_ref[i] = ref[i];
     n_out += (key[i] != 0xFFFFFFFFu) ? 1 : 0;
   }
 }
