@@ -278,9 +278,12 @@ rt_status rt_trace_all(rt_accel accel, const rt_ray* rays, uint32_t n,
  *   d_origins[i] = lambda, d_directions[i] = t lambda,
  *   d_vertices[v_k] += -w_k lambda  (w = (1-u-v, u, v))
  * using the accel's copy of the vertices it was built from.  d_vertices
- * (device, vertex_count*3 float32) is ACCUMULATED with float32 atomics (the
- * summation order is not deterministic); d_origins / d_directions (device,
- * n*3 float32) are overwritten (zero for misses).  t, u, v are recomputed in
+ * (device, vertex_count*3 float32) is ACCUMULATED deterministically: the
+ * contributions are sorted by vertex with a stable radix sort and each
+ * vertex's sum is formed in ray order before it is added, so repeated calls
+ * give bit-identical results (the context keeps 48 bytes of scratch per
+ * contribution, three per ray, grown on demand); d_origins / d_directions
+ * (device, n*3 float32) are overwritten (zero for misses).  t, u, v are recomputed in
  * float64 from the triangle, so `hits` contributes only the triangle id.
  * Errors: RT_ERROR_UNSUPPORTED on a two-level accel (use
  * rt_trace_backward_instances). */

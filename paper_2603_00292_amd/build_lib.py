@@ -22,7 +22,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", f"-I{os.path.join(HERE, '..', '
 # library is built without them.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-fno-fast-math", "-ffp-contract=fast"]
-SOURCES = ["rt_kernels.hip", "bvh_device.hip", "rt_api.cpp", "bvh_build.cpp"]
+SOURCES = ["rt_kernels.hip", "bvh_device.hip", "accumulate.hip", "rt_api.cpp", "bvh_build.cpp"]
 
 
 def _compile(src: str) -> str:

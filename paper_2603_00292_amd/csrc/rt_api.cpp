@@ -94,6 +94,7 @@ struct rt_context_s {
   uint32_t blocks_per_cu = 0;  // 0 = the occupancy API's resident count
   std::mutex mu;
   Scratch scratch;
+  rta::Buffers grad;                          // backward: deterministic vertex-gradient sums
   hipEvent_t last_event = nullptr;
   hipStream_t last_stream = nullptr;
   bool has_last = false;
@@ -249,6 +250,7 @@ rt_status rt_context_destroy(rt_context ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   free_scratch(ctx->scratch);
+  rta::release(ctx->grad);
   if (ctx->last_event) (void)hipEventDestroy(ctx->last_event);
   delete ctx;
   return ok();
@@ -875,16 +877,30 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
     return fail(RT_ERROR_INVALID_VALUE, "rt_trace_backward: rays and hits must be 16-byte aligned");
   rt_status st = check_device(accel->device);
   if (st != RT_SUCCESS) return st;
+  rt_context ctx = accel->ctx;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  const size_t entries = 3 * (size_t)n;
+  RT_HIP(rta::reserve(ctx->grad, entries));
+  if (ctx->has_last && ctx->last_stream != s) RT_HIP(hipStreamWaitEvent(s, ctx->last_event, 0));
   BackwardParams p{};
   p.mesh = accel->host_meshes[0];
   p.rays = rays;
   p.hits = hits;
   p.d_tuv = d_tuv;
   p.n = n;
-  p.d_vertices = d_vertices;
+  p.keys = ctx->grad.keys;
+  p.vals = ctx->grad.vals;
   p.d_origins = d_origins;
   p.d_directions = d_directions;
-  RT_HIP(rtk_launch_backward(p, static_cast<hipStream_t>(stream)));
+  RT_HIP(rtk_launch_backward(p, s));
+  // sort keys on the bits that hold a vertex id; 0xFFFFFFFF (a miss) sorts last
+  int key_bits = 1;
+  while (key_bits < 32 && (1ull << key_bits) <= (uint64_t)p.mesh.vertex_count) ++key_bits;
+  RT_HIP(rta::scatter_add(ctx->grad, entries, key_bits, d_vertices, s));
+  RT_HIP(hipEventRecord(ctx->last_event, s));
+  ctx->last_stream = s;
+  ctx->has_last = true;
   return ok();
 }
 

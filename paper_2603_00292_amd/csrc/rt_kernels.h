@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/rt.h"
+#include "accumulate.h"
 #include "rt_layout.h"
 
 // One batch entry of a batched plan (device copy).
@@ -47,13 +48,17 @@ struct TraceParams {
   uint32_t cap;          // mode 3: list entries per ray
 };
 
+// Single-level adjoint: ray gradients are written directly; the vertex
+// contributions go to (keys, vals) entries 3i..3i+2 (vertex id, -w_k lambda;
+// 0xFFFFFFFF for a miss), summed afterwards by rta::scatter_add.
 struct BackwardParams {
   rt_mesh_dev mesh;
   const rt_ray* rays;
   const rt_hit* hits;
   const float* d_tuv;
   uint32_t n;
-  float* d_vertices;
+  uint32_t* keys;
+  rta_f3* vals;
   float* d_origins;
   float* d_directions;
 };

@@ -638,11 +638,18 @@ __global__ __launch_bounds__(256) void backward_kernel(BackwardParams P) {
   float* gd = P.d_directions + 3 * (size_t)i;
   rt_ray q = load_ray(P.rays, i);
   const float* gr = P.d_tuv + 3 * (size_t)i;
+  uint32_t* keys = P.keys + 3 * (size_t)i;
+  rta_f3* vals = P.vals + 3 * (size_t)i;
   Adjoint64 A;
   if (prim == RT_INVALID_ID || prim >= P.mesh.triangle_count ||
       !adjoint64(P.mesh, prim, q.ox, q.oy, q.oz, q.dx, q.dy, q.dz, gr[0], gr[1], gr[2], A)) {
     zero3(go);
     zero3(gd);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      keys[k] = 0xFFFFFFFFu;
+      vals[k] = rta_f3{0.0f, 0.0f, 0.0f};
+    }
     return;
   }
   go[0] = (float)A.lx; go[1] = (float)A.ly; go[2] = (float)A.lz;
@@ -650,10 +657,8 @@ __global__ __launch_bounds__(256) void backward_kernel(BackwardParams P) {
   double w[3] = {1.0 - A.u - A.v, A.u, A.v};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    float* dv = P.d_vertices + 3 * (size_t)A.id[k];
-    atomicAdd(dv + 0, (float)(-w[k] * A.lx));
-    atomicAdd(dv + 1, (float)(-w[k] * A.ly));
-    atomicAdd(dv + 2, (float)(-w[k] * A.lz));
+    keys[k] = A.id[k];
+    vals[k] = rta_f3{(float)(-w[k] * A.lx), (float)(-w[k] * A.ly), (float)(-w[k] * A.lz)};
   }
 }
 

@@ -186,3 +186,29 @@ def test_backward_rejects_two_level(gpu):
         api.trace_backward(acc, rays, hits, torch.zeros((16, 3), dtype=torch.float32, device="cuda"), dV)
     assert e.value.status == _capi.RT_ERROR_UNSUPPORTED
     acc.close()
+
+
+def test_backward_is_deterministic(gpu):
+    """The vertex gradients are summed in a fixed order: two calls on the
+    same inputs give bit-identical results (and the same ray gradients)."""
+    torch, api, ctx = gpu
+    W = wl.displaced_grid(nx=128, nz=64, n_rays=262144, k=304)
+    m = W.scene.meshes[0]
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    rays = torch.from_numpy(W.rays).cuda()
+    hits, _ = api.trace_closest(acc, rays)
+    g = torch.from_numpy(W.extra["abc"]).cuda()
+    outs = []
+    for _ in range(2):
+        dV = torch.zeros((m.vertices.shape[0], 3), dtype=torch.float32, device="cuda")
+        do, dd = api.trace_backward(acc, rays, hits, g, dV)
+        torch.cuda.synchronize()
+        outs.append((dV, do, dd))
+    assert torch.equal(outs[0][0], outs[1][0])
+    assert torch.equal(outs[0][1], outs[1][1]) and torch.equal(outs[0][2], outs[1][2])
+    # accumulation adds to what the buffer held
+    dV = outs[0][0].clone()
+    api.trace_backward(acc, rays, hits, g, dV)
+    torch.cuda.synchronize()
+    assert torch.allclose(dV, 2 * outs[0][0], rtol=1e-6, atol=1e-7)
+    acc.close()
