@@ -303,14 +303,17 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
  *   d_vertices (device, float32, nullable): gradients of the base meshes'
  *     object-space vertices, ACCUMULATED; mesh m's rows start at the sum of
  *     the vertex counts of meshes 0..m-1 (the mesh order of rt_build), so
- *     the buffer holds 3 * (total vertex count) floats;
+ *     the buffer holds 3 * (total vertex count) floats (RT_ERROR_UNSUPPORTED
+ *     when that count reaches 2^32 - 1);
  *   d_srt (device, instance_count*10 float32, nullable): gradients of each
  *     instance's (sx,sy,sz, qx,qy,qz,qw, tx,ty,tz) as given to rt_build,
  *     ACCUMULATED; the quaternion part is the gradient with respect to the
  *     unnormalised q (orthogonal to q).
- * Accumulation uses float32 atomics (the summation order is not
- * deterministic).  t, u, v are recomputed in float64 with the accel's copies
- * of the meshes and frames.  A hit whose instance id is not an instance of
+ * Both accumulations are deterministic (contributions sorted by row with a
+ * stable radix sort, summed in ray order; repeated calls are bit-identical;
+ * the context keeps 48 bytes of scratch per contribution, 3 vertex and 4
+ * frame contributions per ray).  t, u, v are recomputed in float64 with the
+ * accel's copies of the meshes and frames.  A hit whose instance id is not an instance of
  * the accel, or whose prim_id is not a triangle of that instance's mesh,
  * contributes nothing (zero ray gradients).
  * Errors: RT_ERROR_UNSUPPORTED on a single-level accel (use

@@ -95,6 +95,7 @@ struct rt_context_s {
   std::mutex mu;
   Scratch scratch;
   rta::Buffers grad;                          // backward: deterministic vertex-gradient sums
+  rta::Buffers grad2;                         // two-level backward: frame-gradient sums
   hipEvent_t last_event = nullptr;
   hipStream_t last_stream = nullptr;
   bool has_last = false;
@@ -116,6 +117,8 @@ struct rt_accel_s {
   rt_srt* srts = nullptr;                    // two-level: frames as given to the build
   uint64_t* vertex_base = nullptr;           // two-level: first gradient row per mesh
   uint32_t instance_count = 0;
+  uint64_t vertex_rows = 0;                  // two-level: sum of the meshes' vertex counts
+  float* srt_rows = nullptr;                 // two-level backward: 12 floats per instance
   std::vector<void*> owned;                  // every device allocation
   std::vector<rt_mesh_dev> host_meshes;      // device pointers, host copy
   std::vector<rt_inst_rec> host_insts;       // two-level: host copy of the instance records
@@ -251,6 +254,7 @@ rt_status rt_context_destroy(rt_context ctx) {
   (void)hipDeviceSynchronize();
   free_scratch(ctx->scratch);
   rta::release(ctx->grad);
+  rta::release(ctx->grad2);
   if (ctx->last_event) (void)hipEventDestroy(ctx->last_event);
   delete ctx;
   return ok();
@@ -656,6 +660,9 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
       }
       st = dev_alloc(a, &a->srts, instance_count);
       if (st != RT_SUCCESS) return bail(st);
+      st = dev_alloc(a, &a->srt_rows, (size_t)instance_count * 12);
+      if (st != RT_SUCCESS) return bail(st);
+      a->vertex_rows = acc;
       st = dev_alloc(a, &a->vertex_base, mesh_count);
       if (st != RT_SUCCESS) return bail(st);
       RT_HIP(hipMemcpyAsync(a->srts, instance_srt, instance_count * sizeof(rt_srt), hipMemcpyHostToDevice, s));
@@ -918,8 +925,17 @@ rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const 
   if (!aligned16(rays) || !aligned16(hits))
     return fail(RT_ERROR_INVALID_VALUE,
                 "rt_trace_backward_instances: rays and hits must be 16-byte aligned");
+  if (d_vertices && accel->vertex_rows >= 0xFFFFFFFFull)
+    return fail(RT_ERROR_UNSUPPORTED, "rt_trace_backward_instances: more than 2^32 - 2 vertex rows");
   rt_status st = check_device(accel->device);
   if (st != RT_SUCCESS) return st;
+  rt_context ctx = accel->ctx;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  const size_t ve = d_vertices ? 3 * (size_t)n : 0, se = d_srt ? 4 * (size_t)n : 0;
+  if (ve) RT_HIP(rta::reserve(ctx->grad, ve));
+  if (se) RT_HIP(rta::reserve(ctx->grad2, se));
+  if (ctx->has_last && ctx->last_stream != s) RT_HIP(hipStreamWaitEvent(s, ctx->last_event, 0));
   BackwardInstParams p{};
   p.meshes = accel->meshes;
   p.vertex_base = accel->vertex_base;
@@ -932,11 +948,27 @@ rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const 
   p.inst_ids = inst_ids;
   p.d_tuv = d_tuv;
   p.n = n;
-  p.d_vertices = d_vertices;
-  p.d_srt = d_srt;
+  p.vkeys = ve ? ctx->grad.keys : nullptr;
+  p.vvals = ve ? ctx->grad.vals : nullptr;
+  p.skeys = se ? ctx->grad2.keys : nullptr;
+  p.svals = se ? ctx->grad2.vals : nullptr;
   p.d_origins = d_origins;
   p.d_directions = d_directions;
-  RT_HIP(rtk_launch_backward_inst(p, static_cast<hipStream_t>(stream)));
+  RT_HIP(rtk_launch_backward_inst(p, s));
+  auto bits_for = [](uint64_t rows) {
+    int b = 1;
+    while (b < 32 && (1ull << b) <= rows) ++b;
+    return b;
+  };
+  if (ve) RT_HIP(rta::scatter_add(ctx->grad, ve, bits_for(accel->vertex_rows), d_vertices, s));
+  if (se) {
+    RT_HIP(rtk_launch_fill(reinterpret_cast<uint32_t*>(accel->srt_rows), accel->instance_count * 12u, 0u, s));
+    RT_HIP(rta::scatter_add(ctx->grad2, se, bits_for(4ull * accel->instance_count), accel->srt_rows, s));
+    RT_HIP(rtk_launch_fold_frames(accel->srt_rows, accel->instance_count, d_srt, s));
+  }
+  RT_HIP(hipEventRecord(ctx->last_event, s));
+  ctx->last_stream = s;
+  ctx->has_last = true;
   return ok();
 }
 

@@ -76,8 +76,14 @@ struct BackwardInstParams {
   const uint32_t* inst_ids;
   const float* d_tuv;
   uint32_t n;
-  float* d_vertices;              // may be null
-  float* d_srt;                   // may be null
+  // contributions for rta::scatter_add (0xFFFFFFFF keys for none):
+  //   vkeys/vvals[3i + k]: gradient row (vertex_base[mesh] + vertex id);
+  //   skeys/svals[4i + part]: frame rows 4 * instance + part, holding
+  //   (S xyz), (q xyz), (q w, T x, T y), (T z, 0, 0)
+  uint32_t* vkeys;                // null: no vertex gradients wanted
+  rta_f3* vvals;
+  uint32_t* skeys;                // null: no frame gradients wanted
+  rta_f3* svals;
   float* d_origins;
   float* d_directions;
 };
@@ -109,6 +115,8 @@ hipError_t rtk_launch_finalize(bool inst, int mode, const TraceParams& p, hipStr
 hipError_t rtk_launch_finalize_all(bool inst, const TraceParams& p, hipStream_t stream);
 hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream);
 hipError_t rtk_launch_backward_inst(const BackwardInstParams& p, hipStream_t stream);
+// d_srt[10 j + c] += the frame rows 4 j .. 4 j + 3 (see BackwardInstParams)
+hipError_t rtk_launch_fold_frames(const float* rows, uint32_t inst_count, float* d_srt, hipStream_t stream);
 hipError_t rtk_launch_refit_tris(rt_tri_rec* tris, uint32_t n, const rt_mesh_dev& mesh,
                                  hipStream_t stream);
 hipError_t rtk_launch_refit_nodes(int width, float* nodes, const rt_tri_rec* tris,

@@ -688,9 +688,22 @@ __global__ __launch_bounds__(256) void backward_inst_kernel(BackwardInstParams P
   uint32_t inst = P.inst_ids[i];
   float* go = P.d_origins + 3 * (size_t)i;
   float* gd = P.d_directions + 3 * (size_t)i;
-  if (prim == RT_INVALID_ID || inst >= P.inst_count) {
+  auto no_contribution = [&]() {
     zero3(go);
     zero3(gd);
+    if (P.vkeys)
+      for (int k = 0; k < 3; ++k) {
+        P.vkeys[3 * (size_t)i + k] = 0xFFFFFFFFu;
+        P.vvals[3 * (size_t)i + k] = rta_f3{0.0f, 0.0f, 0.0f};
+      }
+    if (P.skeys)
+      for (int k = 0; k < 4; ++k) {
+        P.skeys[4 * (size_t)i + k] = 0xFFFFFFFFu;
+        P.svals[4 * (size_t)i + k] = rta_f3{0.0f, 0.0f, 0.0f};
+      }
+  };
+  if (prim == RT_INVALID_ID || inst >= P.inst_count) {
+    no_contribution();
     return;
   }
   uint32_t mesh = P.insts[inst].mesh;
@@ -708,8 +721,7 @@ __global__ __launch_bounds__(256) void backward_inst_kernel(BackwardInstParams P
   Adjoint64 A;
   if (prim >= md.triangle_count ||
       !adjoint64(md, prim, xo, yo, zo, xd, yd, zd, gr[0], gr[1], gr[2], A)) {
-    zero3(go);
-    zero3(gd);
+    no_contribution();
     return;
   }
   // lambda_w = (A^-1)^T lambda_o
@@ -719,17 +731,16 @@ __global__ __launch_bounds__(256) void backward_inst_kernel(BackwardInstParams P
   go[0] = (float)lx; go[1] = (float)ly; go[2] = (float)lz;
   gd[0] = (float)(A.t * lx); gd[1] = (float)(A.t * ly); gd[2] = (float)(A.t * lz);
   double w[3] = {1.0 - A.u - A.v, A.u, A.v};
-  if (P.d_vertices) {
-    float* base = P.d_vertices + 3 * P.vertex_base[mesh];
+  if (P.vkeys) {
+    uint32_t base = (uint32_t)P.vertex_base[mesh];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      float* dv = base + 3 * (size_t)A.id[k];
-      atomicAdd(dv + 0, (float)(-w[k] * A.lx));
-      atomicAdd(dv + 1, (float)(-w[k] * A.ly));
-      atomicAdd(dv + 2, (float)(-w[k] * A.lz));
+      P.vkeys[3 * (size_t)i + k] = base + A.id[k];
+      P.vvals[3 * (size_t)i + k] =
+          rta_f3{(float)(-w[k] * A.lx), (float)(-w[k] * A.ly), (float)(-w[k] * A.lz)};
     }
   }
-  if (!P.d_srt) return;
+  if (!P.skeys) return;
   const rt_srt f = P.srts[inst];
   double qx = f.qx, qy = f.qy, qz = f.qz, qw = f.qw;
   double qn = sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
@@ -760,17 +771,24 @@ __global__ __launch_bounds__(256) void backward_inst_kernel(BackwardInstParams P
   double gqy = -2.0 * (qw * t1y + t2y + t3y);
   double gqz = -2.0 * (qw * t1z + t2z + t3z);
   double radial = qx * gqx + qy * gqy + qz * gqz + qw * gqw;
-  float* out = P.d_srt + 10 * (size_t)inst;
-  atomicAdd(out + 0, (float)(-rlx * px));
-  atomicAdd(out + 1, (float)(-rly * py));
-  atomicAdd(out + 2, (float)(-rlz * pz));
-  atomicAdd(out + 3, (float)((gqx - qx * radial) * iq));
-  atomicAdd(out + 4, (float)((gqy - qy * radial) * iq));
-  atomicAdd(out + 5, (float)((gqz - qz * radial) * iq));
-  atomicAdd(out + 6, (float)((gqw - qw * radial) * iq));
-  atomicAdd(out + 7, (float)(-lx));
-  atomicAdd(out + 8, (float)(-ly));
-  atomicAdd(out + 9, (float)(-lz));
+  uint32_t* sk = P.skeys + 4 * (size_t)i;
+  rta_f3* sv = P.svals + 4 * (size_t)i;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sk[k] = 4u * inst + (uint32_t)k;
+  sv[0] = rta_f3{(float)(-rlx * px), (float)(-rly * py), (float)(-rlz * pz)};
+  sv[1] = rta_f3{(float)((gqx - qx * radial) * iq), (float)((gqy - qy * radial) * iq),
+                 (float)((gqz - qz * radial) * iq)};
+  sv[2] = rta_f3{(float)((gqw - qw * radial) * iq), (float)(-lx), (float)(-ly)};
+  sv[3] = rta_f3{(float)(-lz), 0.0f, 0.0f};
+}
+
+__global__ void fold_frames_kernel(const float* rows, uint32_t inst_count, float* d_srt) {
+  uint32_t j = blockIdx.x * 256u + threadIdx.x;
+  if (j >= inst_count) return;
+  const float* r = rows + 12 * (size_t)j;
+  float* o = d_srt + 10 * (size_t)j;
+#pragma unroll
+  for (int c = 0; c < 10; ++c) o[c] += r[c];
 }
 
 // ---------------------------------------------------------------------------
@@ -1141,6 +1159,13 @@ hipError_t rtk_launch_backward_inst(const BackwardInstParams& p, hipStream_t str
   void* args[] = {&q};
   return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::backward_inst_kernel),
                          dim3((p.n + 255) / 256), dim3(256), args, 0, stream);
+}
+
+hipError_t rtk_launch_fold_frames(const float* rows, uint32_t inst_count, float* d_srt, hipStream_t stream) {
+  if (inst_count == 0) return hipSuccess;
+  void* args[] = {&rows, &inst_count, &d_srt};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::fold_frames_kernel),
+                         dim3((inst_count + 255) / 256), dim3(256), args, 0, stream);
 }
 
 hipError_t rtk_launch_finalize(bool inst, int mode, const TraceParams& p, hipStream_t stream) {

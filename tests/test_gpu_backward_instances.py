@@ -259,3 +259,36 @@ def test_backward_instances_errors(gpu):
         api.trace_backward_instances(acc1, rays, hits, inst, g)
     assert e.value.status == _capi.RT_ERROR_UNSUPPORTED
     acc1.close()
+
+
+def test_backward_instances_deterministic(gpu):
+    """Vertex and frame gradients are summed in a fixed order: repeated
+    calls are bit-identical, and a call adds to what the buffers held."""
+    torch, api, ctx = gpu
+    W = wl.aimed_instances(n_inst=8, n_rays=32768, k=319)
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    rays, hits, inst = _forward(gpu, acc, W.rays)
+    g = torch.from_numpy(wl.rng_for(320).standard_normal((W.rays.shape[0], 3)).astype(np.float32)).cuda()
+    nv = int(_bases(W.scene)[-1])
+    outs = []
+    for _ in range(2):
+        dV = torch.zeros((nv, 3), dtype=torch.float32, device="cuda")
+        dS = torch.zeros((8, 10), dtype=torch.float32, device="cuda")
+        do, dd = api.trace_backward_instances(acc, rays, hits, inst, g, dV, dS)
+        torch.cuda.synchronize()
+        outs.append((dV, dS, do, dd))
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+    dV, dS = outs[0][0].clone(), outs[0][1].clone()
+    api.trace_backward_instances(acc, rays, hits, inst, g, dV, dS)
+    torch.cuda.synchronize()
+    assert torch.allclose(dV, 2 * outs[0][0], rtol=1e-6, atol=1e-7)
+    assert torch.allclose(dS, 2 * outs[0][1], rtol=1e-6, atol=1e-7)
+    # only frame gradients, only vertex gradients
+    dS2 = torch.zeros((8, 10), dtype=torch.float32, device="cuda")
+    api.trace_backward_instances(acc, rays, hits, inst, g, None, dS2)
+    dV2 = torch.zeros((nv, 3), dtype=torch.float32, device="cuda")
+    api.trace_backward_instances(acc, rays, hits, inst, g, dV2, None)
+    torch.cuda.synchronize()
+    assert torch.equal(dS2, outs[0][1]) and torch.equal(dV2, outs[0][0])
+    acc.close()
