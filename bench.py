@@ -212,6 +212,8 @@ def main():
 
     if not args.no_secondary:
         secondary.update(device_build_bench(args, torch, api, ctx, stream, V, I, W, width, build_host_s))
+        secondary.update(camera_bench(args, torch, np, api, workloads, ctx, stream))
+        secondary.update(instanced_bench(args, torch, np, api, workloads, ctx, stream))
         secondary.update(backward_bench(args, torch, np, api, workloads, ctx, stream))
         secondary.update(batched_bench(args, torch, np, api, _capi, workloads, ctx, stream))
         secondary.update(ao_bench(args, torch, np, api, workloads, ctx, stream))
@@ -310,6 +312,44 @@ def ao_bench(args, torch, np, api, workloads, ctx, stream):
          "ao_workload": f"{W.name}: {m.indices.shape[0]} triangles, {rays.shape[0]} camera rays, "
                         f"{n_ao} AO rays (closest + AO ray generation + any-hit + resolve)"}
     log(f"ao: {r}")
+    acc.close()
+    return r
+
+
+def camera_bench(args, torch, np, api, workloads, ctx, stream):
+    """The coherent configuration: 2048^2 pinhole primary rays on the same
+    icosphere (closest) and as many shadow rays toward a point light
+    (any-hit)."""
+    W = workloads.icosphere_camera()
+    m = W.scene.meshes[0]
+    dev = torch.device("cuda:0")
+    acc = api.Accel(ctx, [(torch.from_numpy(m.vertices).to(dev), torch.from_numpy(m.indices.view(np.int32)).to(dev))])
+    rays = torch.from_numpy(W.rays).to(dev)
+    shadow = torch.from_numpy(W.extra["shadow_rays"]).to(dev)
+    ms_c, _ = timed(lambda: api.trace_closest(acc, rays), args.steps, stream, torch)
+    ms_a, _ = timed(lambda: api.trace_any(acc, shadow), args.steps, stream, torch)
+    r = {"camera_closest_mrays": round(rays.shape[0] / (ms_c * 1e-3) / 1e6, 3),
+         "shadow_any_mrays": round(shadow.shape[0] / (ms_a * 1e-3) / 1e6, 3),
+         "camera_workload": f"{W.name}: {m.indices.shape[0]} triangles, {rays.shape[0]} primary + "
+                            f"{shadow.shape[0]} shadow rays"}
+    log(f"camera: {r}")
+    acc.close()
+    return r
+
+
+def instanced_bench(args, torch, np, api, workloads, ctx, stream):
+    """The two-level configuration: 1,024 SRT instances of four 10k-triangle
+    grids, 8,388,608 secondary rays (closest, with instance ids)."""
+    W = workloads.instanced_grids()
+    dev = torch.device("cuda:0")
+    meshes = [(torch.from_numpy(m.vertices).to(dev), torch.from_numpy(m.indices.view(np.int32)).to(dev))
+              for m in W.scene.meshes]
+    acc = api.Accel(ctx, meshes, W.scene.inst_mesh, W.scene.inst_srt)
+    rays = torch.from_numpy(W.rays).to(dev)
+    ms, _ = timed(lambda: api.trace_closest(acc, rays, want_inst=True), args.steps, stream, torch)
+    r = {"instanced_closest_mrays": round(rays.shape[0] / (ms * 1e-3) / 1e6, 3),
+         "instanced_workload": f"{W.name}: 1024 instances of 4 x 10000 triangles, {rays.shape[0]} rays"}
+    log(f"instanced: {r}")
     acc.close()
     return r
 
