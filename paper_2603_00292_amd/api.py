@@ -60,17 +60,6 @@ class Context:
         v = capi.rt_variant(int(stack_entries), int(workgroup))
         capi.call("rt_context_set_variant", self.handle, C.byref(v))
 
-    def set_instance_masks(self, masks) -> None:
-        """Visibility masks of the instances (host array, one uint32 each),
-        ANDed with the ray masks of the _ex and all-hit queries."""
-        import numpy as np
-
-        m = np.ascontiguousarray(np.asarray(masks), dtype=np.uint32).reshape(-1)
-        if m.shape[0] != self.instance_count:
-            raise ValueError(f"need {self.instance_count} masks, got {m.shape[0]}")
-        capi.call("rt_accel_set_instance_masks", self.handle, C.c_void_p(m.ctypes.data),
-                  C.c_void_p(_stream()))
-
     def close(self):
         if self.handle:
             capi.call("rt_context_destroy", self.handle)
@@ -453,17 +442,6 @@ class BatchPlan:
         g = C.c_void_p()
         capi.call("rt_batch_plan_graph", self.handle, C.c_void_p(int(stream.cuda_stream)), C.byref(g))
         return int(g.value)
-
-    def set_instance_masks(self, masks) -> None:
-        """Visibility masks of the instances (host array, one uint32 each),
-        ANDed with the ray masks of the _ex and all-hit queries."""
-        import numpy as np
-
-        m = np.ascontiguousarray(np.asarray(masks), dtype=np.uint32).reshape(-1)
-        if m.shape[0] != self.instance_count:
-            raise ValueError(f"need {self.instance_count} masks, got {m.shape[0]}")
-        capi.call("rt_accel_set_instance_masks", self.handle, C.c_void_p(m.ctypes.data),
-                  C.c_void_p(_stream()))
 
     def close(self):
         if self.handle:

@@ -478,79 +478,61 @@ __global__ __launch_bounds__(WG) void trace_kernel(TraceParams P) {
             }
         }
       };
-      if constexpr (!INST) {
-        // ---- internal nodes, one leaf postponed ----------------------------
-        // A lane that reaches a leaf sets it aside and keeps traversing until
-        // it meets a second leaf or every lane of the wave holds a leaf, so
-        // that the wave enters the triangle loop together (leaf postponing,
-        // Aila & Laine 2009).
-        while (cur != RT_CHILD_EMPTY) {
-          if (is_tri_leaf(cur)) {
+      // ---- internal nodes, one leaf postponed ------------------------------
+      // A lane that reaches a leaf sets it aside and keeps traversing until
+      // it meets a second leaf or every lane of the wave holds a leaf, so
+      // that the wave enters the triangle loop together (leaf postponing,
+      // Aila & Laine 2009).  A postponed leaf is tested in the instance frame
+      // it was found in, so a lane holding one stops before a frame change.
+      while (cur != RT_CHILD_EMPTY) {
+        if constexpr (INST) {
+          if (cur == RT_STACK_MARKER || is_inst(cur)) {
             if (pend != RT_CHILD_EMPTY) break;
-            pend = cur;
-            cur = st.pop();
-          } else {
-            step_node();
-          }
-          if (__ballot(pend == RT_CHILD_EMPTY) == 0) break;
-        }
-        // ---- triangle leaves: the postponed one, then those on the stack top
-        while (pend != RT_CHILD_EMPTY) {
-          bool stop = test_leaf(pend);
-          pend = RT_CHILD_EMPTY;
-          if (ANY && stop) {
-            cur = RT_CHILD_EMPTY;
-            st.sp = 0;
-            break;
-          }
-          tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
-          if (cur != RT_CHILD_EMPTY && is_tri_leaf(cur)) {
-            pend = cur;
-            cur = st.pop();
-          }
-        }
-      } else {
-        // ---- internal nodes until this lane holds a leaf or is done --------
-        while (cur != RT_CHILD_EMPTY && !is_tri_leaf(cur)) {
-          if (cur == RT_STACK_MARKER) {
-            world_state(wray, r);
-            r.tmax = best_t;
-            cur = st.pop();
-            continue;
-          }
-          if (is_inst(cur)) {
+            if (cur == RT_STACK_MARKER) {
+              world_state(wray, r);
+              r.tmax = best_t;
+              cur = st.pop();
+              continue;
+            }
             uint32_t j = cur & RT_INST_INDEX_MASK;
             const rt_inst_rec& I = g.insts[j];
-            if constexpr (MODE >= 2) {
-              if ((I.mask & rmask) == 0u) {
-                cur = st.pop();
-                continue;
-              }
+            bool skip = I.root == RT_CHILD_EMPTY;
+            if constexpr (MODE >= 2) skip = skip || (I.mask & rmask) == 0u;
+            if (skip) {
+              cur = st.pop();
+              continue;
             }
             to_object(I, wray, r);
             r.tmin = wray.tmin;
+            r.tmax = best_t;
             cur_inst = j;
             st.push(RT_STACK_MARKER);
             cur = I.root;
             continue;
           }
+        }
+        if (is_tri_leaf(cur)) {
+          if (pend != RT_CHILD_EMPTY) break;
+          pend = cur;
+          cur = st.pop();
+        } else {
           step_node();
         }
-        // ---- triangle leaves ----------------------------------------------
-        while (cur != RT_CHILD_EMPTY && is_tri_leaf(cur)) {
-          bool stop = test_leaf(cur);
-          if (ANY && stop) {
-            cur = RT_CHILD_EMPTY;
-            st.sp = 0;
-            break;
-          }
-          tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
+        if (__ballot(pend == RT_CHILD_EMPTY) == 0) break;
+      }
+      // ---- triangle leaves: the postponed one, then those on the stack top --
+      while (pend != RT_CHILD_EMPTY) {
+        bool stop = test_leaf(pend);
+        pend = RT_CHILD_EMPTY;
+        if (ANY && stop) {
+          cur = RT_CHILD_EMPTY;
+          st.sp = 0;
+          break;
+        }
+        tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
+        if (cur != RT_CHILD_EMPTY && is_tri_leaf(cur)) {
+          pend = cur;
           cur = st.pop();
-          // a marker ends the instance: restore the world ray
-          while (cur == RT_STACK_MARKER) {
-            world_state(wray, r);
-            cur = st.pop();
-          }
         }
       }
       // ---- finished: write the result --------------------------------------
