@@ -1,14 +1,15 @@
 // bvh_device.h -- device-side BVH construction of one mesh (librtq internal).
 //
-// A bottom-up, clustering-family build on the GPU (§6.2 construction
-// paragraph: the bottom-up approach that starts from one cluster per
-// triangle): triangles are ordered along a 30-bit Morton curve of their
-// centroids, the binary radix tree over the sorted codes is formed in one
-// pass (every internal node finds its key range and split from the codes'
-// common prefixes), boxes are fitted bottom-up, and the binary tree is
-// collapsed level by level into the W-wide layout of rt_layout.h, leaves
-// holding up to max_leaf consecutive triangles.  It trades tree quality for
-// build speed against the host binned-SAH build.
+// A bottom-up, clustering build on the GPU (§6.2 construction paragraph:
+// every triangle starts as a cluster and clusters are merged until one
+// remains), by PLOC (Meister & Bittner 2018), the family of the paper's
+// balanced builder: triangles are ordered along a 30-bit Morton curve of
+// their box centres; in each pass every cluster finds the cluster within 32
+// places on either side whose merged box has the least surface area, mutual
+// pairs merge, and the list is compacted.  The binary tree is collapsed level
+// by level into the W-wide layout of rt_layout.h, leaves holding subtrees of
+// up to max_leaf triangles, stored contiguously.  It trades some tree
+// quality for build speed against the host binned-SAH build.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
