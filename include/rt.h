@@ -100,12 +100,14 @@ typedef struct rt_mesh_desc {
 /* Build options.  node_width: 0 = default (4), or 2, 4, 8 (§6.2: wide trees
  * of branching factor 4 or 8).  max_leaf_size: 0 = default (4), at most 15.
  * flags: 0 (host binned-SAH build) or RT_BUILD_DEVICE. */
-/* Build the tree on the GPU (§6.2 construction paragraph, the bottom-up
- * family): Morton order of the triangle centres, a binary radix tree over
- * the sorted codes, boxes fitted bottom-up, collapse to node_width.  Much
- * faster to build than the host SAH build, with a tree that traces slower;
- * single-level builds only (RT_ERROR_UNSUPPORTED with instances); vertex
- * and index pointers and strides must be multiples of 4 bytes. */
+/* Build the trees on the GPU (§6.2 construction paragraph: bottom-up
+ * clustering from one cluster per triangle), by PLOC: clusters in Morton
+ * order of the triangle centres, repeatedly merged with their mutual nearest
+ * neighbour by merged-box surface area, then collapsed to node_width.  Much
+ * faster to build than the host SAH build, with a tree that traces somewhat
+ * slower.  With instances, every mesh's tree is built on the GPU and the
+ * top-level tree over the instance boxes on the host.  Vertex and index
+ * pointers and strides must be multiples of 4 bytes. */
 #define RT_BUILD_DEVICE 0x1u
 
 typedef struct rt_build_options {

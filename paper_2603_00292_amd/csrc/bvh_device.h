@@ -44,11 +44,19 @@ struct Output {
   uint32_t node_count = 0, tri_count = 0, leaf_count = 0, max_depth = 0, max_stack = 0;
   uint32_t root = RT_CHILD_EMPTY;
   double sah_cost = 0.0;
+  float bounds[6] = {0, 0, 0, -1, -1, -1};  // box of all triangles (lo xyz, hi xyz; inverted when empty)
 };
 
 // Returns hipSuccess and fills `out`, or an error (then `out.owned` may hold
 // allocations the caller frees).  `index_error` is set when an index is
 // >= vertex_count (nothing else is valid then).
 hipError_t build(const Input& in, Output& out, bool& index_error, hipStream_t stream);
+
+// Adds node_base to the internal-node references and tri_base to the first
+// record of the triangle-leaf references of node_count W-wide nodes (device),
+// so that a tree can be placed at those offsets of larger node and record
+// arrays.  Instance-leaf and empty references are left as they are.
+hipError_t relocate(float* nodes, uint32_t node_count, int width, uint32_t node_base, uint32_t tri_base,
+                    hipStream_t stream);
 
 }  // namespace rtd

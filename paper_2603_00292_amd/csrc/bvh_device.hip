@@ -446,6 +446,18 @@ __global__ void records_kernel(const float* V, const uint32_t* I, const uint32_t
   out[k] = r;
 }
 
+__global__ void relocate_kernel(float* nodes, uint32_t count, int W, uint32_t nb, uint32_t tb) {
+  uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= count * (uint32_t)W) return;
+  uint32_t i = t / (uint32_t)W, c = t % (uint32_t)W;
+  float* slot = nodes + (size_t)i * 8 * W + 6 * W + c;
+  uint32_t ref = __float_as_uint(*slot);
+  if (ref == RT_CHILD_EMPTY) return;
+  if ((ref & RT_LEAF_BIT) == 0u) ref += nb;
+  else if ((ref & RT_INST_BIT) == 0u) ref += tb;  // the first record is the low bits
+  *slot = __uint_as_float(ref);
+}
+
 __global__ void fill_kernel(uint32_t* p, uint32_t n, uint32_t v) {
   uint32_t i = blockIdx.x * 256u + threadIdx.x;
   if (i < n) p[i] = v;
@@ -674,6 +686,7 @@ hipError_t build(const Input& in, Output& out, bool& index_error, hipStream_t s)
   RTD_TRY(hipMemcpyAsync(root_box, box, sizeof(root_box), hipMemcpyDeviceToHost, s));
   RTD_TRY(hipStreamSynchronize(s));
   out.node_count = node_count;
+  for (int a = 0; a < 6; ++a) out.bounds[a] = root_box[a];
   out.leaf_count = c[2];
   out.max_stack = std::max(c[3], 1u);
   out.max_depth = (uint32_t)level_begin.size() - 1;
@@ -697,6 +710,14 @@ hipError_t build(const Input& in, Output& out, bool& index_error, hipStream_t s)
   RTD_TRY(hipGetLastError());
   RTD_TRY(hipStreamSynchronize(s));
   return hipSuccess;
+}
+
+hipError_t relocate(float* nodes, uint32_t node_count, int width, uint32_t node_base, uint32_t tri_base,
+                    hipStream_t s) {
+  if (node_count == 0) return hipSuccess;
+  hipLaunchKernelGGL(relocate_kernel, dim3(blocks((uint64_t)node_count * width)), dim3(256), 0, s, nodes, node_count,
+                     width, node_base, tri_base);
+  return hipGetLastError();
 }
 
 }  // namespace rtd

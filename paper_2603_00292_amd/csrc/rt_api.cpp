@@ -359,6 +359,59 @@ static rtb::Box world_box(const rtb::Box& b, const rt_srt& f) {
 }
 
 // Single-level accel built on the device (RT_BUILD_DEVICE).
+// Instance records (float32 and float64 world->object maps, bottom-level
+// roots, masks), the frames as given and the per-mesh gradient row offsets of
+// a two-level accel.  blas_root[m] is the root reference of mesh m's tree in
+// the accel's node array (RT_CHILD_EMPTY for a mesh without triangles).
+static rt_status setup_instances(rt_accel_s* a, const rt_mesh_desc* meshes, uint32_t mesh_count,
+                                 const uint32_t* instance_mesh, const rt_srt* instance_srt,
+                                 uint32_t instance_count, const std::vector<uint32_t>& blas_root,
+                                 hipStream_t s) {
+  rt_status st;
+  std::vector<rt_inst_rec> ir(instance_count);
+  std::vector<rt_inst_rec64> ir64(instance_count);
+  for (uint32_t j = 0; j < instance_count; ++j) {
+    double m[12];
+    srt_inverse(instance_srt[j], m);
+    std::memcpy(ir64[j].m, m, sizeof(m));
+    for (int k = 0; k < 4; ++k) {
+      ir[j].r0[k] = (float)m[k];
+      ir[j].r1[k] = (float)m[4 + k];
+      ir[j].r2[k] = (float)m[8 + k];
+    }
+    uint32_t mm = instance_mesh[j];
+    ir[j].root = blas_root[mm];
+    ir[j].mesh = mm;
+    ir[j].mask = 0xFFFFFFFFu;
+    ir[j].pad = 0;
+  }
+  st = dev_alloc(a, &a->insts, ir.size());
+  if (st != RT_SUCCESS) return st;
+  st = dev_alloc(a, &a->insts64, ir64.size());
+  if (st != RT_SUCCESS) return st;
+  RT_HIP(hipMemcpyAsync(a->insts, ir.data(), ir.size() * sizeof(rt_inst_rec), hipMemcpyHostToDevice, s));
+  a->host_insts = ir;
+  RT_HIP(hipMemcpyAsync(a->insts64, ir64.data(), ir64.size() * sizeof(rt_inst_rec64), hipMemcpyHostToDevice, s));
+  // frames and per-mesh gradient rows for the two-level adjoint
+  std::vector<uint64_t> base(mesh_count);
+  uint64_t acc = 0;
+  for (uint32_t m = 0; m < mesh_count; ++m) {
+    base[m] = acc;
+    acc += meshes[m].vertex_count;
+  }
+  st = dev_alloc(a, &a->srts, instance_count);
+  if (st != RT_SUCCESS) return st;
+  st = dev_alloc(a, &a->srt_rows, (size_t)instance_count * 12);
+  if (st != RT_SUCCESS) return st;
+  a->vertex_rows = acc;
+  st = dev_alloc(a, &a->vertex_base, mesh_count);
+  if (st != RT_SUCCESS) return st;
+  RT_HIP(hipMemcpyAsync(a->srts, instance_srt, instance_count * sizeof(rt_srt), hipMemcpyHostToDevice, s));
+  RT_HIP(hipMemcpyAsync(a->vertex_base, base.data(), mesh_count * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  a->instance_count = instance_count;
+  return RT_SUCCESS;
+}
+
 static rt_status build_on_device(rt_context ctx, const rt_mesh_desc& mesh, int width, int max_leaf,
                                  hipStream_t s, rt_accel* out) {
   rt_accel_s* a = new (std::nothrow) rt_accel_s();
@@ -419,6 +472,150 @@ static rt_status build_on_device(rt_context ctx, const rt_mesh_desc& mesh, int w
   return ok();
 }
 
+// Two-level build with every bottom-level tree built on the GPU (one device
+// build per mesh) and the top-level tree over the instances' world boxes
+// built on the host (one box per instance: milliseconds for thousands).  The
+// parts are placed on the device in the layout of the host build -- nodes
+// [top][mesh 0][mesh 1]..., records [mesh 0][mesh 1]... -- with their
+// references relocated there.
+static rt_status build_two_level_on_device(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_count,
+                                           const uint32_t* instance_mesh, const rt_srt* instance_srt,
+                                           uint32_t instance_count, int width, int max_leaf, hipStream_t s,
+                                           rt_accel* out) {
+  rt_accel_s* a = new (std::nothrow) rt_accel_s();
+  if (!a) return fail(RT_ERROR_OUT_OF_MEMORY, "rt_build: host allocation");
+  a->ctx = ctx;
+  a->device = ctx->device;
+  a->width = width;
+  a->two_level = true;
+  a->info.node_width = (uint32_t)width;
+  a->info.instance_count = instance_count;
+  std::vector<rtd::Output> parts;
+  auto free_parts = [&]() {
+    for (rtd::Output& o : parts)
+      for (void* q : o.owned) (void)hipFree(q);
+    parts.clear();
+  };
+  auto bail = [&](rt_status e) {
+    (void)hipStreamSynchronize(s);
+    free_parts();
+    destroy_accel(a);
+    return e;
+  };
+  auto hip_fail = [&](hipError_t e, const char* what) {
+    return bail(fail(e == hipErrorOutOfMemory ? RT_ERROR_OUT_OF_MEMORY : RT_ERROR_HIP, "rt_build (device): %s: %s",
+                     what, hipGetErrorString(e)));
+  };
+  try {
+    parts.resize(mesh_count);
+    uint64_t input_tris = 0;
+    for (uint32_t m = 0; m < mesh_count; ++m) {
+      const rt_mesh_desc& d = meshes[m];
+      rtd::Input in{static_cast<const float*>(d.vertices), d.vertex_count, d.vertex_stride,
+                    static_cast<const uint32_t*>(d.indices), d.triangle_count, d.index_stride, width, max_leaf};
+      bool index_error = false;
+      hipError_t e = rtd::build(in, parts[m], index_error, s);
+      if (e != hipSuccess) return hip_fail(e, "bottom-level build");
+      if (index_error)
+        return bail(fail(RT_ERROR_INDEX_OUT_OF_RANGE, "rt_build: mesh %u: a vertex index is >= vertex_count", m));
+      input_tris += d.triangle_count;
+    }
+    // top level over the instances' world boxes
+    std::vector<rtb::Box> boxes(instance_count);
+    for (uint32_t j = 0; j < instance_count; ++j) {
+      const rtd::Output& o = parts[instance_mesh[j]];
+      if (o.tri_count == 0) {
+        for (int k = 0; k < 3; ++k) {
+          boxes[j].lo[k] = INFINITY;
+          boxes[j].hi[k] = -INFINITY;
+        }
+      } else {
+        rtb::Box b;
+        for (int k = 0; k < 3; ++k) {
+          b.lo[k] = o.bounds[k];
+          b.hi[k] = o.bounds[3 + k];
+        }
+        boxes[j] = world_box(b, instance_srt[j]);
+      }
+    }
+    int threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    rtb::WideTree tlas;
+    rtb::build_instances(boxes, width, tlas, threads);
+    // placement
+    const uint32_t fpn = 8u * (uint32_t)width;
+    uint64_t node_total = tlas.node_count, tri_total = 0;
+    std::vector<uint32_t> node_base(mesh_count), tri_base(mesh_count), blas_root(mesh_count);
+    for (uint32_t m = 0; m < mesh_count; ++m) {
+      const rtd::Output& o = parts[m];
+      node_base[m] = (uint32_t)node_total;
+      tri_base[m] = (uint32_t)tri_total;
+      blas_root[m] = o.tri_count ? node_base[m] : RT_CHILD_EMPTY;
+      node_total += o.tri_count ? o.node_count : 0u;
+      tri_total += o.tri_count;
+    }
+    if (node_total >= 0x7FFFFFFFull || tri_total > RT_MAX_TRI_RECORDS)
+      return bail(fail(RT_ERROR_INVALID_VALUE, "rt_build: scene too large for one accel"));
+    rt_status st = dev_alloc(a, &a->nodes, (size_t)node_total * fpn);
+    if (st != RT_SUCCESS) return bail(st);
+    st = dev_alloc(a, &a->tris, (size_t)tri_total);
+    if (st != RT_SUCCESS) return bail(st);
+    hipError_t e = hipSuccess;
+    if (tlas.node_count)
+      e = hipMemcpyAsync(a->nodes, tlas.nodes.data(), (size_t)tlas.node_count * fpn * 4, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "top-level copy");
+    uint32_t max_blas_stack = 0, max_blas_depth = 0;
+    a->host_meshes.resize(mesh_count);
+    for (uint32_t m = 0; m < mesh_count; ++m) {
+      rtd::Output& o = parts[m];
+      if (o.tri_count) {
+        float* dst = a->nodes + (size_t)node_base[m] * fpn;
+        e = hipMemcpyAsync(dst, o.nodes, (size_t)o.node_count * fpn * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = rtd::relocate(dst, o.node_count, width, node_base[m], tri_base[m], s);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(a->tris + tri_base[m], o.tris, (size_t)o.tri_count * sizeof(rt_tri_rec),
+                             hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "bottom-level placement");
+        max_blas_stack = std::max(max_blas_stack, o.max_stack);
+        max_blas_depth = std::max(max_blas_depth, o.max_depth);
+        a->info.leaf_count += o.leaf_count;
+      }
+      // the compact mesh copies stay with the accel (finalize and adjoint)
+      std::vector<void*>& ow = o.owned;
+      ow.erase(std::remove_if(ow.begin(), ow.end(),
+                              [&](void* q) { return q == (void*)o.vertices || q == (void*)o.indices; }),
+               ow.end());
+      a->owned.push_back(o.vertices);
+      a->owned.push_back(o.indices);
+      a->info.device_bytes += 12ull * (std::max(meshes[m].vertex_count, 1u) + std::max(meshes[m].triangle_count, 1u));
+      a->host_meshes[m] = rt_mesh_dev{o.vertices, o.indices, meshes[m].vertex_count, meshes[m].triangle_count};
+    }
+    st = dev_alloc(a, &a->meshes, mesh_count);
+    if (st != RT_SUCCESS) return bail(st);
+    e = hipMemcpyAsync(a->meshes, a->host_meshes.data(), mesh_count * sizeof(rt_mesh_dev), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "mesh records");
+    st = setup_instances(a, meshes, mesh_count, instance_mesh, instance_srt, instance_count, blas_root, s);
+    if (st != RT_SUCCESS) return bail(st);
+    a->root = tlas.root;
+    a->max_stack = std::max(tlas.max_stack + 1 + max_blas_stack, 1u);
+    a->info.node_count = (uint32_t)node_total;
+    a->info.triangle_count = (uint32_t)tri_total;
+    a->info.input_triangles = (uint32_t)std::min<uint64_t>(input_tris, 0xFFFFFFFFull);
+    a->info.max_depth = tlas.max_depth + max_blas_depth;
+    a->info.max_stack = a->max_stack;
+    a->info.leaf_count += tlas.leaf_count;
+    a->info.sah_cost = tlas.sah_cost;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "synchronize");
+    free_parts();  // the per-mesh node and record arrays, now copied
+  } catch (const std::bad_alloc&) {
+    return bail(fail(RT_ERROR_OUT_OF_MEMORY, "rt_build: host allocation failed"));
+  } catch (const std::exception& ex) {
+    return bail(fail(RT_ERROR_INVALID_VALUE, "rt_build: %s", ex.what()));
+  }
+  *out = a;
+  return ok();
+}
+
 rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_count,
                    const uint32_t* instance_mesh, const rt_srt* instance_srt,
                    uint32_t instance_count, const rt_build_options* options, void* stream,
@@ -469,18 +666,21 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
       return fail(RT_ERROR_INVALID_VALUE, "rt_build: instance %u has a zero quaternion", j);
   }
   if (on_device) {
-    if (instance_count > 0)
-      return fail(RT_ERROR_UNSUPPORTED, "rt_build: the device build takes single-level meshes only");
-    const rt_mesh_desc& d = meshes[0];
-    if (((uintptr_t)d.vertices | (uintptr_t)d.indices | d.vertex_stride | d.index_stride) & 3u)
-      return fail(RT_ERROR_INVALID_VALUE, "rt_build: the device build needs 4-byte aligned pointers and strides");
-    if (d.triangle_count > RT_MAX_TRI_RECORDS)
-      return fail(RT_ERROR_INVALID_VALUE, "rt_build: mesh too large for one accel");
+    for (uint32_t m = 0; m < mesh_count; ++m) {
+      const rt_mesh_desc& d = meshes[m];
+      if (((uintptr_t)d.vertices | (uintptr_t)d.indices | d.vertex_stride | d.index_stride) & 3u)
+        return fail(RT_ERROR_INVALID_VALUE, "rt_build: the device build needs 4-byte aligned pointers and strides");
+      if (d.triangle_count > RT_MAX_TRI_RECORDS)
+        return fail(RT_ERROR_INVALID_VALUE, "rt_build: mesh too large for one accel");
+    }
   }
   rt_status st = check_device(ctx->device);
   if (st != RT_SUCCESS) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (on_device) return build_on_device(ctx, meshes[0], width, max_leaf, s, out);
+  if (on_device)
+    return instance_count > 0 ? build_two_level_on_device(ctx, meshes, mesh_count, instance_mesh, instance_srt,
+                                                          instance_count, width, max_leaf, s, out)
+                              : build_on_device(ctx, meshes[0], width, max_leaf, s, out);
   int threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
 
   rt_accel_s* a = new (std::nothrow) rt_accel_s();
@@ -627,47 +827,11 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
       RT_HIP(hipMemcpyAsync(a->refit_nodes, order.data(), order.size() * 4, hipMemcpyHostToDevice, s));
     }
     if (a->two_level) {
-      std::vector<rt_inst_rec> ir(instance_count);
-      std::vector<rt_inst_rec64> ir64(instance_count);
-      for (uint32_t j = 0; j < instance_count; ++j) {
-        double m[12];
-        srt_inverse(instance_srt[j], m);
-        std::memcpy(ir64[j].m, m, sizeof(m));
-        for (int k = 0; k < 4; ++k) {
-          ir[j].r0[k] = (float)m[k];
-          ir[j].r1[k] = (float)m[4 + k];
-          ir[j].r2[k] = (float)m[8 + k];
-        }
-        uint32_t mm = instance_mesh[j];
-        ir[j].root = blas[mm].root == RT_CHILD_EMPTY ? RT_CHILD_EMPTY : node_base[mm];
-        ir[j].mesh = mm;
-        ir[j].mask = 0xFFFFFFFFu;
-        ir[j].pad = 0;
-      }
-      st = dev_alloc(a, &a->insts, ir.size());
+      std::vector<uint32_t> blas_root(mesh_count);
+      for (uint32_t m = 0; m < mesh_count; ++m)
+        blas_root[m] = blas[m].root == RT_CHILD_EMPTY ? RT_CHILD_EMPTY : node_base[m];
+      st = setup_instances(a, meshes, mesh_count, instance_mesh, instance_srt, instance_count, blas_root, s);
       if (st != RT_SUCCESS) return bail(st);
-      st = dev_alloc(a, &a->insts64, ir64.size());
-      if (st != RT_SUCCESS) return bail(st);
-      RT_HIP(hipMemcpyAsync(a->insts, ir.data(), ir.size() * sizeof(rt_inst_rec), hipMemcpyHostToDevice, s));
-      a->host_insts = ir;
-      RT_HIP(hipMemcpyAsync(a->insts64, ir64.data(), ir64.size() * sizeof(rt_inst_rec64), hipMemcpyHostToDevice, s));
-      // frames and per-mesh gradient rows for the two-level adjoint
-      std::vector<uint64_t> base(mesh_count);
-      uint64_t acc = 0;
-      for (uint32_t m = 0; m < mesh_count; ++m) {
-        base[m] = acc;
-        acc += meshes[m].vertex_count;
-      }
-      st = dev_alloc(a, &a->srts, instance_count);
-      if (st != RT_SUCCESS) return bail(st);
-      st = dev_alloc(a, &a->srt_rows, (size_t)instance_count * 12);
-      if (st != RT_SUCCESS) return bail(st);
-      a->vertex_rows = acc;
-      st = dev_alloc(a, &a->vertex_base, mesh_count);
-      if (st != RT_SUCCESS) return bail(st);
-      RT_HIP(hipMemcpyAsync(a->srts, instance_srt, instance_count * sizeof(rt_srt), hipMemcpyHostToDevice, s));
-      RT_HIP(hipMemcpyAsync(a->vertex_base, base.data(), mesh_count * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-      a->instance_count = instance_count;
     }
     RT_HIP(hipStreamSynchronize(s));
   } catch (const std::bad_alloc&) {

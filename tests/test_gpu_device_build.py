@@ -170,10 +170,15 @@ def test_device_build_degenerate_empty_strided_errors(gpu, orc):
     with pytest.raises(_capi.RtError) as e:
         _capi.call("rt_build", ctxh, C.byref(desc), 1, None, None, 0, C.byref(opt), None, C.byref(C.c_void_p()))
     assert e.value.status == _capi.RT_ERROR_INVALID_VALUE
-    Wi = wl.aimed_instances(n_inst=2, n_rays=16, k=343)
+    # a two-level device build with an index out of range in its second mesh
+    Wi = wl.aimed_instances(n_inst=4, n_rays=16, k=343)
+    meshes = list(Wi.scene.meshes)
+    badi = meshes[1].indices.copy()
+    badi[3, 2] = 10 ** 6
+    meshes[1] = wl.Mesh(meshes[1].vertices, badi)
     with pytest.raises(_capi.RtError) as e:
-        to_gpu_scene(api, torch, ctx, Wi.scene, device_build=True)
-    assert e.value.status == _capi.RT_ERROR_UNSUPPORTED
+        to_gpu_scene(api, torch, ctx, wl.Scene(meshes, Wi.scene.inst_mesh, Wi.scene.inst_srt), device_build=True)
+    assert e.value.status == _capi.RT_ERROR_INDEX_OUT_OF_RANGE
 
 
 def test_refit_of_device_built_accel(gpu):
@@ -201,3 +206,71 @@ def test_refit_of_device_built_accel(gpu):
     assert not torch.equal(h0.view(torch.int32), h1.view(torch.int32))
     acc.close()
     fresh.close()
+
+
+def _two_level_answers(torch, api, acc, rays, d_tuv):
+    hits, inst = api.trace_closest(acc, rays, want_inst=True)
+    occ = api.trace_any(acc, rays)
+    dv = torch.zeros((sum(acc.vertex_counts), 3), dtype=torch.float32, device=rays.device)
+    ds = torch.zeros((acc.instance_count, 10), dtype=torch.float32, device=rays.device)
+    do, dd = api.trace_backward_instances(acc, rays, hits, inst, d_tuv, dv, ds)
+    torch.cuda.synchronize()
+    return [x.cpu().numpy() for x in (hits, inst, occ, do, dd, dv, ds)]
+
+
+def test_device_build_two_level(gpu, orc):
+    """Two-level device builds (every mesh's tree on the GPU, the top level
+    over the instance boxes on the host) answer bit for bit like host builds
+    -- closest hits with instance ids, any-hit, and the two-level adjoint --
+    on a scene with an empty mesh, at widths 2, 4 and 8, and stay inside the
+    oracle's acceptable sets."""
+    torch, api, ctx = gpu
+    W = wl.aimed_instances(n_inst=9, n_rays=8192, k=345)
+    empty = wl.Mesh(np.zeros((3, 3), np.float32), np.zeros((0, 3), np.uint32))
+    meshes = list(W.scene.meshes) + [empty]
+    inst_mesh = W.scene.inst_mesh.copy()
+    inst_mesh[4] = len(meshes) - 1  # one instance of the empty mesh
+    scene = wl.Scene(meshes, inst_mesh, W.scene.inst_srt)
+    rays = torch.from_numpy(W.rays).cuda()
+    g = wl.rng_for(346).standard_normal((W.rays.shape[0], 3)).astype(np.float32)
+    d_tuv = torch.from_numpy(g).cuda()
+    for width in (2, 4, 8):
+        outs = []
+        for dev in (False, True):
+            acc = to_gpu_scene(api, torch, ctx, scene, node_width=width, device_build=dev)
+            outs.append(_two_level_answers(torch, api, acc, rays, d_tuv))
+            say("width", width, "device" if dev else "host", acc.info)
+            acc.close()
+        for a, b in zip(outs[0], outs[1]):
+            assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), f"width {width}"
+    S = orc.OracleScene.from_scene(scene)
+    h, inst = outs[1][0], outs[1][1]
+    st = check_closest(h, orc.accept(S, W.rays), inst=inst, label="two-level device build")
+    say(st)
+    assert st["hits"] > 1000
+    check_any(outs[1][2], orc.accept(S, W.rays), label="two-level device build any")
+
+
+def test_device_build_instanced_workload(gpu):
+    """The 1,024-instance workload (four 10,000-triangle grids, 8,388,608
+    rays): device and host builds answer bit for bit alike."""
+    torch, api, ctx = gpu
+    W = wl.instanced_grids()
+    rays = torch.from_numpy(W.rays).cuda()
+    res = {}
+    for dev in (False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        acc = to_gpu_scene(api, torch, ctx, W.scene, device_build=dev)
+        torch.cuda.synchronize()
+        t_build = time.perf_counter() - t0
+        hits, inst = api.trace_closest(acc, rays, want_inst=True)
+        occ = api.trace_any(acc, rays)
+        torch.cuda.synchronize()
+        res[dev] = (hits.cpu().numpy(), inst.cpu().numpy(), occ.cpu().numpy(), t_build, acc.info)
+        acc.close()
+    say("host build %.3f s %s" % (res[False][3], res[False][4]))
+    say("device build %.3f s %s" % (res[True][3], res[True][4]))
+    for k in range(3):
+        assert np.array_equal(res[False][k].view(np.uint32), res[True][k].view(np.uint32))
+    assert (res[True][0][:, 1].view(np.uint32) != NONE).mean() > 0.05
