@@ -44,6 +44,16 @@ rt_status ok() {
   return RT_SUCCESS;
 }
 
+// As RT_HIP, inside a function that owns a partly built object and a
+// `bail` that releases it.
+#define RT_HIP_BAIL(call)                                                                 \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return bail(fail(e_ == hipErrorOutOfMemory ? RT_ERROR_OUT_OF_MEMORY : RT_ERROR_HIP, \
+                       "%s: %s", #call, hipGetErrorString(e_)));                          \
+  } while (0)
+
 #define RT_HIP(call)                                                                      \
   do {                                                                                    \
     hipError_t e_ = (call);                                                               \
@@ -791,9 +801,9 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
     if (st != RT_SUCCESS) return bail(st);
     st = dev_alloc(a, &a->tris, tris.size());
     if (st != RT_SUCCESS) return bail(st);
-    if (!nodes.empty()) RT_HIP(hipMemcpyAsync(a->nodes, nodes.data(), nodes.size() * 4, hipMemcpyHostToDevice, s));
+    if (!nodes.empty()) RT_HIP_BAIL(hipMemcpyAsync(a->nodes, nodes.data(), nodes.size() * 4, hipMemcpyHostToDevice, s));
     if (!tris.empty())
-      RT_HIP(hipMemcpyAsync(a->tris, tris.data(), tris.size() * sizeof(rt_tri_rec), hipMemcpyHostToDevice, s));
+      RT_HIP_BAIL(hipMemcpyAsync(a->tris, tris.data(), tris.size() * sizeof(rt_tri_rec), hipMemcpyHostToDevice, s));
     a->host_meshes.resize(mesh_count);
     for (uint32_t m = 0; m < mesh_count; ++m) {
       float* dv = nullptr;
@@ -802,13 +812,13 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
       if (st != RT_SUCCESS) return bail(st);
       st = dev_alloc(a, &di, hi[m].size());
       if (st != RT_SUCCESS) return bail(st);
-      if (!hv[m].empty()) RT_HIP(hipMemcpyAsync(dv, hv[m].data(), hv[m].size() * 4, hipMemcpyHostToDevice, s));
-      if (!hi[m].empty()) RT_HIP(hipMemcpyAsync(di, hi[m].data(), hi[m].size() * 4, hipMemcpyHostToDevice, s));
+      if (!hv[m].empty()) RT_HIP_BAIL(hipMemcpyAsync(dv, hv[m].data(), hv[m].size() * 4, hipMemcpyHostToDevice, s));
+      if (!hi[m].empty()) RT_HIP_BAIL(hipMemcpyAsync(di, hi[m].data(), hi[m].size() * 4, hipMemcpyHostToDevice, s));
       a->host_meshes[m] = rt_mesh_dev{dv, di, meshes[m].vertex_count, meshes[m].triangle_count};
     }
     st = dev_alloc(a, &a->meshes, mesh_count);
     if (st != RT_SUCCESS) return bail(st);
-    RT_HIP(hipMemcpyAsync(a->meshes, a->host_meshes.data(), mesh_count * sizeof(rt_mesh_dev), hipMemcpyHostToDevice, s));
+    RT_HIP_BAIL(hipMemcpyAsync(a->meshes, a->host_meshes.data(), mesh_count * sizeof(rt_mesh_dev), hipMemcpyHostToDevice, s));
     if (!a->two_level && blas[0].node_count > 0) {
       // node ids grouped by depth, deepest first, for the bottom-up refit
       const std::vector<uint32_t>& dep = blas[0].node_depth;
@@ -824,7 +834,7 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
       }
       st = dev_alloc(a, &a->refit_nodes, order.size());
       if (st != RT_SUCCESS) return bail(st);
-      RT_HIP(hipMemcpyAsync(a->refit_nodes, order.data(), order.size() * 4, hipMemcpyHostToDevice, s));
+      RT_HIP_BAIL(hipMemcpyAsync(a->refit_nodes, order.data(), order.size() * 4, hipMemcpyHostToDevice, s));
     }
     if (a->two_level) {
       std::vector<uint32_t> blas_root(mesh_count);
@@ -833,7 +843,7 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
       st = setup_instances(a, meshes, mesh_count, instance_mesh, instance_srt, instance_count, blas_root, s);
       if (st != RT_SUCCESS) return bail(st);
     }
-    RT_HIP(hipStreamSynchronize(s));
+    RT_HIP_BAIL(hipStreamSynchronize(s));
   } catch (const std::bad_alloc&) {
     return bail(fail(RT_ERROR_OUT_OF_MEMORY, "rt_build: host allocation failed"));
   } catch (const std::exception& ex) {
@@ -1215,6 +1225,8 @@ rt_status rt_autotune(rt_context ctx, const rt_mesh_desc* mesh, const rt_ray* pr
   RT_HIP(hipMalloc(&hits, (size_t)n_probe * sizeof(rt_hit)));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(hits);
     return fail(RT_ERROR_HIP, "rt_autotune: hipEventCreate failed");
   }

@@ -274,3 +274,42 @@ def test_device_build_instanced_workload(gpu):
     for k in range(3):
         assert np.array_equal(res[False][k].view(np.uint32), res[True][k].view(np.uint32))
     assert (res[True][0][:, 1].view(np.uint32) != NONE).mean() > 0.05
+
+
+def test_device_build_duplicate_triangles(gpu, orc):
+    """5,000 copies of one triangle plus 3,000 copies of a second and 600
+    small random ones: every merged-box area between copies ties, which the
+    clustering build breaks with its pair hash (or, failing that, with a pass
+    pairing neighbours).  The build ends, and its answers equal the host
+    build's and the oracle's (lowest id among equal hits)."""
+    torch, api, ctx = gpu
+    rng = wl.rng_for(347)
+    A = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0]], np.float32)
+    B = np.array([[0, 0, 0.5], [1, 0, 0.5], [0, 1, 0.5]], np.float32)
+    c = rng.uniform(-1, 1, size=(600, 1, 3))
+    R = (c + rng.uniform(-0.02, 0.02, size=(600, 3, 3))).astype(np.float32)
+    tris = np.concatenate([np.repeat(A[None], 5000, 0), np.repeat(B[None], 3000, 0), R], 0)
+    order = rng.permutation(tris.shape[0])
+    tris = tris[order]
+    V = tris.reshape(-1, 3)
+    I = np.arange(V.shape[0], dtype=np.uint32).reshape(-1, 3)
+    n = 4096
+    o = np.stack([rng.uniform(-0.2, 1.0, n), rng.uniform(-0.2, 1.0, n), np.full(n, 2.0)], 1)
+    rays = wl.pack_rays(o, np.tile([0.0, 0.0, -1.0], (n, 1)))
+    outs = []
+    for dev in (False, True):
+        acc = to_gpu_scene(api, torch, ctx, wl.Scene([wl.Mesh(V, I)]), device_build=dev)
+        h, _ = api.trace_closest(acc, torch.from_numpy(rays).cuda())
+        torch.cuda.synchronize()
+        outs.append(h.cpu().numpy())
+        say("device" if dev else "host", acc.info)
+        acc.close()
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32))
+    S = orc.OracleScene([(V, I)])
+    st = check_closest(outs[1], orc.accept(S, rays), label="duplicate triangles")
+    say(st)
+    prim = outs[1][:, 1].copy().view(np.uint32)
+    # rays through the upper triangle's interior hit its lowest-id copy
+    first_b = int(np.flatnonzero((order >= 5000) & (order < 8000))[0])
+    inside = (o[:, 0] > 0.01) & (o[:, 1] > 0.01) & (o[:, 0] + o[:, 1] < 0.99)
+    assert (prim[inside] == first_b).mean() > 0.9
