@@ -249,6 +249,19 @@ typedef struct rt_query_options {
  * single-level accel; RT_ERROR_INVALID_VALUE for NULL masks. */
 rt_status rt_accel_set_instance_masks(rt_accel accel, const uint32_t* masks, void* stream);
 
+/* Moves the instances of a two-level accel (§6.2 construction paragraph:
+ * for changed geometry, keep the tree's topology and refit its boxes
+ * bottom-up; §7.3 instance frames).  instance_srt: HOST array of
+ * instance_count new frames, under rt_build's rules.  The instance records
+ * are recomputed (meshes and masks kept) and the boxes of the top-level tree
+ * refit over its unchanged topology; the meshes' trees are untouched.  The
+ * tree's quality may degrade for large motions; a new rt_build restores it.
+ * Returns after the update is visible to later queries on any stream; the
+ * caller makes sure no query of this accel is still running.  Errors:
+ * RT_ERROR_UNSUPPORTED on a single-level accel, RT_ERROR_INVALID_VALUE for
+ * a NULL array or an invalid frame (nothing is changed then). */
+rt_status rt_update_instances(rt_accel accel, const rt_srt* instance_srt, void* stream);
+
 /* rt_trace_closest / rt_trace_any with options (NULL options: none).  These
  * queries run the stack-16 / workgroup-256 variant of the context's node
  * width whatever the context's variant is. */

@@ -25,7 +25,7 @@ EXPORTS = [
     "rt_context_create", "rt_context_destroy", "rt_context_set_variant", "rt_context_get_variant",
     "rt_build", "rt_accel_destroy", "rt_accel_get_info",
     "rt_trace_closest", "rt_trace_any", "rt_trace_backward", "rt_trace_backward_instances",
-    "rt_trace_closest_ex", "rt_trace_any_ex", "rt_trace_all", "rt_accel_set_instance_masks",
+    "rt_trace_closest_ex", "rt_trace_any_ex", "rt_trace_all", "rt_accel_set_instance_masks", "rt_update_instances",
     "rt_ao_rays", "rt_ao_resolve",
     "rt_trace_counters", "rt_refit",
     "rt_autotune",
@@ -115,6 +115,7 @@ def load():
             "rt_trace_any_ex": [P, P, U32, P, P, P],
             "rt_trace_all": [P, P, U32, P, U32, P, P, P, P],
             "rt_accel_set_instance_masks": [P, P, P],
+            "rt_update_instances": [P, P, P],
             "rt_ao_rays": [P, P, P, U32, U32, P, C.c_float, C.c_float, P, P],
             "rt_ao_resolve": [P, U32, U32, P, P],
             "rt_refit": [P, P, P],

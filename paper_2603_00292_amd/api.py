@@ -128,6 +128,16 @@ class Accel:
             raise ValueError(f"refit needs {self.vertex_count} vertices, got {vertices.shape[0]}")
         capi.call("rt_refit", self.handle, _ptr(vertices), C.c_void_p(_stream()))
 
+    def update_instances(self, inst_srt) -> None:
+        """rt_update_instances: new (J,10) frames (host array) for every
+        instance; the top-level boxes are refit, the meshes' trees kept."""
+        import numpy as np
+
+        srt = np.ascontiguousarray(np.asarray(inst_srt), dtype=np.float32)
+        if srt.shape != (self.instance_count, 10):
+            raise ValueError(f"need ({self.instance_count}, 10) frames, got {srt.shape}")
+        capi.call("rt_update_instances", self.handle, C.c_void_p(srt.ctypes.data), C.c_void_p(_stream()))
+
     def set_instance_masks(self, masks) -> None:
         """Visibility masks of the instances (host array, one uint32 each),
         ANDed with the ray masks of the _ex and all-hit queries."""

@@ -134,6 +134,13 @@ struct rt_accel_s {
   std::vector<rt_inst_rec> host_insts;       // two-level: host copy of the instance records
   uint32_t* refit_nodes = nullptr;           // node ids, deepest level first (single level)
   std::vector<uint32_t> refit_levels;        // level boundaries in refit_nodes
+  // two-level, for rt_update_instances: the top-level nodes (host copy,
+  // nodes [0, count) of the node array), their depths, the frames and mesh
+  // of every instance and each mesh's bounds
+  std::vector<float> tlas_nodes;
+  std::vector<uint32_t> tlas_depth;
+  std::vector<uint32_t> host_inst_mesh;
+  std::vector<rtb::Box> mesh_bounds;
   rt_accel_info info{};
 };
 
@@ -369,6 +376,21 @@ static rtb::Box world_box(const rtb::Box& b, const rt_srt& f) {
 }
 
 // Single-level accel built on the device (RT_BUILD_DEVICE).
+// Frames must be finite, with non-zero scales and a non-zero quaternion.
+static rt_status check_frames(const rt_srt* srt, uint32_t count, const char* who) {
+  for (uint32_t j = 0; j < count; ++j) {
+    const rt_srt& f = srt[j];
+    const float all[10] = {f.sx, f.sy, f.sz, f.qx, f.qy, f.qz, f.qw, f.tx, f.ty, f.tz};
+    for (float x : all)
+      if (!std::isfinite(x)) return fail(RT_ERROR_INVALID_VALUE, "%s: instance %u frame is not finite", who, j);
+    if (f.sx == 0.0f || f.sy == 0.0f || f.sz == 0.0f)
+      return fail(RT_ERROR_INVALID_VALUE, "%s: instance %u has a zero scale", who, j);
+    if (f.qx == 0.0f && f.qy == 0.0f && f.qz == 0.0f && f.qw == 0.0f)
+      return fail(RT_ERROR_INVALID_VALUE, "%s: instance %u has a zero quaternion", who, j);
+  }
+  return RT_SUCCESS;
+}
+
 // Instance records (float32 and float64 world->object maps, bottom-level
 // roots, masks), the frames as given and the per-mesh gradient row offsets of
 // a two-level accel.  blas_root[m] is the root reference of mesh m's tree in
@@ -419,6 +441,7 @@ static rt_status setup_instances(rt_accel_s* a, const rt_mesh_desc* meshes, uint
   RT_HIP(hipMemcpyAsync(a->srts, instance_srt, instance_count * sizeof(rt_srt), hipMemcpyHostToDevice, s));
   RT_HIP(hipMemcpyAsync(a->vertex_base, base.data(), mesh_count * sizeof(uint64_t), hipMemcpyHostToDevice, s));
   a->instance_count = instance_count;
+  a->host_inst_mesh.assign(instance_mesh, instance_mesh + instance_count);
   return RT_SUCCESS;
 }
 
@@ -605,6 +628,16 @@ static rt_status build_two_level_on_device(rt_context ctx, const rt_mesh_desc* m
     if (e != hipSuccess) return hip_fail(e, "mesh records");
     st = setup_instances(a, meshes, mesh_count, instance_mesh, instance_srt, instance_count, blas_root, s);
     if (st != RT_SUCCESS) return bail(st);
+    a->tlas_nodes = tlas.nodes;
+    a->tlas_nodes.resize((size_t)tlas.node_count * fpn);
+    a->tlas_depth = tlas.node_depth;
+    a->tlas_depth.resize(tlas.node_count);
+    a->mesh_bounds.resize(mesh_count);
+    for (uint32_t m = 0; m < mesh_count; ++m)
+      for (int k = 0; k < 3; ++k) {
+        a->mesh_bounds[m].lo[k] = parts[m].tri_count ? parts[m].bounds[k] : INFINITY;
+        a->mesh_bounds[m].hi[k] = parts[m].tri_count ? parts[m].bounds[3 + k] : -INFINITY;
+      }
     a->root = tlas.root;
     a->max_stack = std::max(tlas.max_stack + 1 + max_blas_stack, 1u);
     a->info.node_count = (uint32_t)node_total;
@@ -662,18 +695,13 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
     if (d.vertex_stride < 12 || d.index_stride < 12)
       return fail(RT_ERROR_INVALID_VALUE, "rt_build: mesh %u stride < 12", m);
   }
-  for (uint32_t j = 0; j < instance_count; ++j) {
+  for (uint32_t j = 0; j < instance_count; ++j)
     if (instance_mesh[j] >= mesh_count)
       return fail(RT_ERROR_INDEX_OUT_OF_RANGE, "rt_build: instance %u refers to mesh %u of %u", j,
                   instance_mesh[j], mesh_count);
-    const rt_srt& f = instance_srt[j];
-    const float all[10] = {f.sx, f.sy, f.sz, f.qx, f.qy, f.qz, f.qw, f.tx, f.ty, f.tz};
-    for (float x : all)
-      if (!std::isfinite(x)) return fail(RT_ERROR_INVALID_VALUE, "rt_build: instance %u frame is not finite", j);
-    if (f.sx == 0.0f || f.sy == 0.0f || f.sz == 0.0f)
-      return fail(RT_ERROR_INVALID_VALUE, "rt_build: instance %u has a zero scale", j);
-    if (f.qx == 0.0f && f.qy == 0.0f && f.qz == 0.0f && f.qw == 0.0f)
-      return fail(RT_ERROR_INVALID_VALUE, "rt_build: instance %u has a zero quaternion", j);
+  if (instance_count > 0) {
+    rt_status fs = check_frames(instance_srt, instance_count, "rt_build");
+    if (fs != RT_SUCCESS) return fs;
   }
   if (on_device) {
     for (uint32_t m = 0; m < mesh_count; ++m) {
@@ -842,6 +870,21 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
         blas_root[m] = blas[m].root == RT_CHILD_EMPTY ? RT_CHILD_EMPTY : node_base[m];
       st = setup_instances(a, meshes, mesh_count, instance_mesh, instance_srt, instance_count, blas_root, s);
       if (st != RT_SUCCESS) return bail(st);
+      a->tlas_nodes = tlas.nodes;
+      a->tlas_nodes.resize((size_t)tlas.node_count * fpn);
+      a->tlas_depth = tlas.node_depth;
+      a->tlas_depth.resize(tlas.node_count);
+      a->mesh_bounds.resize(mesh_count);
+      for (uint32_t m = 0; m < mesh_count; ++m) {
+        if (blas[m].root == RT_CHILD_EMPTY) {
+          for (int k = 0; k < 3; ++k) {
+            a->mesh_bounds[m].lo[k] = INFINITY;
+            a->mesh_bounds[m].hi[k] = -INFINITY;
+          }
+        } else {
+          a->mesh_bounds[m] = blas[m].bounds;
+        }
+      }
     }
     RT_HIP_BAIL(hipStreamSynchronize(s));
   } catch (const std::bad_alloc&) {
@@ -1027,6 +1070,109 @@ rt_status rt_accel_set_instance_masks(rt_accel accel, const uint32_t* masks, voi
   RT_HIP(hipMemcpyAsync(accel->insts, accel->host_insts.data(),
                         accel->host_insts.size() * sizeof(rt_inst_rec), hipMemcpyHostToDevice, s));
   RT_HIP(hipStreamSynchronize(s));
+  return ok();
+}
+
+rt_status rt_update_instances(rt_accel accel, const rt_srt* instance_srt, void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_update_instances: NULL accel");
+  if (!accel->two_level)
+    return fail(RT_ERROR_UNSUPPORTED, "rt_update_instances: single-level accel (no instances)");
+  if (!instance_srt) return fail(RT_ERROR_INVALID_VALUE, "rt_update_instances: instance_srt is NULL");
+  const uint32_t n = accel->instance_count;
+  rt_status st = check_frames(instance_srt, n, "rt_update_instances");
+  if (st != RT_SUCCESS) return st;
+  st = check_device(accel->device);
+  if (st != RT_SUCCESS) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int W = accel->width;
+  const uint32_t fpn = 8u * (uint32_t)W;
+  try {
+    // instance records: new maps, same roots, meshes and masks
+    std::vector<rt_inst_rec64> ir64(n);
+    std::vector<rtb::Box> wb(n);
+    for (uint32_t j = 0; j < n; ++j) {
+      double m[12];
+      srt_inverse(instance_srt[j], m);
+      std::memcpy(ir64[j].m, m, sizeof(m));
+      rt_inst_rec& r = accel->host_insts[j];
+      for (int k = 0; k < 4; ++k) {
+        r.r0[k] = (float)m[k];
+        r.r1[k] = (float)m[4 + k];
+        r.r2[k] = (float)m[8 + k];
+      }
+      const rtb::Box& b = accel->mesh_bounds[accel->host_inst_mesh[j]];
+      if (b.lo[0] <= b.hi[0]) {
+        wb[j] = world_box(b, instance_srt[j]);
+      } else {
+        for (int k = 0; k < 3; ++k) {
+          wb[j].lo[k] = INFINITY;
+          wb[j].hi[k] = -INFINITY;
+        }
+      }
+    }
+    // top-level boxes refit bottom-up: deepest nodes first, each child slot
+    // from its instance's world box or from the union of its node's slots
+    std::vector<float>& T = accel->tlas_nodes;
+    const uint32_t tn = (uint32_t)accel->tlas_depth.size();
+    uint32_t maxd = 0;
+    for (uint32_t d : accel->tlas_depth) maxd = std::max(maxd, d);
+    double area_sum = 0.0;
+    rtb::Box root{};
+    for (uint32_t d = maxd; d >= 1; --d) {
+      for (uint32_t i = 0; i < tn; ++i) {
+        if (accel->tlas_depth[i] != d) continue;
+        float* nd = T.data() + (size_t)i * fpn;
+        rtb::Box nb;
+        for (int k = 0; k < 3; ++k) {
+          nb.lo[k] = INFINITY;
+          nb.hi[k] = -INFINITY;
+        }
+        for (int c = 0; c < W; ++c) {
+          uint32_t ref;
+          std::memcpy(&ref, &nd[6 * W + c], 4);
+          if (ref == RT_CHILD_EMPTY) continue;
+          rtb::Box cb;
+          if ((ref & RT_LEAF_BIT) == 0u) {
+            const float* ch = T.data() + (size_t)ref * fpn;  // top-level refs are node indices
+            for (int k = 0; k < 3; ++k) {
+              cb.lo[k] = INFINITY;
+              cb.hi[k] = -INFINITY;
+            }
+            for (int q = 0; q < W; ++q)
+              for (int k = 0; k < 3; ++k) {
+                cb.lo[k] = std::min(cb.lo[k], ch[(2 * k) * W + q]);
+                cb.hi[k] = std::max(cb.hi[k], ch[(2 * k + 1) * W + q]);
+              }
+          } else {
+            cb = wb[ref & RT_INST_INDEX_MASK];
+          }
+          for (int k = 0; k < 3; ++k) {
+            nd[(2 * k) * W + c] = cb.lo[k];
+            nd[(2 * k + 1) * W + c] = cb.hi[k];
+            nb.lo[k] = std::min(nb.lo[k], cb.lo[k]);
+            nb.hi[k] = std::max(nb.hi[k], cb.hi[k]);
+          }
+        }
+        double dx = (double)nb.hi[0] - nb.lo[0], dy = (double)nb.hi[1] - nb.lo[1], dz = (double)nb.hi[2] - nb.lo[2];
+        if (dx >= 0 && dy >= 0 && dz >= 0) area_sum += 2.0 * (dx * dy + dy * dz + dz * dx);
+        if (i == 0) root = nb;
+      }
+      if (d == 1) break;
+    }
+    if (tn > 0) {
+      double dx = (double)root.hi[0] - root.lo[0], dy = (double)root.hi[1] - root.lo[1],
+             dz = (double)root.hi[2] - root.lo[2];
+      double ra = 2.0 * (dx * dy + dy * dz + dz * dx);
+      accel->info.sah_cost = ra > 0.0 ? area_sum / ra : 0.0;
+      RT_HIP(hipMemcpyAsync(accel->nodes, T.data(), (size_t)tn * fpn * 4, hipMemcpyHostToDevice, s));
+    }
+    RT_HIP(hipMemcpyAsync(accel->insts, accel->host_insts.data(), n * sizeof(rt_inst_rec), hipMemcpyHostToDevice, s));
+    RT_HIP(hipMemcpyAsync(accel->insts64, ir64.data(), n * sizeof(rt_inst_rec64), hipMemcpyHostToDevice, s));
+    RT_HIP(hipMemcpyAsync(accel->srts, instance_srt, n * sizeof(rt_srt), hipMemcpyHostToDevice, s));
+    RT_HIP(hipStreamSynchronize(s));
+  } catch (const std::bad_alloc&) {
+    return fail(RT_ERROR_OUT_OF_MEMORY, "rt_update_instances: host allocation failed");
+  }
   return ok();
 }
 

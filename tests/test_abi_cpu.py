@@ -73,6 +73,10 @@ def test_null_arguments_rejected_on_host(lib):
     assert lib.rt_batch_plan_launch(None, None) == c.RT_ERROR_INVALID_VALUE
     assert lib.rt_batch_plan_graph(None, None, None) == c.RT_ERROR_INVALID_VALUE
     assert lib.rt_batch_plan_destroy(None) == c.RT_ERROR_INVALID_VALUE
+    assert lib.rt_update_instances(None, None, None) == c.RT_ERROR_INVALID_VALUE
+    assert lib.rt_accel_set_instance_masks(None, None, None) == c.RT_ERROR_INVALID_VALUE
+    assert lib.rt_refit(None, None, None) == c.RT_ERROR_INVALID_VALUE
+    assert lib.rt_trace_all(None, None, 0, None, 1, None, None, None, None) == c.RT_ERROR_INVALID_VALUE
     del P
 
 
