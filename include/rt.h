@@ -351,15 +351,20 @@ rt_status rt_trace_counters(rt_accel accel, const rt_ray* rays, uint32_t n, int 
 
 /* Refit (§6.2 construction paragraph: keep the topology of the hierarchy and
  * fit the bounding volumes to the current geometry, bottom-up): replaces the
- * accel's vertices by `vertices` (device, vertex_count records of 3 float32,
- * compact) and recomputes every triangle record and child box on `stream`,
- * without a host round trip.  Single-level accels only (RT_ERROR_UNSUPPORTED
- * otherwise).  Triangles that were degenerate or non-finite when the accel
- * was built stay out of it; triangles that become degenerate or non-finite
- * are disabled (never hit) until a refit makes them valid again.  Query
- * results after a refit equal those of a fresh build on the same vertices
- * (up to ties between distinct triangles at equal t); traversal cost grows as
- * the geometry departs from the one the topology was built for. */
+ * accel's vertices by `vertices` (device, compact records of 3 float32) and
+ * recomputes every triangle record and child box on `stream`.  Single level:
+ * vertex_count records, enqueued without a host round trip.  Two-level: the
+ * vertex_count records of every mesh one after another in build order (the
+ * row layout of rt_trace_backward_instances); the meshes' trees are refit on
+ * the device, their root boxes read back and the top-level boxes refit for
+ * the current frames on the host, so the call returns after the update is
+ * visible to later queries on any stream.  Triangles that were degenerate or
+ * non-finite when the accel was built stay out of it; triangles that become
+ * degenerate or non-finite are disabled (never hit) until a refit makes them
+ * valid again.  Query results after a refit equal those of a fresh build on
+ * the same vertices (up to ties between distinct triangles at equal t);
+ * traversal cost grows as the geometry departs from the one the topology was
+ * built for. */
 rt_status rt_refit(rt_accel accel, const float* vertices, void* stream);
 
 /* ---- batched queries (many meshes, one persistent launch) --------------- */

@@ -122,10 +122,12 @@ class Accel:
 
     def refit(self, vertices: torch.Tensor) -> None:
         """Fits the boxes to new vertex positions on the device, keeping the
-        tree topology (rt_refit; single-level accels)."""
+        tree topology (rt_refit).  Two-level accels take every mesh's vertices
+        one after another in build order."""
         _require(vertices, "vertices", torch.float32, 3)
-        if vertices.shape[0] != self.vertex_count:
-            raise ValueError(f"refit needs {self.vertex_count} vertices, got {vertices.shape[0]}")
+        want = sum(self.vertex_counts) if self.two_level else self.vertex_count
+        if vertices.shape[0] != want:
+            raise ValueError(f"refit needs {want} vertices, got {vertices.shape[0]}")
         capi.call("rt_refit", self.handle, _ptr(vertices), C.c_void_p(_stream()))
 
     def update_instances(self, inst_srt) -> None:

@@ -140,7 +140,10 @@ struct rt_accel_s {
   std::vector<float> tlas_nodes;
   std::vector<uint32_t> tlas_depth;
   std::vector<uint32_t> host_inst_mesh;
+  std::vector<rt_srt> host_srts;             // the current frames
   std::vector<rtb::Box> mesh_bounds;
+  std::vector<uint32_t> mesh_root;           // root node of each mesh's tree (RT_CHILD_EMPTY: none)
+  std::vector<uint32_t> mesh_tri_base;       // first triangle record of each mesh
   rt_accel_info info{};
 };
 
@@ -442,6 +445,8 @@ static rt_status setup_instances(rt_accel_s* a, const rt_mesh_desc* meshes, uint
   RT_HIP(hipMemcpyAsync(a->vertex_base, base.data(), mesh_count * sizeof(uint64_t), hipMemcpyHostToDevice, s));
   a->instance_count = instance_count;
   a->host_inst_mesh.assign(instance_mesh, instance_mesh + instance_count);
+  a->host_srts.assign(instance_srt, instance_srt + instance_count);
+  a->mesh_root = blas_root;
   return RT_SUCCESS;
 }
 
@@ -626,6 +631,41 @@ static rt_status build_two_level_on_device(rt_context ctx, const rt_mesh_desc* m
     if (st != RT_SUCCESS) return bail(st);
     e = hipMemcpyAsync(a->meshes, a->host_meshes.data(), mesh_count * sizeof(rt_mesh_dev), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "mesh records");
+    // refit order: a device build numbers the wide nodes of one depth
+    // consecutively, depth 1 first, and lists the level sizes deepest first
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> ranges(mesh_count);  // per depth - 1: [begin, end)
+    uint32_t maxd = 0;
+    for (uint32_t m = 0; m < mesh_count; ++m) {
+      const rtd::Output& o = parts[m];
+      if (!o.tri_count) continue;
+      const std::vector<uint32_t>& lv = o.refit_levels;
+      const uint32_t L = lv.empty() ? 0u : (uint32_t)lv.size() - 1;
+      std::vector<std::pair<uint32_t, uint32_t>> r(L);
+      uint32_t begin = 0;
+      for (uint32_t d = 1; d <= L; ++d) {
+        uint32_t k = L - d;  // position of depth d in the deepest-first list
+        uint32_t size = lv[k + 1] - lv[k];
+        r[d - 1] = {node_base[m] + begin, node_base[m] + begin + size};
+        begin += size;
+      }
+      ranges[m] = r;
+      maxd = std::max(maxd, L);
+    }
+    std::vector<uint32_t> order;
+    a->refit_levels.assign(1, 0);
+    for (uint32_t d = maxd; d >= 1; --d) {
+      for (uint32_t m = 0; m < mesh_count; ++m)
+        if (d <= ranges[m].size())
+          for (uint32_t i = ranges[m][d - 1].first; i < ranges[m][d - 1].second; ++i) order.push_back(i);
+      a->refit_levels.push_back((uint32_t)order.size());
+    }
+    a->mesh_tri_base = tri_base;
+    if (!order.empty()) {
+      st = dev_alloc(a, &a->refit_nodes, order.size());
+      if (st != RT_SUCCESS) return bail(st);
+      e = hipMemcpyAsync(a->refit_nodes, order.data(), order.size() * 4, hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) return hip_fail(e, "refit order");
+    }
     st = setup_instances(a, meshes, mesh_count, instance_mesh, instance_srt, instance_count, blas_root, s);
     if (st != RT_SUCCESS) return bail(st);
     a->tlas_nodes = tlas.nodes;
@@ -847,22 +887,29 @@ rt_status rt_build(rt_context ctx, const rt_mesh_desc* meshes, uint32_t mesh_cou
     st = dev_alloc(a, &a->meshes, mesh_count);
     if (st != RT_SUCCESS) return bail(st);
     RT_HIP_BAIL(hipMemcpyAsync(a->meshes, a->host_meshes.data(), mesh_count * sizeof(rt_mesh_dev), hipMemcpyHostToDevice, s));
-    if (!a->two_level && blas[0].node_count > 0) {
-      // node ids grouped by depth, deepest first, for the bottom-up refit
-      const std::vector<uint32_t>& dep = blas[0].node_depth;
+    {
+      // the meshes' node ids grouped by depth in their own tree, deepest
+      // first, for the bottom-up refit (a node's children are one deeper)
       uint32_t maxd = 0;
-      for (uint32_t d : dep) maxd = std::max(maxd, d);
+      for (uint32_t m = 0; m < mesh_count; ++m)
+        for (uint32_t i = 0; i < blas[m].node_count && i < blas[m].node_depth.size(); ++i)
+          maxd = std::max(maxd, blas[m].node_depth[i]);
       std::vector<uint32_t> order;
-      order.reserve(dep.size());
       a->refit_levels.assign(1, 0);
       for (uint32_t d = maxd; d >= 1; --d) {
-        for (uint32_t i = 0; i < (uint32_t)dep.size(); ++i)
-          if (dep[i] == d) order.push_back(i + node_base[0]);
+        for (uint32_t m = 0; m < mesh_count; ++m) {
+          const std::vector<uint32_t>& dep = blas[m].node_depth;
+          for (uint32_t i = 0; i < blas[m].node_count && i < dep.size(); ++i)
+            if (dep[i] == d) order.push_back(i + node_base[m]);
+        }
         a->refit_levels.push_back((uint32_t)order.size());
       }
-      st = dev_alloc(a, &a->refit_nodes, order.size());
-      if (st != RT_SUCCESS) return bail(st);
-      RT_HIP_BAIL(hipMemcpyAsync(a->refit_nodes, order.data(), order.size() * 4, hipMemcpyHostToDevice, s));
+      a->mesh_tri_base = tri_base;
+      if (!order.empty()) {
+        st = dev_alloc(a, &a->refit_nodes, order.size());
+        if (st != RT_SUCCESS) return bail(st);
+        RT_HIP_BAIL(hipMemcpyAsync(a->refit_nodes, order.data(), order.size() * 4, hipMemcpyHostToDevice, s));
+      }
     }
     if (a->two_level) {
       std::vector<uint32_t> blas_root(mesh_count);
@@ -1073,6 +1120,84 @@ rt_status rt_accel_set_instance_masks(rt_accel accel, const uint32_t* masks, voi
   return ok();
 }
 
+// Refits the boxes of a two-level accel's top-level tree, bottom-up over
+// its kept topology, to the world boxes of the instances (the current frames
+// applied to the meshes' bounds), and enqueues the upload of its nodes.
+static rt_status refit_top_level(rt_accel_s* a, hipStream_t s) {
+  const uint32_t n = a->instance_count;
+  const int W = a->width;
+  const uint32_t fpn = 8u * (uint32_t)W;
+  std::vector<rtb::Box> wb(n);
+  for (uint32_t j = 0; j < n; ++j) {
+    const rtb::Box& b = a->mesh_bounds[a->host_inst_mesh[j]];
+    if (b.lo[0] <= b.hi[0] && b.lo[1] <= b.hi[1] && b.lo[2] <= b.hi[2]) {
+      wb[j] = world_box(b, a->host_srts[j]);
+    } else {
+      for (int k = 0; k < 3; ++k) {
+        wb[j].lo[k] = INFINITY;
+        wb[j].hi[k] = -INFINITY;
+      }
+    }
+  }
+  // deepest nodes first; each child slot from its instance's world box or
+  // from the union of its node's slots
+  std::vector<float>& T = a->tlas_nodes;
+  const uint32_t tn = (uint32_t)a->tlas_depth.size();
+  uint32_t maxd = 0;
+  for (uint32_t d : a->tlas_depth) maxd = std::max(maxd, d);
+  double area_sum = 0.0;
+  rtb::Box root{};
+  for (uint32_t d = maxd; d >= 1; --d) {
+    for (uint32_t i = 0; i < tn; ++i) {
+      if (a->tlas_depth[i] != d) continue;
+      float* nd = T.data() + (size_t)i * fpn;
+      rtb::Box nb;
+      for (int k = 0; k < 3; ++k) {
+        nb.lo[k] = INFINITY;
+        nb.hi[k] = -INFINITY;
+      }
+      for (int c = 0; c < W; ++c) {
+        uint32_t ref;
+        std::memcpy(&ref, &nd[6 * W + c], 4);
+        if (ref == RT_CHILD_EMPTY) continue;
+        rtb::Box cb;
+        if ((ref & RT_LEAF_BIT) == 0u) {
+          const float* ch = T.data() + (size_t)ref * fpn;  // top-level refs are node indices
+          for (int k = 0; k < 3; ++k) {
+            cb.lo[k] = INFINITY;
+            cb.hi[k] = -INFINITY;
+          }
+          for (int q = 0; q < W; ++q)
+            for (int k = 0; k < 3; ++k) {
+              cb.lo[k] = std::min(cb.lo[k], ch[(2 * k) * W + q]);
+              cb.hi[k] = std::max(cb.hi[k], ch[(2 * k + 1) * W + q]);
+            }
+        } else {
+          cb = wb[ref & RT_INST_INDEX_MASK];
+        }
+        for (int k = 0; k < 3; ++k) {
+          nd[(2 * k) * W + c] = cb.lo[k];
+          nd[(2 * k + 1) * W + c] = cb.hi[k];
+          nb.lo[k] = std::min(nb.lo[k], cb.lo[k]);
+          nb.hi[k] = std::max(nb.hi[k], cb.hi[k]);
+        }
+      }
+      double dx = (double)nb.hi[0] - nb.lo[0], dy = (double)nb.hi[1] - nb.lo[1], dz = (double)nb.hi[2] - nb.lo[2];
+      if (dx >= 0 && dy >= 0 && dz >= 0) area_sum += 2.0 * (dx * dy + dy * dz + dz * dx);
+      if (i == 0) root = nb;
+    }
+    if (d == 1) break;
+  }
+  if (tn > 0) {
+    double dx = (double)root.hi[0] - root.lo[0], dy = (double)root.hi[1] - root.lo[1],
+           dz = (double)root.hi[2] - root.lo[2];
+    double ra = 2.0 * (dx * dy + dy * dz + dz * dx);
+    a->info.sah_cost = ra > 0.0 ? area_sum / ra : 0.0;
+    RT_HIP(hipMemcpyAsync(a->nodes, T.data(), (size_t)tn * fpn * 4, hipMemcpyHostToDevice, s));
+  }
+  return RT_SUCCESS;
+}
+
 rt_status rt_update_instances(rt_accel accel, const rt_srt* instance_srt, void* stream) {
   if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_update_instances: NULL accel");
   if (!accel->two_level)
@@ -1084,12 +1209,9 @@ rt_status rt_update_instances(rt_accel accel, const rt_srt* instance_srt, void* 
   st = check_device(accel->device);
   if (st != RT_SUCCESS) return st;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int W = accel->width;
-  const uint32_t fpn = 8u * (uint32_t)W;
   try {
     // instance records: new maps, same roots, meshes and masks
     std::vector<rt_inst_rec64> ir64(n);
-    std::vector<rtb::Box> wb(n);
     for (uint32_t j = 0; j < n; ++j) {
       double m[12];
       srt_inverse(instance_srt[j], m);
@@ -1100,72 +1222,10 @@ rt_status rt_update_instances(rt_accel accel, const rt_srt* instance_srt, void* 
         r.r1[k] = (float)m[4 + k];
         r.r2[k] = (float)m[8 + k];
       }
-      const rtb::Box& b = accel->mesh_bounds[accel->host_inst_mesh[j]];
-      if (b.lo[0] <= b.hi[0]) {
-        wb[j] = world_box(b, instance_srt[j]);
-      } else {
-        for (int k = 0; k < 3; ++k) {
-          wb[j].lo[k] = INFINITY;
-          wb[j].hi[k] = -INFINITY;
-        }
-      }
     }
-    // top-level boxes refit bottom-up: deepest nodes first, each child slot
-    // from its instance's world box or from the union of its node's slots
-    std::vector<float>& T = accel->tlas_nodes;
-    const uint32_t tn = (uint32_t)accel->tlas_depth.size();
-    uint32_t maxd = 0;
-    for (uint32_t d : accel->tlas_depth) maxd = std::max(maxd, d);
-    double area_sum = 0.0;
-    rtb::Box root{};
-    for (uint32_t d = maxd; d >= 1; --d) {
-      for (uint32_t i = 0; i < tn; ++i) {
-        if (accel->tlas_depth[i] != d) continue;
-        float* nd = T.data() + (size_t)i * fpn;
-        rtb::Box nb;
-        for (int k = 0; k < 3; ++k) {
-          nb.lo[k] = INFINITY;
-          nb.hi[k] = -INFINITY;
-        }
-        for (int c = 0; c < W; ++c) {
-          uint32_t ref;
-          std::memcpy(&ref, &nd[6 * W + c], 4);
-          if (ref == RT_CHILD_EMPTY) continue;
-          rtb::Box cb;
-          if ((ref & RT_LEAF_BIT) == 0u) {
-            const float* ch = T.data() + (size_t)ref * fpn;  // top-level refs are node indices
-            for (int k = 0; k < 3; ++k) {
-              cb.lo[k] = INFINITY;
-              cb.hi[k] = -INFINITY;
-            }
-            for (int q = 0; q < W; ++q)
-              for (int k = 0; k < 3; ++k) {
-                cb.lo[k] = std::min(cb.lo[k], ch[(2 * k) * W + q]);
-                cb.hi[k] = std::max(cb.hi[k], ch[(2 * k + 1) * W + q]);
-              }
-          } else {
-            cb = wb[ref & RT_INST_INDEX_MASK];
-          }
-          for (int k = 0; k < 3; ++k) {
-            nd[(2 * k) * W + c] = cb.lo[k];
-            nd[(2 * k + 1) * W + c] = cb.hi[k];
-            nb.lo[k] = std::min(nb.lo[k], cb.lo[k]);
-            nb.hi[k] = std::max(nb.hi[k], cb.hi[k]);
-          }
-        }
-        double dx = (double)nb.hi[0] - nb.lo[0], dy = (double)nb.hi[1] - nb.lo[1], dz = (double)nb.hi[2] - nb.lo[2];
-        if (dx >= 0 && dy >= 0 && dz >= 0) area_sum += 2.0 * (dx * dy + dy * dz + dz * dx);
-        if (i == 0) root = nb;
-      }
-      if (d == 1) break;
-    }
-    if (tn > 0) {
-      double dx = (double)root.hi[0] - root.lo[0], dy = (double)root.hi[1] - root.lo[1],
-             dz = (double)root.hi[2] - root.lo[2];
-      double ra = 2.0 * (dx * dy + dy * dz + dz * dx);
-      accel->info.sah_cost = ra > 0.0 ? area_sum / ra : 0.0;
-      RT_HIP(hipMemcpyAsync(accel->nodes, T.data(), (size_t)tn * fpn * 4, hipMemcpyHostToDevice, s));
-    }
+    accel->host_srts.assign(instance_srt, instance_srt + n);
+    st = refit_top_level(accel, s);
+    if (st != RT_SUCCESS) return st;
     RT_HIP(hipMemcpyAsync(accel->insts, accel->host_insts.data(), n * sizeof(rt_inst_rec), hipMemcpyHostToDevice, s));
     RT_HIP(hipMemcpyAsync(accel->insts64, ir64.data(), n * sizeof(rt_inst_rec64), hipMemcpyHostToDevice, s));
     RT_HIP(hipMemcpyAsync(accel->srts, instance_srt, n * sizeof(rt_srt), hipMemcpyHostToDevice, s));
@@ -1333,9 +1393,69 @@ rt_status rt_ao_resolve(const uint8_t* occluded, uint32_t n, uint32_t samples, f
   return ok();
 }
 
+// Two-level refit: every mesh's vertex rows (one after another in build
+// order), records and nodes, then the meshes' bounds and the top level.
+static rt_status refit_two_level(rt_accel_s* a, const float* vertices, hipStream_t s) {
+  const uint32_t nm = (uint32_t)a->host_meshes.size();
+  const uint32_t fpn = 8u * (uint32_t)a->width;
+  uint64_t row = 0;
+  for (uint32_t m = 0; m < nm; ++m) {
+    const rt_mesh_dev& md = a->host_meshes[m];
+    if (md.vertex_count > 0)
+      RT_HIP(hipMemcpyAsync(const_cast<float*>(md.vertices), vertices + 3 * row, (size_t)md.vertex_count * 12,
+                            hipMemcpyDefault, s));
+    row += md.vertex_count;
+  }
+  for (uint32_t m = 0; m < nm; ++m) {
+    uint32_t b = a->mesh_tri_base[m];
+    uint32_t e = m + 1 < nm ? a->mesh_tri_base[m + 1] : a->info.triangle_count;
+    if (e > b) RT_HIP(rtk_launch_refit_tris(a->tris + b, e - b, a->host_meshes[m], s));
+  }
+  for (size_t l = 0; l + 1 < a->refit_levels.size(); ++l) {
+    uint32_t b = a->refit_levels[l], e = a->refit_levels[l + 1];
+    RT_HIP(rtk_launch_refit_nodes(a->width, a->nodes, a->tris, a->refit_nodes + b, e - b, s));
+  }
+  // each mesh's bounds: the union of its root node's slots
+  std::vector<float> roots((size_t)nm * fpn, 0.0f);
+  for (uint32_t m = 0; m < nm; ++m)
+    if (a->mesh_root[m] != RT_CHILD_EMPTY)
+      RT_HIP(hipMemcpyAsync(roots.data() + (size_t)m * fpn, a->nodes + (size_t)a->mesh_root[m] * fpn, fpn * 4,
+                            hipMemcpyDeviceToHost, s));
+  RT_HIP(hipStreamSynchronize(s));
+  const int W = a->width;
+  for (uint32_t m = 0; m < nm; ++m) {
+    rtb::Box& bb = a->mesh_bounds[m];
+    for (int k = 0; k < 3; ++k) {
+      bb.lo[k] = INFINITY;
+      bb.hi[k] = -INFINITY;
+    }
+    if (a->mesh_root[m] == RT_CHILD_EMPTY) continue;
+    const float* nd = roots.data() + (size_t)m * fpn;
+    for (int c = 0; c < W; ++c)
+      for (int k = 0; k < 3; ++k) {
+        bb.lo[k] = std::min(bb.lo[k], nd[(2 * k) * W + c]);
+        bb.hi[k] = std::max(bb.hi[k], nd[(2 * k + 1) * W + c]);
+      }
+  }
+  rt_status st = refit_top_level(a, s);
+  if (st != RT_SUCCESS) return st;
+  RT_HIP(hipStreamSynchronize(s));
+  return RT_SUCCESS;
+}
+
 rt_status rt_refit(rt_accel accel, const float* vertices, void* stream) {
   if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_refit: NULL accel");
-  if (accel->two_level) return fail(RT_ERROR_UNSUPPORTED, "rt_refit: two-level accels are not supported");
+  if (accel->two_level) {
+    if (accel->vertex_rows > 0 && !vertices) return fail(RT_ERROR_INVALID_VALUE, "rt_refit: vertices is NULL");
+    rt_status st = check_device(accel->device);
+    if (st != RT_SUCCESS) return st;
+    try {
+      st = refit_two_level(accel, vertices, static_cast<hipStream_t>(stream));
+    } catch (const std::bad_alloc&) {
+      return fail(RT_ERROR_OUT_OF_MEMORY, "rt_refit: host allocation failed");
+    }
+    return st == RT_SUCCESS ? ok() : st;
+  }
   const rt_mesh_dev& m = accel->host_meshes[0];
   if (m.vertex_count > 0 && !vertices) return fail(RT_ERROR_INVALID_VALUE, "rt_refit: vertices is NULL");
   rt_status st = check_device(accel->device);

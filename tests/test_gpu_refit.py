@@ -135,9 +135,12 @@ def test_refit_errors(gpu):
     I = torch.from_numpy(m.indices.view(np.int32)).cuda()
     acc = api.Accel(ctx, [(V, I)], inst_mesh=np.zeros(1, np.uint32),
                     inst_srt=np.array([[1, 1, 1, 0, 0, 0, 1, 0, 0, 0]], np.float32))
+    acc.refit(V)  # a two-level accel takes its meshes' rows one after another
     with pytest.raises(_capi.RtError) as e:
-        acc.refit(V)
-    assert e.value.status == _capi.RT_ERROR_UNSUPPORTED
+        _capi.call("rt_refit", acc.handle, None, None)
+    assert e.value.status == _capi.RT_ERROR_INVALID_VALUE
+    with pytest.raises(ValueError):
+        acc.refit(torch.cat([V, V]))
     acc.close()
     acc = api.Accel(ctx, [(V, I)])
     with pytest.raises(ValueError):

@@ -1,10 +1,11 @@
-"""GPU parity of rt_update_instances: moving the instances of a two-level
-accel (new frames; the top-level boxes refit over the kept topology, the
-meshes' trees untouched) must answer bit for bit like a fresh build with the
-new frames -- closest hits with instance ids, any-hit, masked queries and
-the two-level adjoint -- for host and device builds, stay inside the oracle's
-acceptable sets for the moved scene, and return to the first answers when
-the first frames are restored."""
+"""GPU parity of the dynamic two-level paths.  rt_update_instances (new
+frames; the top-level boxes refit over the kept topology, the meshes' trees
+untouched) and rt_refit of a two-level accel (new vertices for every mesh;
+their trees and the top level refit) must answer bit for bit like a fresh
+build of the changed scene -- closest hits with instance ids, any-hit, masked
+queries and the two-level adjoint -- for host and device builds, stay inside
+the oracle's acceptable sets, and return to the first answers when the first
+frames or vertices are restored."""
 from __future__ import annotations
 
 import numpy as np
@@ -149,3 +150,48 @@ def test_update_instanced_workload(gpu):
     assert torch.equal(h.view(torch.int32), hf.view(torch.int32)) and torch.equal(i, if_)
     acc.close()
     fresh.close()
+
+
+@pytest.mark.parametrize("device_build", [False, True])
+def test_two_level_refit_matches_fresh_build(gpu, orc, device_build):
+    """New vertices for every mesh (heights and a shear changed; mesh 1
+    collapsed to a point, so its triangles drop out) through rt_refit."""
+    torch, api, ctx = gpu
+    W = wl.aimed_instances(n_inst=12, n_rays=8192, k=354)
+    rng = wl.rng_for(355)
+    rays = torch.from_numpy(W.rays).cuda()
+    rmask = torch.from_numpy(rng.integers(0, 4, size=W.rays.shape[0]).astype(np.int32)).cuda()
+    imask = rng.integers(1, 4, size=12).astype(np.uint32)
+    d_tuv = torch.from_numpy(rng.standard_normal((W.rays.shape[0], 3)).astype(np.float32)).cuda()
+    acc = to_gpu_scene(api, torch, ctx, W.scene, device_build=device_build)
+    acc.set_instance_masks(imask)
+    first = answers(torch, api, acc, rays, rmask, d_tuv)
+    new_meshes = []
+    for k, m in enumerate(W.scene.meshes):
+        v = m.vertices.astype(np.float64).copy()
+        if k == 1:
+            v[:] = v[0]
+        else:
+            v[:, 1] += 0.15 * np.sin(3.0 * v[:, 0]) + 0.1 * v[:, 2]
+        new_meshes.append(wl.Mesh(v.astype(np.float32), m.indices))
+    rows = torch.from_numpy(np.concatenate([m.vertices for m in new_meshes])).cuda()
+    acc.refit(rows)
+    got = answers(torch, api, acc, rays, rmask, d_tuv)
+    scene1 = wl.Scene(new_meshes, W.scene.inst_mesh, W.scene.inst_srt)
+    fresh = to_gpu_scene(api, torch, ctx, scene1, device_build=device_build)
+    fresh.set_instance_masks(imask)
+    want = answers(torch, api, fresh, rays, rmask, d_tuv)
+    fresh.close()
+    same(got[:5], want[:5], "refit vs fresh build (queries)")
+    # the adjoint's vertex rows: mesh 1's triangles are absent in both
+    same(got[5:], want[5:], "refit vs fresh build (adjoint)")
+    S1 = orc.OracleScene.from_scene(scene1)
+    st = check_closest(got[0], orc.accept(S1, W.rays), inst=got[1], label="refit two-level")
+    say("device" if device_build else "host", st)
+    assert st["hits"] > 500
+    assert not np.isin(got[1][got[0][:, 1].view(np.uint32) != 0xFFFFFFFF],
+                       np.flatnonzero(W.scene.inst_mesh == 1)).any()
+    rows0 = torch.from_numpy(np.concatenate([m.vertices for m in W.scene.meshes])).cuda()
+    acc.refit(rows0)
+    same(answers(torch, api, acc, rays, rmask, d_tuv), first, "refit back")
+    acc.close()
