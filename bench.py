@@ -347,8 +347,18 @@ def instanced_bench(args, torch, np, api, workloads, ctx, stream):
     acc = api.Accel(ctx, meshes, W.scene.inst_mesh, W.scene.inst_srt)
     rays = torch.from_numpy(W.rays).to(dev)
     ms, _ = timed(lambda: api.trace_closest(acc, rays, want_inst=True), args.steps, stream, torch)
-    r = {"instanced_closest_mrays": round(rays.shape[0] / (ms * 1e-3) / 1e6, 3),
-         "instanced_workload": f"{W.name}: 1024 instances of 4 x 10000 triangles, {rays.shape[0]} rays"}
+    (nodes, tris, _), _ = api.trace_counters(acc, rays)
+    n = rays.shape[0]
+    width = acc.info["node_width"]
+    # algorithmic bytes per ray: ray, hit and instance id, node visits of both
+    # levels, triangle tests, and the finalize's record and float64 map (the
+    # instance records read on entry are not counted: a lower bound)
+    bpr = 32 + 16 + 4 + nodes / n * 32 * width + tris / n * 48 + 48 + 96
+    r = {"instanced_closest_mrays": round(n / (ms * 1e-3) / 1e6, 3),
+         "instanced_nodes_per_ray": round(nodes / n, 3), "instanced_tris_per_ray": round(tris / n, 3),
+         "instanced_bytes_per_ray": round(bpr, 1),
+         "instanced_hbm_frac": round(bpr * n / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+         "instanced_workload": f"{W.name}: 1024 instances of 4 x 10000 triangles, {n} rays"}
     log(f"instanced: {r}")
     acc.close()
     return r

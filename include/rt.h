@@ -343,9 +343,9 @@ rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const 
 /* Diagnostics: the query of rt_trace_closest (any == 0, into hits) or
  * rt_trace_any (any != 0, into occluded) run with a counting kernel variant
  * (stack 16, workgroup 256) that ADDS to counters (device, 3 uint64): node
- * visits, triangle tests, stack entries spilled to global memory.  Used to
- * measure the bytes a query fetches per ray.  Single-level accels only
- * (RT_ERROR_UNSUPPORTED otherwise). */
+ * visits (both levels of a two-level accel), triangle tests, stack entries
+ * spilled to global memory.  Used to measure the bytes a query fetches per
+ * ray.  The instance ids of a two-level closest query are not written. */
 rt_status rt_trace_counters(rt_accel accel, const rt_ray* rays, uint32_t n, int any, rt_hit* hits,
                             uint8_t* occluded, uint64_t* counters, void* stream);
 

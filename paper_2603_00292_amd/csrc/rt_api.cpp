@@ -983,7 +983,7 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   std::lock_guard<std::mutex> lk(ctx->mu);
   rt_variant v = ctx->variant;
   if (counters || mode >= 2) v = rt_variant{16, 256};
-  const void* kern = counters ? rtk_count_kernel(a->width, any)
+  const void* kern = counters ? rtk_count_kernel(a->width, any, a->two_level)
                               : rtk_trace_kernel(a->width, (int)v.stack_entries, (int)v.workgroup,
                                                  any, a->two_level, mode);
   if (!kern) return fail(RT_ERROR_UNSUPPORTED, "trace: variant not compiled");
@@ -1239,8 +1239,6 @@ rt_status rt_update_instances(rt_accel accel, const rt_srt* instance_srt, void* 
 rt_status rt_trace_counters(rt_accel accel, const rt_ray* rays, uint32_t n, int any, rt_hit* hits,
                             uint8_t* occluded, uint64_t* counters, void* stream) {
   if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_counters: NULL accel");
-  if (accel->two_level)
-    return fail(RT_ERROR_UNSUPPORTED, "rt_trace_counters: two-level accels are not supported");
   if (n == 0) return ok();
   if (!rays || !counters || (any ? !occluded : !hits))
     return fail(RT_ERROR_INVALID_VALUE, "rt_trace_counters: NULL buffer with n > 0");

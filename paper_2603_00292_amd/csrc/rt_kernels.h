@@ -106,7 +106,7 @@ struct AoParams {
 // modes 2 and 3 exist for stack 16 / workgroup 256 only); nullptr when the
 // combination is not compiled.
 const void* rtk_trace_kernel(int width, int stack, int wg, bool any, bool inst, int mode);
-const void* rtk_count_kernel(int width, bool any);
+const void* rtk_count_kernel(int width, bool any, bool inst);
 hipError_t rtk_launch_trace(const void* kern, uint32_t grid, uint32_t wg, const TraceParams& p,
                             hipStream_t stream);
 // float64 finalize of closest hits written by a trace launch with the same params

@@ -319,11 +319,12 @@ __device__ __forceinline__ void list_insert(float4* L, uint32_t found, uint32_t 
 // culling by the nearest hit) into per-ray lists of the `cap` nearest.
 // Two-level kernels of width <= 4 are asked to fit six waves per SIMD (80
 // VGPRs): on the 1,024-instance workload 4 -> 6 waves measured +12%, with no
-// spills (8-wide nodes would spill, so they keep the compiler's choice).
-template <int W, bool INST>
-constexpr int trace_min_waves() { return (INST && W <= 4) ? 6 : 1; }
+// spills (8-wide nodes and the counting variants would spill, so they keep
+// the compiler's choice).
+template <int W, bool INST, bool COUNT>
+constexpr int trace_min_waves() { return (INST && W <= 4 && !COUNT) ? 6 : 1; }
 template <int W, int S, int WG, bool ANY, bool INST, int MODE, bool COUNT = false>
-__global__ __launch_bounds__(WG, (trace_min_waves<W, INST>())) void trace_kernel(TraceParams P) {
+__global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT>())) void trace_kernel(TraceParams P) {
   __shared__ uint32_t lds_stack[S * WG];
   // two-level: the world ray's origin and direction, restored on leaving an
   // instance (kept out of registers)
@@ -1079,9 +1080,14 @@ const void* pick_query(bool any, bool inst, int mode) {
   return inst ? kernel_ptr<W, 16, 256, false, true, 2>() : kernel_ptr<W, 16, 256, false, false, 2>();
 }
 
-template <int W, bool ANY>
+template <int W, bool ANY, bool INST>
 const void* kernel_ptr_c() {
-  return reinterpret_cast<const void*>(&rtk::trace_kernel<W, 16, 256, ANY, false, 0, true>);
+  return reinterpret_cast<const void*>(&rtk::trace_kernel<W, 16, 256, ANY, INST, 0, true>);
+}
+template <int W>
+const void* count_kernel_w(bool any, bool inst) {
+  if (inst) return any ? kernel_ptr_c<W, true, true>() : kernel_ptr_c<W, false, true>();
+  return any ? kernel_ptr_c<W, true, false>() : kernel_ptr_c<W, false, false>();
 }
 
 template <int W, int S, int WG>
@@ -1114,12 +1120,12 @@ const void* pick_s(int s, int wg, bool any, bool inst, int mode) {
 }  // namespace
 
 // Counting variants (node visits, triangle tests, stack spills per launch):
-// stack 16, workgroup 256, single level.
-const void* rtk_count_kernel(int width, bool any) {
+// stack 16, workgroup 256; two-level variants count the nodes of both levels.
+const void* rtk_count_kernel(int width, bool any, bool inst) {
   switch (width) {
-    case 2: return any ? kernel_ptr_c<2, true>() : kernel_ptr_c<2, false>();
-    case 4: return any ? kernel_ptr_c<4, true>() : kernel_ptr_c<4, false>();
-    case 8: return any ? kernel_ptr_c<8, true>() : kernel_ptr_c<8, false>();
+    case 2: return count_kernel_w<2>(any, inst);
+    case 4: return count_kernel_w<4>(any, inst);
+    case 8: return count_kernel_w<8>(any, inst);
     default: return nullptr;
   }
 }

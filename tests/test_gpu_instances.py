@@ -155,6 +155,27 @@ def test_instance_transform_kinds(gpu, orc):
     acc.close()
 
 
+def test_counters_two_level(gpu):
+    """The counting variants on a two-level accel (node visits of both
+    levels, triangle tests) give the same hits as the plain query, and counts
+    that bound the work: at least one node per ray that enters the top level."""
+    torch, api, ctx = gpu
+    W = wl.instanced_grids(n_inst=64, n_rays=8192, k=402)
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    rays = torch.from_numpy(W.rays).cuda()
+    h, _ = api.trace_closest(acc, rays, want_inst=True)
+    occ = api.trace_any(acc, rays)
+    (nodes, tris, spills), hc = api.trace_counters(acc, rays)
+    (nodes_a, tris_a, _), oc = api.trace_counters(acc, rays, any_hit=True)
+    torch.cuda.synchronize()
+    assert torch.equal(h.view(torch.int32), hc.view(torch.int32))
+    assert torch.equal(occ, oc)
+    n = rays.shape[0]
+    say("two-level counters per ray: closest", nodes / n, tris / n, spills / n, "any", nodes_a / n, tris_a / n)
+    assert nodes >= n and tris > 0 and nodes_a <= nodes and tris_a <= tris
+    acc.close()
+
+
 def test_build_argument_errors(gpu):
     torch, api, ctx = gpu
     from paper_2603_00292_amd import _capi
