@@ -233,7 +233,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "icosphere_incoherent", "triangles": int(mesh.n_tri), "rays": int(n),
                    "origins": "U[-1,1]^3", "directions": "uniform sphere", "node_width": info["node_width"],
-                   "variant": list(ctx.variant), "autotuned": tuned is not None, "query": "closest"},
+                   "variant": list(ctx.variant), "autotuned": tuned is not None, "query": "closest",
+                   "inputs_sha256": W.checksum()[:16]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_ray": round(bytes_per_launch / n, 1), "kernel_ms": round(mean_launch_ms, 4)},

@@ -221,6 +221,32 @@ class Workload:
     rays: np.ndarray                       # (n,8) float32
     extra: dict = field(default_factory=dict)
 
+    def checksum(self) -> str:
+        """SHA-256 (hex) of every input array in a fixed order: each mesh's
+        vertices and indices, the instance arrays, the rays, then the array
+        entries of `extra` by key.  Each array contributes its dtype, shape
+        and bytes, so the value pins the generator's output exactly."""
+        import hashlib
+
+        h = hashlib.sha256()
+
+        def add(tag, a):
+            a = np.ascontiguousarray(a)
+            h.update(f"{tag}:{a.dtype.str}:{a.shape};".encode())
+            h.update(a.tobytes())
+
+        for i, m in enumerate(self.scene.meshes):
+            add(f"v{i}", m.vertices)
+            add(f"i{i}", m.indices)
+        if self.scene.inst_mesh is not None:
+            add("inst_mesh", self.scene.inst_mesh)
+            add("inst_srt", self.scene.inst_srt)
+        add("rays", self.rays)
+        for k in sorted(self.extra):
+            if isinstance(self.extra[k], np.ndarray):
+                add(f"extra:{k}", self.extra[k])
+        return h.hexdigest()
+
 
 # ----------------------------------------------------------------------------
 # the workloads
