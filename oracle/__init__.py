@@ -73,6 +73,7 @@ def _load():
             "orc_adjoint_inst": [P, P, P, P, i64, P, P, P, P, P],
             "orc_fd_inst": [P, P, P, P, i64, P, C.c_double, P],
             "orc_ao_rays": [P, P, P, P, i64, C.c_int32, P, C.c_double, C.c_double, P],
+            "orc_ao_rays_inst": [P, P, P, P, P, i64, C.c_int32, P, C.c_double, C.c_double, P],
         }.items():
             f = getattr(lib, name)
             f.argtypes = args
@@ -349,9 +350,10 @@ def fd_inst(scene: OracleScene, rays, inst, prim, g, h: float = 1e-6):
     return out
 
 
-def ao_rays(scene: OracleScene, rays, prim, tuv, xi, offset: float, radius: float):
+def ao_rays(scene: OracleScene, rays, prim, tuv, xi, offset: float, radius: float, inst=None):
     """Ambient-occlusion rays (§4): (n*N, 8) float32 for the primary rays'
-    closest hits (prim, tuv) and uniforms xi (n, N, 2)."""
+    closest hits (prim, tuv; and inst, their instances, in a two-level scene)
+    and uniforms xi (n, N, 2)."""
     lib = _load()
     r, n = _rays(rays)
     prim = np.ascontiguousarray(prim, dtype=np.uint32).reshape(-1)
@@ -360,8 +362,13 @@ def ao_rays(scene: OracleScene, rays, prim, tuv, xi, offset: float, radius: floa
     N = xi.shape[1]
     assert xi.shape == (n, N, 2)
     out = np.empty((n * N, 8), np.float32)
-    _check(lib.orc_ao_rays(scene.ptr, _p(r), _p(prim), _p(tuv), n, int(N), _p(xi), float(offset),
-                           float(radius), _p(out)), "ao_rays")
+    if inst is None:
+        _check(lib.orc_ao_rays(scene.ptr, _p(r), _p(prim), _p(tuv), n, int(N), _p(xi), float(offset),
+                               float(radius), _p(out)), "ao_rays")
+    else:
+        inst = np.ascontiguousarray(inst, dtype=np.uint32).reshape(-1)
+        _check(lib.orc_ao_rays_inst(scene.ptr, _p(r), _p(inst), _p(prim), _p(tuv), n, int(N), _p(xi),
+                                    float(offset), float(radius), _p(out)), "ao_rays_inst")
     return out
 
 

@@ -981,13 +981,23 @@ int orc_fd_inst(const orc_scene* s, const float* rays, const uint32_t* inst, con
  * the origin p + offset n (§4.2 self-intersection offset); t in
  * [0, radius] (§4.2 limited ray length).  Misses give void rays
  * (tmin = 1, tmax = 0).  Everything in float64, rounded once to float32. */
-int orc_ao_rays(const orc_scene* s, const float* rays, const uint32_t* prim, const double* tuv,
-                int64_t nr, int32_t N, const float* xi, double offset, double radius,
-                float* out) {
-  if (nr < 0 || N < 1 || !scene_valid(s) || s->n_inst != 0) return -1;
+/* Two-level scenes: the hit triangle is the one of mesh inst_mesh[j] of the
+ * ray's instance j, with its corners mapped to world space by the frame
+ * (world = T + R(qhat)(S*x), §7.3); everything after that as above. */
+static int ao_rays_impl(const orc_scene* s, const float* rays, const uint32_t* inst, const uint32_t* prim,
+                        const double* tuv, int64_t nr, int32_t N, const float* xi, double offset,
+                        double radius, float* out) {
   if (nr > 0 && (!rays || !prim || !tuv || !xi || !out)) return -1;
-  for (int64_t r = 0; r < nr; ++r)
-    if (prim[r] != ORC_NONE && (int64_t)prim[r] >= s->n_triangles[0]) return -1;
+  if (nr > 0 && s->n_inst > 0 && !inst) return -1;
+  for (int64_t r = 0; r < nr; ++r) {
+    if (prim[r] == ORC_NONE) continue;
+    int m = 0;
+    if (s->n_inst > 0) {
+      if ((int64_t)inst[r] >= s->n_inst) return -1;
+      m = (int)s->inst_mesh[inst[r]];
+    }
+    if ((int64_t)prim[r] >= s->n_triangles[m]) return -1;
+  }
   const double two_pi = 6.283185307179586476925286766559;
 #pragma omp parallel for schedule(static)
   for (int64_t r = 0; r < nr; ++r) {
@@ -996,7 +1006,16 @@ int orc_ao_rays(const orc_scene* s, const float* rays, const uint32_t* prim, con
     vec3 n = mk(0, 0, 0), t0 = mk(0, 0, 0), t1 = mk(0, 0, 0), org = mk(0, 0, 0);
     if (hit) {
       vec3 v0, v1, v2;
-      tri(s, 0, prim[r], &v0, &v1, &v2);
+      if (s->n_inst > 0) {
+        uint32_t j = inst[r];
+        tri(s, (int)s->inst_mesh[j], prim[r], &v0, &v1, &v2);
+        frame64 F = load_frame(s->inst_srt + 10 * (int64_t)j);
+        v0 = to_world(&F, v0);
+        v1 = to_world(&F, v1);
+        v2 = to_world(&F, v2);
+      } else {
+        tri(s, 0, prim[r], &v0, &v1, &v2);
+      }
       n = cross(sub(v1, v0), sub(v2, v0));
       n = scl(n, 1.0 / norm(n));
       if (dot(n, q.d) > 0.0) n = scl(n, -1.0);
@@ -1028,6 +1047,20 @@ int orc_ao_rays(const orc_scene* s, const float* rays, const uint32_t* prim, con
     }
   }
   return 0;
+}
+
+int orc_ao_rays(const orc_scene* s, const float* rays, const uint32_t* prim, const double* tuv,
+                int64_t nr, int32_t N, const float* xi, double offset, double radius,
+                float* out) {
+  if (nr < 0 || N < 1 || !scene_valid(s) || s->n_inst != 0) return -1;
+  return ao_rays_impl(s, rays, NULL, prim, tuv, nr, N, xi, offset, radius, out);
+}
+
+int orc_ao_rays_inst(const orc_scene* s, const float* rays, const uint32_t* inst, const uint32_t* prim,
+                     const double* tuv, int64_t nr, int32_t N, const float* xi, double offset,
+                     double radius, float* out) {
+  if (nr < 0 || N < 1 || !scene_valid(s) || s->n_inst < 1) return -1;
+  return ao_rays_impl(s, rays, inst, prim, tuv, nr, N, xi, offset, radius, out);
 }
 
 int orc_num_threads(void) {

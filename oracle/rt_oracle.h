@@ -147,6 +147,14 @@ int orc_ao_rays(const orc_scene* s, const float* rays, const uint32_t* prim, con
                 int64_t nr, int32_t N, const float* xi, double offset, double radius,
                 float* out);
 
+/* The same for two-level scenes: inst[r] is the instance of ray r's closest
+ * hit (as returned by orc_closest); the hit triangle's corners are mapped to
+ * world space by that instance's frame before the normal and tangent frame
+ * are formed. */
+int orc_ao_rays_inst(const orc_scene* s, const float* rays, const uint32_t* inst, const uint32_t* prim,
+                     const double* tuv, int64_t nr, int32_t N, const float* xi, double offset,
+                     double radius, float* out);
+
 int orc_num_threads(void);
 void orc_set_num_threads(int n);
 
