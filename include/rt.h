@@ -214,6 +214,17 @@ rt_status rt_ao_rays(rt_accel accel, const rt_ray* rays, const rt_hit* hits, uin
                      uint32_t samples, const float* xi, float offset, float radius,
                      rt_ray* ao_rays, void* stream);
 
+/* The same for the closest hits of a two-level accel: inst_ids[i] (DEVICE,
+ * as written by rt_trace_closest) names the instance of ray i's hit, whose
+ * frame maps the hit triangle's corners to world space (world = T +
+ * R(qhat)(S x), §7.3) before the normal and tangent frame are formed; a hit
+ * with an instance id >= instance_count gives void rays.  Errors:
+ * RT_ERROR_UNSUPPORTED on a single-level accel; otherwise as rt_ao_rays
+ * (inst_ids may not be NULL with n > 0). */
+rt_status rt_ao_rays_instances(rt_accel accel, const rt_ray* rays, const rt_hit* hits, const uint32_t* inst_ids,
+                               uint32_t n, uint32_t samples, const float* xi, float offset, float radius,
+                               rt_ray* ao_rays, void* stream);
+
 /* ao[i] = (number of k < samples with occluded[i*samples + k] != 0) /
  * samples (DEVICE buffers): the occluded fraction of §4's listing. */
 rt_status rt_ao_resolve(const uint8_t* occluded, uint32_t n, uint32_t samples, float* ao,

@@ -26,7 +26,7 @@ EXPORTS = [
     "rt_build", "rt_accel_destroy", "rt_accel_get_info",
     "rt_trace_closest", "rt_trace_any", "rt_trace_backward", "rt_trace_backward_instances",
     "rt_trace_closest_ex", "rt_trace_any_ex", "rt_trace_all", "rt_accel_set_instance_masks", "rt_update_instances",
-    "rt_ao_rays", "rt_ao_resolve",
+    "rt_ao_rays", "rt_ao_rays_instances", "rt_ao_resolve",
     "rt_trace_counters", "rt_refit",
     "rt_autotune",
     "rt_batch_plan_create", "rt_batch_plan_launch", "rt_batch_plan_graph", "rt_batch_plan_destroy",
@@ -117,6 +117,7 @@ def load():
             "rt_accel_set_instance_masks": [P, P, P],
             "rt_update_instances": [P, P, P],
             "rt_ao_rays": [P, P, P, U32, U32, P, C.c_float, C.c_float, P, P],
+            "rt_ao_rays_instances": [P, P, P, P, U32, U32, P, C.c_float, C.c_float, P, P],
             "rt_ao_resolve": [P, U32, U32, P, P],
             "rt_refit": [P, P, P],
             "rt_autotune": [P, P, P, U32, U32, P, P, P, U32, P],

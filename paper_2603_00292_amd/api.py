@@ -230,19 +230,27 @@ def trace_all(accel: Accel, rays: torch.Tensor, capacity: int, ray_masks=None, s
 
 
 def ao_rays(accel: Accel, rays: torch.Tensor, hits: torch.Tensor, xi: torch.Tensor, offset: float,
-            radius: float) -> torch.Tensor:
-    """rt_ao_rays: (n * samples, 8) ambient-occlusion rays from closest hits;
-    xi (n, samples, 2) float32 uniforms on the device."""
+            radius: float, inst_ids: torch.Tensor | None = None) -> torch.Tensor:
+    """rt_ao_rays (rt_ao_rays_instances with the hits' inst_ids on a
+    two-level accel): (n * samples, 8) ambient-occlusion rays from closest
+    hits; xi (n, samples, 2) float32 uniforms on the device."""
     _require(rays, "rays", torch.float32, 8)
     _require(hits, "hits", torch.float32, 4)
     n = rays.shape[0]
+    if inst_ids is not None and (inst_ids.dtype not in (torch.int32, torch.uint32) or not inst_ids.is_contiguous()
+                                 or inst_ids.shape != (n,) or inst_ids.device.type != "cuda"):
+        raise ValueError("inst_ids must be a contiguous (n,) int32 cuda tensor")
     if xi.dtype != torch.float32 or not xi.is_contiguous() or xi.dim() != 3 or xi.shape[0] != n \
             or xi.shape[2] != 2 or xi.device.type != "cuda":
         raise ValueError("xi must be a contiguous (n, samples, 2) float32 cuda tensor")
     samples = xi.shape[1]
     out = torch.empty((n * samples, 8), dtype=torch.float32, device=rays.device)
-    capi.call("rt_ao_rays", accel.handle, _ptr(rays), _ptr(hits), n, samples, _ptr(xi), float(offset),
-              float(radius), _ptr(out), C.c_void_p(_stream()))
+    if inst_ids is None:
+        capi.call("rt_ao_rays", accel.handle, _ptr(rays), _ptr(hits), n, samples, _ptr(xi), float(offset),
+                  float(radius), _ptr(out), C.c_void_p(_stream()))
+    else:
+        capi.call("rt_ao_rays_instances", accel.handle, _ptr(rays), _ptr(hits), _ptr(inst_ids), n, samples,
+                  _ptr(xi), float(offset), float(radius), _ptr(out), C.c_void_p(_stream()))
     return out
 
 
@@ -261,8 +269,9 @@ def ambient_occlusion(accel: Accel, rays: torch.Tensor, xi: torch.Tensor, offset
     """The ambient-occlusion workload of §4 on the library: closest hits of
     the primary rays, AO rays from them, any-hit queries, occluded fraction.
     Returns (ao (n,), hits (n,4), ao_rays (n*samples, 8), occluded)."""
-    hits, _ = trace_closest(accel, rays)
-    ar = ao_rays(accel, rays, hits, xi, offset, radius)
+    two = bool(getattr(accel, "two_level", False))
+    hits, inst = trace_closest(accel, rays, want_inst=two)
+    ar = ao_rays(accel, rays, hits, xi, offset, radius, inst_ids=inst)
     occ = trace_any(accel, ar)
     return ao_resolve(occ, xi.shape[1]), hits, ar, occ
 

@@ -1350,24 +1350,31 @@ rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const 
   return ok();
 }
 
-rt_status rt_ao_rays(rt_accel accel, const rt_ray* rays, const rt_hit* hits, uint32_t n,
-                     uint32_t samples, const float* xi, float offset, float radius,
-                     rt_ray* ao_rays, void* stream) {
-  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays: NULL accel");
-  if (accel->two_level) return fail(RT_ERROR_UNSUPPORTED, "rt_ao_rays: two-level accels are not supported");
-  if (samples < 1) return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays: samples must be >= 1");
+static rt_status ao_rays_impl(const char* who, rt_accel accel, const rt_ray* rays, const rt_hit* hits,
+                              const uint32_t* inst_ids, uint32_t n, uint32_t samples, const float* xi,
+                              float offset, float radius, rt_ray* ao_rays, void* stream) {
+  if (samples < 1) return fail(RT_ERROR_INVALID_VALUE, "%s: samples must be >= 1", who);
   if (!(radius >= 0.0f) || !(offset >= 0.0f) || !std::isfinite(offset))
-    return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays: offset must be finite and >= 0, radius >= 0");
+    return fail(RT_ERROR_INVALID_VALUE, "%s: offset must be finite and >= 0, radius >= 0", who);
   if (n == 0) return ok();
   if ((uint64_t)n * samples > 0x7FFFFFFFull)
-    return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays: n * samples >= 2^31");
-  if (!rays || !hits || !xi || !ao_rays) return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays: NULL buffer with n > 0");
+    return fail(RT_ERROR_INVALID_VALUE, "%s: n * samples >= 2^31", who);
+  if (!rays || !hits || !xi || !ao_rays || (accel->two_level && !inst_ids))
+    return fail(RT_ERROR_INVALID_VALUE, "%s: NULL buffer with n > 0", who);
   if (!aligned16(rays) || !aligned16(hits) || !aligned16(ao_rays))
-    return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays: rays, hits and ao_rays must be 16-byte aligned");
+    return fail(RT_ERROR_INVALID_VALUE, "%s: rays, hits and ao_rays must be 16-byte aligned", who);
   rt_status st = check_device(accel->device);
   if (st != RT_SUCCESS) return st;
   AoParams p{};
-  p.mesh = accel->host_meshes[0];
+  if (accel->two_level) {
+    p.meshes = accel->meshes;
+    p.insts = accel->insts;
+    p.srts = accel->srts;
+    p.inst_ids = inst_ids;
+    p.inst_count = accel->instance_count;
+  } else {
+    p.mesh = accel->host_meshes[0];
+  }
   p.rays = rays;
   p.hits = hits;
   p.xi = xi;
@@ -1378,6 +1385,25 @@ rt_status rt_ao_rays(rt_accel accel, const rt_ray* rays, const rt_hit* hits, uin
   p.radius = radius;
   RT_HIP(rtk_launch_ao_rays(p, static_cast<hipStream_t>(stream)));
   return ok();
+}
+
+rt_status rt_ao_rays(rt_accel accel, const rt_ray* rays, const rt_hit* hits, uint32_t n,
+                     uint32_t samples, const float* xi, float offset, float radius,
+                     rt_ray* ao_rays, void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays: NULL accel");
+  if (accel->two_level)
+    return fail(RT_ERROR_UNSUPPORTED, "rt_ao_rays: two-level accel (use rt_ao_rays_instances)");
+  return ao_rays_impl("rt_ao_rays", accel, rays, hits, nullptr, n, samples, xi, offset, radius, ao_rays, stream);
+}
+
+rt_status rt_ao_rays_instances(rt_accel accel, const rt_ray* rays, const rt_hit* hits, const uint32_t* inst_ids,
+                               uint32_t n, uint32_t samples, const float* xi, float offset, float radius,
+                               rt_ray* ao_rays, void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_ao_rays_instances: NULL accel");
+  if (!accel->two_level)
+    return fail(RT_ERROR_UNSUPPORTED, "rt_ao_rays_instances: single-level accel (use rt_ao_rays)");
+  return ao_rays_impl("rt_ao_rays_instances", accel, rays, hits, inst_ids, n, samples, xi, offset, radius, ao_rays,
+                      stream);
 }
 
 rt_status rt_ao_resolve(const uint8_t* occluded, uint32_t n, uint32_t samples, float* ao,

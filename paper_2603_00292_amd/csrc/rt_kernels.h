@@ -90,7 +90,12 @@ struct BackwardInstParams {
 
 // Ambient-occlusion rays from closest hits (one thread per ray sample).
 struct AoParams {
-  rt_mesh_dev mesh;
+  rt_mesh_dev mesh;       // single level
+  const rt_mesh_dev* meshes;  // two-level (device): every mesh
+  const rt_inst_rec* insts;   // two-level: instance records (mesh id)
+  const rt_srt* srts;         // two-level: frames
+  const uint32_t* inst_ids;   // two-level: instance of each hit; null for single level
+  uint32_t inst_count;
   const rt_ray* rays;
   const rt_hit* hits;
   const float* xi;        // n * samples * 2 uniforms

@@ -1007,18 +1007,44 @@ __global__ __launch_bounds__(256) void ao_rays_kernel(AoParams P) {
   float4* out = reinterpret_cast<float4*>(P.out + i);
   float4 h = *reinterpret_cast<const float4*>(P.hits + ray);
   uint32_t prim = __float_as_uint(h.y);
-  if (prim == RT_INVALID_ID || prim >= P.mesh.triangle_count) {
+  rt_mesh_dev mesh = P.mesh;
+  uint32_t inst = 0;
+  bool ok = prim != RT_INVALID_ID;
+  if (ok && P.inst_ids) {
+    inst = P.inst_ids[ray];
+    ok = inst < P.inst_count;
+    if (ok) mesh = P.meshes[P.insts[inst].mesh];
+  }
+  if (!ok || prim >= mesh.triangle_count) {
     out[0] = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
     out[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     return;
   }
   rt_ray q = load_ray(P.rays, ray);
-  const uint32_t* ix = P.mesh.indices + 3 * (size_t)prim;
+  const uint32_t* ix = mesh.indices + 3 * (size_t)prim;
   double v[3][3];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) v[k][c] = P.mesh.vertices[3 * (size_t)ix[k] + c];
+    for (int c = 0; c < 3; ++c) v[k][c] = mesh.vertices[3 * (size_t)ix[k] + c];
+  if (P.inst_ids) {
+    // corners to world space: T + R(qhat)(S x), with R a = a + 2w (u x a) + 2u x (u x a)
+    // for the unit quaternion (u, w)
+    const rt_srt f = P.srts[inst];
+    double qx = f.qx, qy = f.qy, qz = f.qz, qw = f.qw;
+    double iq = 1.0 / sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
+    qx *= iq; qy *= iq; qz *= iq; qw *= iq;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double ax = f.sx * v[k][0], ay = f.sy * v[k][1], az = f.sz * v[k][2];
+      double cx, cy, cz, ex, ey, ez;
+      cross3(qx, qy, qz, ax, ay, az, cx, cy, cz);
+      cross3(qx, qy, qz, cx, cy, cz, ex, ey, ez);
+      v[k][0] = f.tx + (ax + 2.0 * qw * cx + 2.0 * ex);
+      v[k][1] = f.ty + (ay + 2.0 * qw * cy + 2.0 * ey);
+      v[k][2] = f.tz + (az + 2.0 * qw * cz + 2.0 * ez);
+    }
+  }
   double ax = v[1][0] - v[0][0], ay = v[1][1] - v[0][1], az = v[1][2] - v[0][2];
   double bx = v[2][0] - v[0][0], by = v[2][1] - v[0][1], bz = v[2][2] - v[0][2];
   double nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;

@@ -1,8 +1,9 @@
 """GPU parity of the ambient-occlusion workload (§4) driven through the
 library: closest hits of camera rays (rt_trace_closest), AO rays from them
-(rt_ao_rays), any-hit queries (rt_trace_any) and the occluded fraction
-(rt_ao_resolve), against the oracle's own closest hits, AO rays and any-hit
-acceptable sets on the same seeded camera rays and uniforms."""
+(rt_ao_rays, or rt_ao_rays_instances on a two-level scene), any-hit queries
+(rt_trace_any) and the occluded fraction (rt_ao_resolve), against the
+oracle's own closest hits, AO rays and any-hit acceptable sets on the same
+seeded rays and uniforms."""
 from __future__ import annotations
 
 import numpy as np
@@ -119,8 +120,12 @@ def test_ao_errors(gpu):
     hits, _ = api.trace_closest(acc, rays)
     xi = torch.zeros((64, 4, 2), dtype=torch.float32, device="cuda")
     with pytest.raises(_capi.RtError) as e:
-        api.ao_rays(acc, rays, hits, xi, 1e-4, 1.0)
+        api.ao_rays(acc, rays, hits, xi, 1e-4, 1.0)  # a two-level accel needs the instance ids
     assert e.value.status == _capi.RT_ERROR_UNSUPPORTED
+    with pytest.raises(_capi.RtError) as e:
+        _capi.call("rt_ao_rays_instances", acc.handle, api._ptr(rays), api._ptr(hits), None, 64, 4,
+                   api._ptr(xi), 1e-4, 1.0, api._ptr(torch.empty((256, 8), device="cuda")), None)
+    assert e.value.status == _capi.RT_ERROR_INVALID_VALUE
     acc.close()
     m = W.scene.meshes[0]
     single = api.Accel(ctx, [(torch.from_numpy(m.vertices).cuda(),
@@ -134,4 +139,54 @@ def test_ao_errors(gpu):
     assert e.value.status == _capi.RT_ERROR_INVALID_VALUE
     out = api.ao_rays(single, rays[:0], hits[:0], xi[:0], 1e-4, 1.0)
     assert out.shape == (0, 8)
+    with pytest.raises(_capi.RtError) as e:
+        api.ao_rays(single, rays, hits, xi, 1e-4, 1.0, inst_ids=torch.zeros(64, dtype=torch.int32, device="cuda"))
+    assert e.value.status == _capi.RT_ERROR_UNSUPPORTED
     single.close()
+
+
+def test_ao_two_level(gpu, orc):
+    """The AO steps on a two-level scene (24 instances of the displaced
+    grids, 4,096 rays aimed at them from outside, 8 samples): the AO rays of
+    every pinned hit equal the oracle's (hit triangle mapped to world space by
+    its instance frame) up to rounding, and every occlusion count lies
+    between the oracle's sure and sure-plus-maybe counts."""
+    torch, api, ctx = gpu
+    W = wl.aimed_instances(n_inst=24, n_rays=4096, k=333)
+    N, offset, radius = 8, 1e-4, 1.0
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    rays = torch.from_numpy(W.rays).cuda()
+    xi_np = wl.rng_for(334).random((W.rays.shape[0], N, 2)).astype(np.float32)
+    xi = torch.from_numpy(xi_np).cuda()
+    ao, hits, ar, occ = api.ambient_occlusion(acc, rays, xi, offset, radius)
+    h2, inst = api.trace_closest(acc, rays, want_inst=True)
+    torch.cuda.synchronize()
+    h, ar, occ, ao, inst = (x.cpu().numpy() for x in (hits, ar, occ, ao, inst))
+    assert np.array_equal(h.view(np.uint32), h2.cpu().numpy().view(np.uint32))
+    S = orc.OracleScene.from_scene(W.scene)
+    A = orc.accept(S, W.rays)
+    oi, op, otuv = orc.closest(S, W.rays)
+    prim = h[:, 1].copy().view(np.uint32)
+    keep = A.pinned & (prim == op) & ((inst.astype(np.uint32) == oi) | (op == NONE))
+    say("pinned and agreeing", int(keep.sum()), "of", len(keep))
+    assert keep.sum() > 0.5 * len(keep)
+    hit = keep & (op != NONE)
+    assert hit.sum() > 300
+    oar = orc.ao_rays(S, W.rays, op, otuv, xi_np, offset, radius, inst=np.where(op != NONE, oi, 0)).reshape(-1, N, 8)
+    gar = ar.reshape(-1, N, 8)
+    t = np.abs(otuv[hit, 0])[:, None]
+    dn = np.linalg.norm(W.rays[hit, 4:7].astype(np.float64), axis=1)[:, None]
+    scale = t * dn + np.abs(oar[hit, :, 0:3]).max(2) + 1.0
+    do = np.abs(gar[hit, :, 0:3].astype(np.float64) - oar[hit, :, 0:3]).max(2)
+    dd = np.abs(gar[hit, :, 4:7].astype(np.float64) - oar[hit, :, 4:7]).max(2)
+    say("two-level AO: max origin err / scale", (do / scale).max(), "max direction err", dd.max())
+    assert (do <= ORIGIN_REL * scale).all() and (dd <= DIR_ABS).all()
+    Ao = orc.accept(S, oar[keep].reshape(-1, 8))
+    must = (Ao.any_class == 1).reshape(-1, N).sum(1)
+    may = (Ao.any_class == 2).reshape(-1, N).sum(1)
+    got = occ.reshape(-1, N)[keep].astype(np.int64).sum(1)
+    bad = (got < must) | (got > must + may)
+    assert not bad.any(), f"{int(bad.sum())} rays outside their occlusion range"
+    assert np.allclose(ao[keep], got / N)
+    say("mean AO of the checked rays", float(ao[keep].mean()), "undecided samples", int(may.sum()))
+    acc.close()
