@@ -91,7 +91,8 @@ def test_batched_small_uneven(gpu, orc):
 def test_batched_full_size(gpu, orc):
     """256 meshes with log-uniform triangle (1k-500k) and ray (1k-1M) counts,
     all traced in one persistent launch and by 256 per-mesh launches; every
-    ray compared bit for bit, 4 meshes x 64 rays against the oracle."""
+    ray compared bit for bit; 16 meshes (the four smallest, the four
+    largest and eight drawn at random) x 64 rays against the oracle."""
     torch, api, ctx = gpu
     works = wl.batched_meshes()
     say("triangles", sum(w.scene.meshes[0].n_tri for w in works), "rays", sum(w.rays.shape[0] for w in works))
@@ -105,7 +106,12 @@ def test_batched_full_size(gpu, orc):
     s.synchronize()
     _check_equal([h.cpu().numpy() for h in plan.hits], per)
     rng = wl.rng_for(501)
-    for b in rng.choice(len(works), 4, replace=False):
+    size = np.array([w.scene.meshes[0].n_tri for w in works])
+    order = np.argsort(size)
+    picked = set(order[:4].tolist()) | set(order[-4:].tolist())
+    rest = np.setdiff1d(np.arange(len(works)), np.array(sorted(picked)))
+    picked |= set(rng.choice(rest, 8, replace=False).tolist())
+    for b in sorted(picked):
         idx = np.sort(rng.choice(works[b].rays.shape[0], 64, replace=False))
         S = orc.OracleScene.from_scene(works[b].scene)
         check_closest(per[b][idx], orc.accept(S, works[b].rays[idx]), label=f"batch {b}")
