@@ -1254,7 +1254,7 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
                             float* d_directions, void* stream) {
   if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_backward: NULL accel");
   if (accel->two_level)
-    return fail(RT_ERROR_UNSUPPORTED, "rt_trace_backward: two-level accels are not supported");
+    return fail(RT_ERROR_UNSUPPORTED, "rt_trace_backward: two-level accel (use rt_trace_backward_instances)");
   if (n == 0) return ok();
   if (!rays || !hits || !d_tuv || !d_vertices || !d_origins || !d_directions)
     return fail(RT_ERROR_INVALID_VALUE, "rt_trace_backward: NULL buffer with n > 0");
