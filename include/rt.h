@@ -382,12 +382,21 @@ rt_status rt_refit(rt_accel accel, const float* vertices, void* stream);
 
 /* Plans closest-hit queries for batch_count (accel, rays, hits, count)
  * tuples: accels, rays, hits and counts are HOST arrays of length
- * batch_count whose rays/hits entries are device pointers.  All accels must
- * be single-level and belong to ctx's device.  The plan copies its
- * descriptors to the device once. */
+ * batch_count whose rays/hits entries are device pointers.  The accels
+ * belong to ctx's device, share one node width, and are either all
+ * single-level or all two-level (RT_ERROR_INVALID_VALUE otherwise).  The
+ * plan copies its descriptors to the device once; the buffers must stay
+ * valid while the plan is used. */
 rt_status rt_batch_plan_create(rt_context ctx, const rt_accel* accels, const rt_ray* const* rays,
                                rt_hit* const* hits, const uint32_t* counts, uint32_t batch_count,
                                rt_batch_plan* out);
+/* The same, also writing instance ids for two-level accels: inst_ids is a
+ * HOST array of batch_count device pointers, each NULL (no ids) or an array
+ * of counts[b] uint32 written as by rt_trace_closest.  inst_ids may be NULL;
+ * a non-NULL entry for a single-level accel is RT_ERROR_INVALID_VALUE. */
+rt_status rt_batch_plan_create_instances(rt_context ctx, const rt_accel* accels, const rt_ray* const* rays,
+                                         rt_hit* const* hits, uint32_t* const* inst_ids, const uint32_t* counts,
+                                         uint32_t batch_count, rt_batch_plan* out);
 /* Enqueues the whole batch: a queue reset and one persistent kernel launch. */
 rt_status rt_batch_plan_launch(rt_batch_plan plan, void* stream);
 /* Captures the launch into a HIP graph (queue reset by a fill kernel, not a

@@ -29,7 +29,7 @@ EXPORTS = [
     "rt_ao_rays", "rt_ao_rays_instances", "rt_ao_resolve",
     "rt_trace_counters", "rt_refit",
     "rt_autotune",
-    "rt_batch_plan_create", "rt_batch_plan_launch", "rt_batch_plan_graph", "rt_batch_plan_destroy",
+    "rt_batch_plan_create", "rt_batch_plan_create_instances", "rt_batch_plan_launch", "rt_batch_plan_graph", "rt_batch_plan_destroy",
     "rt_status_string", "rt_last_error_message", "rt_version",
 ]
 
@@ -122,6 +122,7 @@ def load():
             "rt_refit": [P, P, P],
             "rt_autotune": [P, P, P, U32, U32, P, P, P, U32, P],
             "rt_batch_plan_create": [P, P, P, P, P, U32, P],
+            "rt_batch_plan_create_instances": [P, P, P, P, P, P, U32, P],
             "rt_batch_plan_launch": [P, P],
             "rt_batch_plan_graph": [P, P, P],
             "rt_batch_plan_destroy": [P],

@@ -437,7 +437,9 @@ class BatchPlan:
     """Closest-hit queries of many (accel, rays) pairs in one persistent
     launch; ``graph()`` captures it into a HIP graph for replay."""
 
-    def __init__(self, ctx: Context, accels, rays_list, hits_list=None):
+    def __init__(self, ctx: Context, accels, rays_list, hits_list=None, want_inst: bool = False):
+        """accels all single-level or all two-level; with want_inst (two-level
+        plans) ``self.inst_ids`` receives each batch's instance ids."""
         n = len(accels)
         if hits_list is None:
             hits_list = [torch.empty((r.shape[0], 4), dtype=torch.float32, device=r.device)
@@ -447,12 +449,18 @@ class BatchPlan:
             _require(h, "hits", torch.float32, 4)
         self.hits = hits_list
         self._rays = rays_list
+        self.inst_ids = ([torch.empty((r.shape[0],), dtype=torch.int32, device=r.device) for r in rays_list]
+                         if want_inst else None)
         A = (C.c_void_p * n)(*[a.handle.value for a in accels])
         R = (C.c_void_p * n)(*[r.data_ptr() if r.numel() else None for r in rays_list])
         H = (C.c_void_p * n)(*[h.data_ptr() if h.numel() else None for h in hits_list])
         cnt = (C.c_uint32 * n)(*[r.shape[0] for r in rays_list])
         h = C.c_void_p()
-        capi.call("rt_batch_plan_create", ctx.handle, A, R, H, cnt, n, C.byref(h))
+        if want_inst:
+            I = (C.c_void_p * n)(*[t.data_ptr() if t.numel() else None for t in self.inst_ids])
+            capi.call("rt_batch_plan_create_instances", ctx.handle, A, R, H, I, cnt, n, C.byref(h))
+        else:
+            capi.call("rt_batch_plan_create", ctx.handle, A, R, H, cnt, n, C.byref(h))
         self.handle = h
         self._graph = None
 

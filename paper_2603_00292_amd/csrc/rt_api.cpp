@@ -150,6 +150,7 @@ struct rt_accel_s {
 struct rt_batch_plan_s {
   rt_context ctx = nullptr;
   int width = 4;
+  bool two_level = false;                    // all accels two-level (else all single level)
   uint32_t batch_count = 0;
   uint32_t total = 0;
   uint32_t max_stack = 1;
@@ -1575,9 +1576,9 @@ rt_status rt_autotune(rt_context ctx, const rt_mesh_desc* mesh, const rt_ray* pr
 // batched plans
 // ---------------------------------------------------------------------------
 
-rt_status rt_batch_plan_create(rt_context ctx, const rt_accel* accels, const rt_ray* const* rays,
-                               rt_hit* const* hits, const uint32_t* counts, uint32_t batch_count,
-                               rt_batch_plan* out) {
+static rt_status plan_create(rt_context ctx, const rt_accel* accels, const rt_ray* const* rays,
+                             rt_hit* const* hits, uint32_t* const* inst_ids, const uint32_t* counts,
+                             uint32_t batch_count, rt_batch_plan* out) {
   if (!out) return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_create: out is NULL");
   *out = nullptr;
   if (!ctx || !accels || !rays || !hits || !counts || batch_count == 0)
@@ -1585,10 +1586,15 @@ rt_status rt_batch_plan_create(rt_context ctx, const rt_accel* accels, const rt_
   int width = -1;
   uint64_t total = 0;
   uint32_t max_stack = 1;
+  const bool two_level = accels[0] && accels[0]->two_level;
   for (uint32_t b = 0; b < batch_count; ++b) {
     rt_accel a = accels[b];
     if (!a) return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_create: accel %u is NULL", b);
-    if (a->two_level) return fail(RT_ERROR_UNSUPPORTED, "rt_batch_plan_create: accel %u is two-level", b);
+    if (a->two_level != two_level)
+      return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_create: accel %u: a plan's accels are all single-level "
+                  "or all two-level", b);
+    if (inst_ids && inst_ids[b] && !two_level)
+      return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_create: instance ids for single-level accel %u", b);
     if (a->device != ctx->device)
       return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_create: accel %u is on another device", b);
     if (width < 0) width = a->width;
@@ -1608,6 +1614,7 @@ rt_status rt_batch_plan_create(rt_context ctx, const rt_accel* accels, const rt_
   if (!p) return fail(RT_ERROR_OUT_OF_MEMORY, "rt_batch_plan_create: host allocation");
   p->ctx = ctx;
   p->width = width;
+  p->two_level = two_level;
   p->batch_count = batch_count;
   p->total = (uint32_t)total;
   p->max_stack = max_stack;
@@ -1622,11 +1629,12 @@ rt_status rt_batch_plan_create(rt_context ctx, const rt_accel* accels, const rt_
   std::vector<uint32_t> off(batch_count + 1, 0);
   for (uint32_t b = 0; b < batch_count; ++b) {
     rt_accel a = accels[b];
-    d[b] = BatchDesc{a->nodes, a->tris, a->meshes, rays[b], hits[b], a->root, counts[b]};
+    d[b] = BatchDesc{a->nodes,   a->tris,    a->meshes, rays[b], hits[b], a->root, counts[b],
+                     a->insts,    a->insts64, inst_ids ? inst_ids[b] : nullptr};
     off[b + 1] = off[b] + counts[b];
   }
   rt_variant v = ctx->variant;
-  p->kernel = rtk_trace_kernel(width, (int)v.stack_entries, (int)v.workgroup, false, false, 1);
+  p->kernel = rtk_trace_kernel(width, (int)v.stack_entries, (int)v.workgroup, false, two_level, 1);
   if (!p->kernel) return bail(fail(RT_ERROR_UNSUPPORTED, "rt_batch_plan_create: variant not compiled"));
   uint32_t wg = v.workgroup;
   uint32_t resident;
@@ -1649,6 +1657,18 @@ rt_status rt_batch_plan_create(rt_context ctx, const rt_accel* accels, const rt_
   return ok();
 }
 
+rt_status rt_batch_plan_create(rt_context ctx, const rt_accel* accels, const rt_ray* const* rays,
+                               rt_hit* const* hits, const uint32_t* counts, uint32_t batch_count,
+                               rt_batch_plan* out) {
+  return plan_create(ctx, accels, rays, hits, nullptr, counts, batch_count, out);
+}
+
+rt_status rt_batch_plan_create_instances(rt_context ctx, const rt_accel* accels, const rt_ray* const* rays,
+                                         rt_hit* const* hits, uint32_t* const* inst_ids, const uint32_t* counts,
+                                         uint32_t batch_count, rt_batch_plan* out) {
+  return plan_create(ctx, accels, rays, hits, inst_ids, counts, batch_count, out);
+}
+
 static rt_status enqueue_plan(rt_batch_plan p, hipStream_t s) {
   rt_variant v = p->ctx->variant;
   TraceParams q{};
@@ -1664,7 +1684,7 @@ static rt_status enqueue_plan(rt_batch_plan p, hipStream_t s) {
   q.root = RT_CHILD_EMPTY;
   RT_HIP(rtk_launch_fill(p->scratch.counter, 1, 0u, s));
   RT_HIP(rtk_launch_trace(p->kernel, p->grid, v.workgroup, q, s));
-  RT_HIP(rtk_launch_finalize(false, 1, q, s));
+  RT_HIP(rtk_launch_finalize(p->two_level, 1, q, s));
   return RT_SUCCESS;
 }
 

@@ -17,6 +17,9 @@ struct BatchDesc {
   rt_hit* hits;
   uint32_t root;
   uint32_t count;
+  const rt_inst_rec* insts;      // two-level plans
+  const rt_inst_rec64* insts64;  // two-level plans
+  uint32_t* inst_ids;            // two-level plans: instance ids out (may be null)
 };
 
 struct TraceParams {

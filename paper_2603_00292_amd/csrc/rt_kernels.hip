@@ -319,12 +319,13 @@ __device__ __forceinline__ void list_insert(float4* L, uint32_t found, uint32_t 
 // culling by the nearest hit) into per-ray lists of the `cap` nearest.
 // Two-level kernels of width <= 4 are asked to fit six waves per SIMD (80
 // VGPRs): on the 1,024-instance workload 4 -> 6 waves measured +12%, with no
-// spills (8-wide nodes and the counting variants would spill, so they keep
-// the compiler's choice).
-template <int W, bool INST, bool COUNT>
-constexpr int trace_min_waves() { return (INST && W <= 4 && !COUNT) ? 6 : 1; }
+// spills (8-wide nodes, the counting variants and the batched mode, which
+// keeps per-lane geometry pointers, would spill, so they keep the compiler's
+// choice).
+template <int W, bool INST, bool COUNT, int MODE>
+constexpr int trace_min_waves() { return (INST && W <= 4 && !COUNT && MODE != 1) ? 6 : 1; }
 template <int W, int S, int WG, bool ANY, bool INST, int MODE, bool COUNT = false>
-__global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT>())) void trace_kernel(TraceParams P) {
+__global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void trace_kernel(TraceParams P) {
   __shared__ uint32_t lds_stack[S * WG];
   // two-level: the world ray's origin and direction, restored on leaving an
   // instance (kept out of registers)
@@ -397,6 +398,10 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT>())) void trace
             g.tris = reinterpret_cast<const float4*>(bd.tris);
             g.meshes = bd.meshes;
             g.root = bd.root;
+            if constexpr (INST) {
+              g.insts = bd.insts;
+              g.insts64 = bd.insts64;
+            }
             ray_in = bd.rays;
             hit_out = bd.hits;
           }
@@ -810,6 +815,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(TraceParams P) {
   const rt_ray* rays = P.rays;
   rt_hit* hits = P.hits;
   const float4* tris = reinterpret_cast<const float4*>(P.tris);
+  const rt_inst_rec64* insts64 = P.insts64;
+  uint32_t* inst_ids = P.inst_ids;
   uint32_t local = i;
   if constexpr (MODE == 1) {
     uint32_t lo = 0, hi = P.batch_count;
@@ -822,19 +829,21 @@ __global__ __launch_bounds__(256) void finalize_kernel(TraceParams P) {
     rays = bd.rays;
     hits = bd.hits;
     tris = reinterpret_cast<const float4*>(bd.tris);
+    insts64 = bd.insts64;
+    inst_ids = bd.inst_ids;
   }
   float4* hp = reinterpret_cast<float4*>(hits + local);
   float4 h = *hp;
   uint32_t rec = __float_as_uint(h.y);
   if (rec == RT_INVALID_ID) {
-    if (MODE == 0 && P.inst_ids) P.inst_ids[local] = RT_INVALID_ID;
+    if (inst_ids) inst_ids[local] = RT_INVALID_ID;
     return;
   }
   uint32_t inst = __float_as_uint(h.z);
   rt_ray q = load_ray(rays, local);
   double ox = q.ox, oy = q.oy, oz = q.oz, dx = q.dx, dy = q.dy, dz = q.dz;
   if constexpr (INST) {
-    const rt_inst_rec64& M = P.insts64[inst];
+    const rt_inst_rec64& M = insts64[inst];
     double a = M.m[0] * ox + M.m[1] * oy + M.m[2] * oz + M.m[3];
     double b = M.m[4] * ox + M.m[5] * oy + M.m[6] * oz + M.m[7];
     double c = M.m[8] * ox + M.m[9] * oy + M.m[10] * oz + M.m[11];
@@ -850,7 +859,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(TraceParams P) {
   } else {
     *hp = make_float4(h.x, prim, 0.0f, 0.0f);
   }
-  if (MODE == 0 && P.inst_ids) P.inst_ids[local] = INST ? inst : 0u;
+  if (inst_ids) inst_ids[local] = INST ? inst : 0u;
 }
 
 // float64 finalize of all-hit lists: one thread per list entry; entries past
@@ -1118,7 +1127,7 @@ const void* count_kernel_w(bool any, bool inst) {
 
 template <int W, int S, int WG>
 const void* pick_mode(bool any, bool inst, int mode) {
-  if (mode == 1) return kernel_ptr<W, S, WG, false, false, 1>();
+  if (mode == 1) return inst ? kernel_ptr<W, S, WG, false, true, 1>() : kernel_ptr<W, S, WG, false, false, 1>();
   if (any) return inst ? kernel_ptr<W, S, WG, true, true, 0>() : kernel_ptr<W, S, WG, true, false, 0>();
   return inst ? kernel_ptr<W, S, WG, false, true, 0>() : kernel_ptr<W, S, WG, false, false, 0>();
 }
@@ -1206,7 +1215,8 @@ hipError_t rtk_launch_fold_frames(const float* rows, uint32_t inst_count, float*
 
 hipError_t rtk_launch_finalize(bool inst, int mode, const TraceParams& p, hipStream_t stream) {
   if (p.n == 0) return hipSuccess;
-  const void* k = mode == 1 ? reinterpret_cast<const void*>(&rtk::finalize_kernel<false, 1>)
+  const void* k = mode == 1 ? (inst ? reinterpret_cast<const void*>(&rtk::finalize_kernel<true, 1>)
+                                   : reinterpret_cast<const void*>(&rtk::finalize_kernel<false, 1>))
                   : inst    ? reinterpret_cast<const void*>(&rtk::finalize_kernel<true, 0>)
                             : reinterpret_cast<const void*>(&rtk::finalize_kernel<false, 0>);
   TraceParams q = p;

@@ -118,3 +118,66 @@ def test_batched_full_size(gpu, orc):
     plan.close()
     for a in accs:
         a.close()
+
+
+def test_batched_two_level(gpu, orc):
+    """A plan over five two-level scenes (instanced displaced grids and aimed
+    instances of different sizes, one batch without rays): the batched launch
+    and its graph replays equal per-accel closest-hit queries bit for bit,
+    instance ids included, and a sample matches the oracle."""
+    torch, api, ctx = gpu
+    from paper_2603_00292_amd import _capi
+
+    works = [wl.instanced_grids(n_inst=64, n_rays=50000, k=510),
+             wl.aimed_instances(n_inst=8, n_rays=20000, k=511),
+             wl.instanced_grids(n_inst=16, n_rays=0, k=512),
+             wl.instanced_grids(n_inst=200, n_rays=120000, k=513),
+             wl.aimed_instances(n_inst=30, n_rays=7777, k=514)]
+    accs, rays = _setup(gpu, works)
+    per = [api.trace_closest(a, r, want_inst=True) for a, r in zip(accs, rays)]
+    torch.cuda.synchronize()
+    per_h = [h.cpu().numpy() for h, _ in per]
+    per_i = [i.cpu().numpy() for _, i in per]
+    plan = api.BatchPlan(ctx, accs, rays, want_inst=True)
+    plan.launch()
+    torch.cuda.synchronize()
+    _check_equal([h.cpu().numpy() for h in plan.hits], per_h)
+    _check_equal([i.cpu().numpy() for i in plan.inst_ids], per_i)
+    s = torch.cuda.Stream()
+    g = plan.graph_exec(s)
+    for rep in range(3):
+        for h in plan.hits:
+            h.zero_()
+        for i in plan.inst_ids:
+            i.fill_(-7)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            api.graph_launch(g, s)
+        s.synchronize()
+        _check_equal([h.cpu().numpy() for h in plan.hits], per_h)
+        _check_equal([i.cpu().numpy() for i in plan.inst_ids], per_i)
+    plan.close()
+    # without instance ids
+    plan2 = api.BatchPlan(ctx, accs, rays)
+    plan2.launch()
+    torch.cuda.synchronize()
+    _check_equal([h.cpu().numpy() for h in plan2.hits], per_h)
+    plan2.close()
+    rng = wl.rng_for(515)
+    for b in (0, 3, 4):
+        idx = np.sort(rng.choice(works[b].rays.shape[0], 64, replace=False))
+        S = orc.OracleScene.from_scene(works[b].scene)
+        check_closest(per_h[b][idx], orc.accept(S, works[b].rays[idx]), inst=per_i[b][idx], label=f"batch {b}")
+    # a plan mixing single-level and two-level accels, or asking for
+    # instance ids of a single-level accel, is refused
+    m = works[0].scene.meshes[0]
+    single = api.Accel(ctx, [(torch.from_numpy(m.vertices).cuda(), torch.from_numpy(m.indices.view(np.int32)).cuda())])
+    with pytest.raises(_capi.RtError) as e:
+        api.BatchPlan(ctx, [accs[0], single], [rays[0], rays[1]])
+    assert e.value.status == _capi.RT_ERROR_INVALID_VALUE
+    with pytest.raises(_capi.RtError) as e:
+        api.BatchPlan(ctx, [single], [rays[1]], want_inst=True)
+    assert e.value.status == _capi.RT_ERROR_INVALID_VALUE
+    single.close()
+    for a in accs:
+        a.close()
