@@ -31,11 +31,13 @@ HBM_PEAK_GBS = 8000.0
 TRI_BYTES = 48
 RAY_BYTES = 32
 HIT_BYTES = 16
-FINALIZE_BYTES = 12 + 36  # indices + vertices of the winning triangle
+FINALIZE_BYTES = 48  # the winning triangle's record, read again by the float64 finalize
 BACKWARD_HIT_BYTES = 32 + 16 + 12 + 12 + 36 + 24 + 36  # per hit ray
 BACKWARD_MISS_BYTES = 32 + 16 + 12 + 24
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_closest_icosphere_incoherent_pmc_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2603_00292_amd", "csrc", "rt_kernels.hip")
+SQ_FILE = os.path.join(ROOT, "profiles", "trace_closest_icosphere_incoherent_sq_counters.txt")
+CU_COUNT, CLOCK_HZ = 256, 2.4e9
 
 
 def log(*a):
@@ -63,6 +65,53 @@ def measured_traffic(info, variant):
             elif name in line:
                 val = int(line.split()[-1])
     return val if sha == kernel_sha() else None
+
+
+def measured_valu(info, variant):
+    """Wave-level VALU instructions and active-lane fraction per launch of the
+    closest-hit traversal from the committed SQ counter summary, or None when
+    the kernel source or configuration differs."""
+    if not os.path.exists(SQ_FILE):
+        return None
+    name = "trace_kernel<%d, %d, %d, false, false, 0, false>" % (
+        info["node_width"], variant[0], variant[1])
+    sha, kern, ctr = None, None, {}
+    with open(SQ_FILE) as f:
+        for line in f:
+            if "rt_kernels.hip sha256[:16] =" in line:
+                sha = line.split("=")[-1].strip()
+            elif line.startswith("# kernel:"):
+                kern = line
+            elif line.startswith("SQ_"):
+                k, v = line.split()
+                ctr[k] = int(v)
+    if sha != kernel_sha() or kern is None or name not in kern:
+        return None
+    if not all(k in ctr for k in ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU")):
+        return None
+    lanes = ctr["SQ_THREAD_CYCLES_VALU"] / (ctr["SQ_ACTIVE_INST_VALU"] * 64.0)
+    return ctr["SQ_INSTS_VALU"], lanes
+
+
+def copy_bandwidth(torch, stream, dev, reps=5):
+    """Achievable HBM bandwidth (GB/s, bytes read + written) of a 1 GiB
+    device-to-device copy, mean over `reps` copies timed with HIP events."""
+    x = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2 * x.numel() * 4
+    del x, y
+    torch.cuda.empty_cache()
+    return nbytes / (ms * 1e-3) / 1e9
 
 
 def timed(fn, steps, stream, torch):
@@ -161,18 +210,31 @@ def main():
 
     for _ in range(args.warmup):
         launch()
+    # HIP events around each timed launch's traversal kernel (rt_context_set_timing)
+    ctx.set_timing(args.steps)
     ms_per_step, per = timed(launch, args.steps, stream, torch)
+    kernel_ms = ctx.read_timing(args.steps)
+    ctx.set_timing(0)
+    if len(kernel_ms) != args.steps:
+        raise RuntimeError(f"timing ring returned {len(kernel_ms)} of {args.steps} launches")
+    mean_kernel_ms = sum(kernel_ms) / len(kernel_ms)
     mean_launch_ms = sum(per) / len(per)
     value = n / (ms_per_step * 1e-3) / 1e6
     h = hits.cpu().numpy()
     hit_rows = int((h[:, 1].copy().view(np.uint32) != 0xFFFFFFFF).sum())
-    bytes_per_launch = (n * (RAY_BYTES + HIT_BYTES) + nodes * node_bytes + tris * TRI_BYTES
-                        + hit_rows * FINALIZE_BYTES)
-    achieved = bytes_per_launch / (mean_launch_ms * 1e-3) / 1e9
+    # the traversal kernel's algorithmic bytes: rays in, hits out, node and
+    # triangle fetches (the float64 finalize is a separate kernel)
+    bytes_per_launch = n * (RAY_BYTES + HIT_BYTES) + nodes * node_bytes + tris * TRI_BYTES
+    achieved = bytes_per_launch / (mean_kernel_ms * 1e-3) / 1e9
+    finalize_bytes = n * (RAY_BYTES + 2 * HIT_BYTES) + hit_rows * FINALIZE_BYTES
     log(f"closest: {ms_per_step:.3f} ms/step, {value:.1f} Mrays/s; nodes/ray {nodes / n:.2f}, "
         f"tris/ray {tris / n:.2f}, spills/ray {spills / n:.3f}, hits {hit_rows}")
 
     traffic = measured_traffic(info, ctx.variant)
+    valu = measured_valu(info, ctx.variant)
+    copy_gbs = copy_bandwidth(torch, stream, dev)
+    log(f"traversal kernel {mean_kernel_ms:.4f} ms (events), whole call {mean_launch_ms:.4f} ms; "
+        f"1 GiB copy {copy_gbs:.0f} GB/s")
 
     secondary = {"launch_ms_min": round(per[0], 4), "launch_ms_median": round(per[len(per) // 2], 4),
                  "nodes_per_ray": round(nodes / n, 3), "tris_per_ray": round(tris / n, 3),
@@ -237,7 +299,18 @@ def main():
                    "inputs_sha256": W.checksum()[:16]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "bytes_per_ray": round(bytes_per_launch / n, 1), "kernel_ms": round(mean_launch_ms, 4)},
+                     "kernel": "trace_kernel<%d, %d, %d> closest-hit traversal" % (
+                         info["node_width"], ctx.variant[0], ctx.variant[1]),
+                     "bytes_per_ray": round(bytes_per_launch / n, 1), "kernel_ms": round(mean_kernel_ms, 4),
+                     "call_ms": round(mean_launch_ms, 4),
+                     "finalize_bytes_per_ray": round(finalize_bytes / n, 1),
+                     "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+                     "valu": None if valu is None else {
+                         "bound": "alu", "wave_instructions": valu[0],
+                         "issue_ms": round(valu[0] / (CU_COUNT * CLOCK_HZ) * 1e3, 4),
+                         "frac": round(valu[0] / (CU_COUNT * CLOCK_HZ) * 1e3 / mean_kernel_ms, 4),
+                         "peak": "1 wave instruction per CU per cycle (256 CUs, 2.4 GHz)",
+                         "active_lanes": round(valu[1], 4)}},
         "cpu_baseline": cpu,
         "secondary": secondary,
     }

@@ -157,6 +157,29 @@ rt_status rt_context_destroy(rt_context ctx);
 rt_status rt_context_set_variant(rt_context ctx, const rt_variant* v);
 rt_status rt_context_get_variant(rt_context ctx, rt_variant* out);
 
+/* Traversal-kernel timing.  Measurement support, no operation of the paper:
+ * it lets a caller relate a query's traversal kernel alone (without the
+ * float64 finalize or the queue reset) to the bytes and instructions it
+ * needs.  With slots > 0, every later rt_trace_closest / rt_trace_any /
+ * rt_trace_closest_ex / rt_trace_any_ex / rt_trace_all / rt_trace_counters
+ * call on this context records a pair of HIP events on its stream directly
+ * before and after its traversal kernel, into the next of `slots` pairs used
+ * round-robin; slots == 0 turns this off.  The events are owned by the
+ * context; a new call waits for the recorded ones and replaces them.
+ * Batched plans record nothing.
+ * Errors: RT_ERROR_INVALID_VALUE (NULL context, slots > RT_TIMING_MAX_SLOTS),
+ * RT_ERROR_HIP. */
+#define RT_TIMING_MAX_SLOTS 4096u
+rt_status rt_context_set_timing(rt_context ctx, uint32_t slots);
+/* Waits for the timed launches recorded since the last read (at most the
+ * last `slots` of them) and writes their traversal-kernel durations in
+ * milliseconds, oldest first, into ms[0 .. min(that number, capacity)) (HOST),
+ * and that count into *count (HOST); the launches not returned are dropped.
+ * *count is 0 when timing is off.
+ * Errors: RT_ERROR_INVALID_VALUE (NULL ctx or count, or NULL ms with
+ * capacity > 0), RT_ERROR_HIP. */
+rt_status rt_context_read_timing(rt_context ctx, float* ms, uint32_t capacity, uint32_t* count);
+
 /* ---- build (§7.2, §7.3; top-down construction of §6.2) ----------------- */
 
 /* Builds an acceleration structure.

@@ -23,6 +23,7 @@ RT_INVALID_ID = 0xFFFFFFFF
 
 EXPORTS = [
     "rt_context_create", "rt_context_destroy", "rt_context_set_variant", "rt_context_get_variant",
+    "rt_context_set_timing", "rt_context_read_timing",
     "rt_build", "rt_accel_destroy", "rt_accel_get_info",
     "rt_trace_closest", "rt_trace_any", "rt_trace_backward", "rt_trace_backward_instances",
     "rt_trace_closest_ex", "rt_trace_any_ex", "rt_trace_all", "rt_accel_set_instance_masks", "rt_update_instances",
@@ -103,6 +104,8 @@ def load():
             "rt_context_destroy": [P],
             "rt_context_set_variant": [P, P],
             "rt_context_get_variant": [P, P],
+            "rt_context_set_timing": [P, U32],
+            "rt_context_read_timing": [P, P, U32, P],
             "rt_build": [P, P, U32, P, P, U32, P, P, P],
             "rt_accel_destroy": [P],
             "rt_accel_get_info": [P, P],

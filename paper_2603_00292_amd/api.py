@@ -60,6 +60,19 @@ class Context:
         v = capi.rt_variant(int(stack_entries), int(workgroup))
         capi.call("rt_context_set_variant", self.handle, C.byref(v))
 
+    def set_timing(self, slots: int):
+        """Record HIP events around the traversal kernel of the next query
+        calls, in `slots` pairs used round-robin (0: off)."""
+        capi.call("rt_context_set_timing", self.handle, int(slots))
+
+    def read_timing(self, capacity: int = 4096):
+        """Traversal-kernel durations (ms) of the launches timed since the
+        last read, oldest first."""
+        buf = (C.c_float * max(int(capacity), 1))()
+        cnt = C.c_uint32()
+        capi.call("rt_context_read_timing", self.handle, C.cast(buf, C.c_void_p), int(capacity), C.byref(cnt))
+        return [float(buf[i]) for i in range(cnt.value)]
+
     def close(self):
         if self.handle:
             capi.call("rt_context_destroy", self.handle)

@@ -110,6 +110,10 @@ struct rt_context_s {
   hipStream_t last_stream = nullptr;
   bool has_last = false;
   std::vector<std::pair<const void*, uint32_t>> occupancy;  // kernel -> resident blocks
+  // traversal-kernel timing (rt_context_set_timing): event pairs used
+  // round-robin, and the launches recorded since the last read
+  std::vector<hipEvent_t> tbeg, tend;
+  uint64_t trecorded = 0;
 };
 
 struct rt_accel_s {
@@ -277,7 +281,65 @@ rt_status rt_context_destroy(rt_context ctx) {
   rta::release(ctx->grad);
   rta::release(ctx->grad2);
   if (ctx->last_event) (void)hipEventDestroy(ctx->last_event);
+  for (hipEvent_t e : ctx->tbeg) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->tend) (void)hipEventDestroy(e);
   delete ctx;
+  return ok();
+}
+
+static void drop_timing(rt_context ctx) {
+  for (hipEvent_t e : ctx->tbeg) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->tend) (void)hipEventDestroy(e);
+  ctx->tbeg.clear();
+  ctx->tend.clear();
+  ctx->trecorded = 0;
+}
+
+rt_status rt_context_set_timing(rt_context ctx, uint32_t slots) {
+  if (!ctx) return fail(RT_ERROR_INVALID_VALUE, "rt_context_set_timing: NULL context");
+  if (slots > RT_TIMING_MAX_SLOTS)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_context_set_timing: more than 4096 slots");
+  rt_status st = check_device(ctx->device);
+  if (st != RT_SUCCESS) return st;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  for (hipEvent_t e : ctx->tend) (void)hipEventSynchronize(e);
+  drop_timing(ctx);
+  for (uint32_t i = 0; i < slots; ++i) {
+    hipEvent_t b = nullptr, e = nullptr;
+    hipError_t eb = hipEventCreate(&b);
+    hipError_t ee = eb == hipSuccess ? hipEventCreate(&e) : eb;
+    if (ee != hipSuccess) {
+      if (b) (void)hipEventDestroy(b);
+      drop_timing(ctx);
+      return fail(RT_ERROR_HIP, "rt_context_set_timing: %s", hipGetErrorString(ee));
+    }
+    ctx->tbeg.push_back(b);
+    ctx->tend.push_back(e);
+  }
+  return ok();
+}
+
+rt_status rt_context_read_timing(rt_context ctx, float* ms, uint32_t capacity, uint32_t* count) {
+  if (!ctx || !count || (capacity && !ms))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_context_read_timing: NULL argument");
+  rt_status st = check_device(ctx->device);
+  if (st != RT_SUCCESS) return st;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  *count = 0;
+  size_t slots = ctx->tend.size();
+  if (slots == 0) return ok();
+  uint64_t avail = std::min<uint64_t>(ctx->trecorded, slots);
+  uint64_t k = std::min<uint64_t>(avail, capacity);
+  // the k most recent launches, oldest first
+  for (uint64_t j = 0; j < k; ++j) {
+    size_t slot = (size_t)((ctx->trecorded - k + j) % slots);
+    RT_HIP(hipEventSynchronize(ctx->tend[slot]));
+    float t = 0.0f;
+    RT_HIP(hipEventElapsedTime(&t, ctx->tbeg[slot], ctx->tend[slot]));
+    ms[j] = t;
+  }
+  *count = (uint32_t)k;
+  ctx->trecorded = 0;
   return ok();
 }
 
@@ -1022,7 +1084,13 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   p.counts = counts;
   p.cap = cap;
   RT_HIP(rtk_launch_fill(ctx->scratch.counter, 1, 0u, s));
+  size_t tslot = ctx->tbeg.empty() ? 0 : (size_t)(ctx->trecorded % ctx->tbeg.size());
+  if (!ctx->tbeg.empty()) RT_HIP(hipEventRecord(ctx->tbeg[tslot], s));
   RT_HIP(rtk_launch_trace(kern, blocks, wg, p, s));
+  if (!ctx->tbeg.empty()) {
+    RT_HIP(hipEventRecord(ctx->tend[tslot], s));
+    ctx->trecorded++;
+  }
   if (mode == 3) {
     RT_HIP(rtk_launch_finalize_all(a->two_level, p, s));
   } else if (!any) {

@@ -61,6 +61,9 @@ def test_null_arguments_rejected_on_host(lib):
     assert lib.rt_context_destroy(None) == c.RT_ERROR_INVALID_VALUE
     v = c.rt_variant(16, 256)
     assert lib.rt_context_set_variant(None, C.byref(v)) == c.RT_ERROR_INVALID_VALUE
+    assert lib.rt_context_set_timing(None, 4) == c.RT_ERROR_INVALID_VALUE
+    cnt = C.c_uint32(7)
+    assert lib.rt_context_read_timing(None, None, 0, C.byref(cnt)) == c.RT_ERROR_INVALID_VALUE
     assert lib.rt_build(None, None, 0, None, None, 0, None, None, C.byref(h)) == c.RT_ERROR_INVALID_VALUE
     assert b"NULL context" in lib.rt_last_error_message()
     assert lib.rt_build(None, None, 0, None, None, 0, None, None, None) == c.RT_ERROR_INVALID_VALUE
