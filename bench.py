@@ -223,10 +223,12 @@ def main():
     h = hits.cpu().numpy()
     hit_rows = int((h[:, 1].copy().view(np.uint32) != 0xFFFFFFFF).sum())
     # the traversal kernel's algorithmic bytes: rays in, hits out, node and
-    # triangle fetches (the float64 finalize is a separate kernel)
-    bytes_per_launch = n * (RAY_BYTES + HIT_BYTES) + nodes * node_bytes + tris * TRI_BYTES
-    achieved = bytes_per_launch / (mean_kernel_ms * 1e-3) / 1e9
+    # triangle fetches, and the float64 finalize its waves run at exit (the
+    # ray and hit read again, the winner's record, the final hit written)
     finalize_bytes = n * (RAY_BYTES + 2 * HIT_BYTES) + hit_rows * FINALIZE_BYTES
+    bytes_per_launch = (n * (RAY_BYTES + HIT_BYTES) + nodes * node_bytes + tris * TRI_BYTES
+                        + finalize_bytes)
+    achieved = bytes_per_launch / (mean_kernel_ms * 1e-3) / 1e9
     log(f"closest: {ms_per_step:.3f} ms/step, {value:.1f} Mrays/s; nodes/ray {nodes / n:.2f}, "
         f"tris/ray {tris / n:.2f}, spills/ray {spills / n:.3f}, hits {hit_rows}")
 
@@ -299,7 +301,7 @@ def main():
                    "inputs_sha256": W.checksum()[:16]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "trace_kernel<%d, %d, %d> closest-hit traversal" % (
+                     "kernel": "trace_kernel<%d, %d, %d> closest-hit traversal + float64 finalize" % (
                          info["node_width"], ctx.variant[0], ctx.variant[1]),
                      "bytes_per_ray": round(bytes_per_launch / n, 1), "kernel_ms": round(mean_kernel_ms, 4),
                      "call_ms": round(mean_launch_ms, 4),

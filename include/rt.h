@@ -146,7 +146,8 @@ typedef struct rt_accel_info {
  * calling thread's later library calls.  Errors: RT_ERROR_NO_DEVICE,
  * RT_ERROR_INVALID_VALUE (out == NULL), RT_ERROR_HIP. */
 rt_status rt_context_create(int hip_device, rt_context* out);
-/* Frees the context's scratch (global stacks, queue counters).  An accel
+/* Frees the context's scratch (global stacks, queue counters, the ray-range
+ * lists of single-level closest queries).  An accel
  * keeps the context it was built with and traces with that context's
  * variant and scratch, so destroy every accel and batch plan of a context
  * before the context.  Trace calls of one context on different streams are
@@ -159,8 +160,9 @@ rt_status rt_context_get_variant(rt_context ctx, rt_variant* out);
 
 /* Traversal-kernel timing.  Measurement support, no operation of the paper:
  * it lets a caller relate a query's traversal kernel alone (without the
- * float64 finalize or the queue reset) to the bytes and instructions it
- * needs.  With slots > 0, every later rt_trace_closest / rt_trace_any /
+ * queue reset and, except for single-level closest queries, whose traversal
+ * kernel runs it, without the float64 finalize) to the bytes and
+ * instructions it needs.  With slots > 0, every later rt_trace_closest / rt_trace_any /
  * rt_trace_closest_ex / rt_trace_any_ex / rt_trace_all / rt_trace_counters
  * call on this context records a pair of HIP events on its stream directly
  * before and after its traversal kernel, into the next of `slots` pairs used

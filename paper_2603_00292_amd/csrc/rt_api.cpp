@@ -83,14 +83,17 @@ bool valid_variant(const rt_variant& v) {
 
 // device scratch of one launch: queue counter + global spill stack
 struct Scratch {
-  uint32_t* counter = nullptr;
+  uint32_t* counter = nullptr;   // [0] ray queue head, [1] overflow ranges
   uint32_t* gstack = nullptr;
   size_t gstack_entries = 0;
+  uint32_t* ranges = nullptr;    // fused finalize: per-wave range lists + overflow list
+  size_t ranges_entries = 0;
 };
 
 void free_scratch(Scratch& s) {
   if (s.counter) (void)hipFree(s.counter);
   if (s.gstack) (void)hipFree(s.gstack);
+  if (s.ranges) (void)hipFree(s.ranges);
   s = Scratch();
 }
 
@@ -208,6 +211,33 @@ rt_status ensure_scratch(Scratch& s, size_t entries) {
     RT_HIP(hipMalloc(&s.gstack, entries * sizeof(uint32_t)));
     s.gstack_entries = entries;
   }
+  return RT_SUCCESS;
+}
+
+// Range lists of a fused closest-hit launch of `gstride` threads over n rays:
+// kRtRangesPerWave pairs per wave, then the overflow list.  Every range a
+// wave takes holds at least min(refill_min, 64) rays except the one that
+// reaches the end of the queue, so n / min(refill_min, 64) + 1 overflow
+// pairs always suffice.
+rt_status ensure_ranges(Scratch& s, uint32_t gstride, uint32_t n, uint32_t refill_min,
+                        uint32_t** ranges, uint32_t** ovf, uint32_t* ovf_cap) {
+  size_t waves = gstride / 64u;
+  size_t per_wave = 2 * (size_t)kRtRangesPerWave;
+  size_t cap = (size_t)n / std::max<uint32_t>(1u, std::min<uint32_t>(refill_min, 64u)) + 1;
+  size_t entries = waves * per_wave + 2 * cap;
+  if (entries > s.ranges_entries) {
+    if (s.ranges) {
+      RT_HIP(hipDeviceSynchronize());
+      RT_HIP(hipFree(s.ranges));
+      s.ranges = nullptr;
+      s.ranges_entries = 0;
+    }
+    RT_HIP(hipMalloc(&s.ranges, entries * sizeof(uint32_t)));
+    s.ranges_entries = entries;
+  }
+  *ranges = s.ranges;
+  *ovf = s.ranges + waves * per_wave;
+  *ovf_cap = (uint32_t)cap;
   return RT_SUCCESS;
 }
 
@@ -1083,7 +1113,12 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   }
   p.counts = counts;
   p.cap = cap;
-  RT_HIP(rtk_launch_fill(ctx->scratch.counter, 1, 0u, s));
+  const bool fused = !counters && rtk_trace_fuses_finalize(any, a->two_level, mode);
+  if (fused) {
+    st = ensure_ranges(ctx->scratch, gstride, n, ctx->refill_min, &p.ranges, &p.ovf, &p.ovf_cap);
+    if (st != RT_SUCCESS) return st;
+  }
+  RT_HIP(rtk_launch_fill(ctx->scratch.counter, 2, 0u, s));
   size_t tslot = ctx->tbeg.empty() ? 0 : (size_t)(ctx->trecorded % ctx->tbeg.size());
   if (!ctx->tbeg.empty()) RT_HIP(hipEventRecord(ctx->tbeg[tslot], s));
   RT_HIP(rtk_launch_trace(kern, blocks, wg, p, s));
@@ -1093,6 +1128,8 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   }
   if (mode == 3) {
     RT_HIP(rtk_launch_finalize_all(a->two_level, p, s));
+  } else if (fused) {
+    RT_HIP(rtk_launch_finalize_ovf(p, s));
   } else if (!any) {
     RT_HIP(rtk_launch_finalize(a->two_level, 0, p, s));
   }

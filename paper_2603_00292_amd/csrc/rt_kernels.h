@@ -49,7 +49,19 @@ struct TraceParams {
   const uint32_t* skip_prim;
   uint32_t* counts;      // mode 3: hits per ray
   uint32_t cap;          // mode 3: list entries per ray
+  // single-level closest (mode 0): the float64 finalize runs in the traversal
+  // kernel, each wave finalizing the ray ranges it took from the queue once
+  // they are all finished.  ranges: kRtRangesPerWave (first, count) pairs per
+  // wave of the grid; a wave whose list is full appends further ranges to
+  // ovf (ovf_cap pairs, their number in counter[1], zero before the launch),
+  // finalized by a follow-up kernel.
+  uint32_t* ranges;
+  uint32_t* ovf;
+  uint32_t ovf_cap;
 };
+
+// per-wave ray ranges kept for the finalize inside the closest-hit traversal
+constexpr uint32_t kRtRangesPerWave = 128;
 
 // Single-level adjoint: ray gradients are written directly; the vertex
 // contributions go to (keys, vals) entries 3i..3i+2 (vertex id, -w_k lambda;
@@ -119,6 +131,11 @@ hipError_t rtk_launch_trace(const void* kern, uint32_t grid, uint32_t wg, const 
                             hipStream_t stream);
 // float64 finalize of closest hits written by a trace launch with the same params
 hipError_t rtk_launch_finalize(bool inst, int mode, const TraceParams& p, hipStream_t stream);
+// true when the traversal kernel of (any, inst, mode) finalizes its own hits
+// (it then needs p.ranges / p.ovf and rtk_launch_finalize_ovf afterwards)
+bool rtk_trace_fuses_finalize(bool any, bool inst, int mode);
+// float64 finalize of the overflow ranges of a fused traversal launch
+hipError_t rtk_launch_finalize_ovf(const TraceParams& p, hipStream_t stream);
 // float64 finalize of the hit lists of an all-hits launch (n * cap entries)
 hipError_t rtk_launch_finalize_all(bool inst, const TraceParams& p, hipStream_t stream);
 hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream);

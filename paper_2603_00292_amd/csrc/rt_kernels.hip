@@ -322,6 +322,44 @@ __device__ __forceinline__ void list_insert(float4* L, uint32_t found, uint32_t 
 // spills (8-wide nodes, the counting variants and the batched mode, which
 // keeps per-lane geometry pointers, would spill, so they keep the compiler's
 // choice).
+// float64 finalize of ray `local`'s closest hit: the traversal left float32
+// t, the winner's triangle record and (two-level) its instance in hits[local];
+// (t, u, v) are recomputed in float64 from the record and the record's prim
+// id replaces it.  Misses keep t = +inf and the invalid id.
+template <bool INST>
+__device__ __forceinline__ void finalize_ray(const rt_ray* rays, rt_hit* hits, const float4* tris,
+                                             const rt_inst_rec64* insts64, uint32_t* inst_ids,
+                                             uint32_t local) {
+  float4* hp = reinterpret_cast<float4*>(hits + local);
+  float4 h = *hp;
+  uint32_t rec = __float_as_uint(h.y);
+  if (rec == RT_INVALID_ID) {
+    if (inst_ids) inst_ids[local] = RT_INVALID_ID;
+    return;
+  }
+  uint32_t inst = __float_as_uint(h.z);
+  rt_ray q = load_ray(rays, local);
+  double ox = q.ox, oy = q.oy, oz = q.oz, dx = q.dx, dy = q.dy, dz = q.dz;
+  if constexpr (INST) {
+    const rt_inst_rec64& M = insts64[inst];
+    double a = M.m[0] * ox + M.m[1] * oy + M.m[2] * oz + M.m[3];
+    double b = M.m[4] * ox + M.m[5] * oy + M.m[6] * oz + M.m[7];
+    double c = M.m[8] * ox + M.m[9] * oy + M.m[10] * oz + M.m[11];
+    double e = M.m[0] * dx + M.m[1] * dy + M.m[2] * dz;
+    double f = M.m[4] * dx + M.m[5] * dy + M.m[6] * dz;
+    double gg = M.m[8] * dx + M.m[9] * dy + M.m[10] * dz;
+    ox = a; oy = b; oz = c; dx = e; dy = f; dz = gg;
+  }
+  float t, u, v;
+  float prim = tris[3 * (size_t)rec].w;
+  if (finalize64(tris, rec, ox, oy, oz, dx, dy, dz, t, u, v)) {
+    *hp = make_float4(t, prim, u, v);
+  } else {
+    *hp = make_float4(h.x, prim, 0.0f, 0.0f);
+  }
+  if (inst_ids) inst_ids[local] = INST ? inst : 0u;
+}
+
 template <int W, bool INST, bool COUNT, int MODE>
 constexpr int trace_min_waves() { return (INST && W <= 4 && !COUNT && MODE != 1) ? 6 : 1; }
 template <int W, int S, int WG, bool ANY, bool INST, int MODE, bool COUNT = false>
@@ -333,6 +371,10 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63u;
   const uint32_t gtid = blockIdx.x * WG + tid;
+  // single-level closest queries finalize their own hits (see TraceParams)
+  constexpr bool FUSED = !ANY && !INST && MODE == 0 && !COUNT;
+  uint32_t* my_ranges = FUSED ? P.ranges + (size_t)(gtid >> 6) * (2 * kRtRangesPerWave) : nullptr;
+  uint32_t n_ranges = 0;
   const uint64_t lanemask_lt = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
 
   Geo g;
@@ -379,6 +421,25 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
       uint32_t base = 0;
       if (lane == leader) base = atomicAdd(P.counter, n_need);
       base = (uint32_t)__shfl((int)base, (int)leader);
+      if constexpr (FUSED) {
+        // remember the range [base, base + take) this wave now owns
+        if (base < P.n) {
+          uint32_t take = min(n_need, P.n - base);
+          if (n_ranges < kRtRangesPerWave) {
+            if (lane == 0) {
+              my_ranges[2 * n_ranges] = base;
+              my_ranges[2 * n_ranges + 1] = take;
+            }
+            ++n_ranges;
+          } else if (lane == 0) {
+            uint32_t k = atomicAdd(P.counter + 1, 1u);
+            if (k < P.ovf_cap) {
+              P.ovf[2 * k] = base;
+              P.ovf[2 * k + 1] = take;
+            }
+          }
+        }
+      }
       if (need) {
         uint32_t my = base + __popcll(m & lanemask_lt);
         if (my < P.n) {
@@ -579,6 +640,20 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
                             __uint_as_float(hit ? (INST ? best_inst : 0u) : 0u), 0.0f);
         }
         live = false;
+      }
+    }
+  }
+  if constexpr (FUSED) {
+    // every ray this wave took is finished: float64 finalize of its listed
+    // ranges with full waves, while other waves still trace (the wave's own
+    // hit stores precede these loads)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    for (uint32_t k = 0; k < n_ranges; ++k) {
+      uint32_t b = my_ranges[2 * k], c = my_ranges[2 * k + 1];
+      for (uint32_t o = 0; o < c; o += 64) {
+        if (o + lane < c)
+          finalize_ray<false>(P.rays, P.hits, reinterpret_cast<const float4*>(P.tris), nullptr,
+                              P.inst_ids, b + o + lane);
       }
     }
   }
@@ -832,34 +907,19 @@ __global__ __launch_bounds__(256) void finalize_kernel(TraceParams P) {
     insts64 = bd.insts64;
     inst_ids = bd.inst_ids;
   }
-  float4* hp = reinterpret_cast<float4*>(hits + local);
-  float4 h = *hp;
-  uint32_t rec = __float_as_uint(h.y);
-  if (rec == RT_INVALID_ID) {
-    if (inst_ids) inst_ids[local] = RT_INVALID_ID;
-    return;
+  finalize_ray<INST>(rays, hits, tris, insts64, inst_ids, local);
+}
+
+// float64 finalize of the ranges that fused closest-hit traversal waves could
+// not keep in their lists: one block per range at a time
+__global__ __launch_bounds__(256) void finalize_ovf_kernel(TraceParams P) {
+  uint32_t count = min(P.counter[1], P.ovf_cap);
+  for (uint32_t k = blockIdx.x; k < count; k += gridDim.x) {
+    uint32_t b = P.ovf[2 * k], c = P.ovf[2 * k + 1];
+    for (uint32_t o = threadIdx.x; o < c; o += 256)
+      finalize_ray<false>(P.rays, P.hits, reinterpret_cast<const float4*>(P.tris), nullptr, P.inst_ids,
+                          b + o);
   }
-  uint32_t inst = __float_as_uint(h.z);
-  rt_ray q = load_ray(rays, local);
-  double ox = q.ox, oy = q.oy, oz = q.oz, dx = q.dx, dy = q.dy, dz = q.dz;
-  if constexpr (INST) {
-    const rt_inst_rec64& M = insts64[inst];
-    double a = M.m[0] * ox + M.m[1] * oy + M.m[2] * oz + M.m[3];
-    double b = M.m[4] * ox + M.m[5] * oy + M.m[6] * oz + M.m[7];
-    double c = M.m[8] * ox + M.m[9] * oy + M.m[10] * oz + M.m[11];
-    double e = M.m[0] * dx + M.m[1] * dy + M.m[2] * dz;
-    double f = M.m[4] * dx + M.m[5] * dy + M.m[6] * dz;
-    double gg = M.m[8] * dx + M.m[9] * dy + M.m[10] * dz;
-    ox = a; oy = b; oz = c; dx = e; dy = f; dz = gg;
-  }
-  float t, u, v;
-  float prim = tris[3 * (size_t)rec].w;
-  if (finalize64(tris, rec, ox, oy, oz, dx, dy, dz, t, u, v)) {
-    *hp = make_float4(t, prim, u, v);
-  } else {
-    *hp = make_float4(h.x, prim, 0.0f, 0.0f);
-  }
-  if (inst_ids) inst_ids[local] = INST ? inst : 0u;
 }
 
 // float64 finalize of all-hit lists: one thread per list entry; entries past
@@ -1222,6 +1282,16 @@ hipError_t rtk_launch_finalize(bool inst, int mode, const TraceParams& p, hipStr
   TraceParams q = p;
   void* args[] = {&q};
   return hipLaunchKernel(k, dim3((p.n + 255) / 256), dim3(256), args, 0, stream);
+}
+
+bool rtk_trace_fuses_finalize(bool any, bool inst, int mode) { return !any && !inst && mode == 0; }
+
+hipError_t rtk_launch_finalize_ovf(const TraceParams& p, hipStream_t stream) {
+  if (p.n == 0 || p.ovf_cap == 0) return hipSuccess;
+  TraceParams q = p;
+  void* args[] = {&q};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::finalize_ovf_kernel), dim3(256), dim3(256),
+                         args, 0, stream);
 }
 
 hipError_t rtk_launch_finalize_all(bool inst, const TraceParams& p, hipStream_t stream) {
