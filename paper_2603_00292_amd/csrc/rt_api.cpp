@@ -1129,7 +1129,7 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   if (mode == 3) {
     RT_HIP(rtk_launch_finalize_all(a->two_level, p, s));
   } else if (fused) {
-    RT_HIP(rtk_launch_finalize_ovf(p, s));
+    RT_HIP(rtk_launch_finalize_ovf(a->two_level, p, s));
   } else if (!any) {
     RT_HIP(rtk_launch_finalize(a->two_level, 0, p, s));
   }

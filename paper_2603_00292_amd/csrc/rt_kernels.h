@@ -49,7 +49,7 @@ struct TraceParams {
   const uint32_t* skip_prim;
   uint32_t* counts;      // mode 3: hits per ray
   uint32_t cap;          // mode 3: list entries per ray
-  // single-level closest (mode 0): the float64 finalize runs in the traversal
+  // closest queries on one accel (mode 0): the float64 finalize runs in the traversal
   // kernel, each wave finalizing the ray ranges it took from the queue once
   // they are all finished.  ranges: kRtRangesPerWave (first, count) pairs per
   // wave of the grid; a wave whose list is full appends further ranges to
@@ -135,7 +135,7 @@ hipError_t rtk_launch_finalize(bool inst, int mode, const TraceParams& p, hipStr
 // (it then needs p.ranges / p.ovf and rtk_launch_finalize_ovf afterwards)
 bool rtk_trace_fuses_finalize(bool any, bool inst, int mode);
 // float64 finalize of the overflow ranges of a fused traversal launch
-hipError_t rtk_launch_finalize_ovf(const TraceParams& p, hipStream_t stream);
+hipError_t rtk_launch_finalize_ovf(bool inst, const TraceParams& p, hipStream_t stream);
 // float64 finalize of the hit lists of an all-hits launch (n * cap entries)
 hipError_t rtk_launch_finalize_all(bool inst, const TraceParams& p, hipStream_t stream);
 hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream);

@@ -371,8 +371,8 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63u;
   const uint32_t gtid = blockIdx.x * WG + tid;
-  // single-level closest queries finalize their own hits (see TraceParams)
-  constexpr bool FUSED = !ANY && !INST && MODE == 0 && !COUNT;
+  // closest queries on one accel finalize their own hits (see TraceParams)
+  constexpr bool FUSED = !ANY && MODE == 0 && !COUNT;
   uint32_t* my_ranges = FUSED ? P.ranges + (size_t)(gtid >> 6) * (2 * kRtRangesPerWave) : nullptr;
   uint32_t n_ranges = 0;
   const uint64_t lanemask_lt = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
@@ -652,8 +652,8 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
       uint32_t b = my_ranges[2 * k], c = my_ranges[2 * k + 1];
       for (uint32_t o = 0; o < c; o += 64) {
         if (o + lane < c)
-          finalize_ray<false>(P.rays, P.hits, reinterpret_cast<const float4*>(P.tris), nullptr,
-                              P.inst_ids, b + o + lane);
+          finalize_ray<INST>(P.rays, P.hits, reinterpret_cast<const float4*>(P.tris), P.insts64,
+                             P.inst_ids, b + o + lane);
       }
     }
   }
@@ -912,13 +912,14 @@ __global__ __launch_bounds__(256) void finalize_kernel(TraceParams P) {
 
 // float64 finalize of the ranges that fused closest-hit traversal waves could
 // not keep in their lists: one block per range at a time
+template <bool INST>
 __global__ __launch_bounds__(256) void finalize_ovf_kernel(TraceParams P) {
   uint32_t count = min(P.counter[1], P.ovf_cap);
   for (uint32_t k = blockIdx.x; k < count; k += gridDim.x) {
     uint32_t b = P.ovf[2 * k], c = P.ovf[2 * k + 1];
     for (uint32_t o = threadIdx.x; o < c; o += 256)
-      finalize_ray<false>(P.rays, P.hits, reinterpret_cast<const float4*>(P.tris), nullptr, P.inst_ids,
-                          b + o);
+      finalize_ray<INST>(P.rays, P.hits, reinterpret_cast<const float4*>(P.tris), P.insts64, P.inst_ids,
+                         b + o);
   }
 }
 
@@ -1284,14 +1285,18 @@ hipError_t rtk_launch_finalize(bool inst, int mode, const TraceParams& p, hipStr
   return hipLaunchKernel(k, dim3((p.n + 255) / 256), dim3(256), args, 0, stream);
 }
 
-bool rtk_trace_fuses_finalize(bool any, bool inst, int mode) { return !any && !inst && mode == 0; }
+bool rtk_trace_fuses_finalize(bool any, bool inst, int mode) {
+  (void)inst;
+  return !any && mode == 0;
+}
 
-hipError_t rtk_launch_finalize_ovf(const TraceParams& p, hipStream_t stream) {
+hipError_t rtk_launch_finalize_ovf(bool inst, const TraceParams& p, hipStream_t stream) {
   if (p.n == 0 || p.ovf_cap == 0) return hipSuccess;
   TraceParams q = p;
   void* args[] = {&q};
-  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::finalize_ovf_kernel), dim3(256), dim3(256),
-                         args, 0, stream);
+  const void* k = inst ? reinterpret_cast<const void*>(&rtk::finalize_ovf_kernel<true>)
+                       : reinterpret_cast<const void*>(&rtk::finalize_ovf_kernel<false>);
+  return hipLaunchKernel(k, dim3(256), dim3(256), args, 0, stream);
 }
 
 hipError_t rtk_launch_finalize_all(bool inst, const TraceParams& p, hipStream_t stream) {
