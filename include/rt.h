@@ -147,7 +147,7 @@ typedef struct rt_accel_info {
  * RT_ERROR_INVALID_VALUE (out == NULL), RT_ERROR_HIP. */
 rt_status rt_context_create(int hip_device, rt_context* out);
 /* Frees the context's scratch (global stacks, queue counters, the ray-range
- * lists of single-level closest queries).  An accel
+ * lists of rt_trace_closest).  An accel
  * keeps the context it was built with and traces with that context's
  * variant and scratch, so destroy every accel and batch plan of a context
  * before the context.  Trace calls of one context on different streams are
@@ -160,8 +160,8 @@ rt_status rt_context_get_variant(rt_context ctx, rt_variant* out);
 
 /* Traversal-kernel timing.  Measurement support, no operation of the paper:
  * it lets a caller relate a query's traversal kernel alone (without the
- * queue reset and, except for single-level closest queries, whose traversal
- * kernel runs it, without the float64 finalize) to the bytes and
+ * queue reset and, except for rt_trace_closest, whose traversal kernel runs
+ * it, without the float64 finalize) to the bytes and
  * instructions it needs.  With slots > 0, every later rt_trace_closest / rt_trace_any /
  * rt_trace_closest_ex / rt_trace_any_ex / rt_trace_all / rt_trace_counters
  * call on this context records a pair of HIP events on its stream directly
