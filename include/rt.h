@@ -411,7 +411,8 @@ rt_status rt_refit(rt_accel accel, const float* vertices, void* stream);
  * belong to ctx's device, share one node width, and are either all
  * single-level or all two-level (RT_ERROR_INVALID_VALUE otherwise).  The
  * plan copies its descriptors to the device once; the buffers must stay
- * valid while the plan is used. */
+ * valid while the plan is used.  The plan keeps the context's variant at
+ * creation (rt_context_set_variant afterwards does not affect it). */
 rt_status rt_batch_plan_create(rt_context ctx, const rt_accel* accels, const rt_ray* const* rays,
                                rt_hit* const* hits, const uint32_t* counts, uint32_t batch_count,
                                rt_batch_plan* out);
@@ -444,8 +445,9 @@ typedef struct rt_tune_entry {
  * queries on `mesh` by measurement: the mesh is built at each candidate
  * node width (2, 4, 8) and every variant is timed with HIP events on
  * `stream` on the n_probe probe rays (device), median of `repeats` launches
- * after one warm-up.  On return *best holds the fastest configuration, the
- * context's variant is set to it, and table (HOST, capacity table_cap,
+ * after one warm-up.  On return *best holds the fastest configuration (the
+ * default, node width 4 / stack 16 / workgroup 256, unless another is faster
+ * by more than 1%), the context's variant is set to it, and table (HOST, capacity table_cap,
  * nullable) receives up to table_cap measured entries (*table_len = how many
  * were measured).  The caller builds its accel with best->node_width.
  * Synchronises the stream.  Errors as rt_build and rt_trace_closest. */

@@ -104,6 +104,7 @@ struct rt_context_s {
   int cu_count = 0;
   rt_variant variant{16, 256};
   uint32_t refill_min = 32;
+  uint32_t fuse_rays_per_wave = 3072;  // see launch_trace
   uint32_t blocks_per_cu = 0;  // 0 = the occupancy API's resident count
   std::mutex mu;
   Scratch scratch;
@@ -165,6 +166,7 @@ struct rt_batch_plan_s {
   uint32_t* offsets = nullptr;
   Scratch scratch;
   uint32_t grid = 0;
+  uint32_t workgroup = 256;                  // of `kernel` (the variant at creation)
   const void* kernel = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -294,6 +296,7 @@ rt_status rt_context_create(int hip_device, rt_context* out) {
   rt_variant v{(uint32_t)env_int("RT_STACK", 16), (uint32_t)env_int("RT_WG", 256)};
   if (valid_variant(v)) c->variant = v;
   c->refill_min = (uint32_t)std::min(64, std::max(1, env_int("RT_REFILL", 32)));
+  c->fuse_rays_per_wave = (uint32_t)std::max(0, env_int("RT_FUSE_RAYS_PER_WAVE", 3072));
   c->blocks_per_cu = (uint32_t)std::min(64, std::max(0, env_int("RT_BLOCKS_PER_CU", 0)));
   if (hipEventCreateWithFlags(&c->last_event, hipEventDisableTiming) != hipSuccess) {
     delete c;
@@ -1113,7 +1116,12 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   }
   p.counts = counts;
   p.cap = cap;
-  const bool fused = !counters && rtk_trace_fuses_finalize(any, a->two_level, mode);
+  // the waves finalize their own rays while the launch gives each of them
+  // at most fuse_rays_per_wave rays on average; beyond that a separate
+  // full-occupancy finalize kernel is faster
+  const bool fused = !counters && rtk_trace_fuses_finalize(any, a->two_level, mode) &&
+                     (uint64_t)n <= (uint64_t)(gstride / 64u) * ctx->fuse_rays_per_wave;
+  p.fuse = fused ? 1u : 0u;
   if (fused) {
     st = ensure_ranges(ctx->scratch, gstride, n, ctx->refill_min, &p.ranges, &p.ovf, &p.ovf_cap);
     if (st != RT_SUCCESS) return st;
@@ -1628,6 +1636,7 @@ rt_status rt_autotune(rt_context ctx, const rt_mesh_desc* mesh, const rt_ray* pr
   }
   rt_variant saved = ctx->variant;
   rt_tune_entry win{0, 0, 0, INFINITY};
+  rt_tune_entry dflt{0, 0, 0, INFINITY};  // width 4, stack 16, workgroup 256
   uint32_t count = 0;
   st = RT_SUCCESS;
   for (uint32_t w : kWidthChoices) {
@@ -1657,6 +1666,7 @@ rt_status rt_autotune(rt_context ctx, const rt_mesh_desc* mesh, const rt_ray* pr
         if (count < table_cap) table[count] = e;
         ++count;
         if (e.ms < win.ms) win = e;
+        if (w == 4 && sn == 16 && wg == 256) dflt = e;
       }
       if (st != RT_SUCCESS) break;
     }
@@ -1672,6 +1682,10 @@ rt_status rt_autotune(rt_context ctx, const rt_mesh_desc* mesh, const rt_ray* pr
     ctx->variant = saved;
     return st;
   }
+  // another configuration replaces the default only when it is faster by
+  // more than the launch-to-launch spread (1%), so that repeated tuning on
+  // the same workload settles on the same choice
+  if (dflt.ms <= win.ms * 1.01f) win = dflt;
   ctx->variant = rt_variant{win.stack_entries, win.workgroup};
   *best = win;
   return ok();
@@ -1748,6 +1762,7 @@ static rt_status plan_create(rt_context ctx, const rt_accel* accels, const rt_ra
     resident = cached_resident(ctx, p->kernel, (int)wg);
   }
   p->grid = std::max(1u, std::min<uint32_t>((p->total + wg - 1) / wg, resident));
+  p->workgroup = wg;
   size_t spill = max_stack > v.stack_entries ? (size_t)(max_stack - v.stack_entries) : 1;
   hipError_t e1 = hipMalloc(&p->descs, d.size() * sizeof(BatchDesc));
   hipError_t e2 = hipMalloc(&p->offsets, off.size() * sizeof(uint32_t));
@@ -1775,7 +1790,8 @@ rt_status rt_batch_plan_create_instances(rt_context ctx, const rt_accel* accels,
 }
 
 static rt_status enqueue_plan(rt_batch_plan p, hipStream_t s) {
-  rt_variant v = p->ctx->variant;
+  // the kernel, grid and scratch were chosen with the context's variant at
+  // creation; a later rt_context_set_variant does not change the plan
   TraceParams q{};
   q.counter = p->scratch.counter;
   q.gstack = p->scratch.gstack;
@@ -1784,11 +1800,11 @@ static rt_status enqueue_plan(rt_batch_plan p, hipStream_t s) {
   q.batch_count = p->batch_count;
   q.n = p->total;
   q.max_stack = p->max_stack;
-  q.gstride = p->grid * v.workgroup;
+  q.gstride = p->grid * p->workgroup;
   q.refill_min = p->ctx->refill_min;
   q.root = RT_CHILD_EMPTY;
   RT_HIP(rtk_launch_fill(p->scratch.counter, 1, 0u, s));
-  RT_HIP(rtk_launch_trace(p->kernel, p->grid, v.workgroup, q, s));
+  RT_HIP(rtk_launch_trace(p->kernel, p->grid, p->workgroup, q, s));
   RT_HIP(rtk_launch_finalize(p->two_level, 1, q, s));
   return RT_SUCCESS;
 }

@@ -360,6 +360,33 @@ __device__ __forceinline__ void finalize_ray(const rt_ray* rays, rt_hit* hits, c
   if (inst_ids) inst_ids[local] = INST ? inst : 0u;
 }
 
+// finalize of ray i of a launch: one accel (MODE 0), or the batch whose ray
+// range holds i (MODE 1, offsets have batch_count + 1 entries)
+template <bool INST, int MODE>
+__device__ __forceinline__ void finalize_index(const TraceParams& P, uint32_t i) {
+  const rt_ray* rays = P.rays;
+  rt_hit* hits = P.hits;
+  const float4* tris = reinterpret_cast<const float4*>(P.tris);
+  const rt_inst_rec64* insts64 = P.insts64;
+  uint32_t* inst_ids = P.inst_ids;
+  uint32_t local = i;
+  if constexpr (MODE == 1) {
+    uint32_t lo = 0, hi = P.batch_count;
+    while (hi - lo > 1) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (P.batch_offsets[mid] <= i) lo = mid; else hi = mid;
+    }
+    const BatchDesc& bd = P.batches[lo];
+    local = i - P.batch_offsets[lo];
+    rays = bd.rays;
+    hits = bd.hits;
+    tris = reinterpret_cast<const float4*>(bd.tris);
+    insts64 = bd.insts64;
+    inst_ids = bd.inst_ids;
+  }
+  finalize_ray<INST>(rays, hits, tris, insts64, inst_ids, local);
+}
+
 template <int W, bool INST, bool COUNT, int MODE>
 constexpr int trace_min_waves() { return (INST && W <= 4 && !COUNT && MODE != 1) ? 6 : 1; }
 template <int W, int S, int WG, bool ANY, bool INST, int MODE, bool COUNT = false>
@@ -371,8 +398,10 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63u;
   const uint32_t gtid = blockIdx.x * WG + tid;
-  // closest queries on one accel finalize their own hits (see TraceParams)
+  // closest queries on one accel finalize their own hits when the host asks
+  // for it (see TraceParams)
   constexpr bool FUSED = !ANY && MODE == 0 && !COUNT;
+  const bool fuse = FUSED && P.fuse != 0u;
   uint32_t* my_ranges = FUSED ? P.ranges + (size_t)(gtid >> 6) * (2 * kRtRangesPerWave) : nullptr;
   uint32_t n_ranges = 0;
   const uint64_t lanemask_lt = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
@@ -421,7 +450,7 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
       uint32_t base = 0;
       if (lane == leader) base = atomicAdd(P.counter, n_need);
       base = (uint32_t)__shfl((int)base, (int)leader);
-      if constexpr (FUSED) {
+      if (fuse) {
         // remember the range [base, base + take) this wave now owns
         if (base < P.n) {
           uint32_t take = min(n_need, P.n - base);
@@ -643,7 +672,7 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
       }
     }
   }
-  if constexpr (FUSED) {
+  if (fuse) {
     // every ray this wave took is finished: float64 finalize of its listed
     // ranges with full waves, while other waves still trace (the wave's own
     // hit stores precede these loads)
@@ -652,8 +681,7 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
       uint32_t b = my_ranges[2 * k], c = my_ranges[2 * k + 1];
       for (uint32_t o = 0; o < c; o += 64) {
         if (o + lane < c)
-          finalize_ray<INST>(P.rays, P.hits, reinterpret_cast<const float4*>(P.tris), P.insts64,
-                             P.inst_ids, b + o + lane);
+          finalize_index<INST, MODE>(P, b + o + lane);
       }
     }
   }
@@ -887,39 +915,18 @@ template <bool INST, int MODE>
 __global__ __launch_bounds__(256) void finalize_kernel(TraceParams P) {
   uint32_t i = blockIdx.x * 256u + threadIdx.x;
   if (i >= P.n) return;
-  const rt_ray* rays = P.rays;
-  rt_hit* hits = P.hits;
-  const float4* tris = reinterpret_cast<const float4*>(P.tris);
-  const rt_inst_rec64* insts64 = P.insts64;
-  uint32_t* inst_ids = P.inst_ids;
-  uint32_t local = i;
-  if constexpr (MODE == 1) {
-    uint32_t lo = 0, hi = P.batch_count;
-    while (hi - lo > 1) {
-      uint32_t mid = (lo + hi) >> 1;
-      if (P.batch_offsets[mid] <= i) lo = mid; else hi = mid;
-    }
-    const BatchDesc& bd = P.batches[lo];
-    local = i - P.batch_offsets[lo];
-    rays = bd.rays;
-    hits = bd.hits;
-    tris = reinterpret_cast<const float4*>(bd.tris);
-    insts64 = bd.insts64;
-    inst_ids = bd.inst_ids;
-  }
-  finalize_ray<INST>(rays, hits, tris, insts64, inst_ids, local);
+  finalize_index<INST, MODE>(P, i);
 }
 
 // float64 finalize of the ranges that fused closest-hit traversal waves could
-// not keep in their lists: one block per range at a time
+// not keep in their lists: one wave per range (a range holds at most 64 rays)
 template <bool INST>
-__global__ __launch_bounds__(256) void finalize_ovf_kernel(TraceParams P) {
+__global__ __launch_bounds__(64) void finalize_ovf_kernel(TraceParams P) {
   uint32_t count = min(P.counter[1], P.ovf_cap);
   for (uint32_t k = blockIdx.x; k < count; k += gridDim.x) {
     uint32_t b = P.ovf[2 * k], c = P.ovf[2 * k + 1];
-    for (uint32_t o = threadIdx.x; o < c; o += 256)
-      finalize_ray<INST>(P.rays, P.hits, reinterpret_cast<const float4*>(P.tris), P.insts64, P.inst_ids,
-                         b + o);
+    for (uint32_t o = threadIdx.x; o < c; o += 64)
+      finalize_index<INST, 0>(P, b + o);
   }
 }
 
@@ -1291,12 +1298,12 @@ bool rtk_trace_fuses_finalize(bool any, bool inst, int mode) {
 }
 
 hipError_t rtk_launch_finalize_ovf(bool inst, const TraceParams& p, hipStream_t stream) {
-  if (p.n == 0 || p.ovf_cap == 0) return hipSuccess;
+  if (p.n == 0 || p.ovf_cap == 0 || !p.fuse) return hipSuccess;
   TraceParams q = p;
   void* args[] = {&q};
   const void* k = inst ? reinterpret_cast<const void*>(&rtk::finalize_ovf_kernel<true>)
                        : reinterpret_cast<const void*>(&rtk::finalize_ovf_kernel<false>);
-  return hipLaunchKernel(k, dim3(256), dim3(256), args, 0, stream);
+  return hipLaunchKernel(k, dim3(2048), dim3(64), args, 0, stream);
 }
 
 hipError_t rtk_launch_finalize_all(bool inst, const TraceParams& p, hipStream_t stream) {

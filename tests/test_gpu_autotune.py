@@ -1,5 +1,6 @@
 """The autotuner (rt_autotune): measures every (node width, stack entries,
-workgroup) configuration, returns the fastest, sets the context's variant,
+workgroup) configuration, returns the fastest (keeping the default unless
+another is faster by more than 1%), sets the context's variant,
 and the tuned configuration answers exactly like the default one."""
 from __future__ import annotations
 
@@ -28,7 +29,13 @@ def test_autotune_picks_fastest_and_keeps_results():
     assert len(table) == 27
     combos = {(e["node_width"], e["stack_entries"], e["workgroup"]) for e in table}
     assert combos == {(w, s, g) for w in (2, 4, 8) for s in (8, 16, 32) for g in (64, 128, 256)}
-    assert best["ms"] == min(e["ms"] for e in table)
+    fastest = min(e["ms"] for e in table)
+    default = [e for e in table if (e["node_width"], e["stack_entries"], e["workgroup"]) == (4, 16, 256)][0]
+    # the default stays unless another configuration is faster by more than 1%
+    if default["ms"] <= fastest * 1.01:
+        assert best == default
+    else:
+        assert best["ms"] == fastest
     assert ctx.variant == (best["stack_entries"], best["workgroup"])
     tuned = api.Accel(ctx, [(V, I)], node_width=best["node_width"])
     h1, _ = api.trace_closest(tuned, rays)

@@ -181,3 +181,88 @@ def test_batched_two_level(gpu, orc):
     single.close()
     for a in accs:
         a.close()
+
+
+def _context_with_refill(api, refill):
+    import os
+
+    old = os.environ.get("RT_REFILL")
+    os.environ["RT_REFILL"] = str(refill)
+    try:
+        return api.Context(0)
+    finally:
+        if old is None:
+            del os.environ["RT_REFILL"]
+        else:
+            os.environ["RT_REFILL"] = old
+
+
+def _soup_works(seed, sizes):
+    rng = wl.rng_for(seed)
+    works = []
+    for m, (nt, nr) in enumerate(sizes):
+        half = 0.025 * np.sqrt(4096.0 / max(nt, 1))
+        V, I = wl.random_triangle_soup(rng, nt, half)
+        works.append(wl.Workload(f"b{m}", wl.Scene([wl.Mesh(V, I)]), wl.box_rays(rng, nr, -1, 2)))
+    return works
+
+
+def test_plan_keeps_its_variant(gpu):
+    """A plan launches with the variant its context had at creation: changing
+    the context's variant (stack and workgroup) before the launch and before
+    a graph capture changes neither the launch nor the answers."""
+    torch, api, _ = gpu
+    ctx = api.Context(0, stack_entries=16, workgroup=256)
+    works = _soup_works(503, [(20000, 30000), (500, 4000), (9000, 12345)])
+    accs = [to_gpu_scene(api, torch, ctx, w.scene) for w in works]
+    rays = [torch.from_numpy(w.rays).cuda() for w in works]
+    per = _per_mesh(gpu, accs, rays)
+    plan = api.BatchPlan(ctx, accs, rays)
+    ctx.set_variant(8, 64)
+    plan.launch()
+    torch.cuda.synchronize()
+    _check_equal([h.cpu().numpy() for h in plan.hits], per)
+    s = torch.cuda.Stream()
+    g = plan.graph_exec(s)
+    for h in plan.hits:
+        h.fill_(-1.0)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        api.graph_launch(g, s)
+    s.synchronize()
+    _check_equal([h.cpu().numpy() for h in plan.hits], per)
+    plan.close()
+    for a in accs:
+        a.close()
+    ctx.close()
+
+
+def test_batched_overflow_ranges(gpu):
+    """A refill threshold of one idle lane (ranges of a few rays per refill)
+    changes neither the batched answers nor the per-mesh ones, whose waves
+    then overflow their finalize range lists: plan launch and graph replay
+    equal per-mesh launches bit for bit."""
+    torch, api, _ = gpu
+    works = _soup_works(504, [(30000, 400000), (2000, 300000), (0, 1000), (15000, 500000), (7, 3)])
+    ctx = _context_with_refill(api, 1)
+    accs = [to_gpu_scene(api, torch, ctx, w.scene) for w in works]
+    rays = [torch.from_numpy(w.rays).cuda() for w in works]
+    per = _per_mesh(gpu, accs, rays)
+    plan = api.BatchPlan(ctx, accs, rays)
+    plan.launch()
+    torch.cuda.synchronize()
+    _check_equal([h.cpu().numpy() for h in plan.hits], per)
+    s = torch.cuda.Stream()
+    g = plan.graph_exec(s)
+    for rep in range(2):
+        for h in plan.hits:
+            h.fill_(-1.0)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            api.graph_launch(g, s)
+        s.synchronize()
+        _check_equal([h.cpu().numpy() for h in plan.hits], per)
+    plan.close()
+    for a in accs:
+        a.close()
+    ctx.close()
