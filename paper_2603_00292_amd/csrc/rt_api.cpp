@@ -104,7 +104,6 @@ struct rt_context_s {
   int cu_count = 0;
   rt_variant variant{16, 256};
   uint32_t refill_min = 32;
-  uint32_t fuse_rays_per_wave = 3072;  // see launch_trace
   uint32_t blocks_per_cu = 0;  // 0 = the occupancy API's resident count
   std::mutex mu;
   Scratch scratch;
@@ -296,7 +295,6 @@ rt_status rt_context_create(int hip_device, rt_context* out) {
   rt_variant v{(uint32_t)env_int("RT_STACK", 16), (uint32_t)env_int("RT_WG", 256)};
   if (valid_variant(v)) c->variant = v;
   c->refill_min = (uint32_t)std::min(64, std::max(1, env_int("RT_REFILL", 32)));
-  c->fuse_rays_per_wave = (uint32_t)std::max(0, env_int("RT_FUSE_RAYS_PER_WAVE", 3072));
   c->blocks_per_cu = (uint32_t)std::min(64, std::max(0, env_int("RT_BLOCKS_PER_CU", 0)));
   if (hipEventCreateWithFlags(&c->last_event, hipEventDisableTiming) != hipSuccess) {
     delete c;
@@ -1116,12 +1114,7 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   }
   p.counts = counts;
   p.cap = cap;
-  // the waves finalize their own rays while the launch gives each of them
-  // at most fuse_rays_per_wave rays on average; beyond that a separate
-  // full-occupancy finalize kernel is faster
-  const bool fused = !counters && rtk_trace_fuses_finalize(any, a->two_level, mode) &&
-                     (uint64_t)n <= (uint64_t)(gstride / 64u) * ctx->fuse_rays_per_wave;
-  p.fuse = fused ? 1u : 0u;
+  const bool fused = !counters && rtk_trace_fuses_finalize(any, a->two_level, mode);
   if (fused) {
     st = ensure_ranges(ctx->scratch, gstride, n, ctx->refill_min, &p.ranges, &p.ovf, &p.ovf_cap);
     if (st != RT_SUCCESS) return st;

@@ -49,8 +49,8 @@ struct TraceParams {
   const uint32_t* skip_prim;
   uint32_t* counts;      // mode 3: hits per ray
   uint32_t cap;          // mode 3: list entries per ray
-  // closest queries on one accel (mode 0) with fuse != 0: the float64
-  // finalize runs in the traversal kernel, each wave finalizing the ray
+  // closest queries on one accel (mode 0): the float64 finalize runs in the
+  // traversal kernel, each wave finalizing the ray
   // ranges it took from the queue once they are all finished.  ranges: kRtRangesPerWave (first, count) pairs per
   // wave of the grid; a wave whose list is full appends further ranges to
   // ovf (ovf_cap pairs, their number in counter[1], zero before the launch),
@@ -58,7 +58,6 @@ struct TraceParams {
   uint32_t* ranges;
   uint32_t* ovf;
   uint32_t ovf_cap;
-  uint32_t fuse;
 };
 
 // per-wave ray ranges kept for the finalize inside the closest-hit traversal

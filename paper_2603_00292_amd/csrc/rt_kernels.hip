@@ -398,10 +398,8 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid & 63u;
   const uint32_t gtid = blockIdx.x * WG + tid;
-  // closest queries on one accel finalize their own hits when the host asks
-  // for it (see TraceParams)
+  // closest queries on one accel finalize their own hits (see TraceParams)
   constexpr bool FUSED = !ANY && MODE == 0 && !COUNT;
-  const bool fuse = FUSED && P.fuse != 0u;
   uint32_t* my_ranges = FUSED ? P.ranges + (size_t)(gtid >> 6) * (2 * kRtRangesPerWave) : nullptr;
   uint32_t n_ranges = 0;
   const uint64_t lanemask_lt = (lane == 0) ? 0ull : (~0ull >> (64u - lane));
@@ -450,7 +448,7 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
       uint32_t base = 0;
       if (lane == leader) base = atomicAdd(P.counter, n_need);
       base = (uint32_t)__shfl((int)base, (int)leader);
-      if (fuse) {
+      if constexpr (FUSED) {
         // remember the range [base, base + take) this wave now owns
         if (base < P.n) {
           uint32_t take = min(n_need, P.n - base);
@@ -672,7 +670,7 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
       }
     }
   }
-  if (fuse) {
+  if constexpr (FUSED) {
     // every ray this wave took is finished: float64 finalize of its listed
     // ranges with full waves, while other waves still trace (the wave's own
     // hit stores precede these loads)
@@ -1298,7 +1296,7 @@ bool rtk_trace_fuses_finalize(bool any, bool inst, int mode) {
 }
 
 hipError_t rtk_launch_finalize_ovf(bool inst, const TraceParams& p, hipStream_t stream) {
-  if (p.n == 0 || p.ovf_cap == 0 || !p.fuse) return hipSuccess;
+  if (p.n == 0 || p.ovf_cap == 0) return hipSuccess;
   TraceParams q = p;
   void* args[] = {&q};
   const void* k = inst ? reinterpret_cast<const void*>(&rtk::finalize_ovf_kernel<true>)
