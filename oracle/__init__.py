@@ -7,8 +7,11 @@ loads it: it is the independent reference the HIP path is checked against.
 The arithmetic lives in ``rt_oracle.c`` (plain C, double precision, OpenMP
 over rays); this module compiles it with gcc and marshals numpy arrays.
 
-Every query is a linear search over all triangles, the definition of the
-closest hit in the paper's §3.3, with the plane-then-edge test of §3.1.  See
+Every query is defined by the linear search over all triangles (the
+paper's §3.3 search for the closest hit) with the plane-then-edge test of
+§3.1; a scene built with ``accel=True`` carries an FP64 BVH whose walk only
+skips pairs that cannot matter, so it returns the same answers bit for bit
+(§6.2: the hierarchy accelerates the search).  See
 the header of ``rt_oracle.c`` for the readings taken where the paper is
 silent.  ``accept`` implements the FP32 tolerance model (acceptable sets),
 ``adjoint`` the implicit-function adjoint of (t,u,v) and ``fd`` central finite
@@ -80,6 +83,14 @@ def _load():
             f.restype = C.c_int
         lib.orc_num_threads.restype = C.c_int
         lib.orc_set_num_threads.argtypes = [C.c_int]
+        lib.orc_bvh_create.argtypes = [C.c_void_p, C.POINTER(C.c_void_p)]
+        lib.orc_bvh_create.restype = C.c_int
+        lib.orc_bvh_destroy.argtypes = [C.c_void_p]
+        lib.orc_bvh_destroy.restype = None
+        lib.orc_bvh_stats.argtypes = [C.c_void_p, C.c_void_p]
+        lib.orc_bvh_stats.restype = C.c_int
+        lib.orc_bvh_check.argtypes = [C.c_void_p, C.c_void_p, i64, C.c_int, C.c_double, C.c_void_p]
+        lib.orc_bvh_check.restype = C.c_int
         _lib = lib
         return lib
 
@@ -94,6 +105,7 @@ class _Scene(C.Structure):
         ("n_inst", C.c_int64),
         ("inst_mesh", C.c_void_p),
         ("inst_srt", C.c_void_p),
+        ("bvh", C.c_void_p),
     ]
 
 
@@ -101,9 +113,12 @@ class OracleScene:
     """Holds contiguous float32/uint32 copies of a scene and its C descriptor.
 
     ``meshes``: list of (vertices (V,3) float32, indices (N,3) uint32).
-    ``inst_mesh``/``inst_srt``: optional instance arrays (see workloads)."""
+    ``inst_mesh``/``inst_srt``: optional instance arrays (see workloads).
+    ``accel``: also build the FP64 BVH (``orc_bvh_create``); every query then
+    walks it instead of scanning every triangle, with identical answers."""
 
-    def __init__(self, meshes, inst_mesh=None, inst_srt=None):
+    def __init__(self, meshes, inst_mesh=None, inst_srt=None, accel: bool = False):
+        self._bvh = None
         self._v = [np.ascontiguousarray(v, dtype=np.float32).reshape(-1, 3) for v, _ in meshes]
         self._i = [np.ascontiguousarray(i, dtype=np.uint32).reshape(-1, 3) for _, i in meshes]
         n = len(meshes)
@@ -122,11 +137,44 @@ class OracleScene:
         self.desc = _Scene(
             n, C.cast(self._vp, C.c_void_p), self._nv.ctypes.data, C.cast(self._ip, C.c_void_p),
             self._nt.ctypes.data, ninst,
-            self._im.ctypes.data if ninst else None, self._is.ctypes.data if ninst else None)
+            self._im.ctypes.data if ninst else None, self._is.ctypes.data if ninst else None, None)
+        if accel:
+            lib = _load()
+            h = C.c_void_p()
+            if lib.orc_bvh_create(self.ptr, C.byref(h)) != 0:
+                raise ValueError("oracle: BVH build failed (invalid scene or out of memory)")
+            self._bvh = h
+            self._lib = lib
+            self.desc.bvh = h.value
 
     @classmethod
-    def from_scene(cls, scene):
-        return cls([(m.vertices, m.indices) for m in scene.meshes], scene.inst_mesh, scene.inst_srt)
+    def from_scene(cls, scene, accel: bool = False):
+        return cls([(m.vertices, m.indices) for m in scene.meshes], scene.inst_mesh, scene.inst_srt,
+                   accel=accel)
+
+    @property
+    def accel(self) -> bool:
+        return self._bvh is not None
+
+    def bvh_stats(self) -> dict:
+        """Tree nodes, triangles without a finite box, deepest leaf, instance-tree nodes."""
+        if self._bvh is None:
+            return {}
+        out = np.zeros(4, np.int64)
+        self._lib.orc_bvh_stats(self._bvh, out.ctypes.data)
+        return {"nodes": int(out[0]), "loose": int(out[1]), "depth": int(out[2]),
+                "top_nodes": int(out[3])}
+
+    def linear(self) -> "OracleScene":
+        """The same scene without the BVH (the plain linear search)."""
+        meshes = list(zip(self._v, self._i))
+        return OracleScene(meshes, self._im, self._is, accel=False)
+
+    def __del__(self):
+        if getattr(self, "_bvh", None) is not None:
+            self.desc.bvh = None
+            self._lib.orc_bvh_destroy(self._bvh)
+            self._bvh = None
 
     @property
     def ptr(self):
@@ -370,6 +418,19 @@ def ao_rays(scene: OracleScene, rays, prim, tuv, xi, offset: float, radius: floa
         _check(lib.orc_ao_rays_inst(scene.ptr, _p(r), _p(inst), _p(prim), _p(tuv), n, int(N), _p(xi),
                                     float(offset), float(radius), _p(out)), "ao_rays_inst")
     return out
+
+
+def bvh_check(scene: OracleScene, rays, candidates: bool, delta: float = DELTA):
+    """The BVH's culling invariant on every wanted pair of the linear search
+    (see ``orc_bvh_check``): returns (pairs checked, violations)."""
+    if not scene.accel:
+        raise ValueError("bvh_check needs a scene built with accel=True")
+    lib = _load()
+    r, n = _rays(rays)
+    out = np.zeros(2, np.int64)
+    _check(lib.orc_bvh_check(scene.ptr, _p(r), n, int(bool(candidates)), float(delta), _p(out)),
+           "bvh_check")
+    return int(out[0]), int(out[1])
 
 
 def num_threads() -> int:

@@ -257,161 +257,6 @@ static int skipped(const orc_scene* s, const orc_opts* o, int64_t r, int64_t j, 
   return 1;
 }
 
-int orc_closest_ex(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts,
-                   uint32_t* inst_out, uint32_t* prim_out, double* tuv_out) {
-  if (nr < 0 || (nr > 0 && (!rays || !prim_out || !tuv_out)) || !scene_valid(s)) return -1;
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t r = 0; r < nr; ++r) {
-    ray64 w = load_ray(rays + 8 * r);
-    double minT = INFINITY, bu = 0.0, bv = 0.0;
-    uint32_t bi = ORC_NONE, bp = ORC_NONE;
-    if (!ray_is_void(&w)) {
-      for (int64_t j = 0; j < n_units(s); ++j) {
-        if (!unit_enabled(s, opts, r, j)) continue;
-        ray64 q;
-        int m;
-        double xs, xd;
-        object_ray(s, &w, j, &q, &m, &xs, &xd);
-        for (int64_t k = 0; k < s->n_triangles[m]; ++k) {
-          vec3 v0, v1, v2;
-          double t, u, v;
-          if (skipped(s, opts, r, j, k)) continue;
-          tri(s, m, k, &v0, &v1, &v2);
-          if (intersect_paper(&q, v0, v1, v2, &t, &u, &v) && t < minT) {
-            minT = t; bu = u; bv = v;
-            bi = (uint32_t)j; bp = (uint32_t)k;
-          }
-        }
-      }
-    }
-    if (inst_out) inst_out[r] = bi;
-    prim_out[r] = bp;
-    tuv_out[3 * r + 0] = minT;
-    tuv_out[3 * r + 1] = bu;
-    tuv_out[3 * r + 2] = bv;
-  }
-  return 0;
-}
-
-int orc_closest(const orc_scene* s, const float* rays, int64_t nr, uint32_t* inst_out,
-                uint32_t* prim_out, double* tuv_out) {
-  return orc_closest_ex(s, rays, nr, NULL, inst_out, prim_out, tuv_out);
-}
-
-int orc_any_ex(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts,
-               uint8_t* occluded) {
-  if (nr < 0 || (nr > 0 && (!rays || !occluded)) || !scene_valid(s)) return -1;
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t r = 0; r < nr; ++r) {
-    ray64 w = load_ray(rays + 8 * r);
-    int hit = 0;
-    if (!ray_is_void(&w)) {
-      for (int64_t j = 0; j < n_units(s) && !hit; ++j) {
-        if (!unit_enabled(s, opts, r, j)) continue;
-        ray64 q;
-        int m;
-        double xs, xd;
-        object_ray(s, &w, j, &q, &m, &xs, &xd);
-        for (int64_t k = 0; k < s->n_triangles[m]; ++k) {
-          vec3 v0, v1, v2;
-          double t, u, v;
-          if (skipped(s, opts, r, j, k)) continue;
-          tri(s, m, k, &v0, &v1, &v2);
-          if (intersect_paper(&q, v0, v1, v2, &t, &u, &v)) { hit = 1; break; }
-        }
-      }
-    }
-    occluded[r] = (uint8_t)hit;
-  }
-  return 0;
-}
-
-int orc_any(const orc_scene* s, const float* rays, int64_t nr, uint8_t* occluded) {
-  return orc_any_ex(s, rays, nr, NULL, occluded);
-}
-
-/* All hits of §6.2's enumeration ("all intersections"): every pair the §3.1
- * test accepts within [tmin, tmax], sorted by (t, inst, prim). */
-typedef struct {
-  double t, u, v;
-  uint32_t inst, prim;
-} hit64;
-
-static int hit_less(const hit64* a, const hit64* b) {
-  if (a->t != b->t) return a->t < b->t;
-  if (a->inst != b->inst) return a->inst < b->inst;
-  return a->prim < b->prim;
-}
-
-int orc_all(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts, int32_t K,
-            int64_t* count, uint32_t* inst_out, uint32_t* prim_out, double* tuv_out) {
-  if (nr < 0 || K < 1 || !scene_valid(s)) return -1;
-  if (nr > 0 && (!rays || !count || !prim_out || !tuv_out)) return -1;
-  int bad = 0;
-#pragma omp parallel
-  {
-    int64_t cap = 64;
-    hit64* buf = (hit64*)malloc(sizeof(hit64) * cap);
-    if (!buf) {
-#pragma omp atomic write
-      bad = 1;
-    }
-#pragma omp for schedule(dynamic, 8)
-    for (int64_t r = 0; r < nr; ++r) {
-      if (!buf) continue;
-      int64_t n = 0;
-      ray64 w = load_ray(rays + 8 * r);
-      if (!ray_is_void(&w)) {
-        for (int64_t j = 0; j < n_units(s); ++j) {
-          if (!unit_enabled(s, opts, r, j)) continue;
-          ray64 q;
-          int m;
-          double xs, xd;
-          object_ray(s, &w, j, &q, &m, &xs, &xd);
-          for (int64_t k = 0; k < s->n_triangles[m]; ++k) {
-            vec3 v0, v1, v2;
-            hit64 h;
-            if (skipped(s, opts, r, j, k)) continue;
-            tri(s, m, k, &v0, &v1, &v2);
-            if (!intersect_paper(&q, v0, v1, v2, &h.t, &h.u, &h.v)) continue;
-            h.inst = s->n_inst > 0 ? (uint32_t)j : 0u;
-            h.prim = (uint32_t)k;
-            if (n == cap) {
-              hit64* nb = (hit64*)realloc(buf, sizeof(hit64) * cap * 2);
-              if (!nb) {
-#pragma omp atomic write
-                bad = 1;
-                continue;
-              }
-              buf = nb;
-              cap *= 2;
-            }
-            buf[n++] = h;
-          }
-        }
-      }
-      for (int64_t i = 1; i < n; ++i) {
-        hit64 x = buf[i];
-        int64_t jj = i - 1;
-        while (jj >= 0 && hit_less(&x, &buf[jj])) { buf[jj + 1] = buf[jj]; --jj; }
-        buf[jj + 1] = x;
-      }
-      count[r] = n;
-      for (int64_t i = 0; i < K; ++i) {
-        int64_t o = r * K + i;
-        int in = i < n;
-        if (inst_out) inst_out[o] = in ? buf[i].inst : ORC_NONE;
-        prim_out[o] = in ? buf[i].prim : ORC_NONE;
-        tuv_out[3 * o + 0] = in ? buf[i].t : INFINITY;
-        tuv_out[3 * o + 1] = in ? buf[i].u : 0.0;
-        tuv_out[3 * o + 2] = in ? buf[i].v : 0.0;
-      }
-    }
-    free(buf);
-  }
-  return bad ? -1 : 0;
-}
-
 /* ------------------------------------------------------------------------- */
 /* acceptable sets                                                            */
 /* ------------------------------------------------------------------------- */
@@ -448,8 +293,13 @@ typedef struct {
   int sure;
 } cand;
 
+/* (t, inst, prim) order; a candidate whose t is undefined (a degenerate
+ * triangle's plane formula gives 0/0) sorts after every defined t, so the
+ * order is total and the same whatever order the pairs were found in. */
 static int cand_less(const cand* a, const cand* b) {
-  if (a->t != b->t) return a->t < b->t;
+  int an = isnan(a->t), bn = isnan(b->t);
+  if (an != bn) return bn;
+  if (!an && a->t != b->t) return a->t < b->t;
   if (a->inst != b->inst) return a->inst < b->inst;
   return a->prim < b->prim;
 }
@@ -551,6 +401,974 @@ static int classify(const ray64* q, vec3 v0, vec3 v1, vec3 v2, double delta, dou
   return 1;
 }
 
+/* ------------------------------------------------------------------------- */
+/* the work of one (ray, triangle) pair, for every query                      */
+/* ------------------------------------------------------------------------- */
+/* Both searches below, the linear one and the one through the BVH, hand every
+ * (ray, instance, triangle) pair they do not skip to on_pair, which does what
+ * the query asks of a pair; only the order of the pairs differs.  Each query's
+ * result is a function of the set of pairs, not of their order:
+ *   closest: the lexicographic minimum of (t, inst, prim) -- visited in
+ *            ascending (inst, prim) order, as the linear search of §3.3 does,
+ *            this is the listing's strict "t < minT" update;
+ *   any:     whether some pair is a hit;
+ *   all:     the hits, sorted by (t, inst, prim) afterwards;
+ *   classify: the sure and maybe pairs, sorted afterwards, and t* (the
+ *            smallest upper t of a sure hit). */
+
+typedef struct {
+  double t, u, v;
+  uint32_t inst, prim;
+} hit64;
+
+static int hit_less(const hit64* a, const hit64* b) {
+  if (a->t != b->t) return a->t < b->t;
+  if (a->inst != b->inst) return a->inst < b->inst;
+  return a->prim < b->prim;
+}
+
+enum { Q_CLOSEST = 0, Q_ANY = 1, Q_ALL = 2, Q_CAND = 3 };
+
+typedef struct {
+  int kind;
+  int cull_tstar;      /* Q_CAND: only pairs that can be the closest are wanted */
+  double delta;        /* Q_CAND: relative input slack */
+  double minT, bu, bv; /* Q_CLOSEST */
+  uint32_t bi, bp;
+  int hit;             /* Q_ANY */
+  hit64* hits;         /* Q_ALL */
+  cand* cands;         /* Q_CAND */
+  int64_t n, cap;
+  int bad;             /* a list could not grow */
+  double tstar;        /* Q_CAND */
+  int sures;
+} qstate;
+
+static void qstate_reset(qstate* st) {
+  st->minT = INFINITY;
+  st->bu = st->bv = 0.0;
+  st->bi = st->bp = ORC_NONE;
+  st->hit = 0;
+  st->n = 0;
+  st->tstar = INFINITY;
+  st->sures = 0;
+}
+
+static int grow(void** buf, int64_t* cap, size_t elem) {
+  int64_t nc = *cap ? 2 * *cap : 64;
+  void* nb = realloc(*buf, elem * (size_t)nc);
+  if (!nb) return 0;
+  *buf = nb;
+  *cap = nc;
+  return 1;
+}
+
+/* Returns 1 when the query may stop (an any-hit query found a hit). */
+static int on_pair(qstate* st, const ray64* q, uint32_t inst, uint32_t prim, vec3 v0, vec3 v1,
+                   vec3 v2, double xs, double xd) {
+  if (st->kind == Q_CLOSEST) {
+    double t, u, v;
+    if (!intersect_paper(q, v0, v1, v2, &t, &u, &v)) return 0;
+    if (t < st->minT || (t == st->minT && (inst < st->bi || (inst == st->bi && prim < st->bp)))) {
+      st->minT = t;
+      st->bu = u;
+      st->bv = v;
+      st->bi = inst;
+      st->bp = prim;
+    }
+    return 0;
+  }
+  if (st->kind == Q_ANY) {
+    double t, u, v;
+    if (!intersect_paper(q, v0, v1, v2, &t, &u, &v)) return 0;
+    st->hit = 1;
+    return 1;
+  }
+  if (st->kind == Q_ALL) {
+    hit64 h;
+    if (!intersect_paper(q, v0, v1, v2, &h.t, &h.u, &h.v)) return 0;
+    h.inst = inst;
+    h.prim = prim;
+    if (st->n == st->cap && !grow((void**)&st->hits, &st->cap, sizeof(hit64))) {
+      st->bad = 1;
+      return 0;
+    }
+    st->hits[st->n++] = h;
+    return 0;
+  }
+  cand c;
+  double hi;
+  int cls = classify(q, v0, v1, v2, st->delta, xs, xd, &c, &hi);
+  if (cls == 0) return 0;
+  c.inst = inst;
+  c.prim = prim;
+  c.sure = (cls == 2);
+  c.hi = hi;
+  if (c.sure) {
+    st->sures++;
+    if (hi < st->tstar) st->tstar = hi;
+  }
+  if (st->n == st->cap && !grow((void**)&st->cands, &st->cap, sizeof(cand))) {
+    st->bad = 1;
+    return 0;
+  }
+  st->cands[st->n++] = c;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* the linear search (§3.3)                                                   */
+/* ------------------------------------------------------------------------- */
+
+/* Every triangle of mesh m, in ascending order, for unit j. */
+static int scan_mesh(const orc_scene* s, const orc_opts* opts, int64_t r, int64_t j, int m,
+                     const ray64* q, double xs, double xd, qstate* st) {
+  for (int64_t k = 0; k < s->n_triangles[m]; ++k) {
+    vec3 v0, v1, v2;
+    if (skipped(s, opts, r, j, k)) continue;
+    tri(s, m, k, &v0, &v1, &v2);
+    if (on_pair(st, q, (uint32_t)j, (uint32_t)k, v0, v1, v2, xs, xd)) return 1;
+  }
+  return 0;
+}
+
+static void search_linear(const orc_scene* s, const orc_opts* opts, int64_t r, const ray64* w,
+                          qstate* st) {
+  for (int64_t j = 0; j < n_units(s); ++j) {
+    if (!unit_enabled(s, opts, r, j)) continue;
+    ray64 q;
+    int m;
+    double xs, xd;
+    object_ray(s, w, j, &q, &m, &xs, &xd);
+    if (scan_mesh(s, opts, r, j, m, &q, xs, xd, st)) return;
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* FP64 bounding-volume hierarchy: an exact accelerator of the linear search  */
+/* ------------------------------------------------------------------------- */
+/* §6.2 (traversal paragraph): a hierarchy of boxes only lets the search skip
+ * triangles whose boxes the ray misses, so the answers are those of the
+ * linear search.  This one is deliberately plain: a binary tree split at the
+ * median box centre along the longest axis of the centres' bounds, leaves of
+ * at most four items, boxes that are the exact min/max of the float32
+ * vertices (exact in float64).  The walk hands the surviving pairs to the
+ * same on_pair as the linear search, so every query's answer is identical
+ * bit for bit.  The box tests only skip what provably holds no wanted pair:
+ *   - a hit of §3.1 puts o + t d within float64 rounding of the triangle,
+ *     so its t lies in the slab interval of the box widened by
+ *     2^-34 (|o|_inf + |box|_inf) (far above that rounding);
+ *   - a sure or maybe pair of the tolerance model has its line within eta
+ *     of the triangle and the triangle's extent along the line, widened by
+ *     eta/|d|, meeting [tmin, tmax]; eta is bounded over the box by the same
+ *     formula with the box's largest coordinate and farthest corner;
+ *   - its lowest t (lo) is at least the smallest projection of the box's
+ *     corners minus max(eta, 3 D)/|d| (D = box diagonal: a sure hit needs
+ *     eta/cos <= its distance to the edges <= D, so rho_t <= 2 D/|d|).
+ * Triangles with a non-finite vertex, instances with a non-finite frame or
+ * whose mesh holds such triangles, and rays with a non-finite origin or
+ * direction take the linear search for the part concerned. */
+
+typedef struct {
+  double lo[3], hi[3];
+  int64_t a, b; /* internal: children a, b; leaf: a = -1 - first item slot, b = item count */
+} bnode;
+
+typedef struct {
+  bnode* node;
+  int64_t n_node;
+  int64_t* item;  /* item ids, leaf after leaf */
+  int64_t n_item;
+  int64_t* loose; /* items with no finite box: visited for every ray */
+  int64_t n_loose;
+  double amax_box; /* largest |coordinate| of the root box */
+  int depth;
+  int64_t* parent;  /* [n_node], -1 at the root (for the bound check) */
+  int64_t* leaf_of; /* [n_items] the leaf holding each item, -1 if none */
+  double* nb;       /* instance tree: per node, the largest ||A||, ||A^-1||,
+                     * |T|, ||A|| ||A^-1|| and mesh coordinate of its instances */
+} btree;
+
+struct orc_bvh_s {
+  int32_t n_mesh;
+  int64_t n_inst;
+  const float* const* vertices; /* the scene it was built for */
+  btree* mesh;                  /* [n_mesh] over each mesh's triangles */
+  btree top;                    /* instances, over their world boxes */
+  frame64* frame;               /* [n_inst] */
+};
+enum { NB_A, NB_AINV, NB_T, NB_KAPPA, NB_V, NB_N };
+
+#define BVH_LEAF 4
+#define BVH_STACK 160
+
+typedef struct {
+  double key;
+  int64_t id;
+} kv;
+
+static int kv_less(const kv* a, const kv* b) {
+  return a->key < b->key || (a->key == b->key && a->id < b->id);
+}
+
+/* Rearranges a[0..n) so that a[k] is the element of rank k and no element
+ * before it is larger, none after it smaller (keys are distinct: ids are). */
+static void select_kth(kv* a, int64_t n, int64_t k) {
+  int64_t lo = 0, hi = n - 1;
+  uint64_t seed = 0x9E3779B97F4A7C15ull ^ (uint64_t)n;
+  while (hi > lo) {
+    seed = seed * 6364136223846793005ull + 1442695040888963407ull;
+    int64_t p = lo + (int64_t)((seed >> 33) % (uint64_t)(hi - lo + 1));
+    kv pivot = a[p], tmp;
+    a[p] = a[hi];
+    a[hi] = pivot;
+    int64_t st = lo;
+    for (int64_t i = lo; i < hi; ++i)
+      if (kv_less(&a[i], &pivot)) {
+        tmp = a[i]; a[i] = a[st]; a[st] = tmp;
+        ++st;
+      }
+    tmp = a[st]; a[st] = a[hi]; a[hi] = tmp;
+    if (st == k) return;
+    if (k < st) hi = st - 1; else lo = st + 1;
+  }
+}
+
+/* box: 6 doubles per item (lo xyz, hi xyz); ids: the items of this subtree,
+ * reordered in place (they live in T->item) */
+static int64_t bt_build(btree* T, const double* box, int64_t* ids, int64_t n, kv* tmp, int depth) {
+  int64_t me = T->n_node++;
+  bnode* nd = &T->node[me];
+  if (depth > T->depth) T->depth = depth;
+  for (int c = 0; c < 3; ++c) {
+    nd->lo[c] = INFINITY;
+    nd->hi[c] = -INFINITY;
+  }
+  double cl[3] = {INFINITY, INFINITY, INFINITY}, ch[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = 0; i < n; ++i) {
+    const double* b = box + 6 * ids[i];
+    for (int c = 0; c < 3; ++c) {
+      if (b[c] < nd->lo[c]) nd->lo[c] = b[c];
+      if (b[3 + c] > nd->hi[c]) nd->hi[c] = b[3 + c];
+      double m = 0.5 * (b[c] + b[3 + c]);
+      if (m < cl[c]) cl[c] = m;
+      if (m > ch[c]) ch[c] = m;
+    }
+  }
+  if (n <= BVH_LEAF) {
+    nd->a = -1 - (ids - T->item);
+    nd->b = n;
+    return me;
+  }
+  int axis = 0;
+  if (ch[1] - cl[1] > ch[axis] - cl[axis]) axis = 1;
+  if (ch[2] - cl[2] > ch[axis] - cl[axis]) axis = 2;
+  for (int64_t i = 0; i < n; ++i) {
+    const double* b = box + 6 * ids[i];
+    tmp[i].key = 0.5 * (b[axis] + b[3 + axis]);
+    tmp[i].id = ids[i];
+  }
+  int64_t h = n / 2;
+  select_kth(tmp, n, h);
+  for (int64_t i = 0; i < n; ++i) ids[i] = tmp[i].id;
+  int64_t a = bt_build(T, box, ids, h, tmp, depth + 1);
+  int64_t b = bt_build(T, box, ids + h, n - h, tmp, depth + 1);
+  T->node[me].a = a;
+  T->node[me].b = b;
+  return me;
+}
+
+static int box_finite(const double* b) {
+  for (int c = 0; c < 6; ++c)
+    if (!isfinite(b[c])) return 0;
+  return 1;
+}
+
+static void bt_free(btree* T) {
+  free(T->node);
+  free(T->item);
+  free(T->loose);
+  free(T->parent);
+  free(T->leaf_of);
+  free(T->nb);
+  memset(T, 0, sizeof(*T));
+}
+
+/* A tree over n items with boxes box[6n]; items with a non-finite box or
+ * excluded (skip[i] != 0, may be NULL: none) are left out, and the
+ * non-finite ones listed as loose.  Returns 0 on allocation failure. */
+static int bt_make(btree* T, const double* box, int64_t n, const uint8_t* skip) {
+  memset(T, 0, sizeof(*T));
+  int64_t nf = 0, nl = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (skip && skip[i]) continue;
+    if (box_finite(box + 6 * i)) ++nf; else ++nl;
+  }
+  T->item = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nf ? nf : 1));
+  T->loose = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nl ? nl : 1));
+  T->node = (bnode*)malloc(sizeof(bnode) * (size_t)(nf ? 2 * nf : 1));
+  kv* tmp = (kv*)malloc(sizeof(kv) * (size_t)(nf ? nf : 1));
+  if (!T->item || !T->loose || !T->node || !tmp) {
+    free(tmp);
+    bt_free(T);
+    return 0;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if (skip && skip[i]) continue;
+    if (box_finite(box + 6 * i)) T->item[T->n_item++] = i; else T->loose[T->n_loose++] = i;
+  }
+  T->parent = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nf ? 2 * nf : 1));
+  T->leaf_of = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+  if (!T->parent || !T->leaf_of) {
+    free(tmp);
+    bt_free(T);
+    return 0;
+  }
+  for (int64_t i = 0; i < n; ++i) T->leaf_of[i] = -1;
+  if (nf > 0) {
+    bt_build(T, box, T->item, nf, tmp, 0);
+    T->parent[0] = -1;
+    for (int64_t i = 0; i < T->n_node; ++i) {
+      const bnode* nd = &T->node[i];
+      if (nd->a < 0) {
+        for (int64_t k = 0; k < nd->b; ++k) T->leaf_of[T->item[-1 - nd->a + k]] = i;
+      } else {
+        T->parent[nd->a] = i;
+        T->parent[nd->b] = i;
+      }
+    }
+    double m = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      if (fabs(T->node[0].lo[c]) > m) m = fabs(T->node[0].lo[c]);
+      if (fabs(T->node[0].hi[c]) > m) m = fabs(T->node[0].hi[c]);
+    }
+    T->amax_box = m;
+  }
+  free(tmp);
+  return T->depth < BVH_STACK - 4;
+}
+
+/* infinity norm of the linear part R(q) diag(S) */
+static double linear_norm(const frame64* F) {
+  double S[3] = {fabs(F->S.x), fabs(F->S.y), fabs(F->S.z)}, m = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    double row = 0.0;
+    for (int k = 0; k < 3; ++k) row += fabs(F->R[i][k]) * S[k];
+    if (row > m) m = row;
+  }
+  return m;
+}
+
+void orc_bvh_destroy(orc_bvh* B) {
+  if (!B) return;
+  if (B->mesh)
+    for (int m = 0; m < B->n_mesh; ++m) bt_free(&B->mesh[m]);
+  free(B->mesh);
+  bt_free(&B->top);
+  free(B->frame);
+  free(B);
+}
+
+int orc_bvh_create(const orc_scene* s, orc_bvh** out) {
+  if (!out) return -1;
+  *out = NULL;
+  if (!scene_valid(s)) return -1;
+  orc_bvh* B = (orc_bvh*)calloc(1, sizeof(orc_bvh));
+  if (!B) return -1;
+  B->n_mesh = s->n_mesh;
+  B->n_inst = s->n_inst;
+  B->vertices = s->vertices;
+  B->mesh = (btree*)calloc((size_t)s->n_mesh, sizeof(btree));
+  if (!B->mesh) goto fail;
+  for (int m = 0; m < s->n_mesh; ++m) {
+    int64_t nt = s->n_triangles[m];
+    double* box = (double*)malloc(sizeof(double) * 6 * (size_t)(nt ? nt : 1));
+    if (!box) goto fail;
+    for (int64_t k = 0; k < nt; ++k) {
+      vec3 v[3];
+      tri(s, m, k, &v[0], &v[1], &v[2]);
+      double* b = box + 6 * k;
+      b[0] = b[3] = v[0].x;
+      b[1] = b[4] = v[0].y;
+      b[2] = b[5] = v[0].z;
+      for (int c = 1; c < 3; ++c) {
+        double x[3] = {v[c].x, v[c].y, v[c].z};
+        for (int a = 0; a < 3; ++a) {
+          /* a NaN coordinate leaves the box non-finite (loose) */
+          if (!(x[a] >= b[a])) b[a] = x[a];
+          if (!(x[a] <= b[3 + a])) b[3 + a] = x[a];
+        }
+      }
+    }
+    int okm = bt_make(&B->mesh[m], box, nt, NULL);
+    free(box);
+    if (!okm) goto fail;
+  }
+  if (s->n_inst > 0) {
+    int64_t ni = s->n_inst;
+    B->frame = (frame64*)malloc(sizeof(frame64) * (size_t)ni);
+    double* box = (double*)malloc(sizeof(double) * 6 * (size_t)ni);
+    double* ib = (double*)malloc(sizeof(double) * NB_N * (size_t)ni);
+    uint8_t* skip = (uint8_t*)calloc((size_t)ni, 1);
+    if (!B->frame || !box || !ib || !skip) {
+      free(box);
+      free(ib);
+      free(skip);
+      goto fail;
+    }
+    for (int64_t j = 0; j < ni; ++j) {
+      B->frame[j] = load_frame(s->inst_srt + 10 * j);
+      const frame64* F = &B->frame[j];
+      const btree* T = &B->mesh[s->inst_mesh[j]];
+      double* b = box + 6 * j;
+      if (T->n_item == 0 && T->n_loose == 0) {
+        skip[j] = 1; /* an empty mesh: no pair to find */
+        continue;
+      }
+      double A = linear_norm(F), Ai = inv_linear_norm(F);
+      int fin = T->n_loose == 0 && isfinite(A) && isfinite(Ai) && A > 0.0 &&
+                isfinite(F->T.x) && isfinite(F->T.y) && isfinite(F->T.z);
+      for (int c = 0; c < 3; ++c) {
+        b[c] = INFINITY;
+        b[3 + c] = -INFINITY;
+      }
+      if (fin) {
+        const bnode* r0 = &T->node[0];
+        for (int corner = 0; corner < 8; ++corner) {
+          vec3 x = mk((corner & 1) ? r0->hi[0] : r0->lo[0], (corner & 2) ? r0->hi[1] : r0->lo[1],
+                      (corner & 4) ? r0->hi[2] : r0->lo[2]);
+          vec3 wpt = to_world(F, x);
+          double wc[3] = {wpt.x, wpt.y, wpt.z};
+          for (int c = 0; c < 3; ++c) {
+            if (wc[c] < b[c]) b[c] = wc[c];
+            if (wc[c] > b[3 + c]) b[3 + c] = wc[c];
+          }
+        }
+        double slack = 0x1p-40 * (amax(F->T) + A * T->amax_box);
+        for (int c = 0; c < 3; ++c) {
+          b[c] -= slack;
+          b[3 + c] += slack;
+        }
+        fin = box_finite(b);
+      }
+      if (!fin) {
+        b[0] = NAN; /* loose: searched for every ray */
+        continue;
+      }
+      double* e = ib + NB_N * j;
+      e[NB_A] = A;
+      e[NB_AINV] = Ai;
+      e[NB_T] = amax(F->T);
+      e[NB_KAPPA] = A * Ai;
+      e[NB_V] = T->amax_box;
+    }
+    int okt = bt_make(&B->top, box, ni, skip);
+    free(box);
+    btree* TT = &B->top;
+    TT->nb = okt ? (double*)calloc((size_t)NB_N * (size_t)(TT->n_node ? TT->n_node : 1), sizeof(double))
+                 : NULL;
+    if (!TT->nb) {
+      free(ib);
+      free(skip);
+      goto fail;
+    }
+    /* per-node maxima, children before parents (nodes are numbered in
+     * pre-order, so every child has a larger index than its parent) */
+    for (int64_t i = TT->n_node - 1; i >= 0; --i) {
+      const bnode* nd = &TT->node[i];
+      double* e = TT->nb + NB_N * i;
+      if (nd->a < 0) {
+        for (int64_t k = 0; k < nd->b; ++k)
+          for (int c = 0; c < NB_N; ++c)
+            e[c] = fmax(e[c], ib[NB_N * TT->item[-1 - nd->a + k] + c]);
+      } else {
+        for (int c = 0; c < NB_N; ++c)
+          e[c] = fmax(TT->nb[NB_N * nd->a + c], TT->nb[NB_N * nd->b + c]);
+      }
+    }
+    free(ib);
+    free(skip);
+  }
+  *out = B;
+  return 0;
+fail:
+  orc_bvh_destroy(B);
+  return -1;
+}
+
+int orc_bvh_stats(const orc_bvh* B, int64_t* out /* 4: nodes, loose, max depth, top nodes */) {
+  if (!B || !out) return -1;
+  out[0] = out[1] = out[2] = 0;
+  for (int m = 0; m < B->n_mesh; ++m) {
+    out[0] += B->mesh[m].n_node;
+    out[1] += B->mesh[m].n_loose;
+    if (B->mesh[m].depth > out[2]) out[2] = B->mesh[m].depth;
+  }
+  out[3] = B->top.n_node;
+  return 0;
+}
+
+/* ---- walking the trees -------------------------------------------------- */
+
+static int ray_finite(const ray64* q) {
+  if (!isfinite(q->o.x) || !isfinite(q->o.y) || !isfinite(q->o.z)) return 0;
+  if (!isfinite(q->d.x) || !isfinite(q->d.y) || !isfinite(q->d.z)) return 0;
+  double dd = dot(q->d, q->d);
+  return isfinite(dd) && dd > 0.0;
+}
+
+/* Parameters where the line o + t d enters and leaves the box widened by m
+ * (relatively widened beyond the rounding of the divisions); 0 when it
+ * misses. */
+static int slab(const double lo[3], const double hi[3], double m, vec3 o, vec3 d, double* te,
+                double* tx) {
+  double O[3] = {o.x, o.y, o.z}, D[3] = {d.x, d.y, d.z};
+  double a = -INFINITY, b = INFINITY;
+  for (int i = 0; i < 3; ++i) {
+    double l = lo[i] - m, h = hi[i] + m;
+    if (D[i] == 0.0) {
+      if (O[i] < l || O[i] > h) return 0;
+      continue;
+    }
+    double t1 = (l - O[i]) / D[i], t2 = (h - O[i]) / D[i];
+    if (t1 > t2) {
+      double x = t1; t1 = t2; t2 = x;
+    }
+    if (t1 > a) a = t1;
+    if (t2 < b) b = t2;
+  }
+  if (isfinite(a)) a -= fabs(a) * 0x1p-40;
+  if (isfinite(b)) b += fabs(b) * 0x1p-40;
+  if (!(a <= b)) return 0;
+  *te = a;
+  *tx = b;
+  return 1;
+}
+
+/* per (ray, unit) constants of the box tests */
+typedef struct {
+  const ray64* q;
+  double amax_o, m_hit; /* hit queries: the box widening */
+  double xs, tilt, dd, dn; /* candidate queries */
+} wprep;
+
+static void wprep_init(wprep* P, const qstate* st, const ray64* q, double xs, double xd,
+                       double amax_box) {
+  P->q = q;
+  P->amax_o = amax(q->o);
+  P->m_hit = 0x1p-34 * (P->amax_o + amax_box);
+  P->xs = xs;
+  P->dd = dot(q->d, q->d);
+  P->dn = sqrt(P->dd);
+  double dm = amax(q->d);
+  P->tilt = st->delta;
+  if (xd > dm) P->tilt = st->delta * xd / dm;
+}
+
+/* Whether the box may hold a wanted pair; *key orders the children (entry t)
+ * and re-checks a stacked box against the current bound (entry t for the
+ * closest hit, the lowest lo for the acceptable closest answers). */
+static int box_test(const wprep* P, const qstate* st, const bnode* nd, double* key) {
+  const ray64* q = P->q;
+  double te, tx;
+  if (st->kind != Q_CAND) {
+    if (!slab(nd->lo, nd->hi, P->m_hit, q->o, q->d, &te, &tx)) return 0;
+    double tc = q->tmax;
+    if (st->kind == Q_CLOSEST && st->minT < tc) tc = st->minT;
+    if (te > tc || tx < q->tmin) return 0;
+    *key = te;
+    return 1;
+  }
+  double O[3] = {q->o.x, q->o.y, q->o.z}, D[3] = {q->d.x, q->d.y, q->d.z};
+  double ab = 0.0, far2 = 0.0, diag2 = 0.0, pmin = 0.0, pmax = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    double l = nd->lo[i], h = nd->hi[i];
+    if (fabs(l) > ab) ab = fabs(l);
+    if (fabs(h) > ab) ab = fabs(h);
+    double f = fmax(fabs(l - O[i]), fabs(h - O[i]));
+    far2 += f * f;
+    diag2 += (h - l) * (h - l);
+    double pl = (l - O[i]) * D[i], ph = (h - O[i]) * D[i];
+    pmin += fmin(pl, ph);
+    pmax += fmax(pl, ph);
+  }
+  double s = P->amax_o;
+  if (ab > s) s = ab;
+  if (P->xs > s) s = P->xs;
+  double L = sqrt(far2) * (1.0 + 0x1p-40);
+  double eta = 2.0 * st->delta * s + 2.0 * P->tilt * L;
+  double m = eta + 0x1p-34 * (P->amax_o + ab + L);
+  if (!slab(nd->lo, nd->hi, m, q->o, q->d, &te, &tx)) return 0;
+  pmin /= P->dd;
+  pmax /= P->dd;
+  double w = m / P->dn;
+  double plo = pmin - w, phi = pmax + w;
+  plo -= fabs(plo) * 0x1p-40;
+  phi += fabs(phi) * 0x1p-40;
+  if (phi < q->tmin || plo > q->tmax) return 0;
+  double lb = pmin - fmax(m, 3.0 * sqrt(diag2) * (1.0 + 0x1p-40)) / P->dn;
+  lb -= fabs(lb) * 0x1p-40;
+  *key = lb;
+  return !(st->cull_tstar && lb > st->tstar);
+}
+
+static int stale(const qstate* st, const ray64* q, double key) {
+  if (st->kind == Q_CLOSEST) return key > st->minT || key > q->tmax;
+  if (st->kind == Q_CAND) return st->cull_tstar && key > st->tstar;
+  return 0;
+}
+
+typedef struct {
+  int64_t node;
+  double key;
+} sentry;
+
+/* The pairs of unit j (mesh m) that its tree does not rule out. */
+static int walk_mesh(const orc_scene* s, const orc_bvh* B, const orc_opts* opts, int64_t r,
+                     int64_t j, int m, const ray64* q, double xs, double xd, qstate* st) {
+  const btree* T = &B->mesh[m];
+  if (!ray_finite(q)) return scan_mesh(s, opts, r, j, m, q, xs, xd, st);
+  vec3 v0, v1, v2;
+  for (int64_t i = 0; i < T->n_loose; ++i) {
+    int64_t k = T->loose[i];
+    if (skipped(s, opts, r, j, k)) continue;
+    tri(s, m, k, &v0, &v1, &v2);
+    if (on_pair(st, q, (uint32_t)j, (uint32_t)k, v0, v1, v2, xs, xd)) return 1;
+  }
+  if (T->n_node == 0) return 0;
+  wprep P;
+  wprep_init(&P, st, q, xs, xd, T->amax_box);
+  sentry stk[BVH_STACK];
+  int sp = 0;
+  double key;
+  if (box_test(&P, st, &T->node[0], &key)) {
+    stk[0].node = 0;
+    stk[0].key = key;
+    sp = 1;
+  }
+  while (sp > 0) {
+    sentry e = stk[--sp];
+    if (stale(st, q, e.key)) continue;
+    const bnode* nd = &T->node[e.node];
+    if (nd->a < 0) {
+      const int64_t* it = T->item + (-1 - nd->a);
+      for (int64_t i = 0; i < nd->b; ++i) {
+        int64_t k = it[i];
+        if (skipped(s, opts, r, j, k)) continue;
+        tri(s, m, k, &v0, &v1, &v2);
+        if (on_pair(st, q, (uint32_t)j, (uint32_t)k, v0, v1, v2, xs, xd)) return 1;
+      }
+      continue;
+    }
+    double ka = 0.0, kb = 0.0;
+    int ha = box_test(&P, st, &T->node[nd->a], &ka);
+    int hb = box_test(&P, st, &T->node[nd->b], &kb);
+    /* the nearer child on top */
+    if (ha && hb && ka <= kb) {
+      stk[sp].node = nd->b; stk[sp++].key = kb;
+      stk[sp].node = nd->a; stk[sp++].key = ka;
+    } else {
+      if (ha) { stk[sp].node = nd->a; stk[sp++].key = ka; }
+      if (hb) { stk[sp].node = nd->b; stk[sp++].key = kb; }
+    }
+  }
+  return 0;
+}
+
+/* object ray of an instance from its precomputed frame (the same arithmetic
+ * as object_ray) */
+static void instance_ray(const orc_scene* s, const orc_bvh* B, const ray64* w, int64_t j, ray64* q,
+                         int* mesh, double* xs, double* xd) {
+  const frame64* F = &B->frame[j];
+  q->o = to_object_dir(F, sub(w->o, F->T));
+  q->d = to_object_dir(F, w->d);
+  q->tmin = w->tmin;
+  q->tmax = w->tmax;
+  *mesh = (int)s->inst_mesh[j];
+  *xs = inv_linear_norm(F) * (amax(w->o) + amax(F->T));
+  *xd = inv_linear_norm(F) * amax(w->d);
+}
+
+/* World-space widening of an instance-tree box: the object-space widening
+ * bounded over the box's instances (largest inverse norm, translation, mesh
+ * coordinate and condition number ||A|| ||A^-1||, which bounds the tilt of
+ * the direction) mapped to world space by their largest linear norm, plus
+ * the rounding of the world-to-object transform. */
+static double top_margin(const btree* T, int64_t node, const qstate* st, const ray64* w) {
+  const double* e = T->nb + NB_N * node;
+  double ao = amax(w->o), amax_box = 0.0;
+  for (int c = 0; c < 3; ++c) amax_box = fmax(amax_box, fmax(fabs(T->node[node].lo[c]), fabs(T->node[node].hi[c])));
+  double xs_max = e[NB_AINV] * (ao + e[NB_T]) * (1.0 + 0x1p-40);
+  double m_obj = 0x1p-34 * (xs_max + e[NB_V]);
+  if (st->kind == Q_CAND) {
+    double sm = xs_max > e[NB_V] ? xs_max : e[NB_V];
+    double L = sqrt(3.0) * (xs_max + e[NB_V]);
+    double tilt = st->delta * (e[NB_KAPPA] > 1.0 ? e[NB_KAPPA] : 1.0);
+    double eta = 2.0 * st->delta * sm + 2.0 * tilt * L;
+    m_obj = eta + 0x1p-34 * (xs_max + e[NB_V] + L);
+  }
+  return e[NB_A] * m_obj * (1.0 + 0x1p-30) +
+         0x1p-28 * (e[NB_KAPPA] + 1.0) * (ao + e[NB_T] + amax_box + e[NB_V]);
+}
+
+/* An instance-tree box: the line within its widening of it (any t) for
+ * candidate queries; for hit queries also its slab interval against
+ * [tmin, tmax] and the closest hit so far (key = entry t). */
+static int top_test(const btree* T, int64_t node, const qstate* st, const ray64* w, double* key) {
+  const bnode* nd = &T->node[node];
+  double te, tx, mw = top_margin(T, node, st, w);
+  if (!slab(nd->lo, nd->hi, mw, w->o, w->d, &te, &tx)) return 0;
+  if (st->kind == Q_CAND) {
+    *key = -INFINITY;
+    return 1;
+  }
+  double tc = w->tmax;
+  if (st->kind == Q_CLOSEST && st->minT < tc) tc = st->minT;
+  *key = te;
+  return !(te > tc || tx < w->tmin);
+}
+
+static void search_bvh(const orc_scene* s, const orc_bvh* B, const orc_opts* opts, int64_t r,
+                       const ray64* w, qstate* st) {
+  if (!ray_finite(w)) {
+    search_linear(s, opts, r, w, st);
+    return;
+  }
+  if (s->n_inst == 0) {
+    if (unit_enabled(s, opts, r, 0)) walk_mesh(s, B, opts, r, 0, 0, w, 0.0, 0.0, st);
+    return;
+  }
+  const btree* T = &B->top;
+  ray64 q;
+  int m;
+  double xs, xd;
+  for (int64_t i = 0; i < T->n_loose; ++i) {
+    int64_t j = T->loose[i];
+    if (!unit_enabled(s, opts, r, j)) continue;
+    instance_ray(s, B, w, j, &q, &m, &xs, &xd);
+    if (walk_mesh(s, B, opts, r, j, m, &q, xs, xd, st)) return;
+  }
+  if (T->n_node == 0) return;
+  sentry stk[BVH_STACK];
+  int sp = 0;
+  double key;
+  if (top_test(T, 0, st, w, &key)) {
+    stk[0].node = 0;
+    stk[0].key = key;
+    sp = 1;
+  }
+  while (sp > 0) {
+    sentry e = stk[--sp];
+    if (stale(st, w, e.key)) continue;
+    const bnode* nd = &T->node[e.node];
+    if (nd->a < 0) {
+      const int64_t* it = T->item + (-1 - nd->a);
+      for (int64_t i = 0; i < nd->b; ++i) {
+        int64_t j = it[i];
+        if (!unit_enabled(s, opts, r, j)) continue;
+        instance_ray(s, B, w, j, &q, &m, &xs, &xd);
+        if (walk_mesh(s, B, opts, r, j, m, &q, xs, xd, st)) return;
+      }
+      continue;
+    }
+    double ka = 0.0, kb = 0.0;
+    int ha = top_test(T, nd->a, st, w, &ka);
+    int hb = top_test(T, nd->b, st, w, &kb);
+    if (ha && hb && ka <= kb) {
+      stk[sp].node = nd->b; stk[sp++].key = kb;
+      stk[sp].node = nd->a; stk[sp++].key = ka;
+    } else {
+      if (ha) { stk[sp].node = nd->a; stk[sp++].key = ka; }
+      if (hb) { stk[sp].node = nd->b; stk[sp++].key = kb; }
+    }
+  }
+}
+
+/* The search a scene asks for: through its BVH when it has one. */
+static void search(const orc_scene* s, const orc_opts* opts, int64_t r, const ray64* w,
+                   qstate* st) {
+  if (s->bvh) search_bvh(s, s->bvh, opts, r, w, st);
+  else search_linear(s, opts, r, w, st);
+}
+
+/* A BVH belongs to the scene it was built from. */
+static int bvh_matches(const orc_scene* s) {
+  const orc_bvh* B = s->bvh;
+  return !B || (B->n_mesh == s->n_mesh && B->n_inst == s->n_inst && B->vertices == s->vertices);
+}
+
+/* Checks the invariant the walk relies on, pair by pair: for every (ray,
+ * instance, triangle) pair the linear search finds wanted (a §3.1 hit when
+ * kind = 0; a sure or maybe pair of the tolerance model when kind = 1), every
+ * box from the triangle's leaf up to its tree's root, and every instance box
+ * above it, must pass its test with a key no larger than the pair's t (hits)
+ * or its lowest possible t (candidates).  out[0] = pairs checked, out[1] =
+ * violations. */
+static int path_ok(const wprep* P, const qstate* st, const btree* T, int64_t item, double bound) {
+  int64_t nd = T->leaf_of[item];
+  if (nd < 0) return 1; /* loose: visited for every ray */
+  for (; nd >= 0; nd = T->parent[nd]) {
+    double key;
+    if (!box_test(P, st, &T->node[nd], &key) || key > bound) return 0;
+  }
+  return 1;
+}
+
+int orc_bvh_check(const orc_scene* s, const float* rays, int64_t nr, int kind, double delta,
+                  int64_t* out) {
+  if (nr < 0 || !scene_valid(s) || !s->bvh || !bvh_matches(s) || !out || (kind != 0 && kind != 1))
+    return -1;
+  const orc_bvh* B = s->bvh;
+  int64_t pairs = 0, bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : pairs, bad)
+  for (int64_t r = 0; r < nr; ++r) {
+    ray64 w = load_ray(rays + 8 * r);
+    if (ray_is_void(&w) || !ray_finite(&w)) continue;
+    qstate st;
+    memset(&st, 0, sizeof(st));
+    st.kind = kind ? Q_CAND : Q_ALL;
+    st.delta = delta;
+    qstate_reset(&st);
+    for (int64_t j = 0; j < n_units(s); ++j) {
+      ray64 q;
+      int m;
+      double xs, xd;
+      object_ray(s, &w, j, &q, &m, &xs, &xd);
+      if (!ray_finite(&q)) continue;
+      const btree* T = &B->mesh[m];
+      wprep P;
+      wprep_init(&P, &st, &q, xs, xd, T->amax_box);
+      for (int64_t k = 0; k < s->n_triangles[m]; ++k) {
+        vec3 v0, v1, v2;
+        tri(s, m, k, &v0, &v1, &v2);
+        double bound;
+        if (kind == 0) {
+          double t, u, v;
+          if (!intersect_paper(&q, v0, v1, v2, &t, &u, &v)) continue;
+          bound = t;
+        } else {
+          cand c;
+          double hi;
+          if (classify(&q, v0, v1, v2, delta, xs, xd, &c, &hi) == 0) continue;
+          bound = c.lo;
+        }
+        ++pairs;
+        int ok = path_ok(&P, &st, T, k, bound);
+        if (ok && s->n_inst > 0 && B->top.leaf_of[j] >= 0) {
+          for (int64_t nd = B->top.leaf_of[j]; nd >= 0 && ok; nd = B->top.parent[nd]) {
+            double key;
+            ok = top_test(&B->top, nd, &st, &w, &key) && key <= bound;
+          }
+        }
+        if (!ok) ++bad;
+      }
+    }
+  }
+  out[0] = pairs;
+  out[1] = bad;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* closest, any and all                                                       */
+/* ------------------------------------------------------------------------- */
+
+int orc_closest_ex(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts,
+                   uint32_t* inst_out, uint32_t* prim_out, double* tuv_out) {
+  if (nr < 0 || (nr > 0 && (!rays || !prim_out || !tuv_out)) || !scene_valid(s) ||
+      !bvh_matches(s))
+    return -1;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t r = 0; r < nr; ++r) {
+    ray64 w = load_ray(rays + 8 * r);
+    qstate st;
+    memset(&st, 0, sizeof(st));
+    st.kind = Q_CLOSEST;
+    qstate_reset(&st);
+    if (!ray_is_void(&w)) search(s, opts, r, &w, &st);
+    if (inst_out) inst_out[r] = st.bi;
+    prim_out[r] = st.bp;
+    tuv_out[3 * r + 0] = st.minT;
+    tuv_out[3 * r + 1] = st.bu;
+    tuv_out[3 * r + 2] = st.bv;
+  }
+  return 0;
+}
+
+int orc_closest(const orc_scene* s, const float* rays, int64_t nr, uint32_t* inst_out,
+                uint32_t* prim_out, double* tuv_out) {
+  return orc_closest_ex(s, rays, nr, NULL, inst_out, prim_out, tuv_out);
+}
+
+int orc_any_ex(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts,
+               uint8_t* occluded) {
+  if (nr < 0 || (nr > 0 && (!rays || !occluded)) || !scene_valid(s) || !bvh_matches(s)) return -1;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t r = 0; r < nr; ++r) {
+    ray64 w = load_ray(rays + 8 * r);
+    qstate st;
+    memset(&st, 0, sizeof(st));
+    st.kind = Q_ANY;
+    qstate_reset(&st);
+    if (!ray_is_void(&w)) search(s, opts, r, &w, &st);
+    occluded[r] = (uint8_t)st.hit;
+  }
+  return 0;
+}
+
+int orc_any(const orc_scene* s, const float* rays, int64_t nr, uint8_t* occluded) {
+  return orc_any_ex(s, rays, nr, NULL, occluded);
+}
+
+/* All hits of §6.2's enumeration ("all intersections"): every pair the §3.1
+ * test accepts within [tmin, tmax], sorted by (t, inst, prim). */
+int orc_all(const orc_scene* s, const float* rays, int64_t nr, const orc_opts* opts, int32_t K,
+            int64_t* count, uint32_t* inst_out, uint32_t* prim_out, double* tuv_out) {
+  if (nr < 0 || K < 1 || !scene_valid(s) || !bvh_matches(s)) return -1;
+  if (nr > 0 && (!rays || !count || !prim_out || !tuv_out)) return -1;
+  int bad = 0;
+#pragma omp parallel
+  {
+    qstate st;
+    memset(&st, 0, sizeof(st));
+    st.kind = Q_ALL;
+#pragma omp for schedule(dynamic, 8)
+    for (int64_t r = 0; r < nr; ++r) {
+      qstate_reset(&st);
+      ray64 w = load_ray(rays + 8 * r);
+      if (!ray_is_void(&w)) search(s, opts, r, &w, &st);
+      hit64* buf = st.hits;
+      int64_t n = st.n;
+      for (int64_t i = 1; i < n; ++i) {
+        hit64 x = buf[i];
+        int64_t jj = i - 1;
+        while (jj >= 0 && hit_less(&x, &buf[jj])) { buf[jj + 1] = buf[jj]; --jj; }
+        buf[jj + 1] = x;
+      }
+      count[r] = n;
+      for (int64_t i = 0; i < K; ++i) {
+        int64_t o = r * K + i;
+        int in = i < n;
+        if (inst_out) inst_out[o] = in ? buf[i].inst : ORC_NONE;
+        prim_out[o] = in ? buf[i].prim : ORC_NONE;
+        tuv_out[3 * o + 0] = in ? buf[i].t : INFINITY;
+        tuv_out[3 * o + 1] = in ? buf[i].u : 0.0;
+        tuv_out[3 * o + 2] = in ? buf[i].v : 0.0;
+      }
+    }
+    if (st.bad) {
+#pragma omp atomic write
+      bad = 1;
+    }
+    free(st.hits);
+  }
+  return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* acceptable sets of every ray                                               */
+/* ------------------------------------------------------------------------- */
+
 /* The candidates (sure and maybe pairs) of every ray, with the range
  * [lo, hi] their float32 t may take.  mode 0: the acceptable closest answers
  * (pairs whose lowest possible t does not exceed t*); mode 1: every
@@ -560,7 +1378,7 @@ static int accept_impl(const orc_scene* s, const float* rays, int64_t nr, const 
                        int32_t* n_sure, uint32_t* acc_inst, uint32_t* acc_prim, double* acc_tuv,
                        double* acc_scale, double* acc_lo, double* acc_hi, uint8_t* acc_sure,
                        uint8_t* any_class) {
-  if (nr < 0 || K < 1 || !scene_valid(s)) return -1;
+  if (nr < 0 || K < 1 || !scene_valid(s) || !bvh_matches(s)) return -1;
   if (nr > 0 && (!rays || !miss_ok || !count || !acc_inst || !acc_prim || !acc_tuv ||
                  !acc_scale || !any_class))
     return -1;
@@ -568,53 +1386,20 @@ static int accept_impl(const orc_scene* s, const float* rays, int64_t nr, const 
   int bad = 0;
 #pragma omp parallel
   {
-    int64_t cap = 64, n = 0;
-    cand* buf = (cand*)malloc(sizeof(cand) * cap);
-    if (!buf) {
-#pragma omp atomic write
-      bad = 1;
-    }
-#pragma omp for schedule(dynamic, 8)
+    qstate st;
+    memset(&st, 0, sizeof(st));
+    st.kind = Q_CAND;
+    st.cull_tstar = (mode == 0);
+    st.delta = delta;
+#pragma omp for schedule(dynamic, 64)
     for (int64_t r = 0; r < nr; ++r) {
-      if (!buf) continue;
+      qstate_reset(&st);
       ray64 w = load_ray(rays + 8 * r);
-      double tstar = INFINITY;
-      int any_sure = 0, sures = 0;
-      n = 0;
-      if (!ray_is_void(&w)) {
-        for (int64_t j = 0; j < n_units(s); ++j) {
-          if (!unit_enabled(s, opts, r, j)) continue;
-          ray64 q;
-          int m;
-          double xs, xd;
-          object_ray(s, &w, j, &q, &m, &xs, &xd);
-          for (int64_t k = 0; k < s->n_triangles[m]; ++k) {
-            vec3 v0, v1, v2;
-            cand c;
-            if (skipped(s, opts, r, j, k)) continue;
-            tri(s, m, k, &v0, &v1, &v2);
-            double hi;
-            int cls = classify(&q, v0, v1, v2, delta, xs, xd, &c, &hi);
-            if (cls == 0) continue;
-            c.inst = s->n_inst > 0 ? (uint32_t)j : 0u;
-            c.prim = (uint32_t)k;
-            c.sure = (cls == 2);
-            c.hi = hi;
-            if (c.sure) {
-              any_sure = 1;
-              ++sures;
-              if (hi < tstar) tstar = hi;
-            }
-            if (n == cap) {
-              cand* nb = (cand*)realloc(buf, sizeof(cand) * cap * 2);
-              if (!nb) continue;
-              buf = nb;
-              cap *= 2;
-            }
-            buf[n++] = c;
-          }
-        }
-      }
+      if (!ray_is_void(&w)) search(s, opts, r, &w, &st);
+      cand* buf = st.cands;
+      int64_t n = st.n;
+      double tstar = st.tstar;
+      int any_sure = st.sures > 0;
       /* keep the candidates that can still be the closest, sorted by (t, inst, prim) */
       int64_t kept = 0;
       for (int64_t i = 0; i < n; ++i)
@@ -627,7 +1412,7 @@ static int accept_impl(const orc_scene* s, const float* rays, int64_t nr, const 
       }
       miss_ok[r] = (uint8_t)(!any_sure);
       count[r] = (int32_t)kept;
-      if (n_sure) n_sure[r] = sures;
+      if (n_sure) n_sure[r] = st.sures;
       any_class[r] = any_sure ? 1 : (n == 0 ? 0 : 2);
       for (int64_t i = 0; i < K; ++i) {
         int64_t o = r * K + i;
@@ -654,10 +1439,16 @@ static int accept_impl(const orc_scene* s, const float* rays, int64_t nr, const 
         }
       }
     }
-    free(buf);
+    if (st.bad) {
+#pragma omp atomic write
+      bad = 1;
+    }
+    free(st.cands);
   }
   return bad ? -1 : 0;
 }
+
+
 
 
 int orc_accept(const orc_scene* s, const float* rays, int64_t nr, double delta, int32_t K,

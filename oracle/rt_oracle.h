@@ -5,10 +5,13 @@
  * links, loads or calls it, and it shares no code with the HIP library.
  *
  * Everything is computed in double precision from float32 inputs promoted
- * exactly to double.  The functions are plain linear searches over every
- * triangle (the definition of the closest hit in the paper's §3.3 listing of
- * the naive linear search), using the plane-then-edge ray/triangle test of
- * §3.1.  No acceleration structure, blocking or reordering is used.
+ * exactly to double.  The queries are defined by the plain linear search over
+ * every triangle (the paper's §3.3 search for the closest hit), using the
+ * plane-then-edge ray/triangle test of §3.1.  A scene may carry an FP64 BVH
+ * (orc_bvh_create): a median-split binary tree that only skips triangles
+ * whose boxes provably hold no wanted pair, so the answers are identical bit
+ * for bit to the linear search (§6.2: the hierarchy accelerates, it does not
+ * change, the search).  No blocking or reordering of the arithmetic is used.
  *
  * Shared array conventions:
  *   vertices  float[nv*3]           (x,y,z) per vertex
@@ -30,8 +33,12 @@ extern "C" {
 
 #define ORC_NONE 0xFFFFFFFFu
 
+typedef struct orc_bvh_s orc_bvh;
+
 /* A scene: n_mesh meshes; either no instances (n_inst == 0: mesh 0 is traced
- * in world space) or n_inst instances of the meshes with SRT frames. */
+ * in world space) or n_inst instances of the meshes with SRT frames.  bvh:
+ * NULL for the linear search, or a hierarchy built from this very scene
+ * (same arrays) by orc_bvh_create. */
 typedef struct {
   int32_t n_mesh;
   const float* const* vertices;   /* [n_mesh] */
@@ -41,7 +48,24 @@ typedef struct {
   int64_t n_inst;
   const uint32_t* inst_mesh;      /* [n_inst] */
   const float* inst_srt;          /* [n_inst*10] */
+  const orc_bvh* bvh;
 } orc_scene;
+
+/* FP64 BVH of a scene: one median-split binary tree per mesh (boxes: exact
+ * min/max of the float32 vertices) and, with instances, one over the
+ * instances' world boxes.  It keeps pointers into the scene's arrays, which
+ * must outlive it.  Returns 0, or -1 on invalid scenes or allocation failure. */
+int orc_bvh_create(const orc_scene* s, orc_bvh** out);
+void orc_bvh_destroy(orc_bvh* b);
+/* out[4]: tree nodes over all meshes, triangles without a finite box, the
+ * deepest leaf, nodes of the instance tree */
+int orc_bvh_stats(const orc_bvh* b, int64_t* out);
+/* The culling invariant, checked pair by pair against the linear search:
+ * every box above a wanted pair (kind 0: a hit; kind 1: a sure or maybe pair
+ * of the tolerance model with slack delta) admits it with a key no larger
+ * than its t (its lowest possible t).  out[2] = pairs checked, violations. */
+int orc_bvh_check(const orc_scene* s, const float* rays, int64_t nr, int kind, double delta,
+                  int64_t* out);
 
 /* Query options.  §7.5 names ray masks and intersection filters as options
  * of a traversal without fixing their semantics; the readings here:
