@@ -19,6 +19,11 @@
  *    host and returned before anything is enqueued; a device fault surfaces as
  *    RT_ERROR_HIP from a later call.  No C++ exception crosses the boundary.
  *    rt_last_error_message() gives a thread-local detail string.
+ *  - A traversal lane whose stack would grow past the accel's bound
+ *    (rt_accel_info.max_stack, which the global spill stack is sized for)
+ *    drops the entry and flags its context; the next query or batch launch
+ *    on that context returns RT_ERROR_STACK_OVERFLOW without enqueuing
+ *    anything and clears the flag.  With a correct bound this never happens.
  *  - Ray record (32 bytes, float32): origin o, tmin, direction d, tmax.  The
  *    ray is R(t) = o + t d (§3.1); t is measured in units of the given d (d is
  *    never normalised); a hit needs tmin <= t <= tmax (both inclusive, the
@@ -53,7 +58,10 @@ typedef enum rt_status {
   RT_ERROR_NO_DEVICE = 3,          /* no HIP device, or the device id is out of range */
   RT_ERROR_HIP = 4,                /* a HIP runtime call failed (detail in the message) */
   RT_ERROR_UNSUPPORTED = 5,        /* valid request this build does not implement */
-  RT_ERROR_INDEX_OUT_OF_RANGE = 6  /* a triangle index >= vertex_count, a mesh id >= mesh_count */
+  RT_ERROR_INDEX_OUT_OF_RANGE = 6, /* a triangle index >= vertex_count, a mesh id >= mesh_count */
+  RT_ERROR_STACK_OVERFLOW = 7      /* an earlier traversal on this context needed more stack
+                                      entries than the accel's bound (see rt_accel_info.max_stack);
+                                      that query's results may lack hits */
 } rt_status;
 
 /* Miss / no instance (the linear search of §3.3 starts from triIdx = -1). */
@@ -378,10 +386,13 @@ rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const 
 
 /* Diagnostics: the query of rt_trace_closest (any == 0, into hits) or
  * rt_trace_any (any != 0, into occluded) run with a counting kernel variant
- * (stack 16, workgroup 256) that ADDS to counters (device, 3 uint64): node
- * visits (both levels of a two-level accel), triangle tests, stack entries
- * spilled to global memory.  Used to measure the bytes a query fetches per
- * ray.  The instance ids of a two-level closest query are not written. */
+ * (stack 16, workgroup 256).  counters (device, 4 uint64): the call ADDS
+ * node visits (both levels of a two-level accel), triangle tests and stack
+ * entries spilled to global memory to counters[0..2], and raises counters[3]
+ * to the deepest stack fill any ray reached (entries, instance markers
+ * included; at most rt_accel_info.max_stack).  Used to measure the bytes a
+ * query fetches per ray.  The instance ids of a two-level closest query are
+ * not written. */
 rt_status rt_trace_counters(rt_accel accel, const rt_ray* rays, uint32_t n, int any, rt_hit* hits,
                             uint8_t* occluded, uint64_t* counters, void* stream);
 

@@ -307,6 +307,11 @@ class Accept:
     def pinned(self):
         return (self.count + self.miss_ok.astype(np.int32)) == 1
 
+    def subset(self, rows) -> "Accept":
+        """The acceptable sets of the rays ``rows`` only."""
+        return Accept(self.miss_ok[rows], self.count[rows], self.inst[rows], self.prim[rows],
+                      self.tuv[rows], self.scale[rows], self.any_class[rows], self.K)
+
     @property
     def overflow(self):
         return self.count > self.K

@@ -19,6 +19,7 @@ RT_ERROR_NO_DEVICE = 3
 RT_ERROR_HIP = 4
 RT_ERROR_UNSUPPORTED = 5
 RT_ERROR_INDEX_OUT_OF_RANGE = 6
+RT_ERROR_STACK_OVERFLOW = 7
 RT_INVALID_ID = 0xFFFFFFFF
 
 EXPORTS = [

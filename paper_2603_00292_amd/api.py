@@ -304,12 +304,13 @@ def trace_any(accel: Accel, rays: torch.Tensor) -> torch.Tensor:
     return occ
 
 
-def trace_counters(accel: Accel, rays: torch.Tensor, any_hit: bool = False):
+def trace_counters(accel: Accel, rays: torch.Tensor, any_hit: bool = False, peak: bool = False):
     """Runs the counting variant; returns (node visits, triangle tests,
-    spilled stack entries) summed over the rays, and the query's output."""
+    spilled stack entries) summed over the rays (with peak=True also the
+    deepest stack fill of any ray), and the query's output."""
     _require(rays, "rays", torch.float32, 8)
     n = rays.shape[0]
-    cnt = torch.zeros((3,), dtype=torch.int64, device=rays.device)
+    cnt = torch.zeros((4,), dtype=torch.int64, device=rays.device)
     hits = occ = None
     if any_hit:
         occ = torch.empty((n,), dtype=torch.uint8, device=rays.device)
@@ -318,6 +319,8 @@ def trace_counters(accel: Accel, rays: torch.Tensor, any_hit: bool = False):
     capi.call("rt_trace_counters", accel.handle, _ptr(rays), n, int(any_hit), _ptr(hits), _ptr(occ),
               _ptr(cnt), C.c_void_p(_stream()))
     c = cnt.cpu().tolist()
+    if peak:
+        return (c[0], c[1], c[2], c[3]), (occ if any_hit else hits)
     return (c[0], c[1], c[2]), (occ if any_hit else hits)
 
 

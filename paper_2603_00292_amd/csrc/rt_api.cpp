@@ -105,6 +105,9 @@ struct rt_context_s {
   rt_variant variant{16, 256};
   uint32_t refill_min = 32;
   uint32_t blocks_per_cu = 0;  // 0 = the occupancy API's resident count
+  uint32_t stack_limit = 0;    // RT_STACK_LIMIT: caps every lane's stack below the
+                               // accel's bound (exercises the overflow report); 0 = off
+  uint32_t* status = nullptr;  // host-mapped word: set by a lane whose stack overflows
   std::mutex mu;
   Scratch scratch;
   rta::Buffers grad;                          // backward: deterministic vertex-gradient sums
@@ -251,6 +254,18 @@ rt_status check_device(int dev) {
   return RT_SUCCESS;
 }
 
+// Reports (and clears) a stack overflow flagged by an earlier traversal on
+// this context.  The flag is written by the device into host-mapped memory;
+// a launch still running when this is read is reported by a later call.
+rt_status take_overflow(rt_context ctx, const char* who) {
+  volatile uint32_t* f = reinterpret_cast<volatile uint32_t*>(ctx->status);
+  if (*f == 0u) return RT_SUCCESS;
+  *f = 0u;
+  return fail(RT_ERROR_STACK_OVERFLOW,
+              "%s: an earlier traversal on this context exceeded its accel's stack bound; "
+              "that query's results may lack hits", who);
+}
+
 }  // namespace
 
 extern "C" {
@@ -264,6 +279,7 @@ const char* rt_status_string(rt_status s) {
     case RT_ERROR_HIP: return "RT_ERROR_HIP";
     case RT_ERROR_UNSUPPORTED: return "RT_ERROR_UNSUPPORTED";
     case RT_ERROR_INDEX_OUT_OF_RANGE: return "RT_ERROR_INDEX_OUT_OF_RANGE";
+    case RT_ERROR_STACK_OVERFLOW: return "RT_ERROR_STACK_OVERFLOW";
   }
   return "RT_ERROR_UNKNOWN";
 }
@@ -296,10 +312,18 @@ rt_status rt_context_create(int hip_device, rt_context* out) {
   if (valid_variant(v)) c->variant = v;
   c->refill_min = (uint32_t)std::min(64, std::max(1, env_int("RT_REFILL", 32)));
   c->blocks_per_cu = (uint32_t)std::min(64, std::max(0, env_int("RT_BLOCKS_PER_CU", 0)));
+  c->stack_limit = (uint32_t)std::max(0, env_int("RT_STACK_LIMIT", 0));
   if (hipEventCreateWithFlags(&c->last_event, hipEventDisableTiming) != hipSuccess) {
     delete c;
     return fail(RT_ERROR_HIP, "rt_context_create: hipEventCreate failed");
   }
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->status), sizeof(uint32_t), hipHostMallocDefault) !=
+      hipSuccess) {
+    (void)hipEventDestroy(c->last_event);
+    delete c;
+    return fail(RT_ERROR_OUT_OF_MEMORY, "rt_context_create: hipHostMalloc of the status word failed");
+  }
+  *reinterpret_cast<volatile uint32_t*>(c->status) = 0u;
   *out = c;
   return ok();
 }
@@ -314,6 +338,7 @@ rt_status rt_context_destroy(rt_context ctx) {
   if (ctx->last_event) (void)hipEventDestroy(ctx->last_event);
   for (hipEvent_t e : ctx->tbeg) (void)hipEventDestroy(e);
   for (hipEvent_t e : ctx->tend) (void)hipEventDestroy(e);
+  if (ctx->status) (void)hipHostFree(ctx->status);
   delete ctx;
   return ok();
 }
@@ -1075,6 +1100,8 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   rt_status st = check_device(a->device);
   if (st != RT_SUCCESS) return st;
   std::lock_guard<std::mutex> lk(ctx->mu);
+  st = take_overflow(ctx, "trace");
+  if (st != RT_SUCCESS) return st;
   rt_variant v = ctx->variant;
   if (counters || mode >= 2) v = rt_variant{16, 256};
   const void* kern = counters ? rtk_count_kernel(a->width, any, a->two_level)
@@ -1103,10 +1130,11 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   p.gstack = ctx->scratch.gstack;
   p.root = a->root;
   p.n = n;
-  p.max_stack = a->max_stack;
+  p.max_stack = ctx->stack_limit ? std::min(a->max_stack, ctx->stack_limit) : a->max_stack;
   p.gstride = gstride;
   p.refill_min = ctx->refill_min;
   p.counters = counters;
+  p.status = ctx->status;
   if (opts) {
     p.ray_masks = opts->ray_masks;
     p.skip_inst = opts->skip_inst;
@@ -1792,9 +1820,10 @@ static rt_status enqueue_plan(rt_batch_plan p, hipStream_t s) {
   q.batch_offsets = p->offsets;
   q.batch_count = p->batch_count;
   q.n = p->total;
-  q.max_stack = p->max_stack;
+  q.max_stack = p->ctx->stack_limit ? std::min(p->max_stack, p->ctx->stack_limit) : p->max_stack;
   q.gstride = p->grid * p->workgroup;
   q.refill_min = p->ctx->refill_min;
+  q.status = p->ctx->status;
   q.root = RT_CHILD_EMPTY;
   RT_HIP(rtk_launch_fill(p->scratch.counter, 1, 0u, s));
   RT_HIP(rtk_launch_trace(p->kernel, p->grid, p->workgroup, q, s));
@@ -1806,6 +1835,11 @@ rt_status rt_batch_plan_launch(rt_batch_plan plan, void* stream) {
   if (!plan) return fail(RT_ERROR_INVALID_VALUE, "rt_batch_plan_launch: NULL plan");
   if (plan->total == 0) return ok();
   rt_status st = check_device(plan->ctx->device);
+  if (st != RT_SUCCESS) return st;
+  {
+    std::lock_guard<std::mutex> lk(plan->ctx->mu);
+    st = take_overflow(plan->ctx, "rt_batch_plan_launch");
+  }
   if (st != RT_SUCCESS) return st;
   st = enqueue_plan(plan, static_cast<hipStream_t>(stream));
   if (st != RT_SUCCESS) return st;

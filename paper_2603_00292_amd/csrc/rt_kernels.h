@@ -43,6 +43,9 @@ struct TraceParams {
   uint32_t gstride;      // threads in the grid
   uint32_t refill_min;   // refill a wave once this many lanes are idle
   uint64_t* counters;    // counting variants: node visits, triangle tests, spills
+                         // (sums) and the deepest stack fill (maximum)
+  uint32_t* status;      // host-mapped word: a lane sets it to 1 when a push
+                         // would exceed max_stack
   // query options (modes 2 and 3; each may be null)
   const uint32_t* ray_masks;
   const uint32_t* skip_inst;

@@ -72,20 +72,30 @@ __device__ __forceinline__ rt_ray load_ray(const rt_ray* rays, uint32_t i) {
 // ---------------------------------------------------------------------------
 // Entry i of a lane's stack lives in LDS slot (i mod S) while it is one of the
 // S newest entries; older entries live at gstack[(i - S) * gstride + gtid].
-template <int S, int WG>
+// A push beyond `cap` (the builder's bound on the entries a ray can need,
+// which the global stack is sized for) is not stored: the lane raises the
+// launch's status word instead, which the host reports as an error on the
+// context's next call.  With PEAK the stack records its deepest fill.
+template <int S, int WG, bool PEAK = false>
 struct Stack {
   uint32_t* lds;       // this lane's column: lds[slot * WG]
   uint32_t* glob;      // this lane's column: glob[i * gstride]
+  uint32_t* status;    // host-mapped word, set to 1 on an overflow
   uint32_t gstride;
   uint32_t cap;        // total entries this lane may hold
   uint32_t sp;
+  uint32_t peak;       // PEAK: the largest sp reached
 
   __device__ __forceinline__ void push(uint32_t v) {
-    if (sp >= cap) return;  // cannot happen when cap is the builder's bound
+    if (sp >= cap) {
+      __hip_atomic_store(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      return;
+    }
     uint32_t slot = sp & (S - 1);
     if (sp >= S) glob[(size_t)(sp - S) * gstride] = lds[slot * WG];
     lds[slot * WG] = v;
     ++sp;
+    if constexpr (PEAK) peak = max(peak, sp);
   }
   __device__ __forceinline__ uint32_t pop() {
     if (sp == 0) return RT_CHILD_EMPTY;
@@ -413,12 +423,14 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
   g.root = P.root;
   g.max_stack = P.max_stack;
 
-  Stack<S, WG> st;
+  Stack<S, WG, COUNT> st;
   st.lds = lds_stack + tid;
   st.glob = P.gstack + gtid;
+  st.status = P.status;
   st.gstride = P.gstride;
   st.cap = P.max_stack;
   st.sp = 0;
+  st.peak = 0;
 
   RayState r;
   uint32_t ray_id = 0;
@@ -653,8 +665,12 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
       }
       // ---- finished: write the result --------------------------------------
       // (the float64 (t, u, v) and the prim id of a closest hit are written
-      // afterwards by finalize_kernel, one thread per ray; here: float32 t,
-      // the triangle record in the prim slot and the instance in the u slot)
+      // by the finalize: for one-accel closest queries (MODE 0) by this wave
+      // once all rays of its ranges are done, below, and by
+      // finalize_ovf_kernel for ranges past its list; for batched, masked
+      // and counting launches by finalize_kernel, one thread per ray.  Here:
+      // float32 t, the triangle record in the prim slot and the instance in
+      // the u slot)
       if (cur == RT_CHILD_EMPTY && pend == RT_CHILD_EMPTY) {
         if constexpr (MODE == 3) {
           P.counts[ray_id] = found;
@@ -687,6 +703,7 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
     atomicAdd(reinterpret_cast<unsigned long long*>(P.counters) + 0, (unsigned long long)n_nodes);
     atomicAdd(reinterpret_cast<unsigned long long*>(P.counters) + 1, (unsigned long long)n_tris);
     atomicAdd(reinterpret_cast<unsigned long long*>(P.counters) + 2, (unsigned long long)n_spill);
+    atomicMax(reinterpret_cast<unsigned long long*>(P.counters) + 3, (unsigned long long)st.peak);
   }
   (void)batch;
 }

@@ -129,3 +129,75 @@ def check_all(hits: np.ndarray, inst: np.ndarray | None, counts: np.ndarray, C, 
         exact += int(C.n_sure[r] == C.count[r])
     return {"rays": n, "hits": int(counts.sum()), "max_count": int(counts.max()) if n else 0,
             "all_sure_frac": exact / max(n, 1)}
+
+
+
+def _sub_opts(orc, opts, idx):
+    """Query options restricted to the rays idx (instance masks kept)."""
+    if opts is None:
+        return None
+    a = opts._a
+    pick = lambda x: None if x is None else x[idx]
+    return orc.Opts(a[0], pick(a[1]), pick(a[2]), pick(a[3]))
+
+
+def check_chunked(orc, S, rays, hits=None, inst=None, occ=None, opts=None, chunk: int = 1 << 20,
+                  K: int = 8, label: str = ""):
+    """check_closest (hits, inst) and/or check_any (occ) on every ray, in
+    chunks of `chunk` rays; rays whose acceptable set does not fit K entries
+    are classified again with a K that holds it, so no ray is left
+    unverifiable.  ``opts``: oracle query options of all rays.  Returns the
+    summed statistics."""
+    n = rays.shape[0]
+    tally = Tally()
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        idx_all = np.arange(lo, hi)
+        A = orc.accept(S, rays[lo:hi], K=K, opts=_sub_opts(orc, opts, idx_all))
+        ovf = np.flatnonzero(A.overflow)
+        ok = np.flatnonzero(~A.overflow)
+        parts = [(ok, A.subset(ok) if len(ovf) else A)]
+        if len(ovf):
+            k2 = int(A.count[ovf].max())
+            B = orc.accept(S, rays[lo + ovf], K=k2, opts=_sub_opts(orc, opts, lo + ovf))
+            assert not B.overflow.any()
+            parts.append((ovf, B))
+        for rows, AA in parts:
+            if len(rows) == 0:
+                continue
+            if hits is not None:
+                tally.closest(check_closest(hits[lo + rows], AA, None if inst is None else inst[lo + rows],
+                                            label=f"{label} [{lo},{hi})"))
+            if occ is not None:
+                tally.any(check_any(occ[lo + rows], AA, label=f"{label} any [{lo},{hi})"))
+    return tally.summary()
+
+
+class Tally:
+    """Sums of the per-chunk statistics of check_closest / check_any."""
+
+    def __init__(self):
+        self.rays = self.hits = self.pinned = self.occluded = self.decided = self.any_rays = 0
+        self.max_dt_rel = self.max_duv = 0.0
+
+    def closest(self, st):
+        self.rays += st["rays"]
+        self.hits += st["hits"]
+        self.pinned += round(st["pinned_frac"] * st["rays"])
+        self.max_dt_rel = max(self.max_dt_rel, st["max_dt_rel"])
+        self.max_duv = max(self.max_duv, st["max_duv"])
+
+    def any(self, st):
+        self.any_rays += st["rays"]
+        self.occluded += st["occluded"]
+        self.decided += round(st["decided"] * st["rays"])
+
+    def summary(self):
+        out = {}
+        if self.rays:
+            out.update(rays=self.rays, hits=self.hits, pinned_frac=self.pinned / self.rays,
+                       max_dt_rel=self.max_dt_rel, max_duv=self.max_duv)
+        if self.any_rays:
+            out.update(any_rays=self.any_rays, occluded=self.occluded,
+                       any_decided_frac=self.decided / self.any_rays)
+        return out
