@@ -221,6 +221,24 @@ rt_status rt_accel_get_info(rt_accel accel, rt_accel_info* out);
 rt_status rt_trace_closest(rt_accel accel, const rt_ray* rays, uint32_t n, rt_hit* hits,
                            uint32_t* inst_ids, void* stream);
 
+/* rt_trace_closest for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same kernels and bit-identical results, but
+ * the launch's scratch (ray-queue counters, the per-wave ray-range lists of
+ * the float64 finalize and the global spill stack) lives in a fixed device
+ * array of RT_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it
+ * runs on until the process ends; the call allocates nothing.  The grid is
+ * narrowed when the spill stack of a full grid would not fit.  Every call on
+ * a GPU shares that GPU's array: calls that overlap on one GPU (from
+ * different contexts, or on streams the caller does not order) race and
+ * must not be issued; calls of one context are ordered as usual.
+ * Errors: as rt_trace_closest, and RT_ERROR_INVALID_VALUE when n rays need
+ * more scratch than the array holds (about 2^28 rays at the default refill
+ * setting). */
+#define RT_NOALLOC_SCRATCH_BYTES (64u << 20)
+rt_status rt_trace_closest_noalloc(rt_accel accel, const rt_ray* rays, uint32_t n, rt_hit* hits,
+                                   uint32_t* inst_ids, void* stream);
+
 /* Any hit (§4.2: stop at the first hit found within the ray's length):
  * occluded[i] (device, n bytes) = 1 when some triangle is hit with
  * t in [tmin, tmax], else 0. */

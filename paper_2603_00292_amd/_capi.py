@@ -21,12 +21,14 @@ RT_ERROR_UNSUPPORTED = 5
 RT_ERROR_INDEX_OUT_OF_RANGE = 6
 RT_ERROR_STACK_OVERFLOW = 7
 RT_INVALID_ID = 0xFFFFFFFF
+RT_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTS = [
     "rt_context_create", "rt_context_destroy", "rt_context_set_variant", "rt_context_get_variant",
     "rt_context_set_timing", "rt_context_read_timing",
     "rt_build", "rt_accel_destroy", "rt_accel_get_info",
-    "rt_trace_closest", "rt_trace_any", "rt_trace_backward", "rt_trace_backward_instances",
+    "rt_trace_closest", "rt_trace_closest_noalloc", "rt_trace_any", "rt_trace_backward",
+    "rt_trace_backward_instances",
     "rt_trace_closest_ex", "rt_trace_any_ex", "rt_trace_all", "rt_accel_set_instance_masks", "rt_update_instances",
     "rt_ao_rays", "rt_ao_rays_instances", "rt_ao_resolve",
     "rt_trace_counters", "rt_refit",
@@ -111,6 +113,7 @@ def load():
             "rt_accel_destroy": [P],
             "rt_accel_get_info": [P, P],
             "rt_trace_closest": [P, P, U32, P, P, P],
+            "rt_trace_closest_noalloc": [P, P, U32, P, P, P],
             "rt_trace_any": [P, P, U32, P, P],
             "rt_trace_backward": [P, P, P, P, U32, P, P, P, P],
             "rt_trace_backward_instances": [P, P, P, P, P, U32, P, P, P, P, P],

@@ -182,6 +182,20 @@ def trace_closest(accel: Accel, rays: torch.Tensor, want_inst: bool = False):
     return hits, inst
 
 
+def trace_closest_noalloc(accel: Accel, rays: torch.Tensor, hits: torch.Tensor,
+                          inst: torch.Tensor | None = None) -> None:
+    """rt_trace_closest_noalloc into caller-provided outputs (hits (n,4)
+    float32, inst (n,) int32 or None): the library allocates nothing."""
+    _require(rays, "rays", torch.float32, 8)
+    n = rays.shape[0]
+    _require(hits, "hits", torch.float32, 4)
+    if hits.shape[0] != n or (inst is not None and (inst.shape != (n,) or inst.dtype != torch.int32
+                                                     or not inst.is_contiguous())):
+        raise ValueError("hits must be (n,4) float32 and inst (n,) int32, contiguous")
+    capi.call("rt_trace_closest_noalloc", accel.handle, _ptr(rays), n, _ptr(hits), _ptr(inst),
+              C.c_void_p(_stream()))
+
+
 def _u32_vec(t, n, name):
     if t is None:
         return None

@@ -254,6 +254,43 @@ rt_status check_device(int dev) {
   return RT_SUCCESS;
 }
 
+// Scratch of rt_trace_closest_noalloc.  Every GPU the library runs on holds
+// its own copy of this array until the process ends; host code reaches a
+// GPU's copy only through the address hipGetSymbolAddress returns with that
+// GPU current (noalloc_setup), never through the array's name.
+constexpr size_t kNoAllocWords = RT_NOALLOC_SCRATCH_BYTES / sizeof(uint32_t);
+constexpr int kNoAllocMaxDevices = 64;
+std::mutex g_noalloc_mu;
+uint32_t* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) uint32_t scratch[kNoAllocWords];
+
+namespace {
+
+// With device `dev` current: finds the address of that device's copy of the
+// no-alloc scratch (once per device; called by rt_context_create).
+rt_status noalloc_setup(int dev) {
+  if (dev < 0 || dev >= kNoAllocMaxDevices)
+    return fail(RT_ERROR_UNSUPPORTED, "rt_context_create: device id %d >= %d", dev, kNoAllocMaxDevices);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[dev]) return RT_SUCCESS;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(RT_ERROR_HIP, "rt_context_create: hipGetSymbolAddress of the no-alloc scratch: %s",
+                hipGetErrorString(e));
+  g_noalloc_ptr[dev] = static_cast<uint32_t*>(ptr);
+  return RT_SUCCESS;
+}
+
+uint32_t* noalloc_ptr(int dev) {
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  return g_noalloc_ptr[dev];
+}
+
 // Reports (and clears) a stack overflow flagged by an earlier traversal on
 // this context.  The flag is written by the device into host-mapped memory;
 // a launch still running when this is read is reported by a later call.
@@ -324,6 +361,13 @@ rt_status rt_context_create(int hip_device, rt_context* out) {
     return fail(RT_ERROR_OUT_OF_MEMORY, "rt_context_create: hipHostMalloc of the status word failed");
   }
   *reinterpret_cast<volatile uint32_t*>(c->status) = 0u;
+  rt_status ns = noalloc_setup(hip_device);
+  if (ns != RT_SUCCESS) {
+    (void)hipHostFree(c->status);
+    (void)hipEventDestroy(c->last_event);
+    delete c;
+    return ns;
+  }
   *out = c;
   return ok();
 }
@@ -1089,13 +1133,21 @@ static uint32_t cached_resident(rt_context ctx, const void* kern, int wg) {
   return b;
 }
 
+// As cached_resident, without adding to the cache (no host allocation).
+static uint32_t peek_resident(rt_context ctx, const void* kern, int wg) {
+  if (ctx->blocks_per_cu) return ctx->blocks_per_cu * (uint32_t)std::max(ctx->cu_count, 1);
+  for (auto& e : ctx->occupancy)
+    if (e.first == kern) return e.second;
+  return resident_blocks(kern, wg, ctx->cu_count);
+}
+
 // mode 0: plain query; 2: with query options; 3: all hits (options, lists of
 // `cap` entries and per-ray counts)
 static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit* hits,
                               uint32_t* inst_ids, uint8_t* occ, bool any, hipStream_t s,
                               uint64_t* counters = nullptr, int mode = 0,
                               const rt_query_options* opts = nullptr, uint32_t* counts = nullptr,
-                              uint32_t cap = 0) {
+                              uint32_t cap = 0, bool noalloc = false) {
   rt_context ctx = a->ctx;
   rt_status st = check_device(a->device);
   if (st != RT_SUCCESS) return st;
@@ -1109,12 +1161,49 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
                                                  any, a->two_level, mode);
   if (!kern) return fail(RT_ERROR_UNSUPPORTED, "trace: variant not compiled");
   uint32_t wg = v.workgroup;
-  uint32_t blocks = std::min<uint32_t>((n + wg - 1) / wg, cached_resident(ctx, kern, (int)wg));
-  blocks = std::max(blocks, 1u);
-  uint32_t gstride = blocks * wg;
+  uint32_t resident = noalloc ? peek_resident(ctx, kern, (int)wg) : cached_resident(ctx, kern, (int)wg);
+  uint32_t blocks = std::max(std::min<uint32_t>((n + wg - 1) / wg, resident), 1u);
   size_t spill = a->max_stack > v.stack_entries ? (size_t)(a->max_stack - v.stack_entries) : 1;
-  st = ensure_scratch(ctx->scratch, spill * gstride);
-  if (st != RT_SUCCESS) return st;
+  const bool fused = !counters && rtk_trace_fuses_finalize(any, a->two_level, mode);
+  uint32_t* counter = nullptr;
+  uint32_t* gstack = nullptr;
+  uint32_t* ranges = nullptr;
+  uint32_t* ovf = nullptr;
+  uint32_t ovf_cap = 0;
+  if (noalloc) {
+    // the fixed array: 64 counter words, then (fused finalize) the per-wave
+    // range lists and the overflow list, then the spill stack; the grid is
+    // narrowed until they fit
+    uint32_t* base = noalloc_ptr(a->device);
+    if (!base) return fail(RT_ERROR_HIP, "rt_trace_closest_noalloc: no scratch on device %d", a->device);
+    size_t cap_pairs = (size_t)n / std::max<uint32_t>(1u, std::min<uint32_t>(ctx->refill_min, 64u)) + 1;
+    size_t fixed = 64 + (fused ? 2 * cap_pairs : 0);
+    size_t per_block = (fused ? (size_t)(wg / 64u) * 2 * kRtRangesPerWave : 0) + spill * wg;
+    if (fixed + per_block > kNoAllocWords)
+      return fail(RT_ERROR_INVALID_VALUE,
+                  "rt_trace_closest_noalloc: %u rays with a stack bound of %u need more than the %u-byte "
+                  "scratch", n, a->max_stack, (unsigned)RT_NOALLOC_SCRATCH_BYTES);
+    blocks = (uint32_t)std::min<size_t>(blocks, (kNoAllocWords - fixed) / per_block);
+    counter = base;
+    if (fused) {
+      ranges = base + 64;
+      ovf = ranges + (size_t)blocks * (wg / 64u) * 2 * kRtRangesPerWave;
+      ovf_cap = (uint32_t)cap_pairs;
+      gstack = ovf + 2 * cap_pairs;
+    } else {
+      gstack = base + 64;
+    }
+  } else {
+    st = ensure_scratch(ctx->scratch, spill * (size_t)blocks * wg);
+    if (st != RT_SUCCESS) return st;
+    counter = ctx->scratch.counter;
+    gstack = ctx->scratch.gstack;
+    if (fused) {
+      st = ensure_ranges(ctx->scratch, blocks * wg, n, ctx->refill_min, &ranges, &ovf, &ovf_cap);
+      if (st != RT_SUCCESS) return st;
+    }
+  }
+  uint32_t gstride = blocks * wg;
   if (ctx->has_last && ctx->last_stream != s) RT_HIP(hipStreamWaitEvent(s, ctx->last_event, 0));
   TraceParams p{};
   p.nodes = a->nodes;
@@ -1126,8 +1215,8 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   p.hits = hits;
   p.inst_ids = inst_ids;
   p.occluded = occ;
-  p.counter = ctx->scratch.counter;
-  p.gstack = ctx->scratch.gstack;
+  p.counter = counter;
+  p.gstack = gstack;
   p.root = a->root;
   p.n = n;
   p.max_stack = ctx->stack_limit ? std::min(a->max_stack, ctx->stack_limit) : a->max_stack;
@@ -1142,12 +1231,10 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   }
   p.counts = counts;
   p.cap = cap;
-  const bool fused = !counters && rtk_trace_fuses_finalize(any, a->two_level, mode);
-  if (fused) {
-    st = ensure_ranges(ctx->scratch, gstride, n, ctx->refill_min, &p.ranges, &p.ovf, &p.ovf_cap);
-    if (st != RT_SUCCESS) return st;
-  }
-  RT_HIP(rtk_launch_fill(ctx->scratch.counter, 2, 0u, s));
+  p.ranges = ranges;
+  p.ovf = ovf;
+  p.ovf_cap = ovf_cap;
+  RT_HIP(rtk_launch_fill(counter, 2, 0u, s));
   size_t tslot = ctx->tbeg.empty() ? 0 : (size_t)(ctx->trecorded % ctx->tbeg.size());
   if (!ctx->tbeg.empty()) RT_HIP(hipEventRecord(ctx->tbeg[tslot], s));
   RT_HIP(rtk_launch_trace(kern, blocks, wg, p, s));
@@ -1177,6 +1264,18 @@ rt_status rt_trace_closest(rt_accel accel, const rt_ray* rays, uint32_t n, rt_hi
   if (!aligned16(rays) || !aligned16(hits))
     return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest: rays and hits must be 16-byte aligned");
   return launch_trace(accel, rays, n, hits, inst_ids, nullptr, false, static_cast<hipStream_t>(stream));
+}
+
+rt_status rt_trace_closest_noalloc(rt_accel accel, const rt_ray* rays, uint32_t n, rt_hit* hits,
+                                   uint32_t* inst_ids, void* stream) {
+  if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest_noalloc: NULL accel");
+  if (n == 0) return ok();
+  if (!rays || !hits) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest_noalloc: NULL buffer with n > 0");
+  if (n > 0x7FFFFFFFu) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest_noalloc: n >= 2^31");
+  if (!aligned16(rays) || !aligned16(hits))
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_closest_noalloc: rays and hits must be 16-byte aligned");
+  return launch_trace(accel, rays, n, hits, inst_ids, nullptr, false, static_cast<hipStream_t>(stream),
+                      nullptr, 0, nullptr, nullptr, 0, true);
 }
 
 rt_status rt_trace_any(rt_accel accel, const rt_ray* rays, uint32_t n, uint8_t* occluded,
