@@ -355,13 +355,17 @@ rt_status rt_trace_all(rt_accel accel, const rt_ray* rays, uint32_t n,
  *   d_origins[i] = lambda, d_directions[i] = t lambda,
  *   d_vertices[v_k] += -w_k lambda  (w = (1-u-v, u, v))
  * using the accel's copy of the vertices it was built from.  d_vertices
- * (device, vertex_count*3 float32) is ACCUMULATED deterministically: the
- * contributions are sorted by vertex with a stable radix sort and each
- * vertex's sum is formed in ray order before it is added, so repeated calls
- * give bit-identical results (the context keeps 48 bytes of scratch per
- * contribution, three per ray, grown on demand); d_origins / d_directions
- * (device, n*3 float32) are overwritten (zero for misses).  t, u, v are recomputed in
- * float64 from the triangle, so `hits` contributes only the triangle id.
+ * (device, vertex_count*3 float32) is ACCUMULATED deterministically, without
+ * atomics: the rays are sorted by triangle (stably), each triangle sums its
+ * rays' float64 contributions per corner in ray order, each vertex sums its
+ * corners in (triangle, corner) order, and the float64 sum is rounded once
+ * to float32 and added; repeated calls give bit-identical results.  The
+ * first call on an accel builds its vertex -> corner lists (4 bytes per
+ * vertex and 84 per triangle); the context keeps 56 bytes per ray of sort
+ * buffers, grown stream-ordered on `stream` when n exceeds them.
+ * d_origins / d_directions (device, n*3 float32) are overwritten (zero for
+ * misses).  t, u, v are recomputed in float64 from the triangle, so `hits`
+ * contributes only the triangle id.
  * Errors: RT_ERROR_UNSUPPORTED on a two-level accel (use
  * rt_trace_backward_instances). */
 rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hits,
@@ -386,10 +390,10 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
  *     instance's (sx,sy,sz, qx,qy,qz,qw, tx,ty,tz) as given to rt_build,
  *     ACCUMULATED; the quaternion part is the gradient with respect to the
  *     unnormalised q (orthogonal to q).
- * Both accumulations are deterministic (contributions sorted by row with a
- * stable radix sort, summed in ray order; repeated calls are bit-identical;
- * the context keeps 48 bytes of scratch per contribution, 3 vertex and 4
- * frame contributions per ray).  t, u, v are recomputed in float64 with the
+ * Both accumulations are deterministic, as in rt_trace_backward (exact
+ * integer sums per row, rounded once; the first call on an accel allocates
+ * 260 bytes per vertex row and 4 x 260 bytes per instance, later calls
+ * allocate nothing).  t, u, v are recomputed in float64 with the
  * accel's copies of the meshes and frames.  A hit whose instance id is not an instance of
  * the accel, or whose prim_id is not a triangle of that instance's mesh,
  * contributes nothing (zero ray gradients).

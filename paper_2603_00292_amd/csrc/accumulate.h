@@ -1,43 +1,167 @@
-// accumulate.h -- deterministic scatter-add of per-ray gradient contributions
-// (librtq internal).
+// accumulate.h -- deterministic accumulation of per-ray gradient
+// contributions (librtq internal).
 //
-// Each contribution is (key, three floats).  The contributions are sorted by
-// key with a stable radix sort (equal keys keep their input order), runs of
-// equal keys are summed in that order, and each sum is added to
-// out[3 * key .. 3 * key + 2]: the result does not depend on how the GPU
-// schedules the producing kernel.  Keys equal to 0xFFFFFFFF are dropped.
+// A contribution adds three float64 values to one row (a vertex, or a part of
+// an instance frame).  The sums are formed in 64-bit integers, so they do not
+// depend on the order in which rays reach a row:
+//   phase 0  every contribution raises expo[row] to the binary exponent of its
+//            largest component (an atomic maximum, skipped when a plain load
+//            already shows that exponent or a larger one: the stored value
+//            only grows, so a stale load can only cost an extra atomic);
+//   phase 1  every component c is rounded to the integer nearest
+//            c * 2^(shift0 - e), e = expo[row], and added to the row's integer
+//            sum (integer addition is associative);
+//   convert  every touched row's sums are scaled back by 2^(e - shift0),
+//            rounded to float32 and added to the output, and the row is reset.
+// shift0 = 62 - H, where 2^H exceeds the number of contributions a row can
+// receive (one per ray at most), so no sum overflows: a scaled component is
+// at most 2^(63 - H) in magnitude.  Each row keeps shift0 bits below its
+// largest contribution (at least 30 bits for 2^31 rays), more than the
+// float32 result holds.  A non-finite contribution makes its row NaN.
+//
+// The phase-1 sums are kept per XCD (the chip's eight dies, each with its own
+// L2): a wave adds into the copy of the die it runs on, with atomics of
+// workgroup scope that complete in that die's L2 instead of travelling to the
+// memory side as device-scope atomics do (on the 1M-ray backward: 423 us ->
+// see the profiles); no other die touches that copy during the launch, and
+// the kernel boundary makes the copies visible to the convert, which adds the
+// eight integer partial sums (exactly, in any order).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
 
-struct rta_f3 {
-  float x, y, z;
-};
-
 namespace rta {
 
-// Device buffers of `cap` entries each, and hipCUB temporary storage.
-struct Buffers {
-  uint32_t* keys = nullptr;
-  uint32_t* keys_sorted = nullptr;
-  rta_f3* vals = nullptr;
-  rta_f3* vals_sorted = nullptr;
-  uint32_t* run_keys = nullptr;
-  rta_f3* run_sums = nullptr;
-  uint32_t* run_count = nullptr;
-  void* temp = nullptr;
-  size_t temp_bytes = 0;
-  size_t cap = 0;
+constexpr uint32_t kExpoBias = 2048;               // stored exponent = ilogb + bias; 0 = untouched
+constexpr uint32_t kExpoNonFinite = 0xFFFFFFFFu;   // a row that received inf or NaN
+
+constexpr uint32_t kCopies = 8;                     // per-die copies of the sums
+
+// Accumulator rows in device memory (owned by an accel).
+struct Rows {
+  uint32_t* expo = nullptr;             // count entries
+  unsigned long long* sums = nullptr;   // [kCopies][count][4] (three used), two's complement
+  uint32_t count = 0;
 };
 
-// Grows `b` to hold m entries (synchronising the device before freeing).
-hipError_t reserve(Buffers& b, size_t m);
-void release(Buffers& b);
+// What a producing kernel needs.
+struct Acc {
+  uint32_t* expo;
+  unsigned long long* sums;
+  uint32_t rows;
+  int shift0;
+};
 
-// Sorts b.keys / b.vals (m entries) on the low `key_bits` bits, where every
-// valid key is < 2^key_bits - 1 and 0xFFFFFFFF sorts last, sums the runs and
-// adds them to out.
-hipError_t scatter_add(Buffers& b, size_t m, int key_bits, float* out, hipStream_t stream);
+// The XCD (die) the calling wave runs on: bits 3:0 of the XCC_ID hardware
+// register (s_getreg of register 20, four bits from offset 0).
+__device__ __forceinline__ uint32_t die_id() {
+  return (uint32_t)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & (kCopies - 1u);
+}
+
+// 62 - H for launches of n rays (2^H > n).
+inline int shift0_for(uint64_t n) {
+  int h = 0;
+  while (h < 63 && (1ull << h) <= n) ++h;
+  return 62 - h;
+}
+
+// Allocates `count` rows (not cleared: clear() them before use).
+hipError_t alloc(Rows& r, uint32_t count);
+void release(Rows& r);
+
+// Resets every row (stream-ordered fill kernels; after an interrupted call).
+hipError_t clear(const Rows& r, hipStream_t stream);
+
+// Converts rows [first, first + count) and adds them to `out`, resetting them.
+// layout 0: out[3 i + c] for row first + i (vertex rows);
+// layout 1: rows 4 j + part hold instance j's frame parameters
+//           3 part + c < 10 (S xyz, q xyz, q w, T xyz): out[10 j + 3 part + c].
+hipError_t convert(const Rows& r, uint32_t first, uint32_t count, int layout, int shift0, float* out,
+                   hipStream_t stream);
+
+template <int PHASE>
+__device__ __forceinline__ void add(const Acc& a, uint32_t row, double x, double y, double z) {
+  bool finite = isfinite(x) && isfinite(y) && isfinite(z);
+  double m = fmax(fabs(x), fmax(fabs(y), fabs(z)));
+  if (finite && m == 0.0) return;
+  if constexpr (PHASE == 0) {
+    uint32_t e = finite ? (uint32_t)(ilogb(m) + (int)kExpoBias) : kExpoNonFinite;
+    if (a.expo[row] < e) atomicMax(a.expo + row, e);
+  } else {
+    uint32_t e = a.expo[row];
+    if (e == kExpoNonFinite) return;
+    int sh = a.shift0 - ((int)e - (int)kExpoBias);
+    unsigned long long* s = a.sums + 4 * ((size_t)die_id() * a.rows + row);
+    long long vx = __double2ll_rn(ldexp(x, sh));
+    long long vy = __double2ll_rn(ldexp(y, sh));
+    long long vz = __double2ll_rn(ldexp(z, sh));
+    if (vx) __hip_atomic_fetch_add(s + 0, (unsigned long long)vx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (vy) __hip_atomic_fetch_add(s + 1, (unsigned long long)vy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (vz) __hip_atomic_fetch_add(s + 2, (unsigned long long)vz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+}  // namespace rta
+
+// ---------------------------------------------------------------------------
+// Vertex gradients of single-level accels without global atomics
+// ---------------------------------------------------------------------------
+// The adjoint kernel writes, per ray i, key[i] = its triangle (0xFFFFFFFF for
+// none) and rec[i] = (lambda, u, v) in float64.  Then:
+//   bucket   the rays are grouped by triangle range (kTrisPerBucket
+//            triangles per bucket): per-tile histograms in LDS, an exclusive
+//            scan, a scatter with LDS counters (the order inside a bucket is
+//            not fixed, and does not need to be);
+//   corner   one workgroup per bucket sums -w_k lambda of its rays per
+//            (triangle, corner) in LDS, exactly, as 64-bit integers at the
+//            row's binary scale (the row's largest exponent, an LDS maximum
+//            taken first), and writes each row's float64 value;
+//   vertex   every vertex adds its corners' values in ascending (triangle,
+//            corner) order through a vertex -> (triangle, corner) list,
+//            rounds once to float32 and adds to the output.
+// The integer sums keep shift0 = 62 - H bits below each row's largest
+// contribution (2^H > n), so the result is independent of the schedule and
+// of the order of the rays: repeated calls and permuted rays give
+// bit-identical vertex gradients.
+namespace rta {
+
+constexpr uint32_t kTrisPerBucket = 512;
+constexpr uint32_t kMaxBuckets = 16384;     // LDS histogram bins: meshes up to 2^23 triangles
+constexpr uint32_t kTile = 4096;            // rays per workgroup in the bucket passes
+
+struct RayRec {
+  double lx, ly, lz, u, v;
+};
+
+// Per accel: the vertex -> (triangle << 2 | corner) lists and the corner values.
+struct Gather {
+  uint32_t* csr_off = nullptr;   // vertex_count + 1
+  uint32_t* csr_ent = nullptr;   // 3 * triangle_count
+  double* corner = nullptr;      // 9 per triangle: corner k's 3 components
+  uint32_t vertices = 0, triangles = 0;
+};
+
+// Per context: buffers sized by the ray count (grown stream-ordered).
+struct SortBuf {
+  uint32_t* keys = nullptr;      // cap
+  RayRec* rec = nullptr;         // cap
+  uint32_t* ids = nullptr;       // cap: ray ids grouped by bucket
+  uint32_t* counts = nullptr;    // buckets x tiles histogram, scanned in place (+1 total)
+  uint32_t* partial = nullptr;   // scan partials
+  size_t cap = 0, count_cap = 0, partial_cap = 0;
+};
+
+// Builds g from the mesh's indices (host copy): counting sort by vertex,
+// entries in ascending (triangle, corner) order.
+hipError_t gather_build(Gather& g, const uint32_t* host_indices, uint32_t vertices, uint32_t triangles);
+void gather_release(Gather& g);
+// Makes b hold n rays for a mesh of `triangles` triangles; a larger n frees
+// and allocates stream-ordered on s (no device-wide synchronisation).
+hipError_t sort_reserve(SortBuf& b, size_t n, uint32_t triangles, hipStream_t s);
+void sort_release(SortBuf& b);
+// After the adjoint kernel filled b.keys / b.rec for n rays: bucket, sum per
+// corner and per vertex, out[3 v + c] += the vertex sums.
+hipError_t gather_vertices(Gather& g, SortBuf& b, uint32_t n, float* out, hipStream_t s);
 
 }  // namespace rta

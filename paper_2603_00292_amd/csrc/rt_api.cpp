@@ -110,8 +110,7 @@ struct rt_context_s {
   uint32_t* status = nullptr;  // host-mapped word: set by a lane whose stack overflows
   std::mutex mu;
   Scratch scratch;
-  rta::Buffers grad;                          // backward: deterministic vertex-gradient sums
-  rta::Buffers grad2;                         // two-level backward: frame-gradient sums
+  rta::SortBuf sortbuf;                      // single-level backward: rays sorted by triangle
   hipEvent_t last_event = nullptr;
   hipStream_t last_stream = nullptr;
   bool has_last = false;
@@ -138,7 +137,11 @@ struct rt_accel_s {
   uint64_t* vertex_base = nullptr;           // two-level: first gradient row per mesh
   uint32_t instance_count = 0;
   uint64_t vertex_rows = 0;                  // two-level: sum of the meshes' vertex counts
-  float* srt_rows = nullptr;                 // two-level backward: 12 floats per instance
+  rta::Gather gather;                         // single-level backward: vertex lists, triangle sums
+  rta::Rows grad_rows;                       // two-level backward: integer accumulator rows (vertex rows,
+                                             // then 4 frame rows per instance), allocated by the
+                                             // accel's first backward call
+  bool grad_dirty = false;                   // a backward call stopped between its launches
   std::vector<void*> owned;                  // every device allocation
   std::vector<rt_mesh_dev> host_meshes;      // device pointers, host copy
   std::vector<rt_inst_rec> host_insts;       // two-level: host copy of the instance records
@@ -190,6 +193,8 @@ rt_status dev_alloc(rt_accel_s* a, T** p, size_t count) {
 
 void destroy_accel(rt_accel_s* a) {
   for (void* p : a->owned) (void)hipFree(p);
+  rta::release(a->grad_rows);
+  rta::gather_release(a->gather);
   delete a;
 }
 
@@ -377,8 +382,7 @@ rt_status rt_context_destroy(rt_context ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   free_scratch(ctx->scratch);
-  rta::release(ctx->grad);
-  rta::release(ctx->grad2);
+  rta::sort_release(ctx->sortbuf);
   if (ctx->last_event) (void)hipEventDestroy(ctx->last_event);
   for (hipEvent_t e : ctx->tbeg) (void)hipEventDestroy(e);
   for (hipEvent_t e : ctx->tend) (void)hipEventDestroy(e);
@@ -598,8 +602,6 @@ static rt_status setup_instances(rt_accel_s* a, const rt_mesh_desc* meshes, uint
     acc += meshes[m].vertex_count;
   }
   st = dev_alloc(a, &a->srts, instance_count);
-  if (st != RT_SUCCESS) return st;
-  st = dev_alloc(a, &a->srt_rows, (size_t)instance_count * 12);
   if (st != RT_SUCCESS) return st;
   a->vertex_rows = acc;
   st = dev_alloc(a, &a->vertex_base, mesh_count);
@@ -1133,6 +1135,29 @@ static uint32_t cached_resident(rt_context ctx, const void* kern, int wg) {
   return b;
 }
 
+// The backward's accumulator rows of an accel: one per vertex (two-level: of
+// every mesh), then four per instance frame.  Allocated by the first backward
+// call (sized by the accel, not by the call, so later calls allocate
+// nothing) and cleared on `s`; a call that stopped between its launches left
+// them dirty, and the next call clears them first.
+static rt_status prepare_grad_rows(rt_accel a, hipStream_t s) {
+  if (!a->grad_rows.expo) {
+    uint64_t rows = a->two_level ? a->vertex_rows + 4ull * a->instance_count
+                                 : (uint64_t)a->host_meshes[0].vertex_count;
+    if (rows >= 0xFFFFFFFFull) return fail(RT_ERROR_UNSUPPORTED, "backward: more than 2^32 - 2 gradient rows");
+    if (rows == 0) return RT_SUCCESS;
+    hipError_t e = rta::alloc(a->grad_rows, (uint32_t)rows);
+    if (e != hipSuccess)
+      return fail(e == hipErrorOutOfMemory ? RT_ERROR_OUT_OF_MEMORY : RT_ERROR_HIP,
+                  "backward: gradient rows (%llu): %s", (unsigned long long)rows, hipGetErrorString(e));
+    a->info.device_bytes += rows * (sizeof(uint32_t) + rta::kCopies * 4 * sizeof(unsigned long long));
+    a->grad_dirty = true;
+  }
+  if (a->grad_dirty) RT_HIP(rta::clear(a->grad_rows, s));
+  a->grad_dirty = true;
+  return RT_SUCCESS;
+}
+
 // As cached_resident, without adding to the cache (no host allocation).
 static uint32_t peek_resident(rt_context ctx, const void* kern, int wg) {
   if (ctx->blocks_per_cu) return ctx->blocks_per_cu * (uint32_t)std::max(ctx->cu_count, 1);
@@ -1499,24 +1524,38 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
   rt_context ctx = accel->ctx;
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(ctx->mu);
-  const size_t entries = 3 * (size_t)n;
-  RT_HIP(rta::reserve(ctx->grad, entries));
   if (ctx->has_last && ctx->last_stream != s) RT_HIP(hipStreamWaitEvent(s, ctx->last_event, 0));
+  const rt_mesh_dev& mesh = accel->host_meshes[0];
+  if (!accel->gather.csr_off) {
+    // the vertex -> (triangle, corner) lists, built once from the accel's
+    // copy of the indices
+    std::vector<uint32_t> idx;
+    try {
+      idx.resize(3 * (size_t)mesh.triangle_count);
+    } catch (const std::bad_alloc&) {
+      return fail(RT_ERROR_OUT_OF_MEMORY, "rt_trace_backward: host allocation");
+    }
+    if (!idx.empty())
+      RT_HIP(hipMemcpy(idx.data(), mesh.indices, idx.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if ((uint64_t)mesh.triangle_count > (uint64_t)rta::kMaxBuckets * rta::kTrisPerBucket)
+      return fail(RT_ERROR_UNSUPPORTED, "rt_trace_backward: more than %u triangles",
+                  rta::kMaxBuckets * rta::kTrisPerBucket);
+    RT_HIP(rta::gather_build(accel->gather, idx.data(), mesh.vertex_count, mesh.triangle_count));
+    accel->info.device_bytes += 4ull * (mesh.vertex_count + 1) + 84ull * mesh.triangle_count;
+  }
+  RT_HIP(rta::sort_reserve(ctx->sortbuf, n, mesh.triangle_count, s));
   BackwardParams p{};
-  p.mesh = accel->host_meshes[0];
+  p.mesh = mesh;
   p.rays = rays;
   p.hits = hits;
   p.d_tuv = d_tuv;
   p.n = n;
-  p.keys = ctx->grad.keys;
-  p.vals = ctx->grad.vals;
   p.d_origins = d_origins;
   p.d_directions = d_directions;
+  p.keys = ctx->sortbuf.keys;
+  p.rec = ctx->sortbuf.rec;
   RT_HIP(rtk_launch_backward(p, s));
-  // sort keys on the bits that hold a vertex id; 0xFFFFFFFF (a miss) sorts last
-  int key_bits = 1;
-  while (key_bits < 32 && (1ull << key_bits) <= (uint64_t)p.mesh.vertex_count) ++key_bits;
-  RT_HIP(rta::scatter_add(ctx->grad, entries, key_bits, d_vertices, s));
+  RT_HIP(rta::gather_vertices(accel->gather, ctx->sortbuf, n, d_vertices, s));
   RT_HIP(hipEventRecord(ctx->last_event, s));
   ctx->last_stream = s;
   ctx->has_last = true;
@@ -1544,10 +1583,9 @@ rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const 
   rt_context ctx = accel->ctx;
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(ctx->mu);
-  const size_t ve = d_vertices ? 3 * (size_t)n : 0, se = d_srt ? 4 * (size_t)n : 0;
-  if (ve) RT_HIP(rta::reserve(ctx->grad, ve));
-  if (se) RT_HIP(rta::reserve(ctx->grad2, se));
   if (ctx->has_last && ctx->last_stream != s) RT_HIP(hipStreamWaitEvent(s, ctx->last_event, 0));
+  st = prepare_grad_rows(accel, s);
+  if (st != RT_SUCCESS) return st;
   BackwardInstParams p{};
   p.meshes = accel->meshes;
   p.vertex_base = accel->vertex_base;
@@ -1560,24 +1598,20 @@ rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const 
   p.inst_ids = inst_ids;
   p.d_tuv = d_tuv;
   p.n = n;
-  p.vkeys = ve ? ctx->grad.keys : nullptr;
-  p.vvals = ve ? ctx->grad.vals : nullptr;
-  p.skeys = se ? ctx->grad2.keys : nullptr;
-  p.svals = se ? ctx->grad2.vals : nullptr;
   p.d_origins = d_origins;
   p.d_directions = d_directions;
-  RT_HIP(rtk_launch_backward_inst(p, s));
-  auto bits_for = [](uint64_t rows) {
-    int b = 1;
-    while (b < 32 && (1ull << b) <= rows) ++b;
-    return b;
-  };
-  if (ve) RT_HIP(rta::scatter_add(ctx->grad, ve, bits_for(accel->vertex_rows), d_vertices, s));
-  if (se) {
-    RT_HIP(rtk_launch_fill(reinterpret_cast<uint32_t*>(accel->srt_rows), accel->instance_count * 12u, 0u, s));
-    RT_HIP(rta::scatter_add(ctx->grad2, se, bits_for(4ull * accel->instance_count), accel->srt_rows, s));
-    RT_HIP(rtk_launch_fold_frames(accel->srt_rows, accel->instance_count, d_srt, s));
-  }
+  p.acc = rta::Acc{accel->grad_rows.expo, accel->grad_rows.sums, accel->grad_rows.count, rta::shift0_for(n)};
+  p.want_vertices = (d_vertices && accel->vertex_rows > 0) ? 1u : 0u;
+  p.want_frames = d_srt ? 1u : 0u;
+  p.frame_row0 = (uint32_t)accel->vertex_rows;
+  RT_HIP(rtk_launch_backward_inst(p, 0, s));
+  RT_HIP(rtk_launch_backward_inst(p, 1, s));
+  if (d_vertices)
+    RT_HIP(rta::convert(accel->grad_rows, 0, (uint32_t)accel->vertex_rows, 0, p.acc.shift0, d_vertices, s));
+  if (d_srt)
+    RT_HIP(rta::convert(accel->grad_rows, (uint32_t)accel->vertex_rows, 4u * accel->instance_count, 1,
+                        p.acc.shift0, d_srt, s));
+  accel->grad_dirty = false;
   RT_HIP(hipEventRecord(ctx->last_event, s));
   ctx->last_stream = s;
   ctx->has_last = true;

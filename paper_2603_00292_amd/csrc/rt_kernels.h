@@ -66,22 +66,25 @@ struct TraceParams {
 // per-wave ray ranges kept for the finalize inside the closest-hit traversal
 constexpr uint32_t kRtRangesPerWave = 128;
 
-// Single-level adjoint: ray gradients are written directly; the vertex
-// contributions go to (keys, vals) entries 3i..3i+2 (vertex id, -w_k lambda;
-// 0xFFFFFFFF for a miss), summed afterwards by rta::scatter_add.
+// Single-level adjoint (one thread per ray): writes the ray gradients and,
+// for the vertex accumulation of accumulate.h, key[i] = the ray's triangle
+// (0xFFFFFFFF: no contribution) and rec[i] = (lambda, u, v).
 struct BackwardParams {
   rt_mesh_dev mesh;
   const rt_ray* rays;
   const rt_hit* hits;
   const float* d_tuv;
   uint32_t n;
-  uint32_t* keys;
-  rta_f3* vals;
   float* d_origins;
   float* d_directions;
+  uint32_t* keys;
+  rta::RayRec* rec;
 };
 
-// Adjoint of two-level closest hits (one thread per ray).
+// Adjoint of two-level closest hits (one thread per ray, two phases as
+// above).  Vertex rows: vertex_base[mesh] + vertex id; frame rows:
+// frame_row0 + 4 * instance + part, parts holding (S xyz), (q xyz),
+// (q w, T x, T y), (T z, -, -).
 struct BackwardInstParams {
   const rt_mesh_dev* meshes;      // device mesh records (the accel's copies)
   const uint64_t* vertex_base;    // first gradient row of each mesh
@@ -94,16 +97,12 @@ struct BackwardInstParams {
   const uint32_t* inst_ids;
   const float* d_tuv;
   uint32_t n;
-  // contributions for rta::scatter_add (0xFFFFFFFF keys for none):
-  //   vkeys/vvals[3i + k]: gradient row (vertex_base[mesh] + vertex id);
-  //   skeys/svals[4i + part]: frame rows 4 * instance + part, holding
-  //   (S xyz), (q xyz), (q w, T x, T y), (T z, 0, 0)
-  uint32_t* vkeys;                // null: no vertex gradients wanted
-  rta_f3* vvals;
-  uint32_t* skeys;                // null: no frame gradients wanted
-  rta_f3* svals;
   float* d_origins;
   float* d_directions;
+  rta::Acc acc;
+  uint32_t want_vertices;         // add vertex rows
+  uint32_t want_frames;           // add frame rows
+  uint32_t frame_row0;
 };
 
 // Ambient-occlusion rays from closest hits (one thread per ray sample).
@@ -142,9 +141,7 @@ hipError_t rtk_launch_finalize_ovf(bool inst, const TraceParams& p, hipStream_t 
 // float64 finalize of the hit lists of an all-hits launch (n * cap entries)
 hipError_t rtk_launch_finalize_all(bool inst, const TraceParams& p, hipStream_t stream);
 hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream);
-hipError_t rtk_launch_backward_inst(const BackwardInstParams& p, hipStream_t stream);
-// d_srt[10 j + c] += the frame rows 4 j .. 4 j + 3 (see BackwardInstParams)
-hipError_t rtk_launch_fold_frames(const float* rows, uint32_t inst_count, float* d_srt, hipStream_t stream);
+hipError_t rtk_launch_backward_inst(const BackwardInstParams& p, int phase, hipStream_t stream);
 hipError_t rtk_launch_refit_tris(rt_tri_rec* tris, uint32_t n, const rt_mesh_dev& mesh,
                                  hipStream_t stream);
 hipError_t rtk_launch_refit_nodes(int width, float* nodes, const rt_tri_rec* tris,

@@ -757,6 +757,7 @@ __device__ __forceinline__ bool adjoint64(const rt_mesh_dev& mesh, uint32_t prim
 
 __device__ __forceinline__ void zero3(float* a) { a[0] = a[1] = a[2] = 0.0f; }
 
+// dL/do, dL/dd and the vertex-gather inputs of one ray (see accumulate.h).
 __global__ __launch_bounds__(256) void backward_kernel(BackwardParams P) {
   uint32_t i = blockIdx.x * 256u + threadIdx.x;
   if (i >= P.n) return;
@@ -764,30 +765,23 @@ __global__ __launch_bounds__(256) void backward_kernel(BackwardParams P) {
   uint32_t prim = __float_as_uint(hp->y);
   float* go = P.d_origins + 3 * (size_t)i;
   float* gd = P.d_directions + 3 * (size_t)i;
-  rt_ray q = load_ray(P.rays, i);
-  const float* gr = P.d_tuv + 3 * (size_t)i;
-  uint32_t* keys = P.keys + 3 * (size_t)i;
-  rta_f3* vals = P.vals + 3 * (size_t)i;
   Adjoint64 A;
-  if (prim == RT_INVALID_ID || prim >= P.mesh.triangle_count ||
-      !adjoint64(P.mesh, prim, q.ox, q.oy, q.oz, q.dx, q.dy, q.dz, gr[0], gr[1], gr[2], A)) {
+  bool ok = prim != RT_INVALID_ID && prim < P.mesh.triangle_count;
+  if (ok) {
+    rt_ray q = load_ray(P.rays, i);
+    const float* gr = P.d_tuv + 3 * (size_t)i;
+    ok = adjoint64(P.mesh, prim, q.ox, q.oy, q.oz, q.dx, q.dy, q.dz, gr[0], gr[1], gr[2], A);
+  }
+  if (!ok) {
     zero3(go);
     zero3(gd);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      keys[k] = 0xFFFFFFFFu;
-      vals[k] = rta_f3{0.0f, 0.0f, 0.0f};
-    }
+    P.keys[i] = 0xFFFFFFFFu;
     return;
   }
   go[0] = (float)A.lx; go[1] = (float)A.ly; go[2] = (float)A.lz;
   gd[0] = (float)(A.t * A.lx); gd[1] = (float)(A.t * A.ly); gd[2] = (float)(A.t * A.lz);
-  double w[3] = {1.0 - A.u - A.v, A.u, A.v};
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    keys[k] = A.id[k];
-    vals[k] = rta_f3{(float)(-w[k] * A.lx), (float)(-w[k] * A.ly), (float)(-w[k] * A.lz)};
-  }
+  P.keys[i] = prim;
+  P.rec[i] = rta::RayRec{A.lx, A.ly, A.lz, A.u, A.v};
 }
 
 // Two-level hits (§6.2: the hit on an instance is the hit of the object-space
@@ -808,6 +802,7 @@ __device__ __forceinline__ void cross3(double ax, double ay, double az, double b
   cz = ax * by - ay * bx;
 }
 
+template <int PHASE>
 __global__ __launch_bounds__(256) void backward_inst_kernel(BackwardInstParams P) {
   uint32_t i = blockIdx.x * 256u + threadIdx.x;
   if (i >= P.n) return;
@@ -817,18 +812,10 @@ __global__ __launch_bounds__(256) void backward_inst_kernel(BackwardInstParams P
   float* go = P.d_origins + 3 * (size_t)i;
   float* gd = P.d_directions + 3 * (size_t)i;
   auto no_contribution = [&]() {
-    zero3(go);
-    zero3(gd);
-    if (P.vkeys)
-      for (int k = 0; k < 3; ++k) {
-        P.vkeys[3 * (size_t)i + k] = 0xFFFFFFFFu;
-        P.vvals[3 * (size_t)i + k] = rta_f3{0.0f, 0.0f, 0.0f};
-      }
-    if (P.skeys)
-      for (int k = 0; k < 4; ++k) {
-        P.skeys[4 * (size_t)i + k] = 0xFFFFFFFFu;
-        P.svals[4 * (size_t)i + k] = rta_f3{0.0f, 0.0f, 0.0f};
-      }
+    if constexpr (PHASE == 0) {
+      zero3(go);
+      zero3(gd);
+    }
   };
   if (prim == RT_INVALID_ID || inst >= P.inst_count) {
     no_contribution();
@@ -856,19 +843,18 @@ __global__ __launch_bounds__(256) void backward_inst_kernel(BackwardInstParams P
   double lx = M.m[0] * A.lx + M.m[4] * A.ly + M.m[8] * A.lz;
   double ly = M.m[1] * A.lx + M.m[5] * A.ly + M.m[9] * A.lz;
   double lz = M.m[2] * A.lx + M.m[6] * A.ly + M.m[10] * A.lz;
-  go[0] = (float)lx; go[1] = (float)ly; go[2] = (float)lz;
-  gd[0] = (float)(A.t * lx); gd[1] = (float)(A.t * ly); gd[2] = (float)(A.t * lz);
+  if constexpr (PHASE == 0) {
+    go[0] = (float)lx; go[1] = (float)ly; go[2] = (float)lz;
+    gd[0] = (float)(A.t * lx); gd[1] = (float)(A.t * ly); gd[2] = (float)(A.t * lz);
+  }
   double w[3] = {1.0 - A.u - A.v, A.u, A.v};
-  if (P.vkeys) {
+  if (P.want_vertices) {
     uint32_t base = (uint32_t)P.vertex_base[mesh];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      P.vkeys[3 * (size_t)i + k] = base + A.id[k];
-      P.vvals[3 * (size_t)i + k] =
-          rta_f3{(float)(-w[k] * A.lx), (float)(-w[k] * A.ly), (float)(-w[k] * A.lz)};
-    }
+    for (int k = 0; k < 3; ++k)
+      rta::add<PHASE>(P.acc, base + A.id[k], -w[k] * A.lx, -w[k] * A.ly, -w[k] * A.lz);
   }
-  if (!P.skeys) return;
+  if (!P.want_frames) return;
   const rt_srt f = P.srts[inst];
   double qx = f.qx, qy = f.qy, qz = f.qz, qw = f.qw;
   double qn = sqrt(qx * qx + qy * qy + qz * qz + qw * qw);
@@ -899,24 +885,12 @@ __global__ __launch_bounds__(256) void backward_inst_kernel(BackwardInstParams P
   double gqy = -2.0 * (qw * t1y + t2y + t3y);
   double gqz = -2.0 * (qw * t1z + t2z + t3z);
   double radial = qx * gqx + qy * gqy + qz * gqz + qw * gqw;
-  uint32_t* sk = P.skeys + 4 * (size_t)i;
-  rta_f3* sv = P.svals + 4 * (size_t)i;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) sk[k] = 4u * inst + (uint32_t)k;
-  sv[0] = rta_f3{(float)(-rlx * px), (float)(-rly * py), (float)(-rlz * pz)};
-  sv[1] = rta_f3{(float)((gqx - qx * radial) * iq), (float)((gqy - qy * radial) * iq),
-                 (float)((gqz - qz * radial) * iq)};
-  sv[2] = rta_f3{(float)((gqw - qw * radial) * iq), (float)(-lx), (float)(-ly)};
-  sv[3] = rta_f3{(float)(-lz), 0.0f, 0.0f};
-}
-
-__global__ void fold_frames_kernel(const float* rows, uint32_t inst_count, float* d_srt) {
-  uint32_t j = blockIdx.x * 256u + threadIdx.x;
-  if (j >= inst_count) return;
-  const float* r = rows + 12 * (size_t)j;
-  float* o = d_srt + 10 * (size_t)j;
-#pragma unroll
-  for (int c = 0; c < 10; ++c) o[c] += r[c];
+  uint32_t row = P.frame_row0 + 4u * inst;
+  rta::add<PHASE>(P.acc, row + 0, -rlx * px, -rly * py, -rlz * pz);
+  rta::add<PHASE>(P.acc, row + 1, (gqx - qx * radial) * iq, (gqy - qy * radial) * iq,
+                  (gqz - qz * radial) * iq);
+  rta::add<PHASE>(P.acc, row + 2, (gqw - qw * radial) * iq, -lx, -ly);
+  rta::add<PHASE>(P.acc, row + 3, -lz, 0.0, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1277,23 +1251,17 @@ hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream) {
   if (p.n == 0) return hipSuccess;
   BackwardParams q = p;
   void* args[] = {&q};
-  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::backward_kernel),
-                         dim3((p.n + 255) / 256), dim3(256), args, 0, stream);
+  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::backward_kernel), dim3((p.n + 255) / 256),
+                         dim3(256), args, 0, stream);
 }
 
-hipError_t rtk_launch_backward_inst(const BackwardInstParams& p, hipStream_t stream) {
+hipError_t rtk_launch_backward_inst(const BackwardInstParams& p, int phase, hipStream_t stream) {
   if (p.n == 0) return hipSuccess;
   BackwardInstParams q = p;
   void* args[] = {&q};
-  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::backward_inst_kernel),
-                         dim3((p.n + 255) / 256), dim3(256), args, 0, stream);
-}
-
-hipError_t rtk_launch_fold_frames(const float* rows, uint32_t inst_count, float* d_srt, hipStream_t stream) {
-  if (inst_count == 0) return hipSuccess;
-  void* args[] = {&rows, &inst_count, &d_srt};
-  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::fold_frames_kernel),
-                         dim3((inst_count + 255) / 256), dim3(256), args, 0, stream);
+  const void* k = phase == 0 ? reinterpret_cast<const void*>(&rtk::backward_inst_kernel<0>)
+                             : reinterpret_cast<const void*>(&rtk::backward_inst_kernel<1>);
+  return hipLaunchKernel(k, dim3((p.n + 255) / 256), dim3(256), args, 0, stream);
 }
 
 hipError_t rtk_launch_finalize(bool inst, int mode, const TraceParams& p, hipStream_t stream) {

@@ -2,11 +2,12 @@
 the autograd Function over it, against the FP64 oracle's two-level adjoint
 and FP64 finite differences of all 25 inputs of a hit.
 
-Accumulated gradients (vertices, frames) are sums of float32 atomics of
-float64-computed contributions; each entry must lie within the rounding
-bound of such a sum: n * 2^-24 * (sum of |contributions|) for n terms, plus
-the float64 differences between the object-space (library) and world-space
-(oracle) routes, far below that."""
+Accumulated gradients (vertices, frames) are exact integer sums of the
+float64-computed contributions at a per-row scale, rounded once to float32;
+each entry is checked against the (looser) rounding bound of a float32 sum:
+n * 2^-24 * (sum of |contributions|) for n terms, plus the float64
+differences between the object-space (library) and world-space (oracle)
+routes, far below that."""
 from __future__ import annotations
 
 import numpy as np
