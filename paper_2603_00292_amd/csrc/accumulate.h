@@ -107,16 +107,17 @@ __device__ __forceinline__ void add(const Acc& a, uint32_t row, double x, double
 // ---------------------------------------------------------------------------
 // Vertex gradients of single-level accels without global atomics
 // ---------------------------------------------------------------------------
-// The adjoint kernel writes, per ray i, key[i] = its triangle (0xFFFFFFFF for
-// none) and rec[i] = (lambda, u, v) in float64.  Then:
-//   bucket   the rays are grouped by triangle range (kTrisPerBucket
-//            triangles per bucket): per-tile histograms in LDS, an exclusive
-//            scan, a scatter with LDS counters (the order inside a bucket is
-//            not fixed, and does not need to be);
+//   bucket   the rays are grouped by triangle range (buckets of 256, 512 or
+//            1024 triangles, the smallest that keeps the bucket count within
+//            kMaxBuckets): per-tile LDS histograms of the hit triangles and
+//            an exclusive scan; then the adjoint kernel writes each hit ray's
+//            48-byte record (float64 lambda, u, v and its triangle) straight
+//            into its bucket through LDS counters (the order inside a bucket
+//            is not fixed, and does not need to be);
 //   corner   one workgroup per bucket sums -w_k lambda of its rays per
 //            (triangle, corner) in LDS, exactly, as 64-bit integers at the
-//            row's binary scale (the row's largest exponent, an LDS maximum
-//            taken first), and writes each row's float64 value;
+//            row's binary scale (an LDS maximum of the exponents first), and
+//            writes each row's float64 value;
 //   vertex   every vertex adds its corners' values in ascending (triangle,
 //            corner) order through a vertex -> (triangle, corner) list,
 //            rounds once to float32 and adds to the output.
@@ -126,42 +127,59 @@ __device__ __forceinline__ void add(const Acc& a, uint32_t row, double x, double
 // bit-identical vertex gradients.
 namespace rta {
 
-constexpr uint32_t kTrisPerBucket = 512;
-constexpr uint32_t kMaxBuckets = 16384;     // LDS histogram bins: meshes up to 2^23 triangles
-constexpr uint32_t kTile = 4096;            // rays per workgroup in the bucket passes
+constexpr uint32_t kMaxBuckets = 16384;     // LDS counters: meshes up to 2^24 triangles
+constexpr uint32_t kTile = 4096;            // rays per workgroup of the histogram and the adjoint
 
 struct RayRec {
   double lx, ly, lz, u, v;
+  uint32_t prim, pad;
 };
+
+// log2 of the bucket size for a mesh of `triangles` triangles (0: too many)
+inline uint32_t bucket_shift(uint32_t triangles) {
+  for (uint32_t sh = 8; sh <= 10; ++sh)
+    if (((uint64_t)triangles + (1u << sh) - 1) >> sh <= kMaxBuckets) return sh;
+  return 0;
+}
 
 // Per accel: the vertex -> (triangle << 2 | corner) lists and the corner values.
 struct Gather {
   uint32_t* csr_off = nullptr;   // vertex_count + 1
   uint32_t* csr_ent = nullptr;   // 3 * triangle_count
   double* corner = nullptr;      // 9 per triangle: corner k's 3 components
-  uint32_t vertices = 0, triangles = 0;
+  uint32_t vertices = 0, triangles = 0, shift = 0, buckets = 0;
 };
 
 // Per context: buffers sized by the ray count (grown stream-ordered).
 struct SortBuf {
-  uint32_t* keys = nullptr;      // cap
-  RayRec* rec = nullptr;         // cap
-  uint32_t* ids = nullptr;       // cap: ray ids grouped by bucket
+  RayRec* rec = nullptr;         // cap: records grouped by bucket
   uint32_t* counts = nullptr;    // buckets x tiles histogram, scanned in place (+1 total)
   uint32_t* partial = nullptr;   // scan partials
   size_t cap = 0, count_cap = 0, partial_cap = 0;
+};
+
+// What the adjoint kernel needs to place its records.
+struct Bucketing {
+  const uint32_t* offsets;       // scanned counts: offsets[bucket * tiles + tile]
+  uint32_t tiles, buckets, shift;
+  RayRec* rec;
 };
 
 // Builds g from the mesh's indices (host copy): counting sort by vertex,
 // entries in ascending (triangle, corner) order.
 hipError_t gather_build(Gather& g, const uint32_t* host_indices, uint32_t vertices, uint32_t triangles);
 void gather_release(Gather& g);
-// Makes b hold n rays for a mesh of `triangles` triangles; a larger n frees
-// and allocates stream-ordered on s (no device-wide synchronisation).
-hipError_t sort_reserve(SortBuf& b, size_t n, uint32_t triangles, hipStream_t s);
+// Makes b hold n rays for g's mesh; a larger n frees and allocates
+// stream-ordered on s (no device-wide synchronisation).
+hipError_t sort_reserve(SortBuf& b, const Gather& g, size_t n, hipStream_t s);
 void sort_release(SortBuf& b);
-// After the adjoint kernel filled b.keys / b.rec for n rays: bucket, sum per
-// corner and per vertex, out[3 v + c] += the vertex sums.
+// Histogram of the rays' hit triangles (prim ids at hit_words[4 i + 1],
+// counting those below the mesh's triangle count) and its scan; returns the
+// adjoint kernel's placement.
+hipError_t bucket_rays(const Gather& g, SortBuf& b, const uint32_t* hit_words, uint32_t n, hipStream_t s,
+                       Bucketing* out);
+// After the adjoint kernel placed the records: sum per corner and per
+// vertex, out[3 v + c] += the vertex sums.
 hipError_t gather_vertices(Gather& g, SortBuf& b, uint32_t n, float* out, hipStream_t s);
 
 }  // namespace rta

@@ -116,20 +116,22 @@ namespace {
 
 constexpr uint32_t kScanChunk = 2048;   // elements per workgroup of the scan
 
-// per-tile histogram of the rays' buckets: counts[bucket * tiles + tile]
-__global__ __launch_bounds__(256) void hist_kernel(const uint32_t* keys, uint32_t n, uint32_t buckets,
-                                                   uint32_t tiles, uint32_t* counts) {
+// per-tile histogram of the rays' buckets: counts[bucket * tiles + tile];
+// counts the rays whose prim id is a triangle of the mesh
+__global__ __launch_bounds__(1024) void hist_kernel(const uint32_t* hit_words, uint32_t n, uint32_t triangles,
+                                                    uint32_t shift, uint32_t buckets, uint32_t tiles,
+                                                    uint32_t* counts) {
   extern __shared__ uint32_t h[];
-  for (uint32_t b = threadIdx.x; b < buckets; b += 256) h[b] = 0u;
+  for (uint32_t b = threadIdx.x; b < buckets; b += 1024) h[b] = 0u;
   __syncthreads();
   uint32_t base = blockIdx.x * kTile;
   uint32_t end = min(n, base + kTile);
-  for (uint32_t i = base + threadIdx.x; i < end; i += 256) {
-    uint32_t k = keys[i];
-    if (k != 0xFFFFFFFFu) atomicAdd(&h[k / kTrisPerBucket], 1u);
+  for (uint32_t i = base + threadIdx.x; i < end; i += 1024) {
+    uint32_t k = hit_words[4 * (size_t)i + 1];
+    if (k < triangles) atomicAdd(&h[k >> shift], 1u);
   }
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < buckets; b += 256) counts[(size_t)b * tiles + blockIdx.x] = h[b];
+  for (uint32_t b = threadIdx.x; b < buckets; b += 1024) counts[(size_t)b * tiles + blockIdx.x] = h[b];
 }
 
 // exclusive scan of m elements in three launches: chunk sums, a scan of the
@@ -209,41 +211,25 @@ __global__ __launch_bounds__(256) void scan_down_kernel(uint32_t* x, uint32_t m,
   if (blockIdx.x + 1 == parts && threadIdx.x == 0) x[m] = partial[blockIdx.x] + total;
 }
 
-// writes each ray's id into its bucket: tile t's rays of bucket b go to
-// offsets[b * tiles + t] onwards (in any order)
-__global__ __launch_bounds__(256) void scatter_kernel(const uint32_t* keys, uint32_t n, uint32_t buckets,
-                                                      uint32_t tiles, const uint32_t* offsets, uint32_t* ids) {
-  extern __shared__ uint32_t pos[];
-  for (uint32_t b = threadIdx.x; b < buckets; b += 256) pos[b] = offsets[(size_t)b * tiles + blockIdx.x];
-  __syncthreads();
-  uint32_t base = blockIdx.x * kTile;
-  uint32_t end = min(n, base + kTile);
-  for (uint32_t i = base + threadIdx.x; i < end; i += 256) {
-    uint32_t k = keys[i];
-    if (k != 0xFFFFFFFFu) ids[atomicAdd(&pos[k / kTrisPerBucket], 1u)] = i;
-  }
-}
-
-// one workgroup per bucket: exact corner sums of its rays
-__global__ __launch_bounds__(256) void corner_kernel(const uint32_t* keys, const RayRec* rec, const uint32_t* ids,
-                                                     const uint32_t* offsets, uint32_t tiles, uint32_t triangles,
-                                                     int shift0, double* corner) {
-  constexpr uint32_t R = 3 * kTrisPerBucket;   // rows (triangle, corner)
+// one workgroup per bucket: exact corner sums of its rays (TB triangles)
+template <uint32_t TB>
+__global__ __launch_bounds__(512) void corner_kernel(const RayRec* rec, const uint32_t* offsets, uint32_t tiles,
+                                                     uint32_t triangles, int shift0, double* corner) {
+  constexpr uint32_t R = 3 * TB;   // rows (triangle, corner)
   __shared__ unsigned long long sum[3 * R];
   __shared__ int expo[R];
   const uint32_t b = blockIdx.x;
-  for (uint32_t r = threadIdx.x; r < R; r += 256) {
+  for (uint32_t r = threadIdx.x; r < R; r += 512) {
     expo[r] = INT_MIN;
     sum[3 * r] = sum[3 * r + 1] = sum[3 * r + 2] = 0ull;
   }
   __syncthreads();
   const uint32_t lo = offsets[(size_t)b * tiles], hi = offsets[(size_t)(b + 1) * tiles];
-  const uint32_t t0 = b * kTrisPerBucket;
+  const uint32_t t0 = b * TB;
   // pass 1: each row's largest binary exponent
-  for (uint32_t j = lo + threadIdx.x; j < hi; j += 256) {
-    uint32_t i = ids[j];
-    uint32_t tl = keys[i] - t0;
-    RayRec q = rec[i];
+  for (uint32_t j = lo + threadIdx.x; j < hi; j += 512) {
+    RayRec q = rec[j];
+    uint32_t tl = q.prim - t0;
     double w[3] = {1.0 - q.u - q.v, q.u, q.v};
     // bounds every component of -w_k lambda; a NaN or inf makes the row NaN
     double m = fabs(q.lx) + fabs(q.ly) + fabs(q.lz);
@@ -255,10 +241,9 @@ __global__ __launch_bounds__(256) void corner_kernel(const uint32_t* keys, const
   }
   __syncthreads();
   // pass 2: integer sums at each row's scale
-  for (uint32_t j = lo + threadIdx.x; j < hi; j += 256) {
-    uint32_t i = ids[j];
-    uint32_t tl = keys[i] - t0;
-    RayRec q = rec[i];
+  for (uint32_t j = lo + threadIdx.x; j < hi; j += 512) {
+    RayRec q = rec[j];
+    uint32_t tl = q.prim - t0;
     double w[3] = {1.0 - q.u - q.v, q.u, q.v};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -274,7 +259,7 @@ __global__ __launch_bounds__(256) void corner_kernel(const uint32_t* keys, const
     }
   }
   __syncthreads();
-  for (uint32_t r = threadIdx.x; r < R; r += 256) {
+  for (uint32_t r = threadIdx.x; r < R; r += 512) {
     uint32_t t = t0 + r / 3;
     if (t >= triangles) continue;
     int e = expo[r];
@@ -318,13 +303,12 @@ hipError_t grow(T** p, size_t* cap, size_t n, hipStream_t s) {
   return e;
 }
 
-uint32_t bucket_count(uint32_t triangles) { return (triangles + kTrisPerBucket - 1) / kTrisPerBucket; }
-
 }  // namespace
 
 hipError_t gather_build(Gather& g, const uint32_t* I, uint32_t vertices, uint32_t triangles) {
   gather_release(g);
-  if (bucket_count(triangles) > kMaxBuckets) return hipErrorInvalidValue;
+  uint32_t shift = bucket_shift(triangles);
+  if (shift == 0) return hipErrorInvalidValue;
   std::vector<uint32_t> off((size_t)vertices + 1, 0u), ent(3 * (size_t)triangles);
   for (size_t t = 0; t < triangles; ++t)
     for (int k = 0; k < 3; ++k) off[I[3 * t + k] + 1]++;
@@ -344,6 +328,8 @@ hipError_t gather_build(Gather& g, const uint32_t* I, uint32_t vertices, uint32_
   }
   g.vertices = vertices;
   g.triangles = triangles;
+  g.shift = shift;
+  g.buckets = (uint32_t)(((uint64_t)triangles + (1u << shift) - 1) >> shift);
   return hipSuccess;
 }
 
@@ -354,39 +340,36 @@ void gather_release(Gather& g) {
   g = Gather();
 }
 
-hipError_t sort_reserve(SortBuf& b, size_t n, uint32_t triangles, hipStream_t s) {
+hipError_t sort_reserve(SortBuf& b, const Gather& g, size_t n, hipStream_t s) {
   size_t tiles = (n + kTile - 1) / kTile;
-  size_t m = (size_t)bucket_count(triangles) * tiles;
+  size_t m = (size_t)g.buckets * tiles;
   size_t parts = (m + kScanChunk - 1) / kScanChunk;
-  size_t c0 = b.cap, c1 = b.cap, c2 = b.cap;
-  hipError_t e = grow(&b.keys, &c0, n, s);
-  if (e == hipSuccess) e = grow(&b.rec, &c1, n, s);
-  if (e == hipSuccess) e = grow(&b.ids, &c2, n, s);
-  if (e != hipSuccess) return e;
-  b.cap = std::min(c0, std::min(c1, c2));
-  if ((e = grow(&b.counts, &b.count_cap, m + 1, s)) != hipSuccess) return e;
-  return grow(&b.partial, &b.partial_cap, std::max<size_t>(parts, 1), s);
+  hipError_t e = grow(&b.rec, &b.cap, n, s);
+  if (e == hipSuccess) e = grow(&b.counts, &b.count_cap, m + 1, s);
+  if (e == hipSuccess) e = grow(&b.partial, &b.partial_cap, std::max<size_t>(parts, 1), s);
+  return e;
 }
 
 void sort_release(SortBuf& b) {
-  void* ps[] = {b.keys, b.rec, b.ids, b.counts, b.partial};
+  void* ps[] = {b.rec, b.counts, b.partial};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   b = SortBuf();
 }
 
-hipError_t gather_vertices(Gather& g, SortBuf& b, uint32_t n, float* out, hipStream_t s) {
-  if (n == 0 || g.vertices == 0 || g.triangles == 0) return hipSuccess;
-  uint32_t buckets = bucket_count(g.triangles);
+hipError_t bucket_rays(const Gather& g, SortBuf& b, const uint32_t* hit_words, uint32_t n, hipStream_t s,
+                       Bucketing* out) {
+  uint32_t buckets = g.buckets, shift = g.shift, tris = g.triangles;
   uint32_t tiles = (n + kTile - 1) / kTile;
   uint32_t m = buckets * tiles;
   uint32_t parts = (m + kScanChunk - 1) / kScanChunk;
-  size_t lds = buckets * sizeof(uint32_t);
-  uint32_t* keys = b.keys;
   uint32_t* counts = b.counts;
   uint32_t* partial = b.partial;
-  void* a1[] = {&keys, &n, &buckets, &tiles, &counts};
-  hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(&hist_kernel), dim3(tiles), dim3(256), a1, lds, s);
+  *out = Bucketing{counts, tiles, buckets, shift, b.rec};
+  if (m == 0) return hipSuccess;   // no triangles: no ray has a bucket
+  void* a1[] = {&hit_words, &n, &tris, &shift, &buckets, &tiles, &counts};
+  hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(&hist_kernel), dim3(tiles), dim3(1024), a1,
+                                 buckets * sizeof(uint32_t), s);
   if (e != hipSuccess) return e;
   void* a2[] = {&counts, &m, &partial};
   e = hipLaunchKernel(reinterpret_cast<const void*>(&scan_reduce_kernel), dim3(parts), dim3(256), a2, 0, s);
@@ -395,18 +378,22 @@ hipError_t gather_vertices(Gather& g, SortBuf& b, uint32_t n, float* out, hipStr
   e = hipLaunchKernel(reinterpret_cast<const void*>(&scan_partials_kernel), dim3(1), dim3(256), a3, 0, s);
   if (e != hipSuccess) return e;
   void* a4[] = {&counts, &m, &partial, &parts};
-  e = hipLaunchKernel(reinterpret_cast<const void*>(&scan_down_kernel), dim3(parts), dim3(256), a4, 0, s);
-  if (e != hipSuccess) return e;
-  uint32_t* ids = b.ids;
-  void* a5[] = {&keys, &n, &buckets, &tiles, &counts, &ids};
-  e = hipLaunchKernel(reinterpret_cast<const void*>(&scatter_kernel), dim3(tiles), dim3(256), a5, lds, s);
-  if (e != hipSuccess) return e;
+  return hipLaunchKernel(reinterpret_cast<const void*>(&scan_down_kernel), dim3(parts), dim3(256), a4, 0, s);
+}
+
+hipError_t gather_vertices(Gather& g, SortBuf& b, uint32_t n, float* out, hipStream_t s) {
+  if (n == 0 || g.buckets == 0 || g.vertices == 0) return hipSuccess;
+  uint32_t tiles = (n + kTile - 1) / kTile;
   RayRec* rec = b.rec;
+  uint32_t* counts = b.counts;
   uint32_t tris = g.triangles;
   int shift0 = shift0_for(n);
   double* corner = g.corner;
-  void* a6[] = {&keys, &rec, &ids, &counts, &tiles, &tris, &shift0, &corner};
-  e = hipLaunchKernel(reinterpret_cast<const void*>(&corner_kernel), dim3(buckets), dim3(256), a6, 0, s);
+  void* a6[] = {&rec, &counts, &tiles, &tris, &shift0, &corner};
+  const void* k = g.shift == 8   ? reinterpret_cast<const void*>(&corner_kernel<256>)
+                  : g.shift == 9 ? reinterpret_cast<const void*>(&corner_kernel<512>)
+                                 : reinterpret_cast<const void*>(&corner_kernel<1024>);
+  hipError_t e = hipLaunchKernel(k, dim3(g.buckets), dim3(512), a6, 0, s);
   if (e != hipSuccess) return e;
   uint32_t* off = g.csr_off;
   uint32_t* ent = g.csr_ent;

@@ -1537,13 +1537,12 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
     }
     if (!idx.empty())
       RT_HIP(hipMemcpy(idx.data(), mesh.indices, idx.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
-    if ((uint64_t)mesh.triangle_count > (uint64_t)rta::kMaxBuckets * rta::kTrisPerBucket)
-      return fail(RT_ERROR_UNSUPPORTED, "rt_trace_backward: more than %u triangles",
-                  rta::kMaxBuckets * rta::kTrisPerBucket);
+    if (rta::bucket_shift(mesh.triangle_count) == 0)
+      return fail(RT_ERROR_UNSUPPORTED, "rt_trace_backward: more than %u triangles", rta::kMaxBuckets << 10);
     RT_HIP(rta::gather_build(accel->gather, idx.data(), mesh.vertex_count, mesh.triangle_count));
     accel->info.device_bytes += 4ull * (mesh.vertex_count + 1) + 84ull * mesh.triangle_count;
   }
-  RT_HIP(rta::sort_reserve(ctx->sortbuf, n, mesh.triangle_count, s));
+  RT_HIP(rta::sort_reserve(ctx->sortbuf, accel->gather, n, s));
   BackwardParams p{};
   p.mesh = mesh;
   p.rays = rays;
@@ -1552,8 +1551,7 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
   p.n = n;
   p.d_origins = d_origins;
   p.d_directions = d_directions;
-  p.keys = ctx->sortbuf.keys;
-  p.rec = ctx->sortbuf.rec;
+  RT_HIP(rta::bucket_rays(accel->gather, ctx->sortbuf, reinterpret_cast<const uint32_t*>(hits), n, s, &p.bk));
   RT_HIP(rtk_launch_backward(p, s));
   RT_HIP(rta::gather_vertices(accel->gather, ctx->sortbuf, n, d_vertices, s));
   RT_HIP(hipEventRecord(ctx->last_event, s));

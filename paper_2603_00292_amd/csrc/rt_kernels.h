@@ -66,9 +66,9 @@ struct TraceParams {
 // per-wave ray ranges kept for the finalize inside the closest-hit traversal
 constexpr uint32_t kRtRangesPerWave = 128;
 
-// Single-level adjoint (one thread per ray): writes the ray gradients and,
-// for the vertex accumulation of accumulate.h, key[i] = the ray's triangle
-// (0xFFFFFFFF: no contribution) and rec[i] = (lambda, u, v).
+// Single-level adjoint (a workgroup of 1024 threads per tile of rta::kTile
+// rays): writes the ray gradients and places each hit ray's record in its
+// bucket for the vertex accumulation of accumulate.h.
 struct BackwardParams {
   rt_mesh_dev mesh;
   const rt_ray* rays;
@@ -77,8 +77,7 @@ struct BackwardParams {
   uint32_t n;
   float* d_origins;
   float* d_directions;
-  uint32_t* keys;
-  rta::RayRec* rec;
+  rta::Bucketing bk;
 };
 
 // Adjoint of two-level closest hits (one thread per ray, two phases as

@@ -757,31 +757,54 @@ __device__ __forceinline__ bool adjoint64(const rt_mesh_dev& mesh, uint32_t prim
 
 __device__ __forceinline__ void zero3(float* a) { a[0] = a[1] = a[2] = 0.0f; }
 
-// dL/do, dL/dd and the vertex-gather inputs of one ray (see accumulate.h).
-__global__ __launch_bounds__(256) void backward_kernel(BackwardParams P) {
-  uint32_t i = blockIdx.x * 256u + threadIdx.x;
-  if (i >= P.n) return;
-  const float4* hp = reinterpret_cast<const float4*>(P.hits + i);
-  uint32_t prim = __float_as_uint(hp->y);
-  float* go = P.d_origins + 3 * (size_t)i;
-  float* gd = P.d_directions + 3 * (size_t)i;
-  Adjoint64 A;
-  bool ok = prim != RT_INVALID_ID && prim < P.mesh.triangle_count;
-  if (ok) {
-    rt_ray q = load_ray(P.rays, i);
-    const float* gr = P.d_tuv + 3 * (size_t)i;
-    ok = adjoint64(P.mesh, prim, q.ox, q.oy, q.oz, q.dx, q.dy, q.dz, gr[0], gr[1], gr[2], A);
+// dL/do and dL/dd of the rays of one tile, and each hit ray's record
+// (lambda, u, v, triangle) placed in its triangle's bucket (LDS counters
+// start at the tile's scanned offsets; see accumulate.h).  A hit whose
+// adjoint is undefined (a singular M) still takes its slot, with a zero
+// record.
+__global__ __launch_bounds__(1024) void backward_kernel(BackwardParams P) {
+  extern __shared__ uint32_t pos[];
+  const rta::Bucketing& B = P.bk;
+  for (uint32_t b = threadIdx.x; b < B.buckets; b += 1024)
+    pos[b] = B.offsets[(size_t)b * B.tiles + blockIdx.x];
+  __syncthreads();
+  const uint32_t base = blockIdx.x * rta::kTile;
+  for (uint32_t r = 0; r < rta::kTile / 1024; ++r) {
+    uint32_t i = base + r * 1024 + threadIdx.x;
+    if (i >= P.n) break;
+    const float4* hp = reinterpret_cast<const float4*>(P.hits + i);
+    uint32_t prim = __float_as_uint(hp->y);
+    float* go = P.d_origins + 3 * (size_t)i;
+    float* gd = P.d_directions + 3 * (size_t)i;
+    Adjoint64 A;
+    const bool valid = prim < P.mesh.triangle_count;
+    bool ok = false;
+    if (valid) {
+      rt_ray q = load_ray(P.rays, i);
+      const float* gr = P.d_tuv + 3 * (size_t)i;
+      ok = adjoint64(P.mesh, prim, q.ox, q.oy, q.oz, q.dx, q.dy, q.dz, gr[0], gr[1], gr[2], A);
+    }
+    if (ok) {
+      go[0] = (float)A.lx; go[1] = (float)A.ly; go[2] = (float)A.lz;
+      gd[0] = (float)(A.t * A.lx); gd[1] = (float)(A.t * A.ly); gd[2] = (float)(A.t * A.lz);
+    } else {
+      zero3(go);
+      zero3(gd);
+    }
+    if (valid) {
+      uint32_t p = atomicAdd(&pos[prim >> B.shift], 1u);
+      // three 16-byte stores (records are 48 bytes, the buffer 256-byte aligned)
+      float4* f = reinterpret_cast<float4*>(B.rec + p);
+      double r0 = ok ? A.lx : 0.0, r1 = ok ? A.ly : 0.0, r2 = ok ? A.lz : 0.0;
+      double r3 = ok ? A.u : 0.0, r4 = ok ? A.v : 0.0;
+      f[0] = make_float4(__int_as_float(__double2loint(r0)), __int_as_float(__double2hiint(r0)),
+                         __int_as_float(__double2loint(r1)), __int_as_float(__double2hiint(r1)));
+      f[1] = make_float4(__int_as_float(__double2loint(r2)), __int_as_float(__double2hiint(r2)),
+                         __int_as_float(__double2loint(r3)), __int_as_float(__double2hiint(r3)));
+      f[2] = make_float4(__int_as_float(__double2loint(r4)), __int_as_float(__double2hiint(r4)),
+                         __uint_as_float(prim), 0.0f);
+    }
   }
-  if (!ok) {
-    zero3(go);
-    zero3(gd);
-    P.keys[i] = 0xFFFFFFFFu;
-    return;
-  }
-  go[0] = (float)A.lx; go[1] = (float)A.ly; go[2] = (float)A.lz;
-  gd[0] = (float)(A.t * A.lx); gd[1] = (float)(A.t * A.ly); gd[2] = (float)(A.t * A.lz);
-  P.keys[i] = prim;
-  P.rec[i] = rta::RayRec{A.lx, A.ly, A.lz, A.u, A.v};
 }
 
 // Two-level hits (§6.2: the hit on an instance is the hit of the object-space
@@ -1251,8 +1274,8 @@ hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream) {
   if (p.n == 0) return hipSuccess;
   BackwardParams q = p;
   void* args[] = {&q};
-  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::backward_kernel), dim3((p.n + 255) / 256),
-                         dim3(256), args, 0, stream);
+  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::backward_kernel), dim3(p.bk.tiles), dim3(1024),
+                         args, p.bk.buckets * sizeof(uint32_t), stream);
 }
 
 hipError_t rtk_launch_backward_inst(const BackwardInstParams& p, int phase, hipStream_t stream) {

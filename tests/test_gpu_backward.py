@@ -302,3 +302,48 @@ def test_backward_is_deterministic(gpu):
     torch.cuda.synchronize()
     assert torch.allclose(dV, 2 * outs[0][0], rtol=1e-6, atol=1e-7)
     acc.close()
+
+
+@pytest.mark.parametrize("n_tri", [4_500_000, 8_500_000])
+def test_backward_large_meshes(gpu, orc, n_tri):
+    """Meshes large enough to group the rays in buckets of 512 and of 1,024
+    triangles: every pinned hit ray's gradients and the whole vertex tensor
+    against the oracle."""
+    torch, api, ctx = gpu
+    rng = wl.rng_for(309 + n_tri // 1_000_000)
+    V, I = wl.random_triangle_soup(rng, n_tri, 0.025 * np.sqrt(4096.0 / n_tri) * 4)
+    rays = wl.box_rays(rng, 65536, 0.0, 1.0)
+    W = wl.Workload("large", wl.Scene([wl.Mesh(V, I)]), rays, {})
+    S = orc.OracleScene.from_scene(W.scene, accel=True)
+    A = orc.accept(S, rays)
+    _, oprim, _ = orc.closest(S, rays)
+    pinned_hit = A.pinned & (oprim != NONE)
+    g = wl.rng_for(320).normal(size=(rays.shape[0], 3)).astype(np.float32).astype(np.float64)
+    g *= pinned_hit[:, None]
+    acc, (h, dV, do, dd) = _run(gpu, W, g)
+    prim = h[:, 1].copy().view(np.uint32)
+    assert (prim[pinned_hit] == oprim[pinned_hit]).all()
+    assert pinned_hit.sum() > 20000
+    rV, ro, rd = orc.adjoint(S, rays, np.where(pinned_hit, oprim, NONE), g)
+    r = np.flatnonzero(pinned_hit)
+    eo = np.linalg.norm(do[r] - ro[r], axis=1) / np.maximum(np.linalg.norm(ro[r], axis=1), 1e-30)
+    assert eo.max() <= GRAD_REL
+    frob = np.linalg.norm(dV - rV) / np.linalg.norm(rV)
+    rms = np.sqrt((rV ** 2).sum(1)[np.abs(rV).sum(1) > 0].mean())
+    say(n_tri, "triangles: pinned hits", int(pinned_hit.sum()), "Frobenius rel err", frob)
+    assert frob <= DV_FROB_REL
+    assert (np.abs(dV - rV) <= 2.0 ** -22 * np.abs(rV) + 1e-9 * rms).all()
+    acc.close()
+
+
+def test_backward_empty_mesh(gpu):
+    """A mesh whose triangles are all degenerate: every ray misses, the ray
+    gradients are zero and the vertex gradients untouched."""
+    torch, api, ctx = gpu
+    V = np.array([[0, 0, 0], [1, 0, 0], [2, 0, 0]], np.float32)
+    I = np.array([[0, 1, 2]], np.uint32)
+    W = wl.Workload("empty", wl.Scene([wl.Mesh(V, I)]), wl.box_rays(wl.rng_for(321), 1000, -1, 1), {})
+    acc, (h, dV, do, dd) = _run(gpu, W, np.ones((1000, 3)))
+    assert (h[:, 1].copy().view(np.uint32) == NONE).all()
+    assert (dV == 0).all() and (do == 0).all() and (dd == 0).all()
+    acc.close()
