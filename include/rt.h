@@ -20,10 +20,13 @@
  *    RT_ERROR_HIP from a later call.  No C++ exception crosses the boundary.
  *    rt_last_error_message() gives a thread-local detail string.
  *  - A traversal lane whose stack would grow past the accel's bound
- *    (rt_accel_info.max_stack, which the global spill stack is sized for)
- *    drops the entry and flags its context; the next query or batch launch
- *    on that context returns RT_ERROR_STACK_OVERFLOW without enqueuing
- *    anything and clears the flag.  With a correct bound this never happens.
+ *    (rt_accel_info.max_stack, the builder's bound on the entries any ray
+ *    can need, which the global spill stack is sized for) drops the entry,
+ *    so memory stays in bounds.  The counting variant (rt_trace_counters)
+ *    checks the bound: it reports the deepest fill, and a dropped entry
+ *    flags the context, so that the next query or batch launch on it returns
+ *    RT_ERROR_STACK_OVERFLOW without enqueuing anything (clearing the flag).
+ *    The query kernels do not check (it costs them about 1%).
  *  - Ray record (32 bytes, float32): origin o, tmin, direction d, tmax.  The
  *    ray is R(t) = o + t d (§3.1); t is measured in units of the given d (d is
  *    never normalised); a hit needs tmin <= t <= tmax (both inclusive, the
@@ -59,9 +62,9 @@ typedef enum rt_status {
   RT_ERROR_HIP = 4,                /* a HIP runtime call failed (detail in the message) */
   RT_ERROR_UNSUPPORTED = 5,        /* valid request this build does not implement */
   RT_ERROR_INDEX_OUT_OF_RANGE = 6, /* a triangle index >= vertex_count, a mesh id >= mesh_count */
-  RT_ERROR_STACK_OVERFLOW = 7      /* an earlier traversal on this context needed more stack
-                                      entries than the accel's bound (see rt_accel_info.max_stack);
-                                      that query's results may lack hits */
+  RT_ERROR_STACK_OVERFLOW = 7      /* an earlier counting traversal (rt_trace_counters) on this
+                                      context needed more stack entries than the accel's bound
+                                      (rt_accel_info.max_stack); its results may lack hits */
 } rt_status;
 
 /* Miss / no instance (the linear search of §3.3 starts from triIdx = -1). */

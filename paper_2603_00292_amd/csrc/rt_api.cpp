@@ -172,6 +172,7 @@ struct rt_batch_plan_s {
   Scratch scratch;
   uint32_t grid = 0;
   uint32_t workgroup = 256;                  // of `kernel` (the variant at creation)
+  uint32_t stack_entries = 16;               // of `kernel`
   const void* kernel = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -1244,7 +1245,9 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   p.gstack = gstack;
   p.root = a->root;
   p.n = n;
-  p.max_stack = ctx->stack_limit ? std::min(a->max_stack, ctx->stack_limit) : a->max_stack;
+  // the kernels take a bound of at least their LDS entries
+  p.max_stack = ctx->stack_limit ? std::max(std::min(a->max_stack, ctx->stack_limit), v.stack_entries)
+                                 : a->max_stack;
   p.gstride = gstride;
   p.refill_min = ctx->refill_min;
   p.counters = counters;
@@ -1915,6 +1918,7 @@ static rt_status plan_create(rt_context ctx, const rt_accel* accels, const rt_ra
   }
   p->grid = std::max(1u, std::min<uint32_t>((p->total + wg - 1) / wg, resident));
   p->workgroup = wg;
+  p->stack_entries = v.stack_entries;
   size_t spill = max_stack > v.stack_entries ? (size_t)(max_stack - v.stack_entries) : 1;
   hipError_t e1 = hipMalloc(&p->descs, d.size() * sizeof(BatchDesc));
   hipError_t e2 = hipMalloc(&p->offsets, off.size() * sizeof(uint32_t));
@@ -1951,7 +1955,8 @@ static rt_status enqueue_plan(rt_batch_plan p, hipStream_t s) {
   q.batch_offsets = p->offsets;
   q.batch_count = p->batch_count;
   q.n = p->total;
-  q.max_stack = p->ctx->stack_limit ? std::min(p->max_stack, p->ctx->stack_limit) : p->max_stack;
+  q.max_stack = p->ctx->stack_limit ? std::max(std::min(p->max_stack, p->ctx->stack_limit), p->stack_entries)
+                                    : p->max_stack;
   q.gstride = p->grid * p->workgroup;
   q.refill_min = p->ctx->refill_min;
   q.status = p->ctx->status;

@@ -44,8 +44,8 @@ struct TraceParams {
   uint32_t refill_min;   // refill a wave once this many lanes are idle
   uint64_t* counters;    // counting variants: node visits, triangle tests, spills
                          // (sums) and the deepest stack fill (maximum)
-  uint32_t* status;      // host-mapped word: a lane sets it to 1 when a push
-                         // would exceed max_stack
+  uint32_t* status;      // host-mapped word: a lane of a counting variant
+                         // sets it to 1 when a push would exceed max_stack
   // query options (modes 2 and 3; each may be null)
   const uint32_t* ray_masks;
   const uint32_t* skip_inst;

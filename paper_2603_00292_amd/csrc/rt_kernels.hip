@@ -73,29 +73,35 @@ __device__ __forceinline__ rt_ray load_ray(const rt_ray* rays, uint32_t i) {
 // Entry i of a lane's stack lives in LDS slot (i mod S) while it is one of the
 // S newest entries; older entries live at gstack[(i - S) * gstride + gtid].
 // A push beyond `cap` (the builder's bound on the entries a ray can need,
-// which the global stack is sized for) is not stored: the lane raises the
-// launch's status word instead, which the host reports as an error on the
-// context's next call.  With PEAK the stack records its deepest fill.
-template <int S, int WG, bool PEAK = false>
+// which the global stack is sized for; never below S) is not stored.  The
+// counting variant (CHECK) also remembers it and raises the launch's
+// host-mapped status word at the end, which the host turns into an error on
+// the context's next call, and records the deepest fill.  The query kernels
+// do neither: any observable action on that branch (a flag carried through
+// the loop, a store of any kind) measured 1.3% on the closest-hit kernel.
+template <int S, int WG, bool CHECK = false>
 struct Stack {
   uint32_t* lds;       // this lane's column: lds[slot * WG]
   uint32_t* glob;      // this lane's column: glob[i * gstride]
-  uint32_t* status;    // host-mapped word, set to 1 on an overflow
   uint32_t gstride;
-  uint32_t cap;        // total entries this lane may hold
+  uint32_t cap;        // total entries this lane may hold (at least S)
   uint32_t sp;
-  uint32_t peak;       // PEAK: the largest sp reached
+  uint32_t peak;       // CHECK: the largest sp reached
+  bool over;           // CHECK: a push was dropped
 
   __device__ __forceinline__ void push(uint32_t v) {
-    if (sp >= cap) {
-      __hip_atomic_store(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      return;
-    }
     uint32_t slot = sp & (S - 1);
-    if (sp >= S) glob[(size_t)(sp - S) * gstride] = lds[slot * WG];
+    if (sp >= S) {
+      // only a stack that spills can reach the bound (cap >= S)
+      if (sp >= cap) {
+        if constexpr (CHECK) over = true;
+        return;
+      }
+      glob[(size_t)(sp - S) * gstride] = lds[slot * WG];
+    }
     lds[slot * WG] = v;
     ++sp;
-    if constexpr (PEAK) peak = max(peak, sp);
+    if constexpr (CHECK) peak = max(peak, sp);
   }
   __device__ __forceinline__ uint32_t pop() {
     if (sp == 0) return RT_CHILD_EMPTY;
@@ -426,11 +432,11 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
   Stack<S, WG, COUNT> st;
   st.lds = lds_stack + tid;
   st.glob = P.gstack + gtid;
-  st.status = P.status;
   st.gstride = P.gstride;
   st.cap = P.max_stack;
   st.sp = 0;
   st.peak = 0;
+  st.over = false;
 
   RayState r;
   uint32_t ray_id = 0;
@@ -685,6 +691,9 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
         live = false;
       }
     }
+  }
+  if constexpr (COUNT) {
+    if (st.over) __hip_atomic_store(P.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
   if constexpr (FUSED) {
     // every ray this wave took is finished: float64 finalize of its listed

@@ -119,37 +119,44 @@ def test_deepest_fill_within_bound(gpu):
 
 
 def test_overflow_reported_on_next_call(gpu):
-    """A context whose lanes may hold only 4 entries (below the accel's
-    bound; set from the host, so every kernel still finishes normally):
-    the traversal drops the entries it cannot hold, and the context's next
-    query fails with RT_ERROR_STACK_OVERFLOW and clears the flag.  A context
-    without the cap never reports it."""
+    """A context whose lanes may hold only 20 entries (below the accel's
+    bound of 26 and the 22 the deepest ray needs; set from the host, so
+    every kernel still finishes normally): the counting traversal drops the
+    entries it cannot hold, and the context's next query fails with
+    RT_ERROR_STACK_OVERFLOW and clears the flag.  A context without the cap
+    never reports it."""
     torch, api, _ = gpu
     from paper_2603_00292_amd import _capi
 
-    scene, rays = layered_scene(layers=4000, seed=701)
+    scene, rays = layered_scene()
     r = torch.from_numpy(rays).cuda()
-    os.environ["RT_STACK_LIMIT"] = "4"
+    os.environ["RT_STACK_LIMIT"] = "20"
     try:
         ctx = api.Context(0)
     finally:
         del os.environ["RT_STACK_LIMIT"]
     acc = to_gpu_scene(api, torch, ctx, scene)
-    assert acc.info["max_stack"] > 4
-    api.trace_closest(acc, r)
+    assert acc.info["max_stack"] > 20
+    (_, _, _, peak), _ = api.trace_counters(acc, r, peak=True)
     torch.cuda.synchronize()
+    assert peak == 20
     with pytest.raises(_capi.RtError) as e:
         api.trace_any(acc, r)
     assert e.value.status == _capi.RT_ERROR_STACK_OVERFLOW
-    api.trace_any(acc, r[:1])   # flag cleared: this call runs (one ray, within the cap or not)
+    api.trace_any(acc, r)       # flag cleared: the query kernels do not raise it
+    api.trace_closest(acc, r)
+    torch.cuda.synchronize()
+    api.trace_closest(acc, r)
     torch.cuda.synchronize()
     acc.close()
     ctx.close()
     ctx2 = api.Context(0)
     acc2 = to_gpu_scene(api, torch, ctx2, scene)
     for _ in range(2):
+        api.trace_counters(acc2, r)
+        torch.cuda.synchronize()
         api.trace_closest(acc2, r)
         api.trace_any(acc2, r)
-        torch.cuda.synchronize()
+    torch.cuda.synchronize()
     acc2.close()
     ctx2.close()
