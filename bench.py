@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--probe", type=int, default=0,
                     help="rays the autotuner times (0: all rays of the workload)")
+    ap.add_argument("--only", choices=["backward", "batched", "instanced", "camera", "ao"],
+                    help="run one secondary leg alone and print its figures (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the ray-query path is built and measured on a single "
@@ -162,6 +164,16 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     sptr = C.c_void_p(int(stream.cuda_stream))
+    if args.only:
+        ctx = api.Context(0)
+        legs = {"backward": lambda: backward_bench(args, torch, np, api, workloads, ctx, stream),
+                "batched": lambda: batched_bench(args, torch, np, api, _capi, workloads, ctx, stream),
+                "instanced": lambda: instanced_bench(args, torch, np, api, workloads, ctx, stream),
+                "camera": lambda: camera_bench(args, torch, np, api, workloads, ctx, stream),
+                "ao": lambda: ao_bench(args, torch, np, api, workloads, ctx, stream)}
+        print(json.dumps({"leg": args.only, **legs[args.only]()}), flush=True)
+        ctx.close()
+        return
     if args.copy_calibration:
         x = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)
@@ -181,6 +193,7 @@ def main():
     I = torch.from_numpy(mesh.indices.view(np.int32)).to(dev)
     rays = torch.from_numpy(W.rays).to(dev)
     tuned = None
+    cached = False
     width = args.width
     if not args.no_autotune:
         # untimed: pick node width, stack entries and workgroup on a probe of
@@ -189,9 +202,9 @@ def main():
 
         t0 = time.time()
         probe = rays if args.probe <= 0 else rays[: args.probe].contiguous()
-        tuned, _ = autotune.autotune(ctx, V, I, probe, repeats=5)
+        tuned, cached = autotune.choose(ctx, V, I, probe, n, repeats=5)
         width = tuned["node_width"]
-        log(f"autotune {time.time() - t0:.1f}s: {tuned}")
+        log(f"autotune {time.time() - t0:.1f}s ({'cached' if cached else 'measured'}): {tuned}")
     torch.cuda.synchronize()
     t0 = time.time()
     acc = api.Accel(ctx, [(V, I)], node_width=width)
@@ -251,8 +264,12 @@ def main():
 
     launch_any()
     ms_any, _ = timed(launch_any, args.steps, stream, torch)
+    (nodes_a, tris_a, _), _ = api.trace_counters(acc, rays, any_hit=True)
+    any_bytes = n * (RAY_BYTES + 1) + nodes_a * node_bytes + tris_a * TRI_BYTES
     secondary["any_hit_mrays"] = round(n / (ms_any * 1e-3) / 1e6, 3)
-    log(f"any-hit: {secondary['any_hit_mrays']} Mrays/s")
+    secondary["any_hit_bytes_per_ray"] = round(any_bytes / n, 1)
+    secondary["any_hit_hbm_frac"] = round(any_bytes / (ms_any * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+    log(f"any-hit: {secondary['any_hit_mrays']} Mrays/s, {any_bytes / n:.1f} B/ray")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -312,7 +329,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "icosphere_incoherent", "triangles": int(mesh.n_tri), "rays": int(n),
                    "origins": "U[-1,1]^3", "directions": "uniform sphere", "node_width": info["node_width"],
-                   "variant": list(ctx.variant), "autotuned": tuned is not None, "query": "closest",
+                   "variant": list(ctx.variant), "autotuned": tuned is not None,
+                   "autotune_cached": bool(tuned is not None and cached), "query": "closest",
                    "inputs_sha256": W.checksum()[:16]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -512,10 +530,24 @@ def batched_bench(args, torch, np, api, _capi, workloads, ctx, stream):
     ms_pm, _ = timed(per_mesh, steps, stream, torch)
     ms_b, _ = timed(batched, steps, stream, torch)
     same = all(torch.equal(a.view(torch.int32), b.view(torch.int32)) for a, b in zip(hits, plan.hits))
+    # algorithmic bytes of the whole plan: sum over meshes of rays x (ray +
+    # hit + finalize) plus their node and triangle fetches (counting variant)
+    alg = 0
+    footprint = 0
+    for a, r, h in zip(accs, rays, hits):
+        (nodes, tris, _), _ = api.trace_counters(a, r)
+        n_hit = int((h[:, 1].view(torch.int32) != -1).sum().item())
+        nb = 32 * a.info["node_width"]
+        alg += r.shape[0] * (RAY_BYTES + HIT_BYTES) + nodes * nb + tris * TRI_BYTES
+        alg += r.shape[0] * (RAY_BYTES + 2 * HIT_BYTES) + n_hit * FINALIZE_BYTES
+        footprint += a.info["device_bytes"]
     r = {"batched_mrays": round(total / (ms_b * 1e-3) / 1e6, 3),
          "per_mesh_mrays": round(total / (ms_pm * 1e-3) / 1e6, 3),
          "batched_vs_per_mesh": round(ms_pm / ms_b, 3),
          "batched_identical": bool(same),
+         "batched_bytes_per_ray": round(alg / total, 1),
+         "batched_hbm_frac": round(alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+         "batched_accel_bytes": int(footprint),
          "batched_workload": f"256 meshes, {total} rays"}
     log(f"batched: {r}")
     plan.close()

@@ -21,8 +21,7 @@ import torch
 from . import _capi as capi
 from . import api
 
-CACHE = os.environ.get("RTQ_AUTOTUNE_CACHE",
-                       os.path.join(os.path.expanduser("~"), ".cache", "rtq", "autotune.json"))
+CACHE = os.path.join(os.path.expanduser("~"), ".cache", "rtq", "autotune.json")
 
 
 def scene_class(n_triangles: int, n_rays: int) -> str:
@@ -36,6 +35,25 @@ def device_key(device: int) -> str:
     p = torch.cuda.get_device_properties(device)
     arch = getattr(p, "gcnArchName", "unknown").split(":")[0]
     return f"{arch}_cu{p.multi_processor_count}"
+
+
+def choose(ctx: api.Context, vertices: torch.Tensor, indices: torch.Tensor, probe_rays: torch.Tensor,
+           n_rays: int, repeats: int = 3, use_cache: bool = True):
+    """The configuration for a mesh of this size traced with n_rays rays on
+    this device: the cached choice for (device, scene class) when there is
+    one, otherwise rt_autotune on the probe rays, saved to the cache.  Sets
+    the context's variant; returns (choice, from_cache)."""
+    dev = ctx.device
+    cls = scene_class(indices.shape[0], n_rays)
+    if use_cache:
+        hit = cached_choice(dev, cls)
+        if hit is not None:
+            ctx.set_variant(hit["stack_entries"], hit["workgroup"])
+            return hit, True
+    best, _ = autotune(ctx, vertices, indices, probe_rays, repeats)
+    if use_cache:
+        save_choice(dev, cls, best)
+    return best, False
 
 
 def autotune(ctx: api.Context, vertices: torch.Tensor, indices: torch.Tensor, probe_rays: torch.Tensor,
@@ -56,23 +74,34 @@ def autotune(ctx: api.Context, vertices: torch.Tensor, indices: torch.Tensor, pr
     return to(best), [to(table[i]) for i in range(min(n.value, cap))]
 
 
+def cache_path() -> str:
+    return os.environ.get("RTQ_AUTOTUNE_CACHE", CACHE)
+
+
 def load_cache() -> dict:
-    if os.path.exists(CACHE):
-        with open(CACHE) as f:
+    p = cache_path()
+    if os.path.exists(p):
+        with open(p) as f:
             return json.load(f)
     return {}
 
 
-def save_choice(device: int, cls: str, best: dict) -> None:
+def save_choice(device, cls: str, best: dict) -> None:
+    """device: a HIP device id, or a device key string."""
+    key = device if isinstance(device, str) else device_key(device)
     c = load_cache()
-    c.setdefault(device_key(device), {})[cls] = best
-    os.makedirs(os.path.dirname(CACHE), exist_ok=True)
-    with open(CACHE, "w") as f:
+    c.setdefault(key, {})[cls] = best
+    p = cache_path()
+    os.makedirs(os.path.dirname(p) or ".", exist_ok=True)
+    tmp = p + f".tmp{os.getpid()}"
+    with open(tmp, "w") as f:
         json.dump(c, f, indent=1)
+    os.replace(tmp, p)
 
 
-def cached_choice(device: int, cls: str):
-    return load_cache().get(device_key(device), {}).get(cls)
+def cached_choice(device, cls: str):
+    key = device if isinstance(device, str) else device_key(device)
+    return load_cache().get(key, {}).get(cls)
 
 
 def main():

@@ -113,3 +113,24 @@ def test_product_and_oracle_share_no_code():
         s = open(p).read()
         assert "paper_2603_00292_amd" not in s, p
         assert "rt_layout" not in s and "rt_kernels" not in s, p
+
+
+def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
+    """The autotuner's JSON cache (host logic): keyed by device and scene
+    class (powers of four of the triangle and ray counts), atomic rewrite,
+    choices of other classes and devices kept."""
+    from paper_2603_00292_amd import autotune
+
+    monkeypatch.setenv("RTQ_AUTOTUNE_CACHE", str(tmp_path / "sub" / "tune.json"))
+    assert autotune.scene_class(1_310_720, 4_194_304) == "tri4^10_ray4^11"
+    assert autotune.scene_class(4096, 65536) == "tri4^6_ray4^8"
+    assert autotune.cached_choice("gfx950_cu256", "tri4^10_ray4^11") is None
+    a = {"node_width": 4, "stack_entries": 16, "workgroup": 256, "ms": 1.9}
+    b = {"node_width": 8, "stack_entries": 32, "workgroup": 128, "ms": 0.1}
+    autotune.save_choice("gfx950_cu256", "tri4^10_ray4^11", a)
+    autotune.save_choice("gfx950_cu256", "tri4^6_ray4^8", b)
+    autotune.save_choice("gfx942_cu304", "tri4^10_ray4^11", b)
+    assert autotune.cached_choice("gfx950_cu256", "tri4^10_ray4^11") == a
+    assert autotune.cached_choice("gfx950_cu256", "tri4^6_ray4^8") == b
+    assert autotune.cached_choice("gfx942_cu304", "tri4^10_ray4^11") == b
+    assert not [p for p in (tmp_path / "sub").iterdir() if ".tmp" in p.name]
