@@ -550,39 +550,36 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
     if (live) {
       float tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
       // Tests the triangles of one leaf; true when an any-hit query may stop.
-      auto test_leaf = [&](uint32_t ref) -> bool {
-        uint32_t first = ref & RT_LEAF_FIRST_MASK;
-        uint32_t count = (ref >> RT_LEAF_COUNT_SHIFT) & RT_LEAF_COUNT_MASK;
-        for (uint32_t k = 0; k < count; ++k) {
-          const float4* tp = g.tris + 3 * (size_t)(first + k);
-          if constexpr (COUNT) n_tris++;
-          float4 A = tp[0], B = tp[1], C = tp[2];
-          float t;
-          if (tri_test(A, B, C, r, t) && t >= r.tmin && t <= best_t) {
-            uint32_t prim = __float_as_uint(A.w);
-            if constexpr (MODE >= 2) {
-              if (prim == skip_p && (!INST || cur_inst == skip_i)) continue;
-            }
-            if constexpr (MODE == 3) {
-              list_insert(reinterpret_cast<float4*>(hit_out) + (size_t)ray_id * P.cap, found, P.cap, t,
-                          INST ? cur_inst : 0u, prim, first + k);
-              ++found;
-              continue;
-            }
-            if constexpr (ANY) {
-              best_rec = first + k;
-              return true;
-            } else {
-              // lexicographic (t, inst, prim); t <= best_t here
-              uint32_t inst = INST ? cur_inst : 0u;
-              bool better = (t < best_t) || (inst < best_inst);
-              if (!better && inst == best_inst)
-                better = prim < __float_as_uint(g.tris[3 * (size_t)best_rec].w);
-              if (better) {
-                best_t = t;
-                best_inst = inst;
-                best_rec = first + k;
-              }
+      // Tests triangle record `rec`; true when an any-hit query may stop.
+      auto test_tri = [&](uint32_t rec) -> bool {
+        const float4* tp = g.tris + 3 * (size_t)rec;
+        if constexpr (COUNT) n_tris++;
+        float4 A = tp[0], B = tp[1], C = tp[2];
+        float t;
+        if (tri_test(A, B, C, r, t) && t >= r.tmin && t <= best_t) {
+          uint32_t prim = __float_as_uint(A.w);
+          if constexpr (MODE >= 2) {
+            if (prim == skip_p && (!INST || cur_inst == skip_i)) return false;
+          }
+          if constexpr (MODE == 3) {
+            list_insert(reinterpret_cast<float4*>(hit_out) + (size_t)ray_id * P.cap, found, P.cap, t,
+                        INST ? cur_inst : 0u, prim, rec);
+            ++found;
+            return false;
+          }
+          if constexpr (ANY) {
+            best_rec = rec;
+            return true;
+          } else {
+            // lexicographic (t, inst, prim); t <= best_t here
+            uint32_t inst = INST ? cur_inst : 0u;
+            bool better = (t < best_t) || (inst < best_inst);
+            if (!better && inst == best_inst)
+              better = prim < __float_as_uint(g.tris[3 * (size_t)best_rec].w);
+            if (better) {
+              best_t = t;
+              best_inst = inst;
+              best_rec = rec;
             }
           }
         }
@@ -655,18 +652,29 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
         if (__ballot(pend == RT_CHILD_EMPTY) == 0) break;
       }
       // ---- triangle leaves: the postponed one, then those on the stack top --
-      while (pend != RT_CHILD_EMPTY) {
-        bool stop = test_leaf(pend);
-        pend = RT_CHILD_EMPTY;
+      // One triangle per iteration: a lane whose leaf is done moves on to
+      // its next leaf while others finish longer leaves (leaves hold 1-15
+      // triangles), instead of waiting for the longest leaf of the wave.
+      // The nearest-hit cull distance is updated after each leaf, as before.
+      uint32_t tnext = pend & RT_LEAF_FIRST_MASK;
+      uint32_t tleft = pend != RT_CHILD_EMPTY ? (pend >> RT_LEAF_COUNT_SHIFT) & RT_LEAF_COUNT_MASK : 0u;
+      pend = RT_CHILD_EMPTY;
+      while (tleft > 0) {
+        bool stop = test_tri(tnext);
+        ++tnext;
+        --tleft;
         if (ANY && stop) {
           cur = RT_CHILD_EMPTY;
           st.sp = 0;
           break;
         }
-        tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
-        if (cur != RT_CHILD_EMPTY && is_tri_leaf(cur)) {
-          pend = cur;
-          cur = st.pop();
+        if (tleft == 0) {
+          tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
+          if (cur != RT_CHILD_EMPTY && is_tri_leaf(cur)) {
+            tnext = cur & RT_LEAF_FIRST_MASK;
+            tleft = (cur >> RT_LEAF_COUNT_SHIFT) & RT_LEAF_COUNT_MASK;
+            cur = st.pop();
+          }
         }
       }
       // ---- finished: write the result --------------------------------------
