@@ -74,6 +74,41 @@ def autotune(ctx: api.Context, vertices: torch.Tensor, indices: torch.Tensor, pr
     return to(best), [to(table[i]) for i in range(min(n.value, cap))]
 
 
+VARIANTS = [(s, wg) for s in (8, 16, 32) for wg in (64, 128, 256)]
+DEFAULT_VARIANT = (16, 256)
+
+
+def tune_variant(ctx: api.Context, make_run, repeats: int = 3, margin: float = 0.01):
+    """Picks (stack entries, workgroup) for any query on an existing accel:
+    for every variant the context is set to it, ``make_run()`` returns a
+    callable that enqueues one query on the current stream (for a batched
+    plan: a plan created under that variant, whose launch it returns), which
+    is timed with HIP events (median of ``repeats`` after a warm-up).  The
+    default variant stays unless another is faster by more than ``margin``.
+    Sets the context's variant to the choice; returns (choice, table)."""
+    stream = torch.cuda.current_stream()
+    table = []
+    for s, wg in VARIANTS:
+        ctx.set_variant(s, wg)
+        run = make_run()
+        run()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(repeats):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            run()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        table.append({"stack_entries": s, "workgroup": wg, "ms": round(sorted(times)[len(times) // 2], 5)})
+    default = next(e for e in table if (e["stack_entries"], e["workgroup"]) == DEFAULT_VARIANT)
+    fastest = min(table, key=lambda e: e["ms"])
+    best = default if default["ms"] <= fastest["ms"] * (1 + margin) else fastest
+    ctx.set_variant(best["stack_entries"], best["workgroup"])
+    return best, table
+
+
 def cache_path() -> str:
     return os.environ.get("RTQ_AUTOTUNE_CACHE", CACHE)
 

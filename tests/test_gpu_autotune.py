@@ -73,3 +73,57 @@ def test_autotune_cache(tmp_path, monkeypatch):
     assert cached and again == best
     assert ctx2.variant == (best["stack_entries"], best["workgroup"])
     ctx.close(); ctx2.close()
+
+
+def test_tune_variant_other_queries():
+    """tune_variant picks the (stack, workgroup) variant for any-hit, two-level
+    closest and batched plans on existing accels; every variant answers the
+    same."""
+    import torch
+
+    from paper_2603_00292_amd import api, autotune
+    from helpers import to_gpu_scene
+
+    torch.cuda.set_device(0)
+    ctx = api.Context(0)
+    W = wl.random_triangles(n_tri=20000, n_rays=65536, k=602, half=0.02)
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    rays = torch.from_numpy(W.rays).cuda()
+    outs = []
+
+    def make_any():
+        def run():
+            outs.append(api.trace_any(acc, rays))
+        return run
+    best, table = autotune.tune_variant(ctx, make_any, repeats=2)
+    assert len(table) == 9 and ctx.variant == (best["stack_entries"], best["workgroup"])
+    torch.cuda.synchronize()
+    assert all(torch.equal(o, outs[0]) for o in outs)
+    # two-level closest with instance ids
+    W2 = wl.instanced_grids(n_inst=64, n_rays=20000, k=603)
+    acc2 = to_gpu_scene(api, torch, ctx, W2.scene)
+    rays2 = torch.from_numpy(W2.rays).cuda()
+    outs2 = []
+
+    def make_inst():
+        def run():
+            outs2.append(api.trace_closest(acc2, rays2, want_inst=True))
+        return run
+    autotune.tune_variant(ctx, make_inst, repeats=2)
+    torch.cuda.synchronize()
+    assert all(torch.equal(h.view(torch.int32), outs2[0][0].view(torch.int32)) and torch.equal(i, outs2[0][1])
+               for h, i in outs2)
+    # batched plans (a plan keeps the variant it was created with)
+    plans = []
+
+    def make_plan():
+        plan = api.BatchPlan(ctx, [acc, acc], [rays[:30000].contiguous(), rays[30000:].contiguous()])
+        plans.append(plan)
+        return plan.launch
+    autotune.tune_variant(ctx, make_plan, repeats=2)
+    torch.cuda.synchronize()
+    ref = [h.clone() for h in plans[0].hits]
+    for p in plans:
+        assert all(torch.equal(a.view(torch.int32), b.view(torch.int32)) for a, b in zip(p.hits, ref))
+        p.close()
+    acc.close(); acc2.close(); ctx.close()
