@@ -359,13 +359,17 @@ rt_status rt_trace_all(rt_accel accel, const rt_ray* rays, uint32_t n,
  *   d_vertices[v_k] += -w_k lambda  (w = (1-u-v, u, v))
  * using the accel's copy of the vertices it was built from.  d_vertices
  * (device, vertex_count*3 float32) is ACCUMULATED deterministically, without
- * atomics: the rays are sorted by triangle (stably), each triangle sums its
- * rays' float64 contributions per corner in ray order, each vertex sums its
- * corners in (triangle, corner) order, and the float64 sum is rounded once
- * to float32 and added; repeated calls give bit-identical results.  The
- * first call on an accel builds its vertex -> corner lists (4 bytes per
- * vertex and 84 per triangle); the context keeps 56 bytes per ray of sort
- * buffers, grown stream-ordered on `stream` when n exceeds them.
+ * global atomics: the hit rays are grouped by triangle range, each
+ * (triangle, corner) sums its rays' float64 contributions exactly, as 64-bit
+ * integers at the row's binary scale, each vertex adds its corners' values
+ * in (triangle, corner) order, and the float64 sum is rounded once to
+ * float32 and added; repeated calls, and calls with the rays permuted, give
+ * bit-identical results.  The first call on an accel builds its vertex ->
+ * corner lists and a per-triangle copy of the vertices (4 bytes per vertex
+ * and 120 per triangle; rt_refit marks the copy stale and the next call
+ * refreshes it); the context keeps 48 bytes per ray plus 4 per (4096-ray
+ * tile, triangle range) of sort buffers, grown stream-ordered on `stream`
+ * when n exceeds them.
  * d_origins / d_directions (device, n*3 float32) are overwritten (zero for
  * misses).  t, u, v are recomputed in float64 from the triangle, so `hits`
  * contributes only the triangle id.

@@ -109,11 +109,13 @@ __device__ __forceinline__ void add(const Acc& a, uint32_t row, double x, double
 // ---------------------------------------------------------------------------
 //   bucket   the rays are grouped by triangle range (buckets of 256, 512 or
 //            1024 triangles, the smallest that keeps the bucket count within
-//            kMaxBuckets): per-tile LDS histograms of the hit triangles and
-//            an exclusive scan; then the adjoint kernel writes each hit ray's
-//            48-byte record (float64 lambda, u, v and its triangle) straight
-//            into its bucket through LDS counters (the order inside a bucket
-//            is not fixed, and does not need to be);
+//            kMaxBuckets): per-tile LDS histograms of the hit triangles, then
+//            one launch that scans every bucket's column of tile counts;
+//            then the adjoint kernel scans the bucket totals in LDS and
+//            writes each hit ray's 48-byte record (float64 lambda, u, v and
+//            its triangle) straight into its bucket through LDS counters
+//            (the order inside a bucket is not fixed, and does not need to
+//            be);
 //   corner   one workgroup per bucket sums -w_k lambda of its rays per
 //            (triangle, corner) in LDS, exactly, as 64-bit integers at the
 //            row's binary scale (an LDS maximum of the exponents first), and
@@ -142,25 +144,33 @@ inline uint32_t bucket_shift(uint32_t triangles) {
   return 0;
 }
 
-// Per accel: the vertex -> (triangle << 2 | corner) lists and the corner values.
+// Per accel: the vertex -> (triangle << 2 | corner) lists, the corner values
+// and a copy of every triangle's three vertices (so the adjoint reads one
+// 36-byte record per hit instead of an index triple and three vertices).
 struct Gather {
   uint32_t* csr_off = nullptr;   // vertex_count + 1
   uint32_t* csr_ent = nullptr;   // 3 * triangle_count
   double* corner = nullptr;      // 9 per triangle: corner k's 3 components
+  float* tri_vertices = nullptr; // 9 per triangle: vertex k's x, y, z
+  bool tri_vertices_valid = false;
   uint32_t vertices = 0, triangles = 0, shift = 0, buckets = 0;
 };
 
 // Per context: buffers sized by the ray count (grown stream-ordered).
 struct SortBuf {
   RayRec* rec = nullptr;         // cap: records grouped by bucket
-  uint32_t* counts = nullptr;    // buckets x tiles histogram, scanned in place (+1 total)
-  uint32_t* partial = nullptr;   // scan partials
-  size_t cap = 0, count_cap = 0, partial_cap = 0;
+  uint32_t* counts = nullptr;    // tiles x buckets histogram (tile-major), scanned per bucket in place
+  uint32_t* scan = nullptr;      // bucket totals (buckets), bucket starts (buckets + 1)
+  size_t cap = 0, count_cap = 0, scan_cap = 0;
 };
 
-// What the adjoint kernel needs to place its records.
+// What the adjoint kernel needs to place its records: tile t's first slot
+// in bucket b is base[b] + counts[t * buckets + b], base the exclusive scan
+// of the totals (which the adjoint kernel's workgroup 0 stores).
 struct Bucketing {
-  const uint32_t* offsets;       // scanned counts: offsets[bucket * tiles + tile]
+  const uint32_t* counts;
+  const uint32_t* totals;        // rays per bucket
+  uint32_t* base;                // buckets + 1 bucket starts (the last one: the hit count)
   uint32_t tiles, buckets, shift;
   RayRec* rec;
 };
@@ -168,13 +178,16 @@ struct Bucketing {
 // Builds g from the mesh's indices (host copy): counting sort by vertex,
 // entries in ascending (triangle, corner) order.
 hipError_t gather_build(Gather& g, const uint32_t* host_indices, uint32_t vertices, uint32_t triangles);
+// Refreshes g.tri_vertices from the mesh's device indices and vertices when
+// it is not valid (after the build, and after each refit).
+hipError_t gather_tri_vertices(Gather& g, const uint32_t* indices, const float* vertices, hipStream_t s);
 void gather_release(Gather& g);
 // Makes b hold n rays for g's mesh; a larger n frees and allocates
 // stream-ordered on s (no device-wide synchronisation).
 hipError_t sort_reserve(SortBuf& b, const Gather& g, size_t n, hipStream_t s);
 void sort_release(SortBuf& b);
 // Histogram of the rays' hit triangles (prim ids at hit_words[4 i + 1],
-// counting those below the mesh's triangle count) and its scan; returns the
+// counting those below the mesh's triangle count) and its scans; returns the
 // adjoint kernel's placement.
 hipError_t bucket_rays(const Gather& g, SortBuf& b, const uint32_t* hit_words, uint32_t n, hipStream_t s,
                        Bucketing* out);

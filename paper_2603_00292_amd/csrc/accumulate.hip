@@ -114,13 +114,10 @@ hipError_t convert(const Rows& r, uint32_t first, uint32_t count, int layout, in
 namespace rta {
 namespace {
 
-constexpr uint32_t kScanChunk = 2048;   // elements per workgroup of the scan
-
-// per-tile histogram of the rays' buckets: counts[bucket * tiles + tile];
+// per-tile histogram of the rays' buckets: counts[tile * buckets + bucket];
 // counts the rays whose prim id is a triangle of the mesh
 __global__ __launch_bounds__(1024) void hist_kernel(const uint32_t* hit_words, uint32_t n, uint32_t triangles,
-                                                    uint32_t shift, uint32_t buckets, uint32_t tiles,
-                                                    uint32_t* counts) {
+                                                    uint32_t shift, uint32_t buckets, uint32_t* counts) {
   extern __shared__ uint32_t h[];
   for (uint32_t b = threadIdx.x; b < buckets; b += 1024) h[b] = 0u;
   __syncthreads();
@@ -131,91 +128,77 @@ __global__ __launch_bounds__(1024) void hist_kernel(const uint32_t* hit_words, u
     if (k < triangles) atomicAdd(&h[k >> shift], 1u);
   }
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < buckets; b += 1024) counts[(size_t)b * tiles + blockIdx.x] = h[b];
+  uint32_t* row = counts + (size_t)blockIdx.x * buckets;
+  for (uint32_t b = threadIdx.x; b < buckets; b += 1024) row[b] = h[b];
 }
 
-// exclusive scan of m elements in three launches: chunk sums, a scan of the
-// sums (one workgroup), then each chunk scanned from its offset
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-  const uint32_t lane = threadIdx.x & 63u;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    uint32_t o = (uint32_t)__shfl_up((int)v, d);
-    if (lane >= (uint32_t)d) v += o;
-  }
-  return v;
-}
-
-// exclusive scan of one value per thread over a 256-thread workgroup; *total
-// receives the sum
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
-  uint32_t inc = wave_incl_scan(v);
-  uint32_t w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63u) == 63u) wsum[w] = inc;
-  __syncthreads();
-  uint32_t off = 0, all = 0;
-#pragma unroll
-  for (uint32_t k = 0; k < 4; ++k) {
-    uint32_t x = wsum[k];
-    off += (k < w) ? x : 0u;
-    all += x;
-  }
-  __syncthreads();
-  *total = all;
-  return off + inc - v;
-}
-
-__global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t* x, uint32_t m, uint32_t* partial) {
-  __shared__ uint32_t wsum[4];
-  uint32_t base = blockIdx.x * kScanChunk;
-  uint32_t s = 0;
-  for (uint32_t i = base + threadIdx.x; i < min(m, base + kScanChunk); i += 256) s += x[i];
-  uint32_t total;
-  (void)block_excl_scan(s, wsum, &total);
-  if (threadIdx.x == 0) partial[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(256) void scan_partials_kernel(uint32_t* partial, uint32_t parts) {
-  __shared__ uint32_t wsum[4];
-  uint32_t carry = 0;
-  for (uint32_t base = 0; base < parts; base += 256) {
-    uint32_t i = base + threadIdx.x;
-    uint32_t v = i < parts ? partial[i] : 0u;
-    uint32_t total;
-    uint32_t ex = block_excl_scan(v, wsum, &total);
-    if (i < parts) partial[i] = carry + ex;
-    carry += total;
-  }
-}
-
-// scans chunk blockIdx.x in place from its offset (8 elements per thread);
-// element m receives the grand total
-__global__ __launch_bounds__(256) void scan_down_kernel(uint32_t* x, uint32_t m, const uint32_t* partial,
-                                                        uint32_t parts) {
-  __shared__ uint32_t wsum[4];
-  uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * 8;
-  uint32_t v[8];
+// Column scan: workgroup g owns buckets 64 g .. 64 g + 63 (one per lane) and
+// splits the tiles over its 16 waves; each bucket's tile counts become the
+// offsets of the tiles inside the bucket, and its total goes to totals[]
+// (the adjoint kernel scans the totals into bucket starts).
+__global__ __launch_bounds__(1024) void colscan_kernel(uint32_t* counts, uint32_t tiles, uint32_t buckets,
+                                                       uint32_t* totals) {
+  __shared__ uint32_t part[16][64];
+  const uint32_t l = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  const uint32_t b = blockIdx.x * 64u + l;
+  const uint32_t per = (tiles + 15u) / 16u;
+  const uint32_t t0 = min(tiles, w * per), t1 = min(tiles, t0 + per);
+  // the loads of a block of kU tiles are issued together; the first block
+  // stays in registers for the second pass (all of it when tiles <= 16 kU)
+  constexpr uint32_t kU = 16;
+  uint32_t first[kU];
   uint32_t s = 0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    v[k] = (base + k < m) ? x[base + k] : 0u;
-    s += v[k];
+  for (uint32_t k = 0; k < kU; ++k) {
+    first[k] = (b < buckets && t0 + k < t1) ? counts[(size_t)(t0 + k) * buckets + b] : 0u;
+    s += first[k];
   }
-  uint32_t total;
-  uint32_t run = partial[blockIdx.x] + block_excl_scan(s, wsum, &total);
+  if (b < buckets)
+    for (uint32_t t = t0 + kU; t < t1; t += kU) {
+      uint32_t v[kU];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    if (base + k < m) x[base + k] = run;
-    run += v[k];
+      for (uint32_t k = 0; k < kU; ++k) v[k] = t + k < t1 ? counts[(size_t)(t + k) * buckets + b] : 0u;
+#pragma unroll
+      for (uint32_t k = 0; k < kU; ++k) s += v[k];
+    }
+  part[w][l] = s;
+  __syncthreads();
+  uint32_t run = 0, total = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < 16; ++k) {
+    uint32_t x = part[k][l];
+    run += k < w ? x : 0u;
+    total += x;
   }
-  if (blockIdx.x + 1 == parts && threadIdx.x == 0) x[m] = partial[blockIdx.x] + total;
+  if (b < buckets) {
+#pragma unroll
+    for (uint32_t k = 0; k < kU; ++k)
+      if (t0 + k < t1) {
+        counts[(size_t)(t0 + k) * buckets + b] = run;
+        run += first[k];
+      }
+    for (uint32_t t = t0 + kU; t < t1; t += kU) {
+      uint32_t v[kU];
+#pragma unroll
+      for (uint32_t k = 0; k < kU; ++k) v[k] = t + k < t1 ? counts[(size_t)(t + k) * buckets + b] : 0u;
+#pragma unroll
+      for (uint32_t k = 0; k < kU; ++k)
+        if (t + k < t1) {
+          counts[(size_t)(t + k) * buckets + b] = run;
+          run += v[k];
+        }
+    }
+    if (w == 0) totals[b] = total;
+  }
 }
 
-// one workgroup per bucket: exact corner sums of its rays (TB triangles)
+// one workgroup per bucket: exact corner sums of its rays (TB triangles).
+// A thread's first kCache records stay in registers between the two passes.
 template <uint32_t TB>
-__global__ __launch_bounds__(512) void corner_kernel(const RayRec* rec, const uint32_t* offsets, uint32_t tiles,
+__global__ __launch_bounds__(512) void corner_kernel(const RayRec* rec, const uint32_t* bucket_base,
                                                      uint32_t triangles, int shift0, double* corner) {
   constexpr uint32_t R = 3 * TB;   // rows (triangle, corner)
+  constexpr uint32_t kCache = 4;
   __shared__ unsigned long long sum[3 * R];
   __shared__ int expo[R];
   const uint32_t b = blockIdx.x;
@@ -223,12 +206,17 @@ __global__ __launch_bounds__(512) void corner_kernel(const RayRec* rec, const ui
     expo[r] = INT_MIN;
     sum[3 * r] = sum[3 * r + 1] = sum[3 * r + 2] = 0ull;
   }
-  __syncthreads();
-  const uint32_t lo = offsets[(size_t)b * tiles], hi = offsets[(size_t)(b + 1) * tiles];
+  const uint32_t lo = bucket_base[b], hi = bucket_base[b + 1];
   const uint32_t t0 = b * TB;
+  RayRec cache[kCache];
+#pragma unroll
+  for (uint32_t k = 0; k < kCache; ++k) {
+    uint32_t j = lo + threadIdx.x + k * 512;
+    if (j < hi) cache[k] = rec[j];
+  }
+  __syncthreads();
   // pass 1: each row's largest binary exponent
-  for (uint32_t j = lo + threadIdx.x; j < hi; j += 512) {
-    RayRec q = rec[j];
+  auto bound = [&](const RayRec& q) {
     uint32_t tl = q.prim - t0;
     double w[3] = {1.0 - q.u - q.v, q.u, q.v};
     // bounds every component of -w_k lambda; a NaN or inf makes the row NaN
@@ -238,11 +226,14 @@ __global__ __launch_bounds__(512) void corner_kernel(const RayRec* rec, const ui
       double a = fabs(w[k]) * m;
       if (a != 0.0) atomicMax(&expo[3 * tl + k], a <= DBL_MAX ? ilogb(a) : INT_MAX);
     }
-  }
+  };
+#pragma unroll
+  for (uint32_t k = 0; k < kCache; ++k)
+    if (lo + threadIdx.x + k * 512 < hi) bound(cache[k]);
+  for (uint32_t j = lo + threadIdx.x + kCache * 512; j < hi; j += 512) bound(rec[j]);
   __syncthreads();
   // pass 2: integer sums at each row's scale
-  for (uint32_t j = lo + threadIdx.x; j < hi; j += 512) {
-    RayRec q = rec[j];
+  auto add = [&](const RayRec& q) {
     uint32_t tl = q.prim - t0;
     double w[3] = {1.0 - q.u - q.v, q.u, q.v};
 #pragma unroll
@@ -257,7 +248,11 @@ __global__ __launch_bounds__(512) void corner_kernel(const RayRec* rec, const ui
         if (v) atomicAdd(&sum[3 * (3 * tl + k) + d], (unsigned long long)v);
       }
     }
-  }
+  };
+#pragma unroll
+  for (uint32_t k = 0; k < kCache; ++k)
+    if (lo + threadIdx.x + k * 512 < hi) add(cache[k]);
+  for (uint32_t j = lo + threadIdx.x + kCache * 512; j < hi; j += 512) add(rec[j]);
   __syncthreads();
   for (uint32_t r = threadIdx.x; r < R; r += 512) {
     uint32_t t = t0 + r / 3;
@@ -273,17 +268,50 @@ __global__ __launch_bounds__(512) void corner_kernel(const RayRec* rec, const ui
   }
 }
 
+// every triangle's vertices, in index order, 9 floats per triangle
+__global__ __launch_bounds__(256) void tri_vertices_kernel(const uint32_t* I, const float* V, uint32_t triangles,
+                                                           float* out) {
+  uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= triangles) return;
+  float* o = out + 9 * (size_t)t;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float* v = V + 3 * (size_t)I[3 * (size_t)t + k];
+    o[3 * k] = v[0];
+    o[3 * k + 1] = v[1];
+    o[3 * k + 2] = v[2];
+  }
+}
+
+// each vertex: its corner values added in list order (the loads of up to
+// eight entries issued together; the sum order is the list order)
 __global__ __launch_bounds__(256) void vertex_kernel(const uint32_t* csr_off, const uint32_t* csr_ent,
                                                      const double* corner, uint32_t vertices, float* out) {
   uint32_t v = blockIdx.x * 256u + threadIdx.x;
   if (v >= vertices) return;
+  constexpr uint32_t U = 8;
   double x = 0.0, y = 0.0, z = 0.0;
-  for (uint32_t j = csr_off[v]; j < csr_off[v + 1]; ++j) {
-    uint32_t e = csr_ent[j];
-    const double* c = corner + 9 * (size_t)(e >> 2) + 3 * (e & 3u);
-    x += c[0];
-    y += c[1];
-    z += c[2];
+  const uint32_t j1 = csr_off[v + 1];
+  for (uint32_t j = csr_off[v]; j < j1; j += U) {
+    uint32_t e[U];
+#pragma unroll
+    for (uint32_t k = 0; k < U; ++k) e[k] = j + k < j1 ? csr_ent[j + k] : 0u;
+    double c[U][3];
+#pragma unroll
+    for (uint32_t k = 0; k < U; ++k)
+      if (j + k < j1) {
+        const double* p = corner + 9 * (size_t)(e[k] >> 2) + 3 * (e[k] & 3u);
+        c[k][0] = p[0];
+        c[k][1] = p[1];
+        c[k][2] = p[2];
+      }
+#pragma unroll
+    for (uint32_t k = 0; k < U; ++k)
+      if (j + k < j1) {
+        x += c[k][0];
+        y += c[k][1];
+        z += c[k][2];
+      }
   }
   if (x == 0.0 && y == 0.0 && z == 0.0) return;
   out[3 * (size_t)v + 0] += (float)x;
@@ -319,6 +347,7 @@ hipError_t gather_build(Gather& g, const uint32_t* I, uint32_t vertices, uint32_
   hipError_t e = hipMalloc(&g.csr_off, off.size() * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc(&g.csr_ent, std::max<size_t>(ent.size(), 1) * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc(&g.corner, std::max<size_t>(9 * (size_t)triangles, 1) * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&g.tri_vertices, std::max<size_t>(9 * (size_t)triangles, 1) * sizeof(float));
   if (e == hipSuccess) e = hipMemcpy(g.csr_off, off.data(), off.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess && !ent.empty())
     e = hipMemcpy(g.csr_ent, ent.data(), ent.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
@@ -333,8 +362,19 @@ hipError_t gather_build(Gather& g, const uint32_t* I, uint32_t vertices, uint32_
   return hipSuccess;
 }
 
+hipError_t gather_tri_vertices(Gather& g, const uint32_t* indices, const float* vertices, hipStream_t s) {
+  if (g.tri_vertices_valid || g.triangles == 0) return hipSuccess;
+  float* out = g.tri_vertices;
+  uint32_t tris = g.triangles;
+  void* a[] = {&indices, &vertices, &tris, &out};
+  hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(&tri_vertices_kernel), dim3((tris + 255) / 256),
+                                 dim3(256), a, 0, s);
+  if (e == hipSuccess) g.tri_vertices_valid = true;
+  return e;
+}
+
 void gather_release(Gather& g) {
-  void* ps[] = {g.csr_off, g.csr_ent, g.corner};
+  void* ps[] = {g.csr_off, g.csr_ent, g.corner, g.tri_vertices};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   g = Gather();
@@ -343,15 +383,14 @@ void gather_release(Gather& g) {
 hipError_t sort_reserve(SortBuf& b, const Gather& g, size_t n, hipStream_t s) {
   size_t tiles = (n + kTile - 1) / kTile;
   size_t m = (size_t)g.buckets * tiles;
-  size_t parts = (m + kScanChunk - 1) / kScanChunk;
   hipError_t e = grow(&b.rec, &b.cap, n, s);
-  if (e == hipSuccess) e = grow(&b.counts, &b.count_cap, m + 1, s);
-  if (e == hipSuccess) e = grow(&b.partial, &b.partial_cap, std::max<size_t>(parts, 1), s);
+  if (e == hipSuccess) e = grow(&b.counts, &b.count_cap, std::max<size_t>(m, 1), s);
+  if (e == hipSuccess) e = grow(&b.scan, &b.scan_cap, 2 * (size_t)g.buckets + 1, s);
   return e;
 }
 
 void sort_release(SortBuf& b) {
-  void* ps[] = {b.rec, b.counts, b.partial};
+  void* ps[] = {b.rec, b.counts, b.scan};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   b = SortBuf();
@@ -361,35 +400,28 @@ hipError_t bucket_rays(const Gather& g, SortBuf& b, const uint32_t* hit_words, u
                        Bucketing* out) {
   uint32_t buckets = g.buckets, shift = g.shift, tris = g.triangles;
   uint32_t tiles = (n + kTile - 1) / kTile;
-  uint32_t m = buckets * tiles;
-  uint32_t parts = (m + kScanChunk - 1) / kScanChunk;
   uint32_t* counts = b.counts;
-  uint32_t* partial = b.partial;
-  *out = Bucketing{counts, tiles, buckets, shift, b.rec};
-  if (m == 0) return hipSuccess;   // no triangles: no ray has a bucket
-  void* a1[] = {&hit_words, &n, &tris, &shift, &buckets, &tiles, &counts};
+  uint32_t* totals = b.scan;
+  uint32_t* base = b.scan + buckets;
+  *out = Bucketing{counts, totals, base, tiles, buckets, shift, b.rec};
+  if (buckets == 0 || tiles == 0) return hipSuccess;   // no triangles or no rays: no ray has a bucket
+  void* a1[] = {&hit_words, &n, &tris, &shift, &buckets, &counts};
   hipError_t e = hipLaunchKernel(reinterpret_cast<const void*>(&hist_kernel), dim3(tiles), dim3(1024), a1,
                                  buckets * sizeof(uint32_t), s);
   if (e != hipSuccess) return e;
-  void* a2[] = {&counts, &m, &partial};
-  e = hipLaunchKernel(reinterpret_cast<const void*>(&scan_reduce_kernel), dim3(parts), dim3(256), a2, 0, s);
-  if (e != hipSuccess) return e;
-  void* a3[] = {&partial, &parts};
-  e = hipLaunchKernel(reinterpret_cast<const void*>(&scan_partials_kernel), dim3(1), dim3(256), a3, 0, s);
-  if (e != hipSuccess) return e;
-  void* a4[] = {&counts, &m, &partial, &parts};
-  return hipLaunchKernel(reinterpret_cast<const void*>(&scan_down_kernel), dim3(parts), dim3(256), a4, 0, s);
+  void* a2[] = {&counts, &tiles, &buckets, &totals};
+  return hipLaunchKernel(reinterpret_cast<const void*>(&colscan_kernel), dim3((buckets + 63) / 64), dim3(1024),
+                         a2, 0, s);
 }
 
 hipError_t gather_vertices(Gather& g, SortBuf& b, uint32_t n, float* out, hipStream_t s) {
   if (n == 0 || g.buckets == 0 || g.vertices == 0) return hipSuccess;
-  uint32_t tiles = (n + kTile - 1) / kTile;
   RayRec* rec = b.rec;
-  uint32_t* counts = b.counts;
+  uint32_t* base = b.scan + g.buckets;
   uint32_t tris = g.triangles;
   int shift0 = shift0_for(n);
   double* corner = g.corner;
-  void* a6[] = {&rec, &counts, &tiles, &tris, &shift0, &corner};
+  void* a6[] = {&rec, &base, &tris, &shift0, &corner};
   const void* k = g.shift == 8   ? reinterpret_cast<const void*>(&corner_kernel<256>)
                   : g.shift == 9 ? reinterpret_cast<const void*>(&corner_kernel<512>)
                                  : reinterpret_cast<const void*>(&corner_kernel<1024>);

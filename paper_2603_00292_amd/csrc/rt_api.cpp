@@ -1543,11 +1543,13 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
     if (rta::bucket_shift(mesh.triangle_count) == 0)
       return fail(RT_ERROR_UNSUPPORTED, "rt_trace_backward: more than %u triangles", rta::kMaxBuckets << 10);
     RT_HIP(rta::gather_build(accel->gather, idx.data(), mesh.vertex_count, mesh.triangle_count));
-    accel->info.device_bytes += 4ull * (mesh.vertex_count + 1) + 84ull * mesh.triangle_count;
+    accel->info.device_bytes += 4ull * (mesh.vertex_count + 1) + 120ull * mesh.triangle_count;
   }
+  RT_HIP(rta::gather_tri_vertices(accel->gather, mesh.indices, mesh.vertices, s));
   RT_HIP(rta::sort_reserve(ctx->sortbuf, accel->gather, n, s));
   BackwardParams p{};
   p.mesh = mesh;
+  p.tri_vertices = accel->gather.tri_vertices;
   p.rays = rays;
   p.hits = hits;
   p.d_tuv = d_tuv;
@@ -1757,6 +1759,7 @@ rt_status rt_refit(rt_accel accel, const float* vertices, void* stream) {
   if (m.vertex_count > 0)
     RT_HIP(hipMemcpyAsync(const_cast<float*>(m.vertices), vertices, (size_t)m.vertex_count * 12,
                           hipMemcpyDefault, s));
+  accel->gather.tri_vertices_valid = false;   // the backward's per-triangle vertex copy
   RT_HIP(rtk_launch_refit_tris(accel->tris, accel->info.triangle_count, m, s));
   for (size_t l = 0; l + 1 < accel->refit_levels.size(); ++l) {
     uint32_t b = accel->refit_levels[l], e = accel->refit_levels[l + 1];

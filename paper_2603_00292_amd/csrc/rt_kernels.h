@@ -71,6 +71,7 @@ constexpr uint32_t kRtRangesPerWave = 128;
 // bucket for the vertex accumulation of accumulate.h.
 struct BackwardParams {
   rt_mesh_dev mesh;
+  const float* tri_vertices;   // 9 floats per triangle: its vertices in index order
   const rt_ray* rays;
   const rt_hit* hits;
   const float* d_tuv;

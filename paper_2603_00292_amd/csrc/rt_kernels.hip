@@ -739,17 +739,14 @@ struct Adjoint64 {
   uint32_t id[3];        // their indices
 };
 
-__device__ __forceinline__ bool adjoint64(const rt_mesh_dev& mesh, uint32_t prim, double ox,
-                                          double oy, double oz, double dx, double dy, double dz,
-                                          double gt, double gu, double gv, Adjoint64& A) {
-  const uint32_t* ix = mesh.indices + 3 * (size_t)prim;
-  const float* V = mesh.vertices;
+// the solve from the triangle's vertices pv (float32, vertex-major)
+__device__ __forceinline__ bool adjoint64_solve(const float* pv, double ox, double oy, double oz, double dx,
+                                                double dy, double dz, double gt, double gu, double gv,
+                                                Adjoint64& A) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    A.id[k] = ix[k];
+  for (int k = 0; k < 3; ++k)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) A.p[k][c] = V[3 * (size_t)A.id[k] + c];
-  }
+    for (int c = 0; c < 3; ++c) A.p[k][c] = pv[3 * k + c];
   double v0x = A.p[0][0], v0y = A.p[0][1], v0z = A.p[0][2];
   double e1x = A.p[1][0] - v0x, e1y = A.p[1][1] - v0y, e1z = A.p[1][2] - v0z;
   double e2x = A.p[2][0] - v0x, e2y = A.p[2][1] - v0y, e2z = A.p[2][2] - v0z;
@@ -772,54 +769,135 @@ __device__ __forceinline__ bool adjoint64(const rt_mesh_dev& mesh, uint32_t prim
   return true;
 }
 
+__device__ __forceinline__ bool adjoint64(const rt_mesh_dev& mesh, uint32_t prim, double ox,
+                                          double oy, double oz, double dx, double dy, double dz,
+                                          double gt, double gu, double gv, Adjoint64& A) {
+  const uint32_t* ix = mesh.indices + 3 * (size_t)prim;
+  const float* V = mesh.vertices;
+  float pv[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    A.id[k] = ix[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pv[3 * k + c] = V[3 * (size_t)A.id[k] + c];
+  }
+  return adjoint64_solve(pv, ox, oy, oz, dx, dy, dz, gt, gu, gv, A);
+}
+
 __device__ __forceinline__ void zero3(float* a) { a[0] = a[1] = a[2] = 0.0f; }
 
 // dL/do and dL/dd of the rays of one tile, and each hit ray's record
 // (lambda, u, v, triangle) placed in its triangle's bucket (LDS counters
-// start at the tile's scanned offsets; see accumulate.h).  A hit whose
-// adjoint is undefined (a singular M) still takes its slot, with a zero
-// record.
+// start at the tile's offsets; see accumulate.h).  A hit whose adjoint is
+// undefined (a singular M) still takes its slot, with a zero record.  Every
+// thread handles kTile / 1024 rays, two at a time with all of their loads
+// issued before either solve (the chain hit -> triangle vertices is what
+// the kernel waits on).
 __global__ __launch_bounds__(1024) void backward_kernel(BackwardParams P) {
   extern __shared__ uint32_t pos[];
+  constexpr uint32_t R = rta::kTile / 1024, G = 2;
+  static_assert(R % G == 0, "rays per thread");
   const rta::Bucketing& B = P.bk;
-  for (uint32_t b = threadIdx.x; b < B.buckets; b += 1024)
-    pos[b] = B.offsets[(size_t)b * B.tiles + blockIdx.x];
-  __syncthreads();
   const uint32_t base = blockIdx.x * rta::kTile;
-  for (uint32_t r = 0; r < rta::kTile / 1024; ++r) {
+  const uint32_t tc = P.mesh.triangle_count;
+  uint32_t prim[R];
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
     uint32_t i = base + r * 1024 + threadIdx.x;
-    if (i >= P.n) break;
-    const float4* hp = reinterpret_cast<const float4*>(P.hits + i);
-    uint32_t prim = __float_as_uint(hp->y);
-    float* go = P.d_origins + 3 * (size_t)i;
-    float* gd = P.d_directions + 3 * (size_t)i;
-    Adjoint64 A;
-    const bool valid = prim < P.mesh.triangle_count;
-    bool ok = false;
-    if (valid) {
-      rt_ray q = load_ray(P.rays, i);
-      const float* gr = P.d_tuv + 3 * (size_t)i;
-      ok = adjoint64(P.mesh, prim, q.ox, q.oy, q.oz, q.dx, q.dy, q.dz, gr[0], gr[1], gr[2], A);
+    prim[r] = i < P.n ? P.hits[i].prim_id : RT_INVALID_ID;
+  }
+  // bucket starts: an exclusive scan of the bucket totals over the
+  // workgroup (at most 16 buckets per thread); workgroup 0 stores them for
+  // the corner sums
+  {
+    __shared__ uint32_t wsum[16];
+    constexpr uint32_t C = rta::kMaxBuckets / 1024;
+    const uint32_t chunk = (B.buckets + 1023u) / 1024u;
+    const uint32_t c0 = min(B.buckets, threadIdx.x * chunk), c1 = min(B.buckets, c0 + chunk);
+    const uint32_t* tile_off = B.counts + (size_t)blockIdx.x * B.buckets;
+    uint32_t tot[C], off[C];
+    uint32_t own = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < C; ++k) {
+      const bool in = c0 + k < c1;
+      tot[k] = in ? B.totals[c0 + k] : 0u;
+      off[k] = in ? tile_off[c0 + k] : 0u;
+      own += tot[k];
     }
-    if (ok) {
-      go[0] = (float)A.lx; go[1] = (float)A.ly; go[2] = (float)A.lz;
-      gd[0] = (float)(A.t * A.lx); gd[1] = (float)(A.t * A.ly); gd[2] = (float)(A.t * A.lz);
-    } else {
-      zero3(go);
-      zero3(gd);
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    uint32_t inc = own;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      uint32_t o = (uint32_t)__shfl_up((int)inc, d);
+      if (lane >= (uint32_t)d) inc += o;
     }
-    if (valid) {
-      uint32_t p = atomicAdd(&pos[prim >> B.shift], 1u);
-      // three 16-byte stores (records are 48 bytes, the buffer 256-byte aligned)
-      float4* f = reinterpret_cast<float4*>(B.rec + p);
-      double r0 = ok ? A.lx : 0.0, r1 = ok ? A.ly : 0.0, r2 = ok ? A.lz : 0.0;
-      double r3 = ok ? A.u : 0.0, r4 = ok ? A.v : 0.0;
-      f[0] = make_float4(__int_as_float(__double2loint(r0)), __int_as_float(__double2hiint(r0)),
-                         __int_as_float(__double2loint(r1)), __int_as_float(__double2hiint(r1)));
-      f[1] = make_float4(__int_as_float(__double2loint(r2)), __int_as_float(__double2hiint(r2)),
-                         __int_as_float(__double2loint(r3)), __int_as_float(__double2hiint(r3)));
-      f[2] = make_float4(__int_as_float(__double2loint(r4)), __int_as_float(__double2hiint(r4)),
-                         __uint_as_float(prim), 0.0f);
+    if (lane == 63u) wsum[w] = inc;
+    __syncthreads();
+    uint32_t r = inc - own;
+    for (uint32_t k = 0; k < w; ++k) r += wsum[k];
+#pragma unroll
+    for (uint32_t k = 0; k < C; ++k)
+      if (c0 + k < c1) {
+        pos[c0 + k] = r + off[k];
+        if (blockIdx.x == 0) B.base[c0 + k] = r;
+        r += tot[k];
+      }
+    if (blockIdx.x == 0 && threadIdx.x == 1023u) B.base[B.buckets] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (uint32_t r0 = 0; r0 < R; r0 += G) {
+    float4 ra[G], rb[G];
+    float gr[G][3], pv[G][9];
+#pragma unroll
+    for (uint32_t g = 0; g < G; ++g) {
+      uint32_t i = base + (r0 + g) * 1024 + threadIdx.x;
+      if (prim[r0 + g] < tc) {
+        const float4* rp = reinterpret_cast<const float4*>(P.rays + i);
+        ra[g] = rp[0];
+        rb[g] = rp[1];
+        const float* q = P.d_tuv + 3 * (size_t)i;
+        gr[g][0] = q[0];
+        gr[g][1] = q[1];
+        gr[g][2] = q[2];
+        const float* tv = P.tri_vertices + 9 * (size_t)prim[r0 + g];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) pv[g][k] = tv[k];
+      }
+    }
+#pragma unroll
+    for (uint32_t g = 0; g < G; ++g) {
+      uint32_t i = base + (r0 + g) * 1024 + threadIdx.x;
+      if (i >= P.n) continue;
+      const uint32_t pr = prim[r0 + g];
+      float* go = P.d_origins + 3 * (size_t)i;
+      float* gd = P.d_directions + 3 * (size_t)i;
+      Adjoint64 A;
+      const bool valid = pr < tc;
+      bool ok = false;
+      if (valid)
+        ok = adjoint64_solve(pv[g], ra[g].x, ra[g].y, ra[g].z, rb[g].x, rb[g].y, rb[g].z, gr[g][0], gr[g][1],
+                             gr[g][2], A);
+      if (ok) {
+        go[0] = (float)A.lx; go[1] = (float)A.ly; go[2] = (float)A.lz;
+        gd[0] = (float)(A.t * A.lx); gd[1] = (float)(A.t * A.ly); gd[2] = (float)(A.t * A.lz);
+      } else {
+        zero3(go);
+        zero3(gd);
+      }
+      if (valid) {
+        uint32_t p = atomicAdd(&pos[pr >> B.shift], 1u);
+        // three 16-byte stores (records are 48 bytes, the buffer 256-byte aligned)
+        float4* f = reinterpret_cast<float4*>(B.rec + p);
+        double q0 = ok ? A.lx : 0.0, q1 = ok ? A.ly : 0.0, q2 = ok ? A.lz : 0.0;
+        double q3 = ok ? A.u : 0.0, q4 = ok ? A.v : 0.0;
+        f[0] = make_float4(__int_as_float(__double2loint(q0)), __int_as_float(__double2hiint(q0)),
+                           __int_as_float(__double2loint(q1)), __int_as_float(__double2hiint(q1)));
+        f[1] = make_float4(__int_as_float(__double2loint(q2)), __int_as_float(__double2hiint(q2)),
+                           __int_as_float(__double2loint(q3)), __int_as_float(__double2hiint(q3)));
+        f[2] = make_float4(__int_as_float(__double2loint(q4)), __int_as_float(__double2hiint(q4)),
+                           __uint_as_float(pr), 0.0f);
+      }
     }
   }
 }

@@ -304,6 +304,48 @@ def test_backward_is_deterministic(gpu):
     acc.close()
 
 
+def test_backward_after_refit(gpu):
+    """The adjoint reads a per-triangle copy of the vertices made on its first
+    call; a refit makes the next call refresh it.  After moving the vertices
+    (refit), the gradients equal those of a fresh accel built on the moved
+    vertices, bit for bit, and refitting back gives the first call's again."""
+    torch, api, ctx = gpu
+    W = wl.displaced_grid(nx=128, nz=64, n_rays=65536, k=307)
+    m = W.scene.meshes[0]
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    rays = torch.from_numpy(W.rays).cuda()
+    g = torch.from_numpy(W.extra["abc"]).cuda()
+    V0 = torch.from_numpy(m.vertices).cuda()
+    V1 = V0.clone()
+    V1[:, 1] += 0.02 * torch.sin(3.0 * V0[:, 0]) * torch.cos(2.0 * V0[:, 2])
+
+    def grads(a):
+        hits, _ = api.trace_closest(a, rays)
+        dV = torch.zeros_like(V0)
+        do, dd = api.trace_backward(a, rays, hits, g, dV)
+        torch.cuda.synchronize()
+        return hits, dV, do, dd
+
+    first = grads(acc)
+    acc.refit(V1)
+    moved = grads(acc)
+    fresh_acc = api.Accel(ctx, [(V1, torch.from_numpy(m.indices.view(np.int32)).cuda())])
+    fresh = grads(fresh_acc)
+    hit = moved[0][:, 1].view(torch.int32) != -1
+    assert torch.equal(moved[0].view(torch.int32), fresh[0].view(torch.int32))
+    say("refit: hit rays", int(hit.sum()), "of", hit.numel())
+    for a, b in zip(moved[1:], fresh[1:]):
+        assert torch.equal(a, b)
+    assert not torch.equal(moved[1], first[1])
+    acc.refit(V0)
+    back = grads(acc)
+    assert torch.equal(back[0].view(torch.int32), first[0].view(torch.int32))
+    for a, b in zip(back[1:], first[1:]):
+        assert torch.equal(a, b)
+    fresh_acc.close()
+    acc.close()
+
+
 @pytest.mark.parametrize("n_tri", [4_500_000, 8_500_000])
 def test_backward_large_meshes(gpu, orc, n_tri):
     """Meshes large enough to group the rays in buckets of 512 and of 1,024
