@@ -155,7 +155,13 @@ typedef struct rt_accel_info {
 
 /* Creates a context on HIP device `hip_device` and makes it current for the
  * calling thread's later library calls.  Errors: RT_ERROR_NO_DEVICE,
- * RT_ERROR_INVALID_VALUE (out == NULL), RT_ERROR_HIP. */
+ * RT_ERROR_INVALID_VALUE (out == NULL), RT_ERROR_OUT_OF_MEMORY, RT_ERROR_HIP.
+ * Test hook for the out-of-memory paths: with the environment variable
+ * RT_FAULT_ALLOC = k (k >= 1) set at this call, the k-th device or pinned
+ * allocation the library makes after it (by any context) fails once; the
+ * call that made it returns RT_ERROR_OUT_OF_MEMORY and frees what it had
+ * allocated, and objects it was to create are not created.  Unset or 0:
+ * no failure (this call disarms an earlier one). */
 rt_status rt_context_create(int hip_device, rt_context* out);
 /* Frees the context's scratch (global stacks, queue counters, the ray-range
  * lists of rt_trace_closest).  An accel

@@ -1,6 +1,7 @@
 // accumulate.hip -- conversion and reset of the integer accumulator rows
 // (see accumulate.h).
 #include "accumulate.h"
+#include "rt_alloc.h"
 
 namespace rta {
 namespace {
@@ -63,8 +64,8 @@ hipError_t alloc(Rows& r, uint32_t count) {
   release(r);
   if (count == 0) return hipSuccess;
   const size_t nsum = (size_t)kCopies * 4 * count;
-  hipError_t e = hipMalloc(&r.expo, count * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMalloc(&r.sums, nsum * sizeof(unsigned long long));
+  hipError_t e = rt_malloc(&r.expo, count * sizeof(uint32_t));
+  if (e == hipSuccess) e = rt_malloc(&r.sums, nsum * sizeof(unsigned long long));
   if (e != hipSuccess) {
     release(r);
     return e;
@@ -326,7 +327,7 @@ hipError_t grow(T** p, size_t* cap, size_t n, hipStream_t s) {
   if (*p) (void)hipFreeAsync(*p, s);
   *p = nullptr;
   *cap = 0;
-  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(p), c * sizeof(T), s);
+  hipError_t e = rt_malloc_async(reinterpret_cast<void**>(p), c * sizeof(T), s);
   if (e == hipSuccess) *cap = c;
   return e;
 }
@@ -344,10 +345,10 @@ hipError_t gather_build(Gather& g, const uint32_t* I, uint32_t vertices, uint32_
   std::vector<uint32_t> fill(off.begin(), off.end() - 1);
   for (size_t t = 0; t < triangles; ++t)
     for (uint32_t k = 0; k < 3; ++k) ent[fill[I[3 * t + k]]++] = (uint32_t)(t << 2) | k;
-  hipError_t e = hipMalloc(&g.csr_off, off.size() * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMalloc(&g.csr_ent, std::max<size_t>(ent.size(), 1) * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMalloc(&g.corner, std::max<size_t>(9 * (size_t)triangles, 1) * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&g.tri_vertices, std::max<size_t>(9 * (size_t)triangles, 1) * sizeof(float));
+  hipError_t e = rt_malloc(&g.csr_off, off.size() * sizeof(uint32_t));
+  if (e == hipSuccess) e = rt_malloc(&g.csr_ent, std::max<size_t>(ent.size(), 1) * sizeof(uint32_t));
+  if (e == hipSuccess) e = rt_malloc(&g.corner, std::max<size_t>(9 * (size_t)triangles, 1) * sizeof(double));
+  if (e == hipSuccess) e = rt_malloc(&g.tri_vertices, std::max<size_t>(9 * (size_t)triangles, 1) * sizeof(float));
   if (e == hipSuccess) e = hipMemcpy(g.csr_off, off.data(), off.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess && !ent.empty())
     e = hipMemcpy(g.csr_ent, ent.data(), ent.size() * sizeof(uint32_t), hipMemcpyHostToDevice);

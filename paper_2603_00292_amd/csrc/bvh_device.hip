@@ -23,6 +23,7 @@
 //      triangle records, handed down from its parent;
 //   8. triangle records in that order (vertices sorted, corner order kept).
 #include "bvh_device.h"
+#include "rt_alloc.h"
 
 #include <hipcub/hipcub.hpp>
 
@@ -480,7 +481,7 @@ struct Temps {
   hipError_t alloc(T** out, size_t count) {
     *out = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(out), count * sizeof(T));
+    hipError_t e = rt_malloc(reinterpret_cast<void**>(out), count * sizeof(T));
     if (e == hipSuccess) p.push_back(*out);
     return e;
   }
@@ -490,7 +491,7 @@ template <typename T>
 hipError_t keep(Output& out, T** p, size_t count) {
   *p = nullptr;
   if (count == 0) count = 1;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+  hipError_t e = rt_malloc(reinterpret_cast<void**>(p), count * sizeof(T));
   if (e == hipSuccess) {
     out.owned.push_back(*p);
     out.owned_bytes += count * sizeof(T);

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -23,6 +24,7 @@
 #include "bvh_build.h"
 #include "bvh_device.h"
 #include "rt_kernels.h"
+#include "rt_alloc.h"
 #include "rt_layout.h"
 
 namespace {
@@ -185,7 +187,7 @@ rt_status dev_alloc(rt_accel_s* a, T** p, size_t count) {
   *p = nullptr;
   if (count == 0) return RT_SUCCESS;
   void* q = nullptr;
-  RT_HIP(hipMalloc(&q, count * sizeof(T)));
+  RT_HIP(rt_malloc(&q, count * sizeof(T)));
   a->owned.push_back(q);
   a->info.device_bytes += count * sizeof(T);
   *p = static_cast<T*>(q);
@@ -210,7 +212,7 @@ uint32_t resident_blocks(const void* kern, int wg, int cu_count) {
 
 // Makes sure scratch holds a counter and a spill stack of `entries` entries.
 rt_status ensure_scratch(Scratch& s, size_t entries) {
-  if (!s.counter) RT_HIP(hipMalloc(&s.counter, 256));
+  if (!s.counter) RT_HIP(rt_malloc(&s.counter, 256));
   if (entries > s.gstack_entries) {
     if (s.gstack) {
       RT_HIP(hipDeviceSynchronize());
@@ -218,7 +220,7 @@ rt_status ensure_scratch(Scratch& s, size_t entries) {
       s.gstack = nullptr;
       s.gstack_entries = 0;
     }
-    RT_HIP(hipMalloc(&s.gstack, entries * sizeof(uint32_t)));
+    RT_HIP(rt_malloc(&s.gstack, entries * sizeof(uint32_t)));
     s.gstack_entries = entries;
   }
   return RT_SUCCESS;
@@ -242,7 +244,7 @@ rt_status ensure_ranges(Scratch& s, uint32_t gstride, uint32_t n, uint32_t refil
       s.ranges = nullptr;
       s.ranges_entries = 0;
     }
-    RT_HIP(hipMalloc(&s.ranges, entries * sizeof(uint32_t)));
+    RT_HIP(rt_malloc(&s.ranges, entries * sizeof(uint32_t)));
     s.ranges_entries = entries;
   }
   *ranges = s.ranges;
@@ -311,6 +313,16 @@ rt_status take_overflow(rt_context ctx, const char* who) {
 
 }  // namespace
 
+// allocations left until the injected failure (0: none armed; see rt_alloc.h)
+static std::atomic<int64_t> g_fault_alloc{0};
+
+bool rt_alloc_fault() {
+  int64_t v = g_fault_alloc.load(std::memory_order_relaxed);
+  while (v > 0)
+    if (g_fault_alloc.compare_exchange_weak(v, v - 1, std::memory_order_relaxed)) return v == 1;
+  return false;
+}
+
 extern "C" {
 
 const char* rt_status_string(rt_status s) {
@@ -334,6 +346,7 @@ uint32_t rt_version(void) { return 100; }
 rt_status rt_context_create(int hip_device, rt_context* out) {
   if (!out) return fail(RT_ERROR_INVALID_VALUE, "rt_context_create: out is NULL");
   *out = nullptr;
+  g_fault_alloc.store(std::max<int64_t>(0, env_int("RT_FAULT_ALLOC", 0)), std::memory_order_relaxed);
   int n = 0;
   hipError_t e = hipGetDeviceCount(&n);
   if (e != hipSuccess || n == 0)
@@ -360,7 +373,7 @@ rt_status rt_context_create(int hip_device, rt_context* out) {
     delete c;
     return fail(RT_ERROR_HIP, "rt_context_create: hipEventCreate failed");
   }
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->status), sizeof(uint32_t), hipHostMallocDefault) !=
+  if (rt_host_malloc(reinterpret_cast<void**>(&c->status), sizeof(uint32_t), hipHostMallocDefault) !=
       hipSuccess) {
     (void)hipEventDestroy(c->last_event);
     delete c;
@@ -1784,7 +1797,7 @@ rt_status rt_autotune(rt_context ctx, const rt_mesh_desc* mesh, const rt_ray* pr
   rt_status st = check_device(ctx->device);
   if (st != RT_SUCCESS) return st;
   rt_hit* hits = nullptr;
-  RT_HIP(hipMalloc(&hits, (size_t)n_probe * sizeof(rt_hit)));
+  RT_HIP(rt_malloc(&hits, (size_t)n_probe * sizeof(rt_hit)));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -1923,8 +1936,8 @@ static rt_status plan_create(rt_context ctx, const rt_accel* accels, const rt_ra
   p->workgroup = wg;
   p->stack_entries = v.stack_entries;
   size_t spill = max_stack > v.stack_entries ? (size_t)(max_stack - v.stack_entries) : 1;
-  hipError_t e1 = hipMalloc(&p->descs, d.size() * sizeof(BatchDesc));
-  hipError_t e2 = hipMalloc(&p->offsets, off.size() * sizeof(uint32_t));
+  hipError_t e1 = rt_malloc(&p->descs, d.size() * sizeof(BatchDesc));
+  hipError_t e2 = rt_malloc(&p->offsets, off.size() * sizeof(uint32_t));
   if (e1 != hipSuccess || e2 != hipSuccess)
     return bail(fail(RT_ERROR_OUT_OF_MEMORY, "rt_batch_plan_create: device allocation failed"));
   st = ensure_scratch(p->scratch, spill * p->grid * wg);
