@@ -105,41 +105,56 @@ __device__ __forceinline__ void add(const Acc& a, uint32_t row, double x, double
 }  // namespace rta
 
 // ---------------------------------------------------------------------------
-// Vertex gradients of single-level accels without global atomics
+// Gradients without global atomics: rays grouped by what they add to
 // ---------------------------------------------------------------------------
-//   bucket   the rays are grouped by triangle range (buckets of 256, 512 or
-//            1024 triangles, the smallest that keeps the bucket count within
-//            kMaxBuckets): per-tile LDS histograms of the hit triangles, then
-//            one launch that scans every bucket's column of tile counts;
-//            then the adjoint kernel scans the bucket totals in LDS and
-//            writes each hit ray's 48-byte record (float64 lambda, u, v and
-//            its triangle) straight into its bucket through LDS counters
-//            (the order inside a bucket is not fixed, and does not need to
-//            be);
-//   corner   one workgroup per bucket sums -w_k lambda of its rays per
-//            (triangle, corner) in LDS, exactly, as 64-bit integers at the
-//            row's binary scale (an LDS maximum of the exponents first), and
-//            writes each row's float64 value;
+//   bucket   the hit rays are grouped by key (a triangle range: buckets of
+//            2^shift triangles, the smallest shift that keeps the bucket
+//            count within kMaxBuckets; or an instance): per-tile LDS
+//            histograms of the keys, then one launch that scans every
+//            bucket's column of tile counts; then the adjoint kernel scans
+//            the bucket totals in LDS and writes each hit ray's 48-byte
+//            record straight into its bucket through LDS counters (the
+//            order inside a bucket is not fixed, and does not need to be);
+//   corner   one workgroup per triangle bucket sums -w_k lambda of its rays
+//            per (triangle, corner) in LDS, exactly, as 64-bit integers at
+//            the row's binary scale (an LDS maximum of the exponents first),
+//            and writes each row's float64 value;
 //   vertex   every vertex adds its corners' values in ascending (triangle,
 //            corner) order through a vertex -> (triangle, corner) list,
-//            rounds once to float32 and adds to the output.
-// The integer sums keep shift0 = 62 - H bits below each row's largest
-// contribution (2^H > n), so the result is independent of the schedule and
-// of the order of the rays: repeated calls and permuted rays give
-// bit-identical vertex gradients.
+//            rounds once to float32 and adds to the output;
+//   frame    (two-level) one workgroup per instance forms each ray's ten
+//            frame derivatives from its record and sums them exactly per
+//            row as in the atomic rows above (a workgroup maximum of the
+//            exponents, then 64-bit integer sums reduced over the
+//            workgroup), and adds the rounded sums to the output.
+// Two-level accels number the triangles and vertices of all meshes one
+// after another in build order (global ids).  The integer sums keep
+// shift0 = 62 - H bits below each row's largest contribution (2^H > n), so
+// the result is independent of the schedule and of the order of the rays:
+// repeated calls and permuted rays give bit-identical gradients.
 namespace rta {
 
-constexpr uint32_t kMaxBuckets = 16384;     // LDS counters: meshes up to 2^24 triangles
+constexpr uint32_t kMaxBuckets = 16384;     // LDS counters
 constexpr uint32_t kTile = 4096;            // rays per workgroup of the histogram and the adjoint
+constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 
+// per hit ray: float64 lambda (object space for two-level hits), u, v and
+// the (global) triangle
 struct RayRec {
   double lx, ly, lz, u, v;
   uint32_t prim, pad;
 };
 
-// log2 of the bucket size for a mesh of `triangles` triangles (0: too many)
-inline uint32_t bucket_shift(uint32_t triangles) {
-  for (uint32_t sh = 8; sh <= 10; ++sh)
+// per two-level hit ray: float64 world-space lambda and object hit point
+struct FrameRec {
+  double lx, ly, lz, px, py, pz;
+};
+static_assert(sizeof(FrameRec) == sizeof(RayRec), "one record buffer type");
+
+// log2 of the bucket size for `triangles` triangles, at least min_shift
+// (0: too many triangles)
+inline uint32_t bucket_shift(uint32_t triangles, uint32_t min_shift = 8) {
+  for (uint32_t sh = min_shift; sh <= 10; ++sh)
     if (((uint64_t)triangles + (1u << sh) - 1) >> sh <= kMaxBuckets) return sh;
   return 0;
 }
@@ -147,14 +162,41 @@ inline uint32_t bucket_shift(uint32_t triangles) {
 // Per accel: the vertex -> (triangle << 2 | corner) lists, the corner values
 // and a copy of every triangle's three vertices (so the adjoint reads one
 // 36-byte record per hit instead of an index triple and three vertices).
+// Two-level: global triangle and vertex ids, plus each mesh's first global
+// triangle and each instance's mesh.
 struct Gather {
-  uint32_t* csr_off = nullptr;   // vertex_count + 1
-  uint32_t* csr_ent = nullptr;   // 3 * triangle_count
+  uint32_t* csr_off = nullptr;   // vertices + 1
+  uint32_t* csr_ent = nullptr;   // 3 * triangles
   double* corner = nullptr;      // 9 per triangle: corner k's 3 components
   float* tri_vertices = nullptr; // 9 per triangle: vertex k's x, y, z
+  uint32_t* tri_base = nullptr;  // two-level: meshes + 1
+  uint32_t* inst_mesh = nullptr; // two-level: instances
   bool tri_vertices_valid = false;
   uint32_t vertices = 0, triangles = 0, shift = 0, buckets = 0;
 };
+
+// Where a ray's key comes from: kind 0, its triangle (single level); 1, its
+// global triangle; 2, its instance.  Rays without a valid hit have no key.
+struct KeySource {
+  const uint32_t* hit_words;     // prim id at hit_words[4 i + 1]
+  const uint32_t* inst_ids;      // two-level
+  const uint32_t* inst_mesh;     // two-level
+  const uint32_t* tri_base;      // two-level
+  uint32_t inst_count;
+  uint32_t triangles;            // single level
+  uint32_t kind;
+};
+
+__device__ __forceinline__ uint32_t ray_key(const KeySource& k, uint32_t i) {
+  const uint32_t prim = k.hit_words[4 * (size_t)i + 1];
+  if (k.kind == 0) return prim < k.triangles ? prim : kNoKey;
+  const uint32_t inst = k.inst_ids[i];
+  if (inst >= k.inst_count) return kNoKey;
+  const uint32_t m = k.inst_mesh[inst];
+  const uint32_t b0 = k.tri_base[m];
+  if (prim >= k.tri_base[m + 1] - b0) return kNoKey;
+  return k.kind == 1 ? b0 + prim : inst;
+}
 
 // Per context: buffers sized by the ray count (grown stream-ordered).
 struct SortBuf {
@@ -178,21 +220,30 @@ struct Bucketing {
 // Builds g from the mesh's indices (host copy): counting sort by vertex,
 // entries in ascending (triangle, corner) order.
 hipError_t gather_build(Gather& g, const uint32_t* host_indices, uint32_t vertices, uint32_t triangles);
-// Refreshes g.tri_vertices from the mesh's device indices and vertices when
-// it is not valid (after the build, and after each refit).
-hipError_t gather_tri_vertices(Gather& g, const uint32_t* indices, const float* vertices, hipStream_t s);
+// The same over several meshes (two-level): host indices of mesh m at
+// indices[m], global ids in mesh order; inst_mesh: host, one per instance.
+hipError_t gather_build_multi(Gather& g, const uint32_t* const* host_indices, const uint32_t* vertex_counts,
+                              const uint32_t* triangle_counts, uint32_t meshes, const uint32_t* inst_mesh,
+                              uint32_t instances, uint32_t min_shift);
 void gather_release(Gather& g);
-// Makes b hold n rays for g's mesh; a larger n frees and allocates
-// stream-ordered on s (no device-wide synchronisation).
-hipError_t sort_reserve(SortBuf& b, const Gather& g, size_t n, hipStream_t s);
+// Refreshes g.tri_vertices of mesh m (first global triangle `first`) from its
+// device indices and vertices; mark_valid after the last mesh.
+hipError_t gather_tri_vertices(Gather& g, const uint32_t* indices, const float* vertices, uint32_t triangles,
+                               uint32_t first, hipStream_t s);
+// Makes b hold n rays in `buckets` buckets; a larger n or bucket count
+// frees and allocates stream-ordered on s (no device-wide synchronisation).
+hipError_t sort_reserve(SortBuf& b, uint32_t buckets, size_t n, hipStream_t s);
 void sort_release(SortBuf& b);
-// Histogram of the rays' hit triangles (prim ids at hit_words[4 i + 1],
-// counting those below the mesh's triangle count) and its scans; returns the
-// adjoint kernel's placement.
-hipError_t bucket_rays(const Gather& g, SortBuf& b, const uint32_t* hit_words, uint32_t n, hipStream_t s,
-                       Bucketing* out);
+// Histogram of the rays' keys (buckets of 2^shift keys) and its scans;
+// returns the adjoint kernel's placement.
+hipError_t bucket_rays(const KeySource& keys, uint32_t buckets, uint32_t shift, SortBuf& b, uint32_t n,
+                       hipStream_t s, Bucketing* out);
 // After the adjoint kernel placed the records: sum per corner and per
 // vertex, out[3 v + c] += the vertex sums.
 hipError_t gather_vertices(Gather& g, SortBuf& b, uint32_t n, float* out, hipStream_t s);
+// After the adjoint kernel placed the frame records (one bucket per
+// instance): out[10 j + k] += instance j's frame gradients; srt: 10 floats
+// per instance (sx sy sz qx qy qz qw tx ty tz).
+hipError_t frame_sums(SortBuf& b, uint32_t instances, const float* srt, uint32_t n, float* out, hipStream_t s);
 
 }  // namespace rta

@@ -110,9 +110,11 @@ struct rt_context_s {
   uint32_t stack_limit = 0;    // RT_STACK_LIMIT: caps every lane's stack below the
                                // accel's bound (exercises the overflow report); 0 = off
   uint32_t* status = nullptr;  // host-mapped word: set by a lane whose stack overflows
+  bool backward_atomic = false;  // RT_BACKWARD_ATOMIC: two-level backward through the atomic rows
   std::mutex mu;
   Scratch scratch;
-  rta::SortBuf sortbuf;                      // single-level backward: rays sorted by triangle
+  rta::SortBuf sortbuf;                      // backward: rays grouped by triangle range
+  rta::SortBuf sortbuf2;                     // two-level backward: rays grouped by instance
   hipEvent_t last_event = nullptr;
   hipStream_t last_stream = nullptr;
   bool has_last = false;
@@ -369,6 +371,7 @@ rt_status rt_context_create(int hip_device, rt_context* out) {
   c->refill_min = (uint32_t)std::min(64, std::max(1, env_int("RT_REFILL", 32)));
   c->blocks_per_cu = (uint32_t)std::min(64, std::max(0, env_int("RT_BLOCKS_PER_CU", 0)));
   c->stack_limit = (uint32_t)std::max(0, env_int("RT_STACK_LIMIT", 0));
+  c->backward_atomic = env_int("RT_BACKWARD_ATOMIC", 0) != 0;
   if (hipEventCreateWithFlags(&c->last_event, hipEventDisableTiming) != hipSuccess) {
     delete c;
     return fail(RT_ERROR_HIP, "rt_context_create: hipEventCreate failed");
@@ -397,6 +400,7 @@ rt_status rt_context_destroy(rt_context ctx) {
   (void)hipDeviceSynchronize();
   free_scratch(ctx->scratch);
   rta::sort_release(ctx->sortbuf);
+  rta::sort_release(ctx->sortbuf2);
   if (ctx->last_event) (void)hipEventDestroy(ctx->last_event);
   for (hipEvent_t e : ctx->tbeg) (void)hipEventDestroy(e);
   for (hipEvent_t e : ctx->tend) (void)hipEventDestroy(e);
@@ -1558,8 +1562,11 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
     RT_HIP(rta::gather_build(accel->gather, idx.data(), mesh.vertex_count, mesh.triangle_count));
     accel->info.device_bytes += 4ull * (mesh.vertex_count + 1) + 120ull * mesh.triangle_count;
   }
-  RT_HIP(rta::gather_tri_vertices(accel->gather, mesh.indices, mesh.vertices, s));
-  RT_HIP(rta::sort_reserve(ctx->sortbuf, accel->gather, n, s));
+  if (!accel->gather.tri_vertices_valid) {
+    RT_HIP(rta::gather_tri_vertices(accel->gather, mesh.indices, mesh.vertices, mesh.triangle_count, 0, s));
+    accel->gather.tri_vertices_valid = true;
+  }
+  RT_HIP(rta::sort_reserve(ctx->sortbuf, accel->gather.buckets, n, s));
   BackwardParams p{};
   p.mesh = mesh;
   p.tri_vertices = accel->gather.tri_vertices;
@@ -1569,7 +1576,8 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
   p.n = n;
   p.d_origins = d_origins;
   p.d_directions = d_directions;
-  RT_HIP(rta::bucket_rays(accel->gather, ctx->sortbuf, reinterpret_cast<const uint32_t*>(hits), n, s, &p.bk));
+  rta::KeySource keys{reinterpret_cast<const uint32_t*>(hits), nullptr, nullptr, nullptr, 0, mesh.triangle_count, 0};
+  RT_HIP(rta::bucket_rays(keys, accel->gather.buckets, accel->gather.shift, ctx->sortbuf, n, s, &p.bk));
   RT_HIP(rtk_launch_backward(p, s));
   RT_HIP(rta::gather_vertices(accel->gather, ctx->sortbuf, n, d_vertices, s));
   RT_HIP(hipEventRecord(ctx->last_event, s));
@@ -1600,8 +1608,6 @@ rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const 
   hipStream_t s = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> lk(ctx->mu);
   if (ctx->has_last && ctx->last_stream != s) RT_HIP(hipStreamWaitEvent(s, ctx->last_event, 0));
-  st = prepare_grad_rows(accel, s);
-  if (st != RT_SUCCESS) return st;
   BackwardInstParams p{};
   p.meshes = accel->meshes;
   p.vertex_base = accel->vertex_base;
@@ -1616,9 +1622,77 @@ rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const 
   p.n = n;
   p.d_origins = d_origins;
   p.d_directions = d_directions;
-  p.acc = rta::Acc{accel->grad_rows.expo, accel->grad_rows.sums, accel->grad_rows.count, rta::shift0_for(n)};
   p.want_vertices = (d_vertices && accel->vertex_rows > 0) ? 1u : 0u;
   p.want_frames = d_srt ? 1u : 0u;
+  const uint32_t nm = (uint32_t)accel->host_meshes.size();
+  uint64_t total_tris = 0;
+  for (const rt_mesh_dev& md : accel->host_meshes) total_tris += md.triangle_count;
+  if (!ctx->backward_atomic && accel->instance_count <= rta::kMaxBuckets && total_tris < (1ull << 30) &&
+      rta::bucket_shift((uint32_t)total_tris, 6) != 0) {
+    // rays grouped by triangle range and by instance, exact sums per group
+    rta::Gather& g = accel->gather;
+    if (!g.csr_off) {
+      std::vector<std::vector<uint32_t>> idx(nm);
+      std::vector<const uint32_t*> ip(nm);
+      std::vector<uint32_t> vc(nm), tc(nm), im(accel->instance_count);
+      try {
+        for (uint32_t m = 0; m < nm; ++m) {
+          const rt_mesh_dev& md = accel->host_meshes[m];
+          idx[m].resize(3 * (size_t)md.triangle_count);
+          vc[m] = md.vertex_count;
+          tc[m] = md.triangle_count;
+        }
+      } catch (const std::bad_alloc&) {
+        return fail(RT_ERROR_OUT_OF_MEMORY, "rt_trace_backward_instances: host allocation");
+      }
+      for (uint32_t m = 0; m < nm; ++m) {
+        if (!idx[m].empty())
+          RT_HIP(hipMemcpy(idx[m].data(), accel->host_meshes[m].indices, idx[m].size() * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost));
+        ip[m] = idx[m].data();
+      }
+      for (uint32_t j = 0; j < accel->instance_count; ++j) im[j] = accel->host_insts[j].mesh;
+      RT_HIP(rta::gather_build_multi(g, ip.data(), vc.data(), tc.data(), nm, im.data(), accel->instance_count, 6));
+      accel->info.device_bytes += 4ull * (accel->vertex_rows + 1) + 120ull * total_tris + 4ull * (nm + 1) +
+                                  4ull * accel->instance_count;
+    }
+    if (!g.tri_vertices_valid) {
+      uint32_t first = 0;
+      for (uint32_t m = 0; m < nm; ++m) {
+        const rt_mesh_dev& md = accel->host_meshes[m];
+        RT_HIP(rta::gather_tri_vertices(g, md.indices, md.vertices, md.triangle_count, first, s));
+        first += md.triangle_count;
+      }
+      g.tri_vertices_valid = true;
+    }
+    p.tri_vertices = g.tri_vertices;
+    p.tri_base = g.tri_base;
+    p.inst_mesh = g.inst_mesh;
+    rta::KeySource keys{reinterpret_cast<const uint32_t*>(hits), inst_ids, g.inst_mesh, g.tri_base,
+                        accel->instance_count, 0, 1};
+    if (p.want_vertices) {
+      RT_HIP(rta::sort_reserve(ctx->sortbuf, g.buckets, n, s));
+      RT_HIP(rta::bucket_rays(keys, g.buckets, g.shift, ctx->sortbuf, n, s, &p.vb));
+    }
+    if (p.want_frames) {
+      keys.kind = 2;
+      RT_HIP(rta::sort_reserve(ctx->sortbuf2, accel->instance_count, n, s));
+      RT_HIP(rta::bucket_rays(keys, accel->instance_count, 0, ctx->sortbuf2, n, s, &p.fb));
+    }
+    RT_HIP(rtk_launch_backward_inst_tiles(p, s));
+    if (p.want_vertices) RT_HIP(rta::gather_vertices(g, ctx->sortbuf, n, d_vertices, s));
+    if (p.want_frames)
+      RT_HIP(rta::frame_sums(ctx->sortbuf2, accel->instance_count, reinterpret_cast<const float*>(accel->srts), n,
+                             d_srt, s));
+    RT_HIP(hipEventRecord(ctx->last_event, s));
+    ctx->last_stream = s;
+    ctx->has_last = true;
+    return ok();
+  }
+  // more instances than LDS counters: fixed-point rows with global atomics
+  st = prepare_grad_rows(accel, s);
+  if (st != RT_SUCCESS) return st;
+  p.acc = rta::Acc{accel->grad_rows.expo, accel->grad_rows.sums, accel->grad_rows.count, rta::shift0_for(n)};
   p.frame_row0 = (uint32_t)accel->vertex_rows;
   RT_HIP(rtk_launch_backward_inst(p, 0, s));
   RT_HIP(rtk_launch_backward_inst(p, 1, s));
@@ -1705,6 +1779,7 @@ rt_status rt_ao_resolve(const uint8_t* occluded, uint32_t n, uint32_t samples, f
 // order), records and nodes, then the meshes' bounds and the top level.
 static rt_status refit_two_level(rt_accel_s* a, const float* vertices, hipStream_t s) {
   const uint32_t nm = (uint32_t)a->host_meshes.size();
+  a->gather.tri_vertices_valid = false;   // the backward's per-triangle vertex copy
   const uint32_t fpn = 8u * (uint32_t)a->width;
   uint64_t row = 0;
   for (uint32_t m = 0; m < nm; ++m) {

@@ -103,6 +103,12 @@ struct BackwardInstParams {
   uint32_t want_vertices;         // add vertex rows
   uint32_t want_frames;           // add frame rows
   uint32_t frame_row0;
+  // bucketed form (backward_inst_tile_kernel): global-triangle vertex copy,
+  // first global triangle of each mesh, mesh of each instance, placements
+  const float* tri_vertices;
+  const uint32_t* tri_base;
+  const uint32_t* inst_mesh;
+  rta::Bucketing vb, fb;
 };
 
 // Ambient-occlusion rays from closest hits (one thread per ray sample).
@@ -142,6 +148,8 @@ hipError_t rtk_launch_finalize_ovf(bool inst, const TraceParams& p, hipStream_t 
 hipError_t rtk_launch_finalize_all(bool inst, const TraceParams& p, hipStream_t stream);
 hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream);
 hipError_t rtk_launch_backward_inst(const BackwardInstParams& p, int phase, hipStream_t stream);
+// the bucketed two-level adjoint (p.vb / p.fb placements; grid of kTile-ray tiles)
+hipError_t rtk_launch_backward_inst_tiles(const BackwardInstParams& p, hipStream_t stream);
 hipError_t rtk_launch_refit_tris(rt_tri_rec* tris, uint32_t n, const rt_mesh_dev& mesh,
                                  hipStream_t stream);
 hipError_t rtk_launch_refit_nodes(int width, float* nodes, const rt_tri_rec* tris,

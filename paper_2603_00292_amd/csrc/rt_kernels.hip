@@ -786,6 +786,71 @@ __device__ __forceinline__ bool adjoint64(const rt_mesh_dev& mesh, uint32_t prim
 
 __device__ __forceinline__ void zero3(float* a) { a[0] = a[1] = a[2] = 0.0f; }
 
+// Bucket starts of one tile: an exclusive scan of the bucket totals over
+// the workgroup (1024 threads, at most 16 buckets per thread) plus the
+// tile's offsets, into pos[]; workgroup 0 also stores the starts for the
+// summing kernels.  The caller synchronises before reading pos.
+__device__ __forceinline__ void bucket_starts(const rta::Bucketing& B, uint32_t* pos) {
+  __shared__ uint32_t wsum[16];
+  constexpr uint32_t C = rta::kMaxBuckets / 1024;
+  const uint32_t chunk = (B.buckets + 1023u) / 1024u;
+  const uint32_t c0 = min(B.buckets, threadIdx.x * chunk), c1 = min(B.buckets, c0 + chunk);
+  const uint32_t* tile_off = B.counts + (size_t)blockIdx.x * B.buckets;
+  uint32_t tot[C], off[C];
+  uint32_t own = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < C; ++k) {
+    const bool in = c0 + k < c1;
+    tot[k] = in ? B.totals[c0 + k] : 0u;
+    off[k] = in ? tile_off[c0 + k] : 0u;
+    own += tot[k];
+  }
+  const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  uint32_t inc = own;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t o = (uint32_t)__shfl_up((int)inc, d);
+    if (lane >= (uint32_t)d) inc += o;
+  }
+  if (lane == 63u) wsum[w] = inc;
+  __syncthreads();
+  uint32_t r = inc - own;
+  for (uint32_t k = 0; k < w; ++k) r += wsum[k];
+#pragma unroll
+  for (uint32_t k = 0; k < C; ++k)
+    if (c0 + k < c1) {
+      pos[c0 + k] = r + off[k];
+      if (blockIdx.x == 0) B.base[c0 + k] = r;
+      r += tot[k];
+    }
+  if (blockIdx.x == 0 && threadIdx.x == 1023u) B.base[B.buckets] = r;
+  __syncthreads();   // wsum is reused by a second call
+}
+
+// Record stores: three 16-byte stores each (record buffers are 256-byte
+// aligned, records 48 bytes).
+__device__ __forceinline__ float2 dwords(double x) {
+  return make_float2(__int_as_float(__double2loint(x)), __int_as_float(__double2hiint(x)));
+}
+
+__device__ __forceinline__ void store_rayrec(rta::RayRec* dst, double lx, double ly, double lz, double u, double v,
+                                             uint32_t prim) {
+  float4* p = reinterpret_cast<float4*>(dst);
+  float2 a = dwords(lx), b = dwords(ly), c = dwords(lz), d = dwords(u), e = dwords(v);
+  p[0] = make_float4(a.x, a.y, b.x, b.y);
+  p[1] = make_float4(c.x, c.y, d.x, d.y);
+  p[2] = make_float4(e.x, e.y, __uint_as_float(prim), 0.0f);
+}
+
+__device__ __forceinline__ void store_framerec(rta::RayRec* dst, double lx, double ly, double lz, double px,
+                                               double py, double pz) {
+  float4* p = reinterpret_cast<float4*>(dst);
+  float2 a = dwords(lx), b = dwords(ly), c = dwords(lz), d = dwords(px), e = dwords(py), f = dwords(pz);
+  p[0] = make_float4(a.x, a.y, b.x, b.y);
+  p[1] = make_float4(c.x, c.y, d.x, d.y);
+  p[2] = make_float4(e.x, e.y, f.x, f.y);
+}
+
 // dL/do and dL/dd of the rays of one tile, and each hit ray's record
 // (lambda, u, v, triangle) placed in its triangle's bucket (LDS counters
 // start at the tile's offsets; see accumulate.h).  A hit whose adjoint is
@@ -806,44 +871,7 @@ __global__ __launch_bounds__(1024) void backward_kernel(BackwardParams P) {
     uint32_t i = base + r * 1024 + threadIdx.x;
     prim[r] = i < P.n ? P.hits[i].prim_id : RT_INVALID_ID;
   }
-  // bucket starts: an exclusive scan of the bucket totals over the
-  // workgroup (at most 16 buckets per thread); workgroup 0 stores them for
-  // the corner sums
-  {
-    __shared__ uint32_t wsum[16];
-    constexpr uint32_t C = rta::kMaxBuckets / 1024;
-    const uint32_t chunk = (B.buckets + 1023u) / 1024u;
-    const uint32_t c0 = min(B.buckets, threadIdx.x * chunk), c1 = min(B.buckets, c0 + chunk);
-    const uint32_t* tile_off = B.counts + (size_t)blockIdx.x * B.buckets;
-    uint32_t tot[C], off[C];
-    uint32_t own = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < C; ++k) {
-      const bool in = c0 + k < c1;
-      tot[k] = in ? B.totals[c0 + k] : 0u;
-      off[k] = in ? tile_off[c0 + k] : 0u;
-      own += tot[k];
-    }
-    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-    uint32_t inc = own;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      uint32_t o = (uint32_t)__shfl_up((int)inc, d);
-      if (lane >= (uint32_t)d) inc += o;
-    }
-    if (lane == 63u) wsum[w] = inc;
-    __syncthreads();
-    uint32_t r = inc - own;
-    for (uint32_t k = 0; k < w; ++k) r += wsum[k];
-#pragma unroll
-    for (uint32_t k = 0; k < C; ++k)
-      if (c0 + k < c1) {
-        pos[c0 + k] = r + off[k];
-        if (blockIdx.x == 0) B.base[c0 + k] = r;
-        r += tot[k];
-      }
-    if (blockIdx.x == 0 && threadIdx.x == 1023u) B.base[B.buckets] = r;
-  }
+  bucket_starts(B, pos);
   __syncthreads();
 #pragma unroll
   for (uint32_t r0 = 0; r0 < R; r0 += G) {
@@ -887,16 +915,8 @@ __global__ __launch_bounds__(1024) void backward_kernel(BackwardParams P) {
       }
       if (valid) {
         uint32_t p = atomicAdd(&pos[pr >> B.shift], 1u);
-        // three 16-byte stores (records are 48 bytes, the buffer 256-byte aligned)
-        float4* f = reinterpret_cast<float4*>(B.rec + p);
-        double q0 = ok ? A.lx : 0.0, q1 = ok ? A.ly : 0.0, q2 = ok ? A.lz : 0.0;
-        double q3 = ok ? A.u : 0.0, q4 = ok ? A.v : 0.0;
-        f[0] = make_float4(__int_as_float(__double2loint(q0)), __int_as_float(__double2hiint(q0)),
-                           __int_as_float(__double2loint(q1)), __int_as_float(__double2hiint(q1)));
-        f[1] = make_float4(__int_as_float(__double2loint(q2)), __int_as_float(__double2hiint(q2)),
-                           __int_as_float(__double2loint(q3)), __int_as_float(__double2hiint(q3)));
-        f[2] = make_float4(__int_as_float(__double2loint(q4)), __int_as_float(__double2hiint(q4)),
-                           __uint_as_float(pr), 0.0f);
+        store_rayrec(B.rec + p, ok ? A.lx : 0.0, ok ? A.ly : 0.0, ok ? A.lz : 0.0, ok ? A.u : 0.0, ok ? A.v : 0.0,
+                     pr);
       }
     }
   }
@@ -1009,6 +1029,85 @@ __global__ __launch_bounds__(256) void backward_inst_kernel(BackwardInstParams P
                   (gqz - qz * radial) * iq);
   rta::add<PHASE>(P.acc, row + 2, (gqw - qw * radial) * iq, -lx, -ly);
   rta::add<PHASE>(P.acc, row + 3, -lz, 0.0, 0.0);
+}
+
+// Two-level adjoint of one tile without global atomics: dL/do and dL/dd of
+// its rays, and each hit ray's records placed in their buckets through LDS
+// counters: (lambda_o, u, v, global triangle) by triangle range for the
+// vertex sums, (lambda_w, object hit point) by instance for the frame sums
+// (see accumulate.h).  A hit whose adjoint is undefined keeps its slots with
+// zero records.  Validity is rta::ray_key's: an instance below the count and
+// a triangle of its mesh.
+__global__ __launch_bounds__(1024) void backward_inst_tile_kernel(BackwardInstParams P) {
+  extern __shared__ uint32_t lds_pos[];
+  uint32_t* vpos = lds_pos;
+  uint32_t* fpos = lds_pos + (P.want_vertices ? P.vb.buckets : 0u);
+  if (P.want_vertices) bucket_starts(P.vb, vpos);
+  if (P.want_frames) bucket_starts(P.fb, fpos);
+  __syncthreads();
+  const uint32_t base = blockIdx.x * rta::kTile;
+  for (uint32_t r = 0; r < rta::kTile / 1024; ++r) {
+    const uint32_t i = base + r * 1024 + threadIdx.x;
+    if (i >= P.n) break;
+    const uint32_t prim = P.hits[i].prim_id;
+    const uint32_t inst = P.inst_ids[i];
+    float* go = P.d_origins + 3 * (size_t)i;
+    float* gd = P.d_directions + 3 * (size_t)i;
+    bool valid = inst < P.inst_count;
+    uint32_t gt = 0;
+    if (valid) {
+      const uint32_t m = P.inst_mesh[inst];
+      const uint32_t b0 = P.tri_base[m];
+      valid = prim < P.tri_base[m + 1] - b0;
+      gt = b0 + prim;
+    }
+    bool ok = false;
+    Adjoint64 A;
+    double lx = 0.0, ly = 0.0, lz = 0.0;
+    if (valid) {
+      const rt_inst_rec64& M = P.insts64[inst];
+      rt_ray q = load_ray(P.rays, i);
+      double ox = q.ox, oy = q.oy, oz = q.oz, dx = q.dx, dy = q.dy, dz = q.dz;
+      double xo = M.m[0] * ox + M.m[1] * oy + M.m[2] * oz + M.m[3];
+      double yo = M.m[4] * ox + M.m[5] * oy + M.m[6] * oz + M.m[7];
+      double zo = M.m[8] * ox + M.m[9] * oy + M.m[10] * oz + M.m[11];
+      double xd = M.m[0] * dx + M.m[1] * dy + M.m[2] * dz;
+      double yd = M.m[4] * dx + M.m[5] * dy + M.m[6] * dz;
+      double zd = M.m[8] * dx + M.m[9] * dy + M.m[10] * dz;
+      const float* gr = P.d_tuv + 3 * (size_t)i;
+      ok = adjoint64_solve(P.tri_vertices + 9 * (size_t)gt, xo, yo, zo, xd, yd, zd, gr[0], gr[1], gr[2], A);
+      if (ok) {
+        // lambda_w = (A^-1)^T lambda_o
+        lx = M.m[0] * A.lx + M.m[4] * A.ly + M.m[8] * A.lz;
+        ly = M.m[1] * A.lx + M.m[5] * A.ly + M.m[9] * A.lz;
+        lz = M.m[2] * A.lx + M.m[6] * A.ly + M.m[10] * A.lz;
+      }
+    }
+    if (ok) {
+      go[0] = (float)lx; go[1] = (float)ly; go[2] = (float)lz;
+      gd[0] = (float)(A.t * lx); gd[1] = (float)(A.t * ly); gd[2] = (float)(A.t * lz);
+    } else {
+      zero3(go);
+      zero3(gd);
+    }
+    if (!valid) continue;
+    if (P.want_vertices) {
+      uint32_t p = atomicAdd(&vpos[gt >> P.vb.shift], 1u);
+      store_rayrec(P.vb.rec + p, ok ? A.lx : 0.0, ok ? A.ly : 0.0, ok ? A.lz : 0.0, ok ? A.u : 0.0,
+                   ok ? A.v : 0.0, gt);
+    }
+    if (P.want_frames) {
+      double px = 0.0, py = 0.0, pz = 0.0;
+      if (ok) {
+        const double w0 = 1.0 - A.u - A.v, w1 = A.u, w2 = A.v;
+        px = w0 * A.p[0][0] + w1 * A.p[1][0] + w2 * A.p[2][0];
+        py = w0 * A.p[0][1] + w1 * A.p[1][1] + w2 * A.p[2][1];
+        pz = w0 * A.p[0][2] + w1 * A.p[1][2] + w2 * A.p[2][2];
+      }
+      uint32_t p = atomicAdd(&fpos[inst], 1u);
+      store_framerec(P.fb.rec + p, lx, ly, lz, px, py, pz);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1371,6 +1470,16 @@ hipError_t rtk_launch_backward(const BackwardParams& p, hipStream_t stream) {
   void* args[] = {&q};
   return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::backward_kernel), dim3(p.bk.tiles), dim3(1024),
                          args, p.bk.buckets * sizeof(uint32_t), stream);
+}
+
+hipError_t rtk_launch_backward_inst_tiles(const BackwardInstParams& p, hipStream_t stream) {
+  if (p.n == 0) return hipSuccess;
+  BackwardInstParams q = p;
+  void* args[] = {&q};
+  uint32_t tiles = (p.n + rta::kTile - 1) / rta::kTile;
+  size_t lds = ((p.want_vertices ? p.vb.buckets : 0u) + (p.want_frames ? p.fb.buckets : 0u)) * sizeof(uint32_t);
+  return hipLaunchKernel(reinterpret_cast<const void*>(&rtk::backward_inst_tile_kernel), dim3(tiles), dim3(1024),
+                         args, lds, stream);
 }
 
 hipError_t rtk_launch_backward_inst(const BackwardInstParams& p, int phase, hipStream_t stream) {

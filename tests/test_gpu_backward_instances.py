@@ -293,3 +293,112 @@ def test_backward_instances_deterministic(gpu):
     torch.cuda.synchronize()
     assert torch.equal(dS2, outs[0][1]) and torch.equal(dV2, outs[0][0])
     acc.close()
+
+
+def test_backward_instances_independent_of_ray_order(gpu):
+    """The rays are grouped by triangle range and by instance and each group
+    sums exactly: the vertex and frame gradients of a permutation of the
+    rays are bit-identical (1,024 frames, 2^20 rays)."""
+    torch, api, ctx = gpu
+    W = wl.instanced_grids(n_rays=1 << 20, k=321)
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    nv = int(_bases(W.scene)[-1])
+    g = wl.rng_for(322).standard_normal((W.rays.shape[0], 3)).astype(np.float32)
+    perm = wl.rng_for(323).permutation(W.rays.shape[0])
+    res = []
+    for order in (np.arange(W.rays.shape[0]), perm):
+        rays, hits, inst = _forward(gpu, acc, W.rays[order])
+        res.append(_backward(gpu, acc, rays, hits, inst, g[order], nv, 1024))
+    (v0, s0, o0, d0), (v1, s1, o1, d1) = res
+    assert np.array_equal(v0, v1) and np.array_equal(s0, s1)
+    assert np.array_equal(o0[perm], o1) and np.array_equal(d0[perm], d1)
+    acc.close()
+
+
+def test_backward_instances_bucketed_matches_atomic_rows(gpu, monkeypatch):
+    """The bucketed sums against the fixed-point atomic rows (the path for
+    more instances than LDS counters, forced with RT_BACKWARD_ATOMIC=1 at
+    context creation): ray gradients identical; frame and vertex gradients
+    equal within two float32 roundings of their values (both are exact sums
+    of the same float64 contributions, the vertex route rounds per corner
+    to float64 first)."""
+    torch, api, ctx = gpu
+    W = wl.instanced_grids(n_rays=1 << 20, k=324)
+    nv = int(_bases(W.scene)[-1])
+    g = wl.rng_for(325).standard_normal((W.rays.shape[0], 3)).astype(np.float32)
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    rays, hits, inst = _forward(gpu, acc, W.rays)
+    a = _backward(gpu, acc, rays, hits, inst, g, nv, 1024)
+    monkeypatch.setenv("RT_BACKWARD_ATOMIC", "1")
+    ctx2 = api.Context(0)
+    monkeypatch.delenv("RT_BACKWARD_ATOMIC")
+    acc2 = to_gpu_scene(api, torch, ctx2, W.scene)
+    b = _backward((torch, api, ctx2), acc2, rays, hits, inst, g, nv, 1024)
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+    for x, y, name in ((a[0], b[0], "vertices"), (a[1], b[1], "frames")):
+        tol = 2 * EPS32 * np.maximum(np.abs(x), np.abs(y)) + 1e-9 * np.abs(x).max()
+        say(name, "identical entries", float((x == y).mean()), "max err/tol", float((np.abs(x - y) / tol).max()))
+        assert (np.abs(x - y) <= tol).all()
+    acc2.close()
+    ctx2.close()
+    acc.close()
+
+
+def test_backward_instances_after_refit(gpu):
+    """The two-level adjoint reads a copy of every triangle's object-space
+    vertices; a refit makes the next call refresh it: gradients after moving
+    the vertices equal those of a fresh accel built on them."""
+    torch, api, ctx = gpu
+    W = wl.aimed_instances(n_inst=8, n_rays=32768, k=326)
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    nv = int(_bases(W.scene)[-1])
+    g = wl.rng_for(327).standard_normal((W.rays.shape[0], 3)).astype(np.float32)
+    rays, hits, inst = _forward(gpu, acc, W.rays)
+    first = _backward(gpu, acc, rays, hits, inst, g, nv, 8)
+    V = np.concatenate([m.vertices for m in W.scene.meshes]).copy()
+    V[:, 1] += 0.05 * np.sin(3.0 * V[:, 0])
+    acc.refit(torch.from_numpy(V).cuda())
+    rays, hits, inst = _forward(gpu, acc, W.rays)
+    moved = _backward(gpu, acc, rays, hits, inst, g, nv, 8)
+    parts = np.split(V, _bases(W.scene)[1:-1])
+    scene2 = wl.Scene([wl.Mesh(p.astype(np.float32), m.indices) for p, m in zip(parts, W.scene.meshes)],
+                      W.scene.inst_mesh, W.scene.inst_srt)
+    acc2 = to_gpu_scene(api, torch, ctx, scene2)
+    rays2, hits2, inst2 = _forward(gpu, acc2, W.rays)
+    assert torch.equal(hits.view(torch.int32), hits2.view(torch.int32)) and torch.equal(inst, inst2)
+    fresh = _backward(gpu, acc2, rays2, hits2, inst2, g, nv, 8)
+    for x, y in zip(moved, fresh):
+        assert np.array_equal(x, y)
+    assert not np.array_equal(moved[0], first[0])
+    acc2.close()
+    acc.close()
+
+
+def test_backward_instances_many_instances(gpu):
+    """More instances than LDS counters (20,000 > 16,384): the frame sums go
+    through the fixed-point atomic rows.  Repeated calls are bit-identical
+    and each frame's translation gradient is minus the sum of its rays'
+    origin gradients."""
+    torch, api, ctx = gpu
+    J = 20000
+    W = wl.aimed_instances(n_inst=J, n_rays=65536, k=328)
+    acc = to_gpu_scene(api, torch, ctx, W.scene)
+    rays, hits, inst = _forward(gpu, acc, W.rays)
+    nv = int(_bases(W.scene)[-1])
+    g = wl.rng_for(329).standard_normal((W.rays.shape[0], 3)).astype(np.float32)
+    a = _backward(gpu, acc, rays, hits, inst, g, nv, J)
+    b = _backward(gpu, acc, rays, hits, inst, g, nv, J)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    dV, dS, do, dd = a
+    ii = inst.cpu().numpy().view(np.uint32)
+    hit = hits.cpu().numpy()[:, 1].copy().view(np.uint32) != NONE
+    say("hit fraction", hit.mean())
+    assert hit.mean() > 0.5
+    cnt = np.bincount(ii[hit], minlength=J).astype(np.float64)
+    for c in range(3):
+        s_o = np.bincount(ii[hit], weights=do[hit, c], minlength=J)
+        a_o = np.bincount(ii[hit], weights=np.abs(do[hit, c]), minlength=J)
+        bound = (cnt + 2) * EPS32 * a_o * 2 + 1e-9
+        assert (np.abs(dS[:, 7 + c] + s_o) <= bound).all()
+    acc.close()
