@@ -162,15 +162,14 @@ inline uint32_t bucket_shift(uint32_t triangles, uint32_t min_shift = 8) {
 // Per accel: the vertex -> (triangle << 2 | corner) lists, the corner values
 // and a copy of every triangle's three vertices (so the adjoint reads one
 // 36-byte record per hit instead of an index triple and three vertices).
-// Two-level: global triangle and vertex ids, plus each mesh's first global
-// triangle and each instance's mesh.
+// Two-level: global triangle and vertex ids, plus each instance's mesh as
+// (first global triangle, triangle count).
 struct Gather {
   uint32_t* csr_off = nullptr;   // vertices + 1
   uint32_t* csr_ent = nullptr;   // 3 * triangles
   double* corner = nullptr;      // 9 per triangle: corner k's 3 components
   float* tri_vertices = nullptr; // 9 per triangle: vertex k's x, y, z
-  uint32_t* tri_base = nullptr;  // two-level: meshes + 1
-  uint32_t* inst_mesh = nullptr; // two-level: instances
+  uint2* inst_tris = nullptr;    // two-level: one per instance
   bool tri_vertices_valid = false;
   uint32_t vertices = 0, triangles = 0, shift = 0, buckets = 0;
 };
@@ -180,8 +179,7 @@ struct Gather {
 struct KeySource {
   const uint32_t* hit_words;     // prim id at hit_words[4 i + 1]
   const uint32_t* inst_ids;      // two-level
-  const uint32_t* inst_mesh;     // two-level
-  const uint32_t* tri_base;      // two-level
+  const uint2* inst_tris;        // two-level
   uint32_t inst_count;
   uint32_t triangles;            // single level
   uint32_t kind;
@@ -192,10 +190,9 @@ __device__ __forceinline__ uint32_t ray_key(const KeySource& k, uint32_t i) {
   if (k.kind == 0) return prim < k.triangles ? prim : kNoKey;
   const uint32_t inst = k.inst_ids[i];
   if (inst >= k.inst_count) return kNoKey;
-  const uint32_t m = k.inst_mesh[inst];
-  const uint32_t b0 = k.tri_base[m];
-  if (prim >= k.tri_base[m + 1] - b0) return kNoKey;
-  return k.kind == 1 ? b0 + prim : inst;
+  const uint2 it = k.inst_tris[inst];
+  if (prim >= it.y) return kNoKey;
+  return k.kind == 1 ? it.x + prim : inst;
 }
 
 // Per context: buffers sized by the ray count (grown stream-ordered).

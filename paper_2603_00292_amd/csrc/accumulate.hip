@@ -490,15 +490,17 @@ hipError_t gather_build_multi(Gather& g, const uint32_t* const* I, const uint32_
   if (e == hipSuccess) e = rt_malloc(&g.csr_ent, std::max<size_t>(ent.size(), 1) * sizeof(uint32_t));
   if (e == hipSuccess) e = rt_malloc(&g.corner, std::max<size_t>(9 * (size_t)triangles, 1) * sizeof(double));
   if (e == hipSuccess) e = rt_malloc(&g.tri_vertices, std::max<size_t>(9 * (size_t)triangles, 1) * sizeof(float));
-  if (e == hipSuccess && instances > 0) e = rt_malloc(&g.tri_base, tbase.size() * sizeof(uint32_t));
-  if (e == hipSuccess && instances > 0) e = rt_malloc(&g.inst_mesh, (size_t)instances * sizeof(uint32_t));
+  std::vector<uint2> it(instances);
+  for (uint32_t j = 0; j < instances; ++j) {
+    uint32_t m = inst_mesh[j] < meshes ? inst_mesh[j] : 0u;
+    it[j] = make_uint2(tbase[m], inst_mesh[j] < meshes ? triangle_counts[m] : 0u);
+  }
+  if (e == hipSuccess && instances > 0) e = rt_malloc(&g.inst_tris, (size_t)instances * sizeof(uint2));
   if (e == hipSuccess) e = hipMemcpy(g.csr_off, off.data(), off.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess && !ent.empty())
     e = hipMemcpy(g.csr_ent, ent.data(), ent.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess && instances > 0)
-    e = hipMemcpy(g.tri_base, tbase.data(), tbase.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess && instances > 0)
-    e = hipMemcpy(g.inst_mesh, inst_mesh, (size_t)instances * sizeof(uint32_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(g.inst_tris, it.data(), (size_t)instances * sizeof(uint2), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     gather_release(g);
     return e;
@@ -525,7 +527,7 @@ hipError_t gather_tri_vertices(Gather& g, const uint32_t* indices, const float* 
 }
 
 void gather_release(Gather& g) {
-  void* ps[] = {g.csr_off, g.csr_ent, g.corner, g.tri_vertices, g.tri_base, g.inst_mesh};
+  void* ps[] = {g.csr_off, g.csr_ent, g.corner, g.tri_vertices, g.inst_tris};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   g = Gather();

@@ -1576,7 +1576,7 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
   p.n = n;
   p.d_origins = d_origins;
   p.d_directions = d_directions;
-  rta::KeySource keys{reinterpret_cast<const uint32_t*>(hits), nullptr, nullptr, nullptr, 0, mesh.triangle_count, 0};
+  rta::KeySource keys{reinterpret_cast<const uint32_t*>(hits), nullptr, nullptr, 0, mesh.triangle_count, 0};
   RT_HIP(rta::bucket_rays(keys, accel->gather.buckets, accel->gather.shift, ctx->sortbuf, n, s, &p.bk));
   RT_HIP(rtk_launch_backward(p, s));
   RT_HIP(rta::gather_vertices(accel->gather, ctx->sortbuf, n, d_vertices, s));
@@ -1653,8 +1653,7 @@ rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const 
       }
       for (uint32_t j = 0; j < accel->instance_count; ++j) im[j] = accel->host_insts[j].mesh;
       RT_HIP(rta::gather_build_multi(g, ip.data(), vc.data(), tc.data(), nm, im.data(), accel->instance_count, 6));
-      accel->info.device_bytes += 4ull * (accel->vertex_rows + 1) + 120ull * total_tris + 4ull * (nm + 1) +
-                                  4ull * accel->instance_count;
+      accel->info.device_bytes += 4ull * (accel->vertex_rows + 1) + 120ull * total_tris + 8ull * accel->instance_count;
     }
     if (!g.tri_vertices_valid) {
       uint32_t first = 0;
@@ -1666,10 +1665,8 @@ rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const 
       g.tri_vertices_valid = true;
     }
     p.tri_vertices = g.tri_vertices;
-    p.tri_base = g.tri_base;
-    p.inst_mesh = g.inst_mesh;
-    rta::KeySource keys{reinterpret_cast<const uint32_t*>(hits), inst_ids, g.inst_mesh, g.tri_base,
-                        accel->instance_count, 0, 1};
+    p.inst_tris = g.inst_tris;
+    rta::KeySource keys{reinterpret_cast<const uint32_t*>(hits), inst_ids, g.inst_tris, accel->instance_count, 0, 1};
     if (p.want_vertices) {
       RT_HIP(rta::sort_reserve(ctx->sortbuf, g.buckets, n, s));
       RT_HIP(rta::bucket_rays(keys, g.buckets, g.shift, ctx->sortbuf, n, s, &p.vb));

@@ -104,10 +104,9 @@ struct BackwardInstParams {
   uint32_t want_frames;           // add frame rows
   uint32_t frame_row0;
   // bucketed form (backward_inst_tile_kernel): global-triangle vertex copy,
-  // first global triangle of each mesh, mesh of each instance, placements
+  // each instance's (first global triangle, triangle count), placements
   const float* tri_vertices;
-  const uint32_t* tri_base;
-  const uint32_t* inst_mesh;
+  const uint2* inst_tris;
   rta::Bucketing vb, fb;
 };
 

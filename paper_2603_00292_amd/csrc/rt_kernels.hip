@@ -1040,47 +1040,67 @@ __global__ __launch_bounds__(256) void backward_inst_kernel(BackwardInstParams P
 // a triangle of its mesh.
 __global__ __launch_bounds__(1024) void backward_inst_tile_kernel(BackwardInstParams P) {
   extern __shared__ uint32_t lds_pos[];
+  constexpr uint32_t R = rta::kTile / 1024;
   uint32_t* vpos = lds_pos;
   uint32_t* fpos = lds_pos + (P.want_vertices ? P.vb.buckets : 0u);
+  const uint32_t base = blockIdx.x * rta::kTile;
+  // every ray's hit and instance, and the instance's triangle range, before
+  // the bucket scans
+  uint32_t prim[R], inst[R];
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
+    const uint32_t i = base + r * 1024 + threadIdx.x;
+    prim[r] = i < P.n ? P.hits[i].prim_id : RT_INVALID_ID;
+    inst[r] = i < P.n ? P.inst_ids[i] : RT_INVALID_ID;
+  }
+  uint32_t gt[R];
+#pragma unroll
+  for (uint32_t r = 0; r < R; ++r) {
+    gt[r] = RT_INVALID_ID;
+    if (inst[r] < P.inst_count) {
+      const uint2 it = P.inst_tris[inst[r]];
+      if (prim[r] < it.y) gt[r] = it.x + prim[r];
+    }
+  }
   if (P.want_vertices) bucket_starts(P.vb, vpos);
   if (P.want_frames) bucket_starts(P.fb, fpos);
   __syncthreads();
-  const uint32_t base = blockIdx.x * rta::kTile;
-  for (uint32_t r = 0; r < rta::kTile / 1024; ++r) {
+#pragma unroll 1
+  for (uint32_t r = 0; r < R; ++r) {
     const uint32_t i = base + r * 1024 + threadIdx.x;
     if (i >= P.n) break;
-    const uint32_t prim = P.hits[i].prim_id;
-    const uint32_t inst = P.inst_ids[i];
     float* go = P.d_origins + 3 * (size_t)i;
     float* gd = P.d_directions + 3 * (size_t)i;
-    bool valid = inst < P.inst_count;
-    uint32_t gt = 0;
-    if (valid) {
-      const uint32_t m = P.inst_mesh[inst];
-      const uint32_t b0 = P.tri_base[m];
-      valid = prim < P.tri_base[m + 1] - b0;
-      gt = b0 + prim;
-    }
+    const bool valid = gt[r] != RT_INVALID_ID;
     bool ok = false;
     Adjoint64 A;
     double lx = 0.0, ly = 0.0, lz = 0.0;
     if (valid) {
-      const rt_inst_rec64& M = P.insts64[inst];
+      // independent loads: the ray, its gradient, the frame, the triangle
+      const rt_inst_rec64& M = P.insts64[inst[r]];
       rt_ray q = load_ray(P.rays, i);
-      double ox = q.ox, oy = q.oy, oz = q.oz, dx = q.dx, dy = q.dy, dz = q.dz;
-      double xo = M.m[0] * ox + M.m[1] * oy + M.m[2] * oz + M.m[3];
-      double yo = M.m[4] * ox + M.m[5] * oy + M.m[6] * oz + M.m[7];
-      double zo = M.m[8] * ox + M.m[9] * oy + M.m[10] * oz + M.m[11];
-      double xd = M.m[0] * dx + M.m[1] * dy + M.m[2] * dz;
-      double yd = M.m[4] * dx + M.m[5] * dy + M.m[6] * dz;
-      double zd = M.m[8] * dx + M.m[9] * dy + M.m[10] * dz;
       const float* gr = P.d_tuv + 3 * (size_t)i;
-      ok = adjoint64_solve(P.tri_vertices + 9 * (size_t)gt, xo, yo, zo, xd, yd, zd, gr[0], gr[1], gr[2], A);
+      const float* tv = P.tri_vertices + 9 * (size_t)gt[r];
+      float pv[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) pv[k] = tv[k];
+      double m[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) m[k] = M.m[k];
+      const double g0 = gr[0], g1 = gr[1], g2 = gr[2];
+      double ox = q.ox, oy = q.oy, oz = q.oz, dx = q.dx, dy = q.dy, dz = q.dz;
+      double xo = m[0] * ox + m[1] * oy + m[2] * oz + m[3];
+      double yo = m[4] * ox + m[5] * oy + m[6] * oz + m[7];
+      double zo = m[8] * ox + m[9] * oy + m[10] * oz + m[11];
+      double xd = m[0] * dx + m[1] * dy + m[2] * dz;
+      double yd = m[4] * dx + m[5] * dy + m[6] * dz;
+      double zd = m[8] * dx + m[9] * dy + m[10] * dz;
+      ok = adjoint64_solve(pv, xo, yo, zo, xd, yd, zd, g0, g1, g2, A);
       if (ok) {
         // lambda_w = (A^-1)^T lambda_o
-        lx = M.m[0] * A.lx + M.m[4] * A.ly + M.m[8] * A.lz;
-        ly = M.m[1] * A.lx + M.m[5] * A.ly + M.m[9] * A.lz;
-        lz = M.m[2] * A.lx + M.m[6] * A.ly + M.m[10] * A.lz;
+        lx = m[0] * A.lx + m[4] * A.ly + m[8] * A.lz;
+        ly = m[1] * A.lx + m[5] * A.ly + m[9] * A.lz;
+        lz = m[2] * A.lx + m[6] * A.ly + m[10] * A.lz;
       }
     }
     if (ok) {
@@ -1092,9 +1112,9 @@ __global__ __launch_bounds__(1024) void backward_inst_tile_kernel(BackwardInstPa
     }
     if (!valid) continue;
     if (P.want_vertices) {
-      uint32_t p = atomicAdd(&vpos[gt >> P.vb.shift], 1u);
+      uint32_t p = atomicAdd(&vpos[gt[r] >> P.vb.shift], 1u);
       store_rayrec(P.vb.rec + p, ok ? A.lx : 0.0, ok ? A.ly : 0.0, ok ? A.lz : 0.0, ok ? A.u : 0.0,
-                   ok ? A.v : 0.0, gt);
+                   ok ? A.v : 0.0, gt[r]);
     }
     if (P.want_frames) {
       double px = 0.0, py = 0.0, pz = 0.0;
@@ -1104,7 +1124,7 @@ __global__ __launch_bounds__(1024) void backward_inst_tile_kernel(BackwardInstPa
         py = w0 * A.p[0][1] + w1 * A.p[1][1] + w2 * A.p[2][1];
         pz = w0 * A.p[0][2] + w1 * A.p[1][2] + w2 * A.p[2][2];
       }
-      uint32_t p = atomicAdd(&fpos[inst], 1u);
+      uint32_t p = atomicAdd(&fpos[inst[r]], 1u);
       store_framerec(P.fb.rec + p, lx, ly, lz, px, py, pz);
     }
   }
