@@ -34,6 +34,9 @@ HIT_BYTES = 16
 FINALIZE_BYTES = 48  # the winning triangle's record, read again by the float64 finalize
 BACKWARD_HIT_BYTES = 32 + 16 + 12 + 12 + 36 + 24 + 36  # per hit ray
 BACKWARD_MISS_BYTES = 32 + 16 + 12 + 24
+# two-level hit ray: the above, its instance id, instance record and float64
+# map, the frame read and its ten gradient words written (miss: + instance id)
+BACKWARD_INST_HIT_BYTES = BACKWARD_HIT_BYTES + 4 + 8 + 96 + 40 + 40
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "trace_closest_icosphere_incoherent_pmc_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2603_00292_amd", "csrc", "rt_kernels.hip")
 SQ_FILE = os.path.join(ROOT, "profiles", "trace_closest_icosphere_incoherent_sq_counters.txt")
@@ -472,10 +475,23 @@ def instanced_bench(args, torch, np, api, workloads, ctx, stream):
     # levels, triangle tests, and the finalize's record and float64 map (the
     # instance records read on entry are not counted: a lower bound)
     bpr = 32 + 16 + 4 + nodes / n * 32 * width + tris / n * 48 + 48 + 96
+    # the two-level adjoint on the same rays: vertex and frame gradients
+    hits, inst = api.trace_closest(acc, rays, want_inst=True)
+    g = torch.from_numpy(np.random.default_rng(316).standard_normal((n, 3)).astype(np.float32)).to(dev)
+    dV = torch.zeros((sum(m.vertices.shape[0] for m in W.scene.meshes), 3), dtype=torch.float32, device=dev)
+    dS = torch.zeros((W.scene.inst_srt.shape[0], 10), dtype=torch.float32, device=dev)
+    bwd = lambda: api.trace_backward_instances(acc, rays, hits, inst, g, dV, dS)
+    bwd()
+    ms_b, _ = timed(bwd, max(3, args.steps // 4), stream, torch)
+    nh = int((hits[:, 1].contiguous().view(torch.int32) != -1).sum().item())
+    alg_b = nh * BACKWARD_INST_HIT_BYTES + (n - nh) * BACKWARD_MISS_BYTES
     r = {"instanced_closest_mrays": round(n / (ms * 1e-3) / 1e6, 3),
          "instanced_nodes_per_ray": round(nodes / n, 3), "instanced_tris_per_ray": round(tris / n, 3),
          "instanced_bytes_per_ray": round(bpr, 1),
          "instanced_hbm_frac": round(bpr * n / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+         "instanced_backward_mrays": round(n / (ms_b * 1e-3) / 1e6, 3),
+         "instanced_backward_ms": round(ms_b, 4),
+         "instanced_backward_hbm_frac": round(alg_b / (ms_b * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
          "instanced_workload": f"{W.name}: 1024 instances of 4 x 10000 triangles, {n} rays"}
     log(f"instanced: {r}")
     acc.close()
@@ -538,6 +554,26 @@ def batched_bench(args, torch, np, api, _capi, workloads, ctx, stream):
     steps = max(3, args.steps // 4)
     ms_pm, _ = timed(per_mesh, steps, stream, torch)
     ms_b, _ = timed(batched, steps, stream, torch)
+    # fixed costs of one rt_trace_closest call: the host time to enqueue it
+    # (Python ctypes call included; the first 64 meshes' calls, so the
+    # queue never fills) and the device time of a 64-ray launch (fill,
+    # persistent traversal and overflow-finalize kernels back to back)
+    torch.cuda.synchronize()
+    t_host = time.perf_counter()
+    for a, r, h in list(zip(accs, rays, hits))[:64]:
+        _capi.call("rt_trace_closest", a.handle, C.c_void_p(r.data_ptr()), r.shape[0],
+                   C.c_void_p(h.data_ptr()), None, sptr)
+    host_us = (time.perf_counter() - t_host) / 64 * 1e6
+    torch.cuda.synchronize()
+    small, hsmall = rays[0][:64].contiguous(), torch.empty((64, 4), dtype=torch.float32, device=dev)
+
+    def tiny():
+        for _ in range(100):
+            _capi.call("rt_trace_closest", accs[0].handle, C.c_void_p(small.data_ptr()), 64,
+                       C.c_void_p(hsmall.data_ptr()), None, sptr)
+
+    tiny()
+    ms_tiny, _ = timed(tiny, 3, stream, torch)
     same = all(torch.equal(a.view(torch.int32), b.view(torch.int32)) for a, b in zip(hits, plan.hits))
     # algorithmic bytes of the whole plan: sum over meshes of rays x (ray +
     # hit + finalize) plus their node and triangle fetches (counting variant)
@@ -557,7 +593,9 @@ def batched_bench(args, torch, np, api, _capi, workloads, ctx, stream):
          "batched_bytes_per_ray": round(alg / total, 1),
          "batched_hbm_frac": round(alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
          "batched_accel_bytes": int(footprint),
-         "batched_workload": f"256 meshes, {total} rays"}
+         "batched_workload": f"256 meshes, {total} rays",
+         "per_call_host_us": round(host_us, 2),
+         "per_call_64_rays_device_us": round(ms_tiny * 1e3 / 100, 2)}
     log(f"batched: {r}")
     plan.close()
     for a in accs:

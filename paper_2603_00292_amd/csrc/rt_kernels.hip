@@ -1533,7 +1533,8 @@ hipError_t rtk_launch_finalize_ovf(bool inst, const TraceParams& p, hipStream_t 
   void* args[] = {&q};
   const void* k = inst ? reinterpret_cast<const void*>(&rtk::finalize_ovf_kernel<true>)
                        : reinterpret_cast<const void*>(&rtk::finalize_ovf_kernel<false>);
-  return hipLaunchKernel(k, dim3(2048), dim3(64), args, 0, stream);
+  // one wave per listed range at most (the list holds no more than ovf_cap)
+  return hipLaunchKernel(k, dim3(std::min<uint32_t>(2048u, p.ovf_cap)), dim3(64), args, 0, stream);
 }
 
 hipError_t rtk_launch_finalize_all(bool inst, const TraceParams& p, hipStream_t stream) {
