@@ -441,7 +441,14 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
   RayState r;
   uint32_t ray_id = 0;
   uint32_t cur = RT_CHILD_EMPTY;
-  uint32_t pend = RT_CHILD_EMPTY;  // postponed triangle leaf (single level)
+  // postponed triangle leaves, oldest first: up to three for closest hits
+  // and six for any-hit on one accel, one on two-level accels (measured:
+  // more leaves per lane slow the two-level kernel, whose lanes stop at each
+  // instance boundary anyway)
+  constexpr int K = INST ? 1 : (ANY ? 6 : 3);
+  uint32_t pq[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) pq[k] = RT_CHILD_EMPTY;
   float best_t = 0.0f;
   // the nearest hit so far: its triangle record (RT_INVALID_ID: none yet;
   // the prim id is read from the record where a tie needs it and by the
@@ -454,14 +461,23 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
   uint32_t batch = 0;
   uint32_t rmask = 0xFFFFFFFFu, skip_i = RT_INVALID_ID, skip_p = RT_INVALID_ID, found = 0;
   uint64_t n_nodes = 0, n_tris = 0, n_spill = 0;
+  // counting variant, wave level: passes of the outer loop, refills, and
+  // iterations of the node and the leaf loops (counted by the wave's first
+  // active lane, so every wave iteration once)
+  uint64_t w_outer = 0, w_refill = 0, w_node = 0, w_leaf = 0;
+  auto first_active = [&]() -> bool {
+    return lane == (uint32_t)(__ffsll((unsigned long long)__ballot(1)) - 1);
+  };
 
   while (true) {
+    if constexpr (COUNT) w_outer += lane == 0 ? 1u : 0u;
     // ---- refill finished lanes (one atomic per wave) --------------------
     bool need = !live && !retired;
     uint64_t m = __ballot(need);
     uint64_t mlive = __ballot(live);
     uint32_t n_need = __popcll(m);
     if (n_need > 0 && (mlive == 0 || n_need >= P.refill_min)) {
+      if constexpr (COUNT) w_refill += lane == 0 ? 1u : 0u;
       uint32_t leader = __ffsll((unsigned long long)m) - 1;
       uint32_t base = 0;
       if (lane == leader) base = atomicAdd(P.counter, n_need);
@@ -527,7 +543,8 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
           best_inst = RT_INVALID_ID;
           cur_inst = 0;
           st.sp = 0;
-          pend = RT_CHILD_EMPTY;
+#pragma unroll
+          for (int k = 0; k < K; ++k) pq[k] = RT_CHILD_EMPTY;
           cur = ray_void(wray) ? RT_CHILD_EMPTY : g.root;
           if constexpr (MODE >= 2) {
             rmask = P.ray_masks ? P.ray_masks[local] : 0xFFFFFFFFu;
@@ -604,16 +621,19 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
             }
         }
       };
-      // ---- internal nodes, one leaf postponed ------------------------------
+      // ---- internal nodes, leaves postponed ---------------------------------
       // A lane that reaches a leaf sets it aside and keeps traversing until
-      // it meets a second leaf or every lane of the wave holds a leaf, so
-      // that the wave enters the triangle loop together (leaf postponing,
-      // Aila & Laine 2009).  A postponed leaf is tested in the instance frame
+      // it holds K leaves and meets another, or every lane of the wave holds
+      // a leaf, so that the wave enters the triangle loop together (leaf
+      // postponing, Aila & Laine 2009, with more than one leaf a lane: the
+      // node loop then runs with more lanes busy, the triangle loop with more
+      // triangles a lane).  A postponed leaf is tested in the instance frame
       // it was found in, so a lane holding one stops before a frame change.
       while (cur != RT_CHILD_EMPTY) {
+        if constexpr (COUNT) w_node += first_active() ? 1u : 0u;
         if constexpr (INST) {
           if (cur == RT_STACK_MARKER || is_inst(cur)) {
-            if (pend != RT_CHILD_EMPTY) break;
+            if (pq[0] != RT_CHILD_EMPTY) break;
             if (cur == RT_STACK_MARKER) {
               r.ox = lds_world[0 * WG + tid];
               r.oy = lds_world[1 * WG + tid];
@@ -643,34 +663,51 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
           }
         }
         if (is_tri_leaf(cur)) {
-          if (pend != RT_CHILD_EMPTY) break;
-          pend = cur;
+          if (pq[K - 1] != RT_CHILD_EMPTY) break;
+          bool placed = false;
+#pragma unroll
+          for (int k = 0; k < K; ++k)
+            if (!placed && pq[k] == RT_CHILD_EMPTY) {
+              pq[k] = cur;
+              placed = true;
+            }
           cur = st.pop();
         } else {
           step_node();
         }
-        if (__ballot(pend == RT_CHILD_EMPTY) == 0) break;
+        if (__ballot(pq[0] == RT_CHILD_EMPTY) == 0) break;
       }
-      // ---- triangle leaves: the postponed one, then those on the stack top --
+      // ---- triangle leaves: the postponed ones, then those on the stack top -
       // One triangle per iteration: a lane whose leaf is done moves on to
       // its next leaf while others finish longer leaves (leaves hold 1-15
       // triangles), instead of waiting for the longest leaf of the wave.
       // The nearest-hit cull distance is updated after each leaf, as before.
-      uint32_t tnext = pend & RT_LEAF_FIRST_MASK;
-      uint32_t tleft = pend != RT_CHILD_EMPTY ? (pend >> RT_LEAF_COUNT_SHIFT) & RT_LEAF_COUNT_MASK : 0u;
-      pend = RT_CHILD_EMPTY;
+      auto take_postponed = [&](uint32_t& first, uint32_t& count) {
+        first = pq[0] & RT_LEAF_FIRST_MASK;
+        count = pq[0] != RT_CHILD_EMPTY ? (pq[0] >> RT_LEAF_COUNT_SHIFT) & RT_LEAF_COUNT_MASK : 0u;
+#pragma unroll
+        for (int k = 0; k + 1 < K; ++k) pq[k] = pq[k + 1];
+        pq[K - 1] = RT_CHILD_EMPTY;
+      };
+      uint32_t tnext, tleft;
+      take_postponed(tnext, tleft);
       while (tleft > 0) {
+        if constexpr (COUNT) w_leaf += first_active() ? 1u : 0u;
         bool stop = test_tri(tnext);
         ++tnext;
         --tleft;
         if (ANY && stop) {
           cur = RT_CHILD_EMPTY;
+#pragma unroll
+          for (int k = 0; k < K; ++k) pq[k] = RT_CHILD_EMPTY;
           st.sp = 0;
           break;
         }
         if (tleft == 0) {
           tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
-          if (cur != RT_CHILD_EMPTY && is_tri_leaf(cur)) {
+          if (pq[0] != RT_CHILD_EMPTY) {
+            take_postponed(tnext, tleft);
+          } else if (cur != RT_CHILD_EMPTY && is_tri_leaf(cur)) {
             tnext = cur & RT_LEAF_FIRST_MASK;
             tleft = (cur >> RT_LEAF_COUNT_SHIFT) & RT_LEAF_COUNT_MASK;
             cur = st.pop();
@@ -685,7 +722,7 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
       // and counting launches by finalize_kernel, one thread per ray.  Here:
       // float32 t, the triangle record in the prim slot and the instance in
       // the u slot)
-      if (cur == RT_CHILD_EMPTY && pend == RT_CHILD_EMPTY) {
+      if (cur == RT_CHILD_EMPTY && pq[0] == RT_CHILD_EMPTY) {
         if constexpr (MODE == 3) {
           P.counts[ray_id] = found;
         } else if constexpr (ANY) {
@@ -721,6 +758,14 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
     atomicAdd(reinterpret_cast<unsigned long long*>(P.counters) + 1, (unsigned long long)n_tris);
     atomicAdd(reinterpret_cast<unsigned long long*>(P.counters) + 2, (unsigned long long)n_spill);
     atomicMax(reinterpret_cast<unsigned long long*>(P.counters) + 3, (unsigned long long)st.peak);
+    if (P.phase_counters) {
+      uint64_t w[4] = {w_outer, w_refill, w_node, w_leaf};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        for (int d = 32; d >= 1; d >>= 1) w[k] += __shfl_xor(w[k], d);
+        if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(P.counters) + 4 + k, (unsigned long long)w[k]);
+      }
+    }
   }
   (void)batch;
 }
