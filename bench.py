@@ -149,7 +149,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--probe", type=int, default=0,
                     help="rays the autotuner times (0: all rays of the workload)")
-    ap.add_argument("--only", choices=["backward", "batched", "instanced", "camera", "ao"],
+    ap.add_argument("--only", choices=["backward", "batched", "instanced", "camera", "ao", "phases"],
                     help="run one secondary leg alone and print its figures (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -173,7 +173,8 @@ def main():
                 "batched": lambda: batched_bench(args, torch, np, api, _capi, workloads, ctx, stream),
                 "instanced": lambda: instanced_bench(args, torch, np, api, workloads, ctx, stream),
                 "camera": lambda: camera_bench(args, torch, np, api, workloads, ctx, stream),
-                "ao": lambda: ao_bench(args, torch, np, api, workloads, ctx, stream)}
+                "ao": lambda: ao_bench(args, torch, np, api, workloads, ctx, stream),
+                "phases": lambda: phases_bench(args, torch, np, api, workloads, ctx, stream)}
         print(json.dumps({"leg": args.only, **legs[args.only]()}), flush=True)
         ctx.close()
         return
@@ -456,6 +457,37 @@ def camera_bench(args, torch, np, api, workloads, ctx, stream):
     log(f"camera: {r}")
     acc.close()
     return r
+
+
+def phases_bench(args, torch, np, api, workloads, ctx, stream):
+    """Closest-hit queries on five single-level workloads of different
+    coherence and depth, each as one untimed and `steps` timed launches of
+    the query kernel followed by one launch of its counting variant with the
+    wave-level loop counts (rt_trace_counters_ex).  Under `rocprofv3 --pmc SQ_INSTS_VALU`
+    the per-dispatch instruction counts of the query launches, fitted against
+    these loop counts, split the kernel's instructions by phase."""
+    dev = torch.device("cuda:0")
+    ao = workloads.ao_terrain()
+    sets = [("icosphere_incoherent", workloads.icosphere_incoherent()),
+            ("icosphere_camera", workloads.icosphere_camera()),
+            ("displaced_grid", workloads.displaced_grid()),
+            ("random_triangles_262144", workloads.random_triangles(n_tri=262144, n_rays=1048576, k=7)),
+            ("ao_terrain_camera", ao)]
+    out = {}
+    for name, W in sets:
+        m = W.scene.meshes[0]
+        acc = api.Accel(ctx, [(torch.from_numpy(m.vertices).to(dev), torch.from_numpy(m.indices.view(np.int32)).to(dev))],
+                        node_width=4)
+        rays = torch.from_numpy(W.rays).to(dev)
+        api.trace_closest(acc, rays)
+        ms, _ = timed(lambda: api.trace_closest(acc, rays), args.steps, stream, torch)
+        c = api.trace_phase_counters(acc, rays)
+        c["query_ms"] = round(ms, 4)
+        c["query_launches"] = args.steps
+        out[name] = c
+        log(f"phases {name}: {c}")
+        acc.close()
+    return {"phases": out}
 
 
 def instanced_bench(args, torch, np, api, workloads, ctx, stream):

@@ -431,6 +431,20 @@ rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const 
 rt_status rt_trace_counters(rt_accel accel, const rt_ray* rays, uint32_t n, int any, rt_hit* hits,
                             uint8_t* occluded, uint64_t* counters, void* stream);
 
+/* rt_trace_counters with n_counters (4 or 8) uint64 counters.  With 8 the
+ * call also ADDS the counting kernel's wave-level loop counts to
+ * counters[4..7]: passes of its outer loop (refill check, node phase, leaf
+ * phase), refills, node-loop iterations and leaf-loop iterations, every
+ * iteration of a wave counted once.  A wave iteration issues its
+ * instructions for all 64 lanes, so node visits / (64 x node-loop
+ * iterations) is the node phase's lane occupancy, triangle tests / (64 x
+ * leaf-loop iterations) the leaf phase's.  A diagnostic of how the work of
+ * §7.5's stack traversal spreads over the lanes of a wave.
+ * Errors: as rt_trace_counters; RT_ERROR_INVALID_VALUE for another
+ * n_counters. */
+rt_status rt_trace_counters_ex(rt_accel accel, const rt_ray* rays, uint32_t n, int any, rt_hit* hits,
+                               uint8_t* occluded, uint64_t* counters, uint32_t n_counters, void* stream);
+
 /* Refit (§6.2 construction paragraph: keep the topology of the hierarchy and
  * fit the bounding volumes to the current geometry, bottom-up): replaces the
  * accel's vertices by `vertices` (device, compact records of 3 float32) and

@@ -31,7 +31,7 @@ EXPORTS = [
     "rt_trace_backward_instances",
     "rt_trace_closest_ex", "rt_trace_any_ex", "rt_trace_all", "rt_accel_set_instance_masks", "rt_update_instances",
     "rt_ao_rays", "rt_ao_rays_instances", "rt_ao_resolve",
-    "rt_trace_counters", "rt_refit",
+    "rt_trace_counters", "rt_trace_counters_ex", "rt_refit",
     "rt_autotune",
     "rt_batch_plan_create", "rt_batch_plan_create_instances", "rt_batch_plan_launch", "rt_batch_plan_graph", "rt_batch_plan_destroy",
     "rt_status_string", "rt_last_error_message", "rt_version",
@@ -118,6 +118,7 @@ def load():
             "rt_trace_backward": [P, P, P, P, U32, P, P, P, P],
             "rt_trace_backward_instances": [P, P, P, P, P, U32, P, P, P, P, P],
             "rt_trace_counters": [P, P, U32, I32, P, P, P, P],
+            "rt_trace_counters_ex": [P, P, U32, I32, P, P, P, U32, P],
             "rt_trace_closest_ex": [P, P, U32, P, P, P, P],
             "rt_trace_any_ex": [P, P, U32, P, P, P],
             "rt_trace_all": [P, P, U32, P, U32, P, P, P, P],

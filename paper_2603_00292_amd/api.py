@@ -338,6 +338,27 @@ def trace_counters(accel: Accel, rays: torch.Tensor, any_hit: bool = False, peak
     return (c[0], c[1], c[2]), (occ if any_hit else hits)
 
 
+def trace_phase_counters(accel: Accel, rays: torch.Tensor, any_hit: bool = False) -> dict:
+    """rt_trace_counters_ex with 8 counters: the lane-level work (node
+    visits, triangle tests) and the wave-level loop counts of the counting
+    kernel (outer passes, refills, node-loop and leaf-loop iterations), with
+    the lane occupancy of the node and leaf phases."""
+    _require(rays, "rays", torch.float32, 8)
+    n = rays.shape[0]
+    cnt = torch.zeros((8,), dtype=torch.int64, device=rays.device)
+    hits = occ = None
+    if any_hit:
+        occ = torch.empty((n,), dtype=torch.uint8, device=rays.device)
+    else:
+        hits = torch.empty((n, 4), dtype=torch.float32, device=rays.device)
+    capi.call("rt_trace_counters_ex", accel.handle, _ptr(rays), n, int(any_hit), _ptr(hits), _ptr(occ),
+              _ptr(cnt), 8, C.c_void_p(_stream()))
+    c = cnt.cpu().tolist()
+    return {"rays": n, "node_visits": c[0], "tri_tests": c[1], "spills": c[2], "deepest": c[3],
+            "outer_passes": c[4], "refills": c[5], "node_iters": c[6], "leaf_iters": c[7],
+            "node_lane_occupancy": c[0] / max(64 * c[6], 1), "leaf_lane_occupancy": c[1] / max(64 * c[7], 1)}
+
+
 def trace_backward(accel: Accel, rays: torch.Tensor, hits: torch.Tensor, d_tuv: torch.Tensor,
                    d_vertices: torch.Tensor):
     """Adjoint at fixed triangles; d_vertices is accumulated in place.

@@ -1190,7 +1190,7 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
                               uint32_t* inst_ids, uint8_t* occ, bool any, hipStream_t s,
                               uint64_t* counters = nullptr, int mode = 0,
                               const rt_query_options* opts = nullptr, uint32_t* counts = nullptr,
-                              uint32_t cap = 0, bool noalloc = false) {
+                              uint32_t cap = 0, bool noalloc = false, bool phases = false) {
   rt_context ctx = a->ctx;
   rt_status st = check_device(a->device);
   if (st != RT_SUCCESS) return st;
@@ -1268,6 +1268,7 @@ static rt_status launch_trace(rt_accel a, const rt_ray* rays, uint32_t n, rt_hit
   p.gstride = gstride;
   p.refill_min = ctx->refill_min;
   p.counters = counters;
+  p.phase_counters = (counters && phases) ? 1u : 0u;
   p.status = ctx->status;
   if (opts) {
     p.ray_masks = opts->ray_masks;
@@ -1517,6 +1518,13 @@ rt_status rt_update_instances(rt_accel accel, const rt_srt* instance_srt, void* 
 
 rt_status rt_trace_counters(rt_accel accel, const rt_ray* rays, uint32_t n, int any, rt_hit* hits,
                             uint8_t* occluded, uint64_t* counters, void* stream) {
+  return rt_trace_counters_ex(accel, rays, n, any, hits, occluded, counters, 4, stream);
+}
+
+rt_status rt_trace_counters_ex(rt_accel accel, const rt_ray* rays, uint32_t n, int any, rt_hit* hits,
+                               uint8_t* occluded, uint64_t* counters, uint32_t n_counters, void* stream) {
+  if (n_counters != 4 && n_counters != 8)
+    return fail(RT_ERROR_INVALID_VALUE, "rt_trace_counters: n_counters must be 4 or 8, got %u", n_counters);
   if (!accel) return fail(RT_ERROR_INVALID_VALUE, "rt_trace_counters: NULL accel");
   if (n == 0) return ok();
   if (!rays || !counters || (any ? !occluded : !hits))
@@ -1525,7 +1533,8 @@ rt_status rt_trace_counters(rt_accel accel, const rt_ray* rays, uint32_t n, int 
   if (!aligned16(rays) || (!any && !aligned16(hits)))
     return fail(RT_ERROR_INVALID_VALUE, "rt_trace_counters: rays and hits must be 16-byte aligned");
   return launch_trace(accel, rays, n, any ? nullptr : hits, nullptr, any ? occluded : nullptr,
-                      any != 0, static_cast<hipStream_t>(stream), counters);
+                      any != 0, static_cast<hipStream_t>(stream), counters, 0, nullptr, nullptr, 0, false,
+                      n_counters == 8);
 }
 
 rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hits,

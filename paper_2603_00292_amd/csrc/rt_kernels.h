@@ -43,6 +43,7 @@ struct TraceParams {
   uint32_t gstride;      // threads in the grid
   uint32_t refill_min;   // refill a wave once this many lanes are idle
   uint64_t* counters;    // counting variants: node visits, triangle tests, spills
+  uint32_t phase_counters;  // counting variants: also the wave-level loop counts (counters[4..7])
                          // (sums) and the deepest stack fill (maximum)
   uint32_t* status;      // host-mapped word: a lane of a counting variant
                          // sets it to 1 when a push would exceed max_stack
