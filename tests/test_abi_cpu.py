@@ -80,6 +80,10 @@ def test_null_arguments_rejected_on_host(lib):
     assert lib.rt_accel_set_instance_masks(None, None, None) == c.RT_ERROR_INVALID_VALUE
     assert lib.rt_refit(None, None, None) == c.RT_ERROR_INVALID_VALUE
     assert lib.rt_trace_all(None, None, 0, None, 1, None, None, None, None) == c.RT_ERROR_INVALID_VALUE
+    assert lib.rt_trace_counters(None, None, 0, 0, None, None, None, None) == c.RT_ERROR_INVALID_VALUE
+    for k in (0, 5, 16):
+        assert lib.rt_trace_counters_ex(None, None, 0, 0, None, None, None, k, None) == c.RT_ERROR_INVALID_VALUE
+        assert b"n_counters" in lib.rt_last_error_message()
     del P
 
 

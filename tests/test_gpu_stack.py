@@ -118,6 +118,32 @@ def test_deepest_fill_within_bound(gpu):
         acc.close()
 
 
+def test_phase_counters_consistent(gpu):
+    """The wave-level loop counts of rt_trace_counters_ex on the headline
+    workload and a two-level scene: the first four counters agree with
+    rt_trace_counters' (to 0.5%: which rays share a wave, and so when a
+    lane's postponed leaves are tested and its cull distance shrinks, depends
+    on the order in which waves take rays), a wave iteration serves at most
+    64 lanes (node visits <= 64 x node-loop iterations, triangle tests <= 64
+    x leaf-loop iterations), refills <= outer passes, and the query's answers
+    are those of the plain kernel."""
+    torch, api, ctx = gpu
+    for W in (wl.icosphere_incoherent(), wl.instanced_grids(n_rays=1 << 20)):
+        acc = to_gpu_scene(api, torch, ctx, W.scene)
+        r = torch.from_numpy(W.rays).cuda()
+        (nodes, tris, sp, peak), h4 = api.trace_counters(acc, r, peak=True)
+        c = api.trace_phase_counters(acc, r)
+        h, _ = api.trace_closest(acc, r)
+        say(W.name, {k: (round(v, 3) if isinstance(v, float) else v) for k, v in c.items()})
+        assert abs(c["node_visits"] - nodes) <= 5e-3 * nodes and abs(c["tri_tests"] - tris) <= 5e-3 * tris
+        assert 0 < c["deepest"] <= acc.info["max_stack"] and 0 < peak <= acc.info["max_stack"]
+        assert 0 < c["node_visits"] <= 64 * c["node_iters"] and 0 < c["tri_tests"] <= 64 * c["leaf_iters"]
+        assert 0 < c["refills"] <= c["outer_passes"]
+        assert c["refills"] * 64 >= W.rays.shape[0]
+        assert torch.equal(h4[:, 1].contiguous().view(torch.int32), h[:, 1].contiguous().view(torch.int32))
+        acc.close()
+
+
 def test_overflow_reported_on_next_call(gpu):
     """A context whose lanes may hold only 20 entries (below the accel's
     bound of 26 and the 22 the deepest ray needs; set from the host, so
