@@ -403,11 +403,23 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
  *     instance's (sx,sy,sz, qx,qy,qz,qw, tx,ty,tz) as given to rt_build,
  *     ACCUMULATED; the quaternion part is the gradient with respect to the
  *     unnormalised q (orthogonal to q).
- * Both accumulations are deterministic, as in rt_trace_backward (exact
- * integer sums per row, rounded once; the first call on an accel allocates
- * 260 bytes per vertex row and 4 x 260 bytes per instance, later calls
- * allocate nothing).  t, u, v are recomputed in float64 with the
- * accel's copies of the meshes and frames.  A hit whose instance id is not an instance of
+ * Both accumulations are deterministic and independent of the order of the
+ * rays, as in rt_trace_backward: the hit rays are grouped by triangle range
+ * of the meshes' triangles taken one after another, and by instance; each
+ * (triangle, corner) and each frame row sums its rays' float64
+ * contributions exactly, as 64-bit integers at the row's binary scale, and
+ * is rounded once.  The first call on an accel builds the vertex -> corner
+ * lists of all meshes and a per-triangle copy of the object-space vertices
+ * (4 bytes per vertex row, 120 per triangle, 8 per instance; rt_refit marks
+ * the copy stale and the next call refreshes it); the context's sort
+ * buffers (48 bytes per ray for each of the two groupings, plus 4 per
+ * (4096-ray tile, group)) grow stream-ordered on `stream`.  Accels with
+ * more than 16,384 instances (or any accel on a context created with the
+ * environment variable RT_BACKWARD_ATOMIC=1) sum into fixed-point rows with
+ * device atomics instead (the same row scale and rounding; the first such
+ * call allocates 260 bytes per vertex row and 4 x 260 per instance).
+ * t, u, v are recomputed in float64 with the accel's copies of the meshes
+ * and frames.  A hit whose instance id is not an instance of
  * the accel, or whose prim_id is not a triangle of that instance's mesh,
  * contributes nothing (zero ray gradients).
  * Errors: RT_ERROR_UNSUPPORTED on a single-level accel (use

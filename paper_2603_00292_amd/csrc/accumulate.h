@@ -1,6 +1,11 @@
 // accumulate.h -- deterministic accumulation of per-ray gradient
 // contributions (librtq internal).
 //
+// Two forms.  The first, below, adds into rows with device atomics: it serves
+// the two-level adjoint of accels with more instances than the bucketed form
+// has LDS counters for.  The second, further below, groups the rays first and
+// needs no global atomic; both form the same exact sums.
+//
 // A contribution adds three float64 values to one row (a vertex, or a part of
 // an instance frame).  The sums are formed in 64-bit integers, so they do not
 // depend on the order in which rays reach a row:
@@ -22,10 +27,11 @@
 // The phase-1 sums are kept per XCD (the chip's eight dies, each with its own
 // L2): a wave adds into the copy of the die it runs on, with atomics of
 // workgroup scope that complete in that die's L2 instead of travelling to the
-// memory side as device-scope atomics do (on the 1M-ray backward: 423 us ->
-// see the profiles); no other die touches that copy during the launch, and
-// the kernel boundary makes the copies visible to the convert, which adds the
-// eight integer partial sums (exactly, in any order).
+// memory side as device-scope atomics do; no other die touches that copy
+// during the launch, and the kernel boundary makes the copies visible to the
+// convert, which adds the eight integer partial sums (exactly, in any order).
+// Random atomics still run at about 25 G per second on this chip whatever
+// their scope, which is why the grouped form exists.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
