@@ -282,14 +282,18 @@ __device__ __forceinline__ bool finalize64(const float4* tris, uint32_t rec, dou
 // world -> object ray with the float32 instance map (no renormalisation, so
 // t is shared between the two spaces)
 // (r holds the world ray on entry; tmin and tmax carry over unchanged)
-__device__ __forceinline__ void to_object(const rt_inst_rec& I, RayState& r) {
-  const float wox = r.ox, woy = r.oy, woz = r.oz, wdx = r.dx, wdy = r.dy, wdz = r.dz;
+__device__ __forceinline__ void to_object_od(const rt_inst_rec& I, float wox, float woy, float woz, float wdx,
+                                             float wdy, float wdz, RayState& r) {
   r.ox = I.r0[0] * wox + I.r0[1] * woy + I.r0[2] * woz + I.r0[3];
   r.oy = I.r1[0] * wox + I.r1[1] * woy + I.r1[2] * woz + I.r1[3];
   r.oz = I.r2[0] * wox + I.r2[1] * woy + I.r2[2] * woz + I.r2[3];
   r.dx = I.r0[0] * wdx + I.r0[1] * wdy + I.r0[2] * wdz;
   r.dy = I.r1[0] * wdx + I.r1[1] * wdy + I.r1[2] * wdz;
   r.dz = I.r2[0] * wdx + I.r2[1] * wdy + I.r2[2] * wdz;
+}
+
+__device__ __forceinline__ void to_object(const rt_inst_rec& I, RayState& r) {
+  to_object_od(I, r.ox, r.oy, r.oz, r.dx, r.dy, r.dz, r);
   ray_setup(r);
 }
 
@@ -442,10 +446,9 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
   uint32_t ray_id = 0;
   uint32_t cur = RT_CHILD_EMPTY;
   // postponed triangle leaves, oldest first: up to three for closest hits
-  // and six for any-hit on one accel, one on two-level accels (measured:
-  // more leaves per lane slow the two-level kernel, whose lanes stop at each
-  // instance boundary anyway)
-  constexpr int K = INST ? 1 : (ANY ? 6 : 3);
+  // and six for any-hit on one accel, two on two-level accels (the counts
+  // measured fastest)
+  constexpr int K = INST ? 2 : (ANY ? 6 : 3);
   uint32_t pq[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) pq[k] = RT_CHILD_EMPTY;
@@ -454,6 +457,11 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
   // the prim id is read from the record where a tie needs it and by the
   // finalize) and instance
   uint32_t best_rec = RT_INVALID_ID, best_inst = RT_INVALID_ID, cur_inst = 0;
+  // two-level: the instance of each postponed leaf, and whether the
+  // traversal ray is in an instance's object space (cur_inst) or in world
+  // space
+  uint32_t pin[K];
+  bool in_inst = false;
   rt_hit* hit_out = P.hits;
   uint8_t* occ_out = P.occluded;
   const rt_ray* ray_in = P.rays;
@@ -542,6 +550,7 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
           best_rec = RT_INVALID_ID;
           best_inst = RT_INVALID_ID;
           cur_inst = 0;
+          in_inst = false;
           st.sp = 0;
 #pragma unroll
           for (int k = 0; k < K; ++k) pq[k] = RT_CHILD_EMPTY;
@@ -566,6 +575,19 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
     }
     if (live) {
       float tcull = fmaf(fabsf(best_t), kTieWiden, best_t);
+      uint32_t linst = cur_inst;   // instance of the leaf under test
+      // sets r's origin and direction to those of the world ray in instance
+      // j's object space (the reciprocals stay those of the traversal frame)
+      auto frame_od = [&](bool inside, uint32_t j) {
+        const float wox = lds_world[0 * WG + tid], woy = lds_world[1 * WG + tid], woz = lds_world[2 * WG + tid];
+        const float wdx = lds_world[3 * WG + tid], wdy = lds_world[4 * WG + tid], wdz = lds_world[5 * WG + tid];
+        if (inside) {
+          to_object_od(g.insts[j], wox, woy, woz, wdx, wdy, wdz, r);
+        } else {
+          r.ox = wox; r.oy = woy; r.oz = woz;
+          r.dx = wdx; r.dy = wdy; r.dz = wdz;
+        }
+      };
       // Tests the triangles of one leaf; true when an any-hit query may stop.
       // Tests triangle record `rec`; true when an any-hit query may stop.
       auto test_tri = [&](uint32_t rec) -> bool {
@@ -576,11 +598,11 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
         if (tri_test(A, B, C, r, t) && t >= r.tmin && t <= best_t) {
           uint32_t prim = __float_as_uint(A.w);
           if constexpr (MODE >= 2) {
-            if (prim == skip_p && (!INST || cur_inst == skip_i)) return false;
+            if (prim == skip_p && (!INST || linst == skip_i)) return false;
           }
           if constexpr (MODE == 3) {
             list_insert(reinterpret_cast<float4*>(hit_out) + (size_t)ray_id * P.cap, found, P.cap, t,
-                        INST ? cur_inst : 0u, prim, rec);
+                        INST ? linst : 0u, prim, rec);
             ++found;
             return false;
           }
@@ -589,7 +611,7 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
             return true;
           } else {
             // lexicographic (t, inst, prim); t <= best_t here
-            uint32_t inst = INST ? cur_inst : 0u;
+            uint32_t inst = INST ? linst : 0u;
             bool better = (t < best_t) || (inst < best_inst);
             if (!better && inst == best_inst)
               better = prim < __float_as_uint(g.tris[3 * (size_t)best_rec].w);
@@ -627,13 +649,15 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
       // a leaf, so that the wave enters the triangle loop together (leaf
       // postponing, Aila & Laine 2009, with more than one leaf a lane: the
       // node loop then runs with more lanes busy, the triangle loop with more
-      // triangles a lane).  A postponed leaf is tested in the instance frame
-      // it was found in, so a lane holding one stops before a frame change.
+      // triangles a lane).  A postponed leaf remembers its instance, and the
+      // triangle loop takes the world ray into that instance's object space
+      // to test it (the float32 map of the instance entry, applied to the
+      // same world ray, so the object ray is the same), so a lane holding one
+      // keeps traversing across instance boundaries.
       while (cur != RT_CHILD_EMPTY) {
         if constexpr (COUNT) w_node += first_active() ? 1u : 0u;
         if constexpr (INST) {
           if (cur == RT_STACK_MARKER || is_inst(cur)) {
-            if (pq[0] != RT_CHILD_EMPTY) break;
             if (cur == RT_STACK_MARKER) {
               r.ox = lds_world[0 * WG + tid];
               r.oy = lds_world[1 * WG + tid];
@@ -642,6 +666,7 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
               r.dy = lds_world[4 * WG + tid];
               r.dz = lds_world[5 * WG + tid];
               ray_setup(r);
+              in_inst = false;
               r.tmax = best_t;
               cur = st.pop();
               continue;
@@ -657,6 +682,7 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
             to_object(I, r);
             r.tmax = best_t;
             cur_inst = j;
+            in_inst = true;
             st.push(RT_STACK_MARKER);
             cur = I.root;
             continue;
@@ -669,6 +695,7 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
           for (int k = 0; k < K; ++k)
             if (!placed && pq[k] == RT_CHILD_EMPTY) {
               pq[k] = cur;
+              if constexpr (INST) pin[k] = cur_inst;
               placed = true;
             }
           cur = st.pop();
@@ -682,9 +709,23 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
       // its next leaf while others finish longer leaves (leaves hold 1-15
       // triangles), instead of waiting for the longest leaf of the wave.
       // The nearest-hit cull distance is updated after each leaf, as before.
+      // r's origin and direction are in frame rf (RT_INVALID_ID: world)
+      const uint32_t home = in_inst ? cur_inst : RT_INVALID_ID;
+      uint32_t rf = home;
       auto take_postponed = [&](uint32_t& first, uint32_t& count) {
         first = pq[0] & RT_LEAF_FIRST_MASK;
         count = pq[0] != RT_CHILD_EMPTY ? (pq[0] >> RT_LEAF_COUNT_SHIFT) & RT_LEAF_COUNT_MASK : 0u;
+        if constexpr (INST) {
+          if (pq[0] != RT_CHILD_EMPTY) {
+            linst = pin[0];
+            if (rf != pin[0]) {
+              frame_od(true, pin[0]);
+              rf = pin[0];
+            }
+          }
+#pragma unroll
+          for (int k = 0; k + 1 < K; ++k) pin[k] = pin[k + 1];
+        }
 #pragma unroll
         for (int k = 0; k + 1 < K; ++k) pq[k] = pq[k + 1];
         pq[K - 1] = RT_CHILD_EMPTY;
@@ -708,11 +749,22 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
           if (pq[0] != RT_CHILD_EMPTY) {
             take_postponed(tnext, tleft);
           } else if (cur != RT_CHILD_EMPTY && is_tri_leaf(cur)) {
+            if constexpr (INST) {
+              // the leaves on the stack top are in the traversal frame
+              if (rf != home) {
+                frame_od(in_inst, cur_inst);
+                rf = home;
+              }
+              linst = cur_inst;
+            }
             tnext = cur & RT_LEAF_FIRST_MASK;
             tleft = (cur >> RT_LEAF_COUNT_SHIFT) & RT_LEAF_COUNT_MASK;
             cur = st.pop();
           }
         }
+      }
+      if constexpr (INST) {
+        if (rf != home) frame_od(in_inst, cur_inst);   // back to the traversal frame
       }
       // ---- finished: write the result --------------------------------------
       // (the float64 (t, u, v) and the prim id of a closest hit are written
