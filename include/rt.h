@@ -60,7 +60,7 @@ typedef enum rt_status {
   RT_ERROR_OUT_OF_MEMORY = 2,      /* a device or host allocation failed */
   RT_ERROR_NO_DEVICE = 3,          /* no HIP device, or the device id is out of range */
   RT_ERROR_HIP = 4,                /* a HIP runtime call failed (detail in the message) */
-  RT_ERROR_UNSUPPORTED = 5,        /* valid request this build does not implement */
+  RT_ERROR_UNSUPPORTED = 5,        /* a valid request the library does not implement */
   RT_ERROR_INDEX_OUT_OF_RANGE = 6, /* a triangle index >= vertex_count, a mesh id >= mesh_count */
   RT_ERROR_STACK_OVERFLOW = 7      /* an earlier counting traversal (rt_trace_counters) on this
                                       context needed more stack entries than the accel's bound
