@@ -128,19 +128,43 @@ struct Geo {
 
 // W-wide node visit: returns the child refs that the ray enters, nearest
 // first, in keys k[0..W-1] (0xFFFFFFFF = no child).
-template <int W>
+// DIRECT (4-wide nodes only): each lane loads its near and far plane
+// vectors at lane-dependent addresses (lo or hi by the sign of the ray's
+// direction) instead of loading both and selecting; it needs more registers,
+// which pays only where they are free (the single-level any-hit kernel:
+// +2%; the closest-hit kernel loses a wave per SIMD and 5%).
+template <int W, bool DIRECT = false>
 __device__ __forceinline__ void visit_node(const float* nodes, uint32_t idx, const RayState& r,
                                            float tcull, uint32_t* out_ref, int& n_out) {
   constexpr int NF4 = (W == 2) ? 4 : (7 * W) / 4;  // skip trailing pad when it fills a float4
+  constexpr bool PRE = DIRECT && W == 4;            // planes loaded in (near, far) order
   const float4* p = reinterpret_cast<const float4*>(nodes + (size_t)idx * (8 * W));
   float nd[4 * NF4];
+  if constexpr (PRE) {
+    float4 v[7];
+    v[0] = p[r.sx];
+    v[1] = p[1u - r.sx];
+    v[2] = p[2u + r.sy];
+    v[3] = p[3u - r.sy];
+    v[4] = p[4u + r.sz];
+    v[5] = p[5u - r.sz];
+    v[6] = p[6];
 #pragma unroll
-  for (int i = 0; i < NF4; ++i) {
-    float4 v = p[i];
-    nd[4 * i + 0] = v.x;
-    nd[4 * i + 1] = v.y;
-    nd[4 * i + 2] = v.z;
-    nd[4 * i + 3] = v.w;
+    for (int i = 0; i < 7; ++i) {
+      nd[4 * i + 0] = v[i].x;
+      nd[4 * i + 1] = v[i].y;
+      nd[4 * i + 2] = v[i].z;
+      nd[4 * i + 3] = v[i].w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < NF4; ++i) {
+      float4 v = p[i];
+      nd[4 * i + 0] = v.x;
+      nd[4 * i + 1] = v.y;
+      nd[4 * i + 2] = v.z;
+      nd[4 * i + 3] = v.w;
+    }
   }
   constexpr int SH = (W == 2) ? 1 : ((W == 4) ? 2 : 3);
   uint32_t key[W];
@@ -149,9 +173,9 @@ __device__ __forceinline__ void visit_node(const float* nodes, uint32_t idx, con
     float lox = nd[0 * W + i], hix = nd[1 * W + i];
     float loy = nd[2 * W + i], hiy = nd[3 * W + i];
     float loz = nd[4 * W + i], hiz = nd[5 * W + i];
-    float nx = r.sx ? hix : lox, fx = r.sx ? lox : hix;
-    float ny = r.sy ? hiy : loy, fy = r.sy ? loy : hiy;
-    float nz = r.sz ? hiz : loz, fz = r.sz ? loz : hiz;
+    float nx = PRE ? lox : (r.sx ? hix : lox), fx = PRE ? hix : (r.sx ? lox : hix);
+    float ny = PRE ? loy : (r.sy ? hiy : loy), fy = PRE ? hiy : (r.sy ? loy : hiy);
+    float nz = PRE ? loz : (r.sz ? hiz : loz), fz = PRE ? hiz : (r.sz ? loz : hiz);
     float tnx = (nx - r.ox) * r.ix, tfx = (fx - r.ox) * r.ix;
     float tny = (ny - r.oy) * r.iy, tfy = (fy - r.oy) * r.iy;
     float tnz = (nz - r.oz) * r.iz, tfz = (fz - r.oz) * r.iz;
@@ -630,7 +654,7 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
         uint32_t refs[W];
         int nh;
         if constexpr (COUNT) n_nodes++;
-        visit_node<W>(g.nodes, cur, r, tcull, refs, nh);
+        visit_node<W, ANY && !INST>(g.nodes, cur, r, tcull, refs, nh);
         if (nh == 0) {
           cur = st.pop();
         } else {
