@@ -432,7 +432,7 @@ __device__ __forceinline__ void finalize_index(const TraceParams& P, uint32_t i)
 }
 
 template <int W, bool INST, bool COUNT, int MODE>
-constexpr int trace_min_waves() { return (INST && W <= 4 && !COUNT && MODE != 1) ? 6 : 1; }
+constexpr int trace_min_waves() { return (INST && W <= 4 && !COUNT && MODE != 1) ? 5 : 1; }
 template <int W, int S, int WG, bool ANY, bool INST, int MODE, bool COUNT = false>
 __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void trace_kernel(TraceParams P) {
   __shared__ uint32_t lds_stack[S * WG];
@@ -693,27 +693,28 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
               in_inst = false;
               r.tmax = best_t;
               cur = st.pop();
-              continue;
+            } else {
+              uint32_t j = cur & RT_INST_INDEX_MASK;
+              const rt_inst_rec& I = g.insts[j];
+              bool skip = I.root == RT_CHILD_EMPTY;
+              if constexpr (MODE >= 2) skip = skip || (I.mask & rmask) == 0u;
+              if (skip) {
+                cur = st.pop();
+              } else {
+                to_object(I, r);
+                r.tmax = best_t;
+                cur_inst = j;
+                in_inst = true;
+                st.push(RT_STACK_MARKER);
+                cur = I.root;
+              }
             }
-            uint32_t j = cur & RT_INST_INDEX_MASK;
-            const rt_inst_rec& I = g.insts[j];
-            bool skip = I.root == RT_CHILD_EMPTY;
-            if constexpr (MODE >= 2) skip = skip || (I.mask & rmask) == 0u;
-            if (skip) {
-              cur = st.pop();
-              continue;
-            }
-            to_object(I, r);
-            r.tmax = best_t;
-            cur_inst = j;
-            in_inst = true;
-            st.push(RT_STACK_MARKER);
-            cur = I.root;
-            continue;
+            // a node or a leaf after the frame change is taken in the same
+            // iteration; another frame change or the end waits for the next
+            if (cur == RT_CHILD_EMPTY || cur == RT_STACK_MARKER || is_inst(cur)) continue;
           }
         }
-        if (is_tri_leaf(cur)) {
-          if (pq[K - 1] != RT_CHILD_EMPTY) break;
+        auto postpone = [&]() {
           bool placed = false;
 #pragma unroll
           for (int k = 0; k < K; ++k)
@@ -723,8 +724,26 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
               placed = true;
             }
           cur = st.pop();
+        };
+        if constexpr (INST) {
+          // two-level: an internal node under a postponed leaf is visited in
+          // the same iteration, so that a lane's iterations are node visits
+          bool visit = true;
+          if (is_tri_leaf(cur)) {
+            if (pq[K - 1] != RT_CHILD_EMPTY) break;
+            postpone();
+            visit = is_internal(cur);
+          }
+          if (visit) step_node();
         } else {
-          step_node();
+          // (the same fall-through here measured 2% slower on incoherent and
+          // 3% faster on camera rays; the simpler loop stays)
+          if (is_tri_leaf(cur)) {
+            if (pq[K - 1] != RT_CHILD_EMPTY) break;
+            postpone();
+          } else {
+            step_node();
+          }
         }
         if (__ballot(pq[0] == RT_CHILD_EMPTY) == 0) break;
       }
