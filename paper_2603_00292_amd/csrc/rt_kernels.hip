@@ -725,9 +725,10 @@ __global__ __launch_bounds__(WG, (trace_min_waves<W, INST, COUNT, MODE>())) void
             }
           cur = st.pop();
         };
-        if constexpr (INST || !ANY) {
+        if constexpr (INST || (!ANY && MODE != 1)) {
           // an internal node under a postponed leaf is visited in the same
-          // iteration, so that a lane's iterations are node visits
+          // iteration, so that a lane's iterations are node visits (batched
+          // single-level plans: -2% with it)
           bool visit = true;
           if (is_tri_leaf(cur)) {
             if (pq[K - 1] != RT_CHILD_EMPTY) break;
