@@ -389,3 +389,64 @@ def test_backward_empty_mesh(gpu):
     assert (h[:, 1].copy().view(np.uint32) == NONE).all()
     assert (dV == 0).all() and (do == 0).all() and (dd == 0).all()
     acc.close()
+
+
+def _fans(rng, valences, n_rays):
+    """Fans side by side: fan f has one hub vertex shared by valences[f]
+    triangles (rim angles and radii jittered, rim heights +-0.05), and rays
+    from above through interior points of random triangles."""
+    verts, tris = [], []
+    for f, k in enumerate(valences):
+        hub = len(verts)
+        cx = 3.0 * f
+        verts.append([cx, 0.0, 0.0])
+        ang = 2.0 * np.pi * (np.arange(k) + rng.uniform(-0.2, 0.2, k)) / k
+        rad = rng.uniform(0.8, 1.2, k)
+        for a, rr in zip(ang, rad):
+            verts.append([cx + rr * np.cos(a), rng.uniform(-0.05, 0.05), rr * np.sin(a)])
+        for j in range(k):
+            tris.append([hub, hub + 1 + j, hub + 1 + (j + 1) % k])
+    V = np.asarray(verts, np.float32)
+    I = np.asarray(tris, np.uint32)
+    t = rng.integers(0, I.shape[0], n_rays)
+    b = rng.dirichlet([2.0, 2.0, 2.0], n_rays)
+    P = (b[:, :, None] * V[I[t]].astype(np.float64)).sum(1)
+    o = P + np.stack([rng.normal(0, 0.1, n_rays), np.full(n_rays, 2.0), rng.normal(0, 0.1, n_rays)], 1)
+    return V, I, wl.pack_rays(o, P - o)
+
+
+def test_backward_high_valence_vertices(gpu, orc):
+    """Hub vertices that are corners of 8, 9 and 20 triangles (the vertex
+    pass gathers a vertex's corners eight at a time, so 9 and 20 take more
+    than one round): every pinned hit ray's gradients and every vertex row
+    against the oracle's float64 adjoint."""
+    torch, api, ctx = gpu
+    valences = (8, 9, 20)
+    V, I, rays = _fans(wl.rng_for(356), valences, 8192)
+    W = wl.Workload("fans", wl.Scene([wl.Mesh(V, I)]), rays, {})
+    S = orc.OracleScene.from_scene(W.scene)
+    A = orc.accept(S, rays)
+    _, oprim, _ = orc.closest(S, rays)
+    pinned_hit = A.pinned & (oprim != NONE)
+    # every triangle of every fan is hit by pinned rays, so each hub row
+    # gathers as many non-zero corners as its valence
+    assert np.unique(oprim[pinned_hit]).size == I.shape[0]
+    g = wl.rng_for(357).normal(size=(rays.shape[0], 3)).astype(np.float32).astype(np.float64)
+    g *= pinned_hit[:, None]
+    acc, (h, dV, do, dd) = _run(gpu, W, g)
+    prim = h[:, 1].copy().view(np.uint32)
+    assert (prim[pinned_hit] == oprim[pinned_hit]).all()
+    rV, ro, rd = orc.adjoint(S, rays, np.where(pinned_hit, oprim, NONE), g)
+    r = np.flatnonzero(pinned_hit)
+    say("fans", valences, "pinned hits", r.size)
+    assert r.size > 6000
+    eo = np.linalg.norm(do[r] - ro[r], axis=1) / np.maximum(np.linalg.norm(ro[r], axis=1), 1e-30)
+    ed = np.linalg.norm(dd[r] - rd[r], axis=1) / np.maximum(np.linalg.norm(rd[r], axis=1), 1e-30)
+    assert eo.max() <= GRAD_REL and ed.max() <= GRAD_REL
+    hubs = np.cumsum([0] + [k + 1 for k in valences[:-1]])
+    assert (np.abs(rV[hubs]).sum(1) > 0).all()
+    rms = np.sqrt((rV ** 2).sum(1).mean())
+    err = np.abs(dV - rV)
+    say("hub rows max err", err[hubs].max(), "all rows max err / rms", err.max() / rms)
+    assert (err <= 2.0 ** -22 * np.abs(rV) + 1e-9 * rms).all()
+    acc.close()
