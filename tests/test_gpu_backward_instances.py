@@ -402,3 +402,65 @@ def test_backward_instances_many_instances(gpu):
         bound = (cnt + 2) * EPS32 * a_o * 2 + 1e-9
         assert (np.abs(dS[:, 7 + c] + s_o) <= bound).all()
     acc.close()
+
+
+def _large_two_level(rng, n_tri, n_rays):
+    """Two soups of n_tri triangles each under four frames (scales 0.8-1.2,
+    random rotations, translations 1.5 apart), rays from inside the scene."""
+    half = 0.025 * np.sqrt(4096.0 / n_tri) * 4
+    meshes = [wl.Mesh(*wl.random_triangle_soup(rng, n_tri, half)) for _ in range(2)]
+    srt = np.zeros((4, 10), np.float64)
+    srt[:, 0:3] = rng.uniform(0.8, 1.2, (4, 3))
+    srt[:, 3:7] = wl.uniform_quaternions(rng, 4)
+    srt[:, 7:10] = [[0.0, 0.0, 0.0], [1.5, 0.0, 0.0], [0.0, 1.5, 0.0], [1.5, 1.5, 0.0]]
+    scene = wl.Scene(meshes, np.array([0, 1, 0, 1], np.uint32), srt.astype(np.float32))
+    return scene, wl.box_rays(rng, n_rays, -0.5, 2.5)
+
+
+def test_backward_instances_128_triangle_buckets(gpu, orc, monkeypatch):
+    """More than 2^20 triangles over the meshes of a two-level scene, so the
+    rays are grouped in buckets of 128 triangles (64 up to 2^20): every
+    pinned hit's ray gradients and the vertex tensor against the oracle, and
+    vertex and frame gradients against the fixed-point atomic rows within
+    two float32 roundings."""
+    torch, api, ctx = gpu
+    scene, rays_np = _large_two_level(wl.rng_for(358), 600_000, 65536)
+    acc = to_gpu_scene(api, torch, ctx, scene)
+    rays, hits, inst = _forward(gpu, acc, rays_np)
+    h = hits.cpu().numpy()
+    ii = inst.cpu().numpy().view(np.uint32)
+    S = orc.OracleScene.from_scene(scene, accel=True)
+    A = orc.accept(S, rays_np)
+    oinst, oprim, _ = orc.closest(S, rays_np)
+    prim = h[:, 1].copy().view(np.uint32)
+    keep = A.pinned & (oprim != NONE)
+    assert (prim[keep] == oprim[keep]).all() and (ii[keep] == oinst[keep]).all()
+    say("pinned hits", int(keep.sum()))
+    assert keep.sum() > 10000
+    g = wl.rng_for(359).standard_normal((rays_np.shape[0], 3)).astype(np.float32).astype(np.float64)
+    g *= keep[:, None]
+    nv = int(_bases(scene)[-1])
+    dV, dS, do, dd = _backward(gpu, acc, rays, hits, inst, g, nv, 4)
+    rV, rS, ro, rd = orc.adjoint_inst(S, rays_np, oinst, np.where(keep, oprim, NONE).astype(np.uint32), g)
+    rV = np.concatenate(rV)
+    r = np.flatnonzero(keep)
+    eo = np.linalg.norm(do[r] - ro[r], axis=1) / np.linalg.norm(ro[r], axis=1)
+    ed = np.linalg.norm(dd[r] - rd[r], axis=1) / np.linalg.norm(rd[r], axis=1)
+    assert eo.max() <= GRAD_REL and ed.max() <= GRAD_REL
+    fv = np.linalg.norm(dV - rV) / np.linalg.norm(rV)
+    fs = np.linalg.norm(dS - rS) / np.linalg.norm(rS)
+    say("Frobenius rel err: vertices", fv, "frames", fs)
+    assert fv <= 1e-5 and fs <= 1e-5
+    monkeypatch.setenv("RT_BACKWARD_ATOMIC", "1")
+    ctx2 = api.Context(0)
+    monkeypatch.delenv("RT_BACKWARD_ATOMIC")
+    acc2 = to_gpu_scene(api, torch, ctx2, scene)
+    b = _backward((torch, api, ctx2), acc2, rays, hits, inst, g, nv, 4)
+    assert np.array_equal(do, b[2]) and np.array_equal(dd, b[3])
+    for x, y, name in ((dV, b[0], "vertices"), (dS, b[1], "frames")):
+        tol = 2 * EPS32 * np.maximum(np.abs(x), np.abs(y)) + 1e-9 * np.abs(x).max()
+        say(name, "vs atomic rows: max err/tol", float((np.abs(x - y) / tol).max()))
+        assert (np.abs(x - y) <= tol).all()
+    acc2.close()
+    ctx2.close()
+    acc.close()
