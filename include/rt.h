@@ -379,8 +379,12 @@ rt_status rt_trace_all(rt_accel accel, const rt_ray* rays, uint32_t n,
  * d_origins / d_directions (device, n*3 float32) are overwritten (zero for
  * misses).  t, u, v are recomputed in float64 from the triangle, so `hits`
  * contributes only the triangle id.
- * Errors: RT_ERROR_UNSUPPORTED on a two-level accel (use
- * rt_trace_backward_instances). */
+ * Errors: RT_ERROR_INVALID_VALUE for a NULL accel, NULL rays, hits, d_tuv,
+ * d_vertices, d_origins or d_directions with n > 0, or rays/hits not 16-byte
+ * aligned; RT_ERROR_UNSUPPORTED on a two-level accel (use
+ * rt_trace_backward_instances) or a mesh of more than 16,777,216 triangles
+ * (16,384 groups of at most 1,024); RT_ERROR_OUT_OF_MEMORY when the lists,
+ * the vertex copy or the sort buffers cannot be allocated. */
 rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hits,
                             const float* d_tuv, uint32_t n, float* d_vertices, float* d_origins,
                             float* d_directions, void* stream);
@@ -423,9 +427,11 @@ rt_status rt_trace_backward(rt_accel accel, const rt_ray* rays, const rt_hit* hi
  * the accel, or whose prim_id is not a triangle of that instance's mesh,
  * contributes nothing (zero ray gradients).
  * Errors: RT_ERROR_UNSUPPORTED on a single-level accel (use
- * rt_trace_backward); RT_ERROR_INVALID_VALUE for NULL rays, hits, inst_ids,
- * d_tuv, d_origins or d_directions with n > 0, or rays/hits not 16-byte
- * aligned. */
+ * rt_trace_backward), or with d_vertices on an accel of 2^32 - 1 or more
+ * vertex rows; RT_ERROR_INVALID_VALUE for a NULL accel, NULL rays, hits,
+ * inst_ids, d_tuv, d_origins or d_directions with n > 0, or rays/hits not
+ * 16-byte aligned; RT_ERROR_OUT_OF_MEMORY when the lists, the vertex copy,
+ * the sort buffers or the atomic rows cannot be allocated. */
 rt_status rt_trace_backward_instances(rt_accel accel, const rt_ray* rays, const rt_hit* hits,
                                       const uint32_t* inst_ids, const float* d_tuv, uint32_t n,
                                       float* d_vertices, float* d_srt, float* d_origins,
