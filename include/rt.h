@@ -19,8 +19,9 @@
  *    host and returned before anything is enqueued; a device fault surfaces as
  *    RT_ERROR_HIP from a later call.  No C++ exception crosses the boundary.
  *    rt_last_error_message() gives a thread-local detail string.
- *    In every function: a NULL handle (context, accel, plan) or a NULL
- *    output pointer is RT_ERROR_INVALID_VALUE, a failed device or host
+ *    In every function: a NULL handle (context, accel, plan), or a NULL
+ *    pointer that the call would read or write (a query with n = 0 touches
+ *    no buffer), is RT_ERROR_INVALID_VALUE, a failed device or host
  *    allocation RT_ERROR_OUT_OF_MEMORY, a failed HIP call RT_ERROR_HIP.  A
  *    handle used while another device is current is not an error: the call
  *    makes the handle's device current for the calling thread, and it stays
