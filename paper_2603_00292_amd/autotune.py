@@ -114,11 +114,15 @@ def cache_path() -> str:
 
 
 def load_cache() -> dict:
+    """The cache's contents; a missing, unreadable or malformed file reads as
+    empty (it is a cache: the next save rewrites it)."""
     p = cache_path()
-    if os.path.exists(p):
+    try:
         with open(p) as f:
-            return json.load(f)
-    return {}
+            c = json.load(f)
+    except (OSError, ValueError):
+        return {}
+    return c if isinstance(c, dict) and all(isinstance(v, dict) for v in c.values()) else {}
 
 
 def save_choice(device, cls: str, best: dict) -> None:
@@ -135,8 +139,15 @@ def save_choice(device, cls: str, best: dict) -> None:
 
 
 def cached_choice(device, cls: str):
+    """The cached configuration of (device, scene class), or None (also for an
+    entry that does not name a node width, stack depth and workgroup)."""
     key = device if isinstance(device, str) else device_key(device)
-    return load_cache().get(key, {}).get(cls)
+    hit = load_cache().get(key, {}).get(cls)
+    if not isinstance(hit, dict):
+        return None
+    if not all(isinstance(hit.get(k), int) for k in ("node_width", "stack_entries", "workgroup")):
+        return None
+    return hit
 
 
 def main():

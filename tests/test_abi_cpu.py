@@ -47,7 +47,8 @@ def test_status_strings(lib):
                        (c.RT_ERROR_OUT_OF_MEMORY, "RT_ERROR_OUT_OF_MEMORY"),
                        (c.RT_ERROR_NO_DEVICE, "RT_ERROR_NO_DEVICE"), (c.RT_ERROR_HIP, "RT_ERROR_HIP"),
                        (c.RT_ERROR_UNSUPPORTED, "RT_ERROR_UNSUPPORTED"),
-                       (c.RT_ERROR_INDEX_OUT_OF_RANGE, "RT_ERROR_INDEX_OUT_OF_RANGE")]:
+                       (c.RT_ERROR_INDEX_OUT_OF_RANGE, "RT_ERROR_INDEX_OUT_OF_RANGE"),
+                       (c.RT_ERROR_STACK_OVERFLOW, "RT_ERROR_STACK_OVERFLOW")]:
         assert lib.rt_status_string(code).decode() == name
     assert lib.rt_version() == 100
 
@@ -138,3 +139,20 @@ def test_autotune_cache_roundtrip(tmp_path, monkeypatch):
     assert autotune.cached_choice("gfx950_cu256", "tri4^6_ray4^8") == b
     assert autotune.cached_choice("gfx942_cu304", "tri4^10_ray4^11") == b
     assert not [p for p in (tmp_path / "sub").iterdir() if ".tmp" in p.name]
+
+
+@pytest.mark.parametrize("content", ["", "{not json", "[1, 2]", '{"gfx950_cu256": 3}', "\x00\x01",
+                                     '{"gfx950_cu256": {"tri4^10_ray4^11": 5}}',
+                                     '{"gfx950_cu256": {"tri4^10_ray4^11": {"node_width": 4}}}'])
+def test_autotune_cache_malformed_reads_empty(tmp_path, monkeypatch, content):
+    """A truncated or malformed cache file reads as empty, and the next save
+    replaces it with a valid one."""
+    from paper_2603_00292_amd import autotune
+
+    p = tmp_path / "tune.json"
+    p.write_text(content)
+    monkeypatch.setenv("RTQ_AUTOTUNE_CACHE", str(p))
+    assert autotune.cached_choice("gfx950_cu256", "tri4^10_ray4^11") is None
+    a = {"node_width": 4, "stack_entries": 16, "workgroup": 256, "ms": 1.9}
+    autotune.save_choice("gfx950_cu256", "tri4^10_ray4^11", a)
+    assert autotune.cached_choice("gfx950_cu256", "tri4^10_ray4^11") == a
